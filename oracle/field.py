@@ -1,0 +1,112 @@
+"""H(x, t) on the grid from the time-domain source charges (FP64).
+
+By linearity the field is the superposition of translated, rescaled copies of
+the fundamental solution (Section 3, the V_ext step):
+
+    H(x, t_n) = sum_i q_i(t_n) E_G(x - y_i)               [V m^-1 s^-1 per volt]
+
+and it equals the frequency-to-time quadrature of the per-frequency fields,
+because the quadrature and the superposition are both linear.  Three routes
+evaluate the same discrete quantity:
+
+* ``field_superposition``: the sum above with the direct E_G (tiny grids);
+* ``field_fft``: H = sum_k M(k) rho(k, t) exp(i k.x), M(k) = -i k S(k) /
+  (eps |k|^2 V), rho(k, t) = sum_i q_i(t) exp(-i k.y_i), as one full 3D inverse
+  FFT per time sample and component;
+* ``field_columns``: the same mode sum evaluated directly (no FFT) on selected
+  (x, y) grid columns, for every z node; used on grids too large for the FFT
+  route in memory.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import green
+
+
+def grid_points(cell) -> np.ndarray:
+    h = green.spacing(cell)
+    N = cell["N"]
+    ix, iy, iz = np.meshgrid(*(np.arange(N[a]) * h[a] for a in range(3)), indexing="ij")
+    return np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)
+
+
+def field_superposition(points, cell, s, src, q_t) -> np.ndarray:
+    """H at points (n_p, 3) for source charges q_t (n_time, n_src) -> (n_p, n_time, 3)."""
+    n_p = points.shape[0]
+    d = (points[:, None, :] - src[None, :, :]).reshape(-1, 3)
+    E = green.field(d, cell, s).reshape(n_p, src.shape[0], 3)
+    return np.einsum("psa,ts->pta", E, q_t)
+
+
+def _multiplier(cell, s):
+    """M_a(k) on the full FFT grid (numpy ordering), zero at k=0 and Nyquist."""
+    L, N = cell["L"], cell["N"]
+    m = [np.fft.fftfreq(N[a]) * N[a] for a in range(3)]
+    keep = [np.abs(m[a]) < N[a] / 2 for a in range(3)]
+    k = [2 * np.pi * m[a] / L[a] for a in range(3)]
+    KX, KY, KZ = np.meshgrid(*k, indexing="ij")
+    K2 = KX ** 2 + KY ** 2 + KZ ** 2
+    mask = keep[0][:, None, None] & keep[1][None, :, None] & keep[2][None, None, :] & (K2 > 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        w = np.where(mask, np.exp(-0.5 * ((KX * s[0]) ** 2 + (KY * s[1]) ** 2 + (KZ * s[2]) ** 2)) / K2, 0.0)
+    w = w / (green.permittivity(cell) * float(np.prod(L)))
+    return [-1j * Ka * w for Ka in (KX, KY, KZ)], (KX, KY, KZ)
+
+
+def field_fft(cell, s, src, q_t) -> np.ndarray:
+    """H on every grid node by 3D inverse FFTs -> float64 [nx][ny][nz][n_time][3]."""
+    N = cell["N"]
+    Mk, (KX, KY, KZ) = _multiplier(cell, s)
+    n_tot = N[0] * N[1] * N[2]
+    kflat = np.stack([KX.ravel(), KY.ravel(), KZ.ravel()], axis=1)
+    nt = q_t.shape[0]
+    rho = np.empty((n_tot, nt), dtype=np.complex128)
+    step = max(1, (1 << 24) // max(1, src.shape[0]))
+    for i in range(0, n_tot, step):                   # rho(k,t) = sum_i q_i(t) e^{-ik.y_i}
+        rho[i:i + step] = np.exp(-1j * (kflat[i:i + step] @ src.T)) @ q_t.T
+    rho = rho.reshape(N[0], N[1], N[2], nt)
+    H = np.empty((N[0], N[1], N[2], nt, 3))
+    for a in range(3):
+        spec = Mk[a][..., None] * rho
+        H[..., a] = (np.fft.ifftn(spec, axes=(0, 1, 2)) * n_tot).real
+    return H
+
+
+def field_columns(cell, s, src, q_t, cols_ij) -> np.ndarray:
+    """H on grid columns (ix, iy) for all z nodes -> (n_cols, nz, n_time, 3).
+
+    Direct mode sums: the (k_x, k_y) part is summed per source axis position,
+    the k_z part per node; no FFT is used.
+    """
+    L, N = cell["L"], cell["N"]
+    h = green.spacing(cell)
+    mx, my, mz = (green.axis_modes(N[a]) for a in range(3))
+    kx, ky, kz = (2 * np.pi * m / L[a] for a, m in enumerate((mx, my, mz)))
+    KX, KY, KZ = np.meshgrid(kx, ky, kz, indexing="ij")
+    K2 = KX ** 2 + KY ** 2 + KZ ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        w = np.where(K2 > 0, np.exp(-0.5 * ((KX * s[0]) ** 2 + (KY * s[1]) ** 2 + (KZ * s[2]) ** 2)) / K2, 0.0)
+    w = w / (green.permittivity(cell) * float(np.prod(L)))
+    Ma = [(-1j * Ka * w).reshape(kx.size * ky.size, kz.size) for Ka in (KX, KY, KZ)]
+    axes = np.unique(src[:, :2], axis=0)
+    zk = np.arange(N[2]) * h[2]
+    ez = np.exp(1j * np.outer(zk, kz))                                  # (nz, n_kz)
+    nt = q_t.shape[0]
+    out = np.empty((len(cols_ij), N[2], nt, 3))
+    # per axis position: D(kz, t) = sum over its sources of q(t) e^{-i kz z}
+    D = []
+    for ax in axes:
+        sel = np.all(src[:, :2] == ax, axis=1)
+        D.append(np.exp(-1j * np.outer(kz, src[sel, 2])) @ q_t[:, sel].T)     # (n_kz, nt)
+    for c, (ix, iy) in enumerate(cols_ij):
+        X, Y = ix * h[0], iy * h[1]
+        acc = [np.zeros((kz.size, nt), dtype=np.complex128) for _ in range(3)]
+        for ax, Dw in zip(axes, D):
+            ph = np.exp(1j * (np.add.outer(kx * (X - ax[0]), ky * (Y - ax[1])))).ravel()
+            for a in range(3):
+                B = ph @ Ma[a]                                            # (n_kz,)
+                acc[a] += B[:, None] * Dw
+        for a in range(3):
+            out[c, :, :, a] = (ez @ acc[a]).real
+    return out

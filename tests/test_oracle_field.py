@@ -1,0 +1,58 @@
+"""Pins of H(x, t): three independent routes agree, and the cell's symmetry holds."""
+import numpy as np
+from oracle import collocation, field, green, timegrid
+from paper_2605_13987_amd import workloads
+
+
+def _tiny():
+    cfg = workloads.config_small(k=21, n_xy=8, n_z=16, n_freq=4, n_time=5, n_pairs=2, n_colloc=6)
+    return cfg
+
+
+def test_superposition_fft_and_column_routes_agree():
+    cfg = _tiny()
+    cell, cols, spec = cfg["cell"], cfg["columns"], cfg["spectrum"]
+    s = green.smoothing_widths(cell, cols)
+    sol = collocation.solve_spectrum(cell, cols, spec)
+    qt = timegrid.to_time(sol["q"], spec)
+    src = collocation.sources(cols)
+    H2 = field.field_fft(cell, s, src, qt)
+    pts = field.grid_points(cell)
+    H1 = field.field_superposition(pts, cell, s, src, qt).reshape(H2.shape)
+    scale = np.max(np.abs(H2))
+    assert np.max(np.abs(H1 - H2)) <= 1e-12 * scale
+    ij = [(0, 0), (3, 5), (7, 7), (4, 4)]
+    H3 = field.field_columns(cell, s, src, qt, ij)
+    for c, (i, j) in enumerate(ij):
+        assert np.max(np.abs(H3[c] - H2[i, j])) <= 1e-12 * scale
+
+
+def test_column_route_matches_fft_on_c1(c1, c1_oracle):
+    cell, cols = c1["cell"], c1["columns"]
+    s = green.smoothing_widths(cell, cols)
+    ij = [(0, 0), (16, 16), (5, 27), (31, 2)]
+    H3 = field.field_columns(cell, s, c1_oracle["src"], c1_oracle["q_t"], ij)
+    H = c1_oracle["H"]
+    for c, (i, j) in enumerate(ij):
+        assert np.max(np.abs(H3[c] - H[i, j])) <= 1e-11 * np.max(np.abs(H))
+
+
+def test_c4_and_mirror_symmetry_about_the_readout(c1, c1_oracle):
+    """Equal bias quarter-columns on a square cell: the axis charges are C4
+    symmetric about the readout axis, hence so is H (as a vector field)."""
+    H = c1_oracle["H"]
+    N = c1["cell"]["N"][0]
+    i = np.arange(N)
+    # rotation (u, v) -> (-v, u) about the readout axis maps node (i, j) to (N - j, i)
+    I, J = np.meshgrid(i, i, indexing="ij")
+    Hx_rot = H[(N - J) % N, I, :, :, 0]
+    Hy_rot = H[(N - J) % N, I, :, :, 1]
+    Hz_rot = H[(N - J) % N, I, :, :, 2]
+    sc = np.max(np.abs(H))
+    assert np.max(np.abs(Hx_rot + H[I, J, :, :, 1])) <= 1e-12 * sc
+    assert np.max(np.abs(Hy_rot - H[I, J, :, :, 0])) <= 1e-12 * sc
+    assert np.max(np.abs(Hz_rot - H[I, J, :, :, 2])) <= 1e-12 * sc
+    # mirror x -> p - x
+    Hm = H[(N - i) % N]
+    assert np.max(np.abs(Hm[..., 0] + H[..., 0])) <= 1e-12 * sc
+    assert np.max(np.abs(Hm[..., 1:] - H[..., 1:])) <= 1e-12 * sc
