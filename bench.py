@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of the weighting-field path on one MI355X.
+
+One step = the whole hot path on one batch of synthetic input: Green's tables,
+collocation solves for all frequencies, time transform, in-plane field table,
+synthesis of H(x, y, z, t) on the whole grid, and the Eq. 1 current of all
+carriers.  Workload: periodic 50x50x300 um pixel on a 128x128x256 grid, five
+seeded column resistivities, 256 frequencies up to 50 GHz, 200 samples of
+10 ps, one minimum-ionising track along z with 1e4 electron/hole pairs
+(2e4 carriers).  H and the current are computed in float32, the boundary fit
+and time transform in float64.  Inputs are resident on the GPU before timing.
+
+Prints one JSON line.  value = grid points x frequencies per second of the
+whole step; tracks/s and carriers/s of the current stage are extra fields.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "H(x,t) grid·freq pts/s + carrier tracks/s, mixed vs plain FP64 at stated rel err"
+HBM_PEAK_GBS = 8000.0
+SAMPLE_COLUMNS = [(0, 0), (64, 64), (77, 64), (10, 100)]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-carrier-stride", type=int, default=20)
+    return ap.parse_args()
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [p.get("num_threads", 1) for p in threadpool_info()]
+        return max(n) if n else 1
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(cfg, h_cols_gpu, stride):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import numpy as np
+
+    import oracle
+    from paper_2605_13987_amd import workloads
+
+    cell, cols, spec = cfg["cell"], cfg["columns"], cfg["spectrum"]
+    t0 = time.perf_counter()
+    ref = oracle.weighting_field(cell, cols, spec, route="columns", cols_ij=SAMPLE_COLUMNS)
+    t_field = time.perf_counter() - t0
+    pts = len(SAMPLE_COLUMNS) * cell["N"][2] * spec["n_freq"]
+    err = float(np.linalg.norm(h_cols_gpu - ref["H_cols"]) / np.linalg.norm(ref["H_cols"]))
+    # convolution: every stride-th carrier on a synthetic field of the same grid
+    car = cfg["carriers"]
+    sub = np.arange(0, car["pos"].shape[0], stride)
+    f = workloads.synthetic_h_factors(workloads.rng_for(99), cell["N"], spec["n_time"])
+    sub_car = dict(pos=car["pos"][sub], charge=car["charge"][sub], track=car["track"][sub],
+                   n_tracks=car["n_tracks"])
+    t1 = time.perf_counter()
+    oracle.induced_current(lambda ix, iy, iz: workloads.synthetic_h_values(f, ix, iy, iz), cell, sub_car)
+    t_conv = time.perf_counter() - t1
+    frac = sub.size / car["pos"].shape[0]
+    return dict(value=pts / t_field, unit="grid*freq pts/s", cores=blas_threads(), kind="oracle",
+                sample=(f"boundary fit (all {spec['n_freq']} frequencies) + time transform + field on "
+                        f"{len(SAMPLE_COLUMNS)} of {cell['N'][0] * cell['N'][1]} grid columns (all z, t), "
+                        f"{t_field:.1f} s; Eq. 1 on {sub.size} of {car['pos'].shape[0]} carriers, "
+                        f"{t_conv:.1f} s"),
+                tracks_per_s=frac * car["n_tracks"] / t_conv,
+                carriers_per_s=sub.size / t_conv), err
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the path's multi-GPU decomposition is described, not built).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2605_13987_amd import layout, workloads, wt
+
+    cfg = workloads.mip_pixel_128x128x256()
+    cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
+    N = cell["N"]
+    stream = torch.cuda.current_stream()
+    ctx = wt.wt_context_create(0, stream.cuda_stream)
+    plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2, ir_tol=1e-12)
+    ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    h = torch.empty(lay["h_bytes"] // 4, dtype=torch.float32, device="cuda")
+    pos = torch.from_numpy(car["pos"]).to("cuda", torch.float32)
+    q = torch.from_numpy(car["charge"]).to("cuda", torch.float32)
+    tr = torch.from_numpy(car["track"]).to("cuda")
+    n_c, n_tr = pos.shape[0], car["n_tracks"]
+    out = torch.empty((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
+
+    def step():
+        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"])
+        wt.wt_current(ctx, plan, h.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
+                      out.data_ptr())
+
+    st, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"], report=True)
+    print(f"# solve report: {rep}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1) / args.steps
+    print(f"# timed {args.steps} steps: {ms:.3f} ms/step (wall {1e3 * t_wall / args.steps:.3f} ms)",
+          file=sys.stderr, flush=True)
+
+    # per-stage durations from HIP events recorded by the library on the same stream
+    wt.wt_context_enable_timing(ctx, True)
+    stage = {}
+    reps = max(3, min(args.steps, 10))
+    for _ in range(reps):
+        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"])
+        for name, t in wt.wt_context_stage_times(ctx):
+            stage[name] = stage.get(name, 0.0) + t / reps
+        wt.wt_current(ctx, plan, h.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
+                      out.data_ptr())
+        for name, t in wt.wt_context_stage_times(ctx):
+            stage[name] = stage.get(name, 0.0) + t / reps
+    wt.wt_context_enable_timing(ctx, False)
+
+    n_pts = N[0] * N[1] * N[2]
+    t_h = sum(v for k, v in stage.items() if k != "current") * 1e-3
+    t_cur = stage["current"] * 1e-3
+    # synthesis kernel: algorithmic bytes = write of H + read of the field table per column
+    w = len(cfg["columns"])
+    synth_bytes = lay["h_bytes"] + N[0] * N[1] * w * (N[2] // 2) * 3 * 8
+    achieved = synth_bytes / (stage["synthesis"] * 1e-3) / 1e9
+
+    per_col = N[2] * spec["n_time"] * 3
+    idx = torch.tensor([i * N[1] + j for i, j in SAMPLE_COLUMNS], device="cuda")
+    h_cols = layout.to_standard(h.view(-1, per_col).index_select(0, idx).cpu().numpy().astype(np.float64),
+                                N, spec["n_time"], lay["h_time_block"])
+
+    line = {
+        "metric": METRIC,
+        "value": n_pts * spec["n_freq"] / (ms * 1e-3),
+        "unit": "grid*freq pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"plain path: {N[0]}x{N[1]}x{N[2]} grid of a 50x50x300 um pixel, readout + bias "
+                         f"columns (r = 5 um, 5 seeded resistivities), {spec['n_freq']} frequencies to 50 GHz, "
+                         f"{spec['n_time']} x 10 ps, one MIP track with {n_c // 2} e/h pairs ({n_c} carriers); "
+                         f"f32 field/FFT/convolution, f64 boundary fit"),
+            "grid": list(N), "n_freq": spec["n_freq"], "n_time": spec["n_time"], "n_carriers": n_c,
+            "n_tracks": n_tr, "parallelism": "single GPU",
+        },
+        "tracks_per_s": n_tr / t_cur,
+        "carriers_per_s": n_c / t_cur,
+        "h_grid_freq_pts_per_s": n_pts * spec["n_freq"] / t_h,
+        "h_grid_time_pts_per_s": n_pts * spec["n_time"] / t_h,
+        "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "roofline": {"kernel": "k_synthesis", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": synth_bytes},
+        "solve_report": rep,
+    }
+    if not args.no_cpu_baseline:
+        base, err = cpu_baseline(cfg, h_cols, args.cpu_carrier_stride)
+        line["cpu_baseline"] = base
+        line["rel_err"] = {"H_sampled_columns_vs_fp64_oracle": err}
+    print(json.dumps(line), flush=True)
+    wt.wt_h_plan_destroy(plan)
+    wt.wt_context_destroy(ctx)
+
+
+if __name__ == "__main__":
+    main()

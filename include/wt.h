@@ -1,0 +1,206 @@
+/*
+ * wt.h -- time-dependent weighting field H(x,t) of a 3D diamond pixel with
+ * resistive graphitised columns, and the induced current of drifting charge
+ * carriers (extended Ramo-Shockley theorem, Eq. 1 of the paper), on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Two calls carry the method (paper, Section 2 "workflow of micro-steps":
+ * geometry -> correlation function H(x,t); H + carrier paths -> currents):
+ *
+ *   wt_h_solve  geometry + column resistivities + frequency/time grid -> H
+ *               (abstract and Section 3: point charges on the electrode
+ *               boundaries fitted to the boundary conditions, i.e. the
+ *               fundamental solutions, then a spectral extension to the bulk;
+ *               the equation solved is the quasi-static, third-order limit of
+ *               Maxwell's equations, div((sigma + i w eps) grad psi) = 0 per
+ *               frequency, followed by a frequency-to-time transform)
+ *   wt_current  H + carrier polylines -> i_track(t)   (Eq. 1, introduction;
+ *               Section 3: the convolution of every carrier's velocity with H)
+ *
+ * Conventions shared by every call:
+ *  - SI units (m, s, ohm*m, C, V).  V_w = 1 V.
+ *  - All device buffers are caller-owned (e.g. torch tensors); the library
+ *    never allocates, frees or retains device memory.  Pointers prefixed d_
+ *    are device pointers; everything else is host memory read during the
+ *    call only.
+ *  - Work is enqueued on the context's HIP stream and returns without
+ *    waiting, except where a call says it synchronises.
+ *  - Every function returns wt_status (0 = WT_OK, negative = error).  No
+ *    exception or abort crosses this boundary.  On WT_E_HIP the runtime's
+ *    message is kept in the context (wt_context_last_error).
+ *  - A context is not thread-safe; a plan is immutable and may be shared.
+ */
+#ifndef WT_H
+#define WT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WT_OK = 0,
+    WT_E_INVALID_ARG = -1,      /* null pointer, non-positive or non-finite size/value */
+    WT_E_GEOMETRY = -2,         /* column off a grid node, overlapping columns,
+                                   column outside the cell, radius too large */
+    WT_E_UNSUPPORTED_SIZE = -3, /* grid size odd or not 2*3*5-smooth, or beyond a
+                                   limit listed below */
+    WT_E_WORKSPACE = -4,        /* a caller buffer is smaller than required */
+    WT_E_SINGULAR = -5,         /* zero pivot in a collocation solve */
+    WT_E_NOT_CONVERGED = -6,    /* refinement did not reach ir_tol */
+    WT_E_HIP = -7               /* HIP runtime error (message in the context) */
+} wt_status;
+
+typedef enum {
+    WT_F64 = 0,   /* bulk FFTs, H and the convolution in double */
+    WT_F32 = 1    /* bulk FFTs, H and the convolution in float (the boundary
+                     fit and the time transform stay in double) */
+} wt_precision;
+
+/* Periodic cell L_x x L_y x L_z on an N_x x N_y x N_z grid of nodes
+ * (i h_x, j h_y, k h_z), h_a = L_a / N_a.  N_a even, 2*3*5-smooth, 4..1024.
+ * The diamond bulk has relative permittivity eps_r; sigma_bulk must be 0. */
+typedef struct {
+    double Lx, Ly, Lz;
+    int Nx, Ny, Nz;
+    double eps_r;
+    double sigma_bulk;
+} wt_cell;
+
+/* A resistive column: axis (x, y) on a grid node, radius, contact end
+ * z_contact (held at v_applied) and free end z_free, both in [0, L_z].
+ * n_colloc >= 2 nodes z_m = z_contact + m (z_free - z_contact)/(n_colloc-1).
+ * resistivity[0..n_resistivity-1] (ohm*m, > 0) are quarter-columns in
+ * parallel; the column conductivity is the mean of 1/resistivity. */
+typedef struct {
+    double x, y;
+    double radius;
+    double z_contact, z_free;
+    double resistivity[4];
+    int n_resistivity;
+    int n_colloc;
+    double v_applied;
+} wt_column;
+
+/* Frequencies f_j = j df (j < n_freq), times t_n = n dt (n < n_time).
+ * n_freq 1..65535; n_time 1..512. */
+typedef struct {
+    int n_freq;
+    double df;
+    int n_time;
+    double dt;
+} wt_spectrum;
+
+typedef struct {
+    int precision;      /* wt_precision */
+    int ir_max_iter;    /* refinement sweeps after the LU solve, 0..16 */
+    double ir_tol;      /* target normwise backward error (>= 0) */
+} wt_h_options;
+
+/* Filled by wt_h_solve when a report pointer is given (that call then
+ * synchronises the stream). */
+typedef struct {
+    double backward_error_max;  /* max over frequencies, normwise, after refinement */
+    double pivot_ratio_max;     /* max over frequencies of max|U_ii| / min|U_ii| */
+    int ir_iters_max;           /* refinement sweeps used (max over frequencies) */
+    int singular_count;         /* frequencies whose LU met a zero pivot */
+} wt_h_report;
+
+/* Sizes and byte offsets of a plan.  H is stored time-blocked:
+ *   H[x][y][tb][z][tin][a],  t = tb * h_time_block + tin,  a = component x,y,z
+ * where the last block holds n_time - tb*h_time_block samples; for node
+ * (x, y, z), time t and component a the element index is
+ *   (x*Ny + y)*Nz*n_time*3 + tb*h_time_block*Nz*3 + z*Tb*3 + tin*3 + a
+ * with Tb the length of block tb.  Each node's lag series is contiguous
+ * within a block.  The element type is double (WT_F64) or float (WT_F32).
+ * The workspace offsets locate intermediate results (for inspection):
+ *   A      double  [n_q][n_q]        collocation matrix, V/C
+ *   qw     double2 [n_freq][n_q+1]   charges q(w_j) (C/V) then the gauge c
+ *   qt     double  [n_time][n_q]     charges q(t_n), C/(V s)
+ *   qhat   T2      [n_time][n_cols][Nz/2]  per-column z-transform of q(t_n)
+ *   ehat   T2      [Nx][Ny][Nz/2][3] in-plane field table of one unit column */
+typedef struct {
+    size_t workspace_bytes;
+    size_t h_bytes;
+    int h_time_block;
+    int n_q;
+    size_t off_A, off_qw, off_qt, off_qhat, off_ehat;
+} wt_h_layout;
+
+typedef struct wt_context wt_context;
+typedef struct wt_h_plan wt_h_plan;
+
+/* Carriers for wt_current.  Element type of d_pos, d_charge and the output
+ * follows the plan's precision (double or float).
+ *   d_pos    [n_carriers][n_time+1][3]  polyline P_c(t_0..t_n_time), m, any
+ *            real coordinates (the cell is periodic)
+ *   d_charge [n_carriers]  carrier charge, C
+ *   d_track  [n_carriers]  track index in [0, n_tracks); carriers outside
+ *            this range are skipped */
+typedef struct {
+    int n_carriers;
+    int n_tracks;
+    const void* d_pos;
+    const void* d_charge;
+    const int* d_track;
+} wt_carriers;
+
+/* Create a context bound to HIP device `hip_device` and the HIP stream
+ * `hip_stream` (a hipStream_t; NULL = the default stream).  Fails with
+ * WT_E_HIP when no such device exists. */
+wt_status wt_context_create(wt_context** ctx, int hip_device, void* hip_stream);
+wt_status wt_context_destroy(wt_context* ctx);
+/* Last HIP error message of the context ("" if none); owned by the context. */
+const char* wt_context_last_error(const wt_context* ctx);
+
+/* Per-stage timing (HIP events on the context's stream).  When enabled,
+ * every wt_h_solve / wt_current records an event between its stages;
+ * wt_context_stage_times synchronises the stream and returns the stage
+ * durations of the last call, in milliseconds, with their names
+ * (wt_stage_name).  n_out receives the number of stages written. */
+wt_status wt_context_enable_timing(wt_context* ctx, int enable);
+wt_status wt_context_stage_times(wt_context* ctx, double* ms, int max_stages, int* stage_ids, int* n_out);
+const char* wt_stage_name(int stage_id);
+
+/* Validate a problem and build a plan (host only, no GPU work).  The plan
+ * copies everything it needs.  layout receives the required workspace and H
+ * sizes. */
+wt_status wt_h_plan_create(const wt_cell* cell, const wt_column* cols, int n_cols,
+                           const wt_spectrum* spectrum, const wt_h_options* options,
+                           wt_h_plan** plan, wt_h_layout* layout);
+wt_status wt_h_plan_destroy(wt_h_plan* plan);
+wt_status wt_h_plan_layout(const wt_h_plan* plan, wt_h_layout* layout);
+
+/* Solve for H: Green's tables and collocation matrix, one bordered complex
+ * FP64 collocation solve (LU with partial pivoting + refinement) per
+ * frequency, time transform of the charges, in-plane field table, and the
+ * per-column synthesis of H(x, y, z, t) for every grid node and time sample.
+ * d_workspace: >= layout.workspace_bytes, 256-byte aligned; d_h: >=
+ * layout.h_bytes.  With report != NULL the call synchronises, fills the
+ * report and returns WT_E_SINGULAR / WT_E_NOT_CONVERGED when they occurred
+ * (H is still written).  Without a report these conditions are not checked. */
+wt_status wt_h_solve(wt_context* ctx, const wt_h_plan* plan,
+                     void* d_workspace, size_t workspace_bytes,
+                     void* d_h, size_t h_bytes, wt_h_report* report);
+
+/* Induced current (Eq. 1): for every carrier and every polyline step m with a
+ * non-zero displacement dx = P(t_{m+1}) - P(t_m), the field at the step
+ * midpoint (trilinear interpolation of the nodal H, periodic wrap) at lag
+ * n - m is projected on dx and accumulated:
+ *   i[track][n] = -(1/V_w) sum_{c in track} q_c sum_{m<=n} H(xbar_{c,m}, t_{n-m}) . dx_{c,m}
+ * d_h is H as written by wt_h_solve for the same plan; d_i_out [n_tracks]
+ * [n_time] is overwritten.  No workspace is needed (d_workspace may be NULL
+ * and workspace_bytes 0).  Summation order across carriers is not fixed
+ * (atomic accumulation), so results can differ in the last bits. */
+wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h,
+                     const wt_carriers* carriers, void* d_workspace, size_t workspace_bytes,
+                     void* d_i_out);
+
+const char* wt_status_string(wt_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WT_H */

@@ -1,0 +1,395 @@
+// C ABI of the library (declared in include/wt.h): argument validation, plan
+// and workspace layout, and the order of the kernel launches.
+#include "wt.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+struct wt_context {
+    int device;
+    hipStream_t stream;
+    std::string last_error;
+    bool timing;
+    hipEvent_t ev[8];
+    int n_events;       // events recorded by the last call
+    int stage_ids[8];   // stage id of the interval ending at ev[i+1]
+};
+
+struct wt_h_plan {
+    wt::Plan p;
+};
+
+namespace {
+
+using wt::Plan;
+
+constexpr int kMaxUnknowns = 528;
+constexpr int kStageTables = 0, kStageSolve = 1, kStageTime = 2, kStageFieldTable = 3, kStageSynthesis = 4,
+              kStageCurrent = 5;
+const char* const kStageNames[] = {"green_tables", "collocation_solve", "time_transform",
+                                   "field_table",  "synthesis",         "current"};
+
+bool pos_finite(double v) { return std::isfinite(v) && v > 0.0; }
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+wt_status hip_fail(wt_context* ctx, hipError_t e, const char* where) {
+    if (ctx) {
+        ctx->last_error = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return WT_E_HIP;
+}
+
+#define WT_HIP(ctx, call, where)                          \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+    } while (0)
+
+wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_cols, const wt_spectrum* sp,
+                             const wt_h_options* opt, Plan& p) {
+    std::memset(&p, 0, sizeof(p));
+    if (!cell || !cols || !sp || !opt) return WT_E_INVALID_ARG;
+    if (n_cols < 1 || n_cols > wt::kMaxCols) return WT_E_INVALID_ARG;
+    const double L[3] = {cell->Lx, cell->Ly, cell->Lz};
+    const int N[3] = {cell->Nx, cell->Ny, cell->Nz};
+    for (int a = 0; a < 3; ++a) {
+        if (!pos_finite(L[a])) return WT_E_INVALID_ARG;
+        if (N[a] <= 0) return WT_E_INVALID_ARG;
+        if (N[a] < 4 || N[a] > 1024 || (N[a] & 1)) return WT_E_UNSUPPORTED_SIZE;
+        p.nrad[a] = wt::factorize(N[a], p.rad[a]);
+        if (p.nrad[a] < 0) return WT_E_UNSUPPORTED_SIZE;
+        p.L[a] = L[a];
+        p.N[a] = N[a];
+    }
+    if (!pos_finite(cell->eps_r)) return WT_E_INVALID_ARG;
+    if (!(cell->sigma_bulk == 0.0)) return WT_E_INVALID_ARG;   // conducting bulk not supported
+    if (sp->n_freq < 1 || sp->n_freq > 65535 || sp->n_time < 1) return WT_E_INVALID_ARG;
+    if (sp->n_time > wt::kMaxTime) return WT_E_UNSUPPORTED_SIZE;
+    if (!pos_finite(sp->dt)) return WT_E_INVALID_ARG;
+    if (sp->n_freq > 1 ? !pos_finite(sp->df) : !(std::isfinite(sp->df) && sp->df >= 0.0)) return WT_E_INVALID_ARG;
+    if (opt->precision != WT_F64 && opt->precision != WT_F32) return WT_E_INVALID_ARG;
+    if (opt->ir_max_iter < 0 || opt->ir_max_iter > 16) return WT_E_INVALID_ARG;
+    if (!(std::isfinite(opt->ir_tol) && opt->ir_tol >= 0.0)) return WT_E_INVALID_ARG;
+
+    p.eps = cell->eps_r * wt::kEps0;
+    p.n_cols = n_cols;
+    const double h[3] = {L[0] / N[0], L[1] / N[1], L[2] / N[2]};
+    int offset = 0;
+    double max_node_spacing = 0.0;
+    for (int w = 0; w < n_cols; ++w) {
+        const wt_column& c = cols[w];
+        if (!std::isfinite(c.x) || !std::isfinite(c.y) || !pos_finite(c.radius) || !std::isfinite(c.z_contact) ||
+            !std::isfinite(c.z_free) || !std::isfinite(c.v_applied))
+            return WT_E_INVALID_ARG;
+        if (c.n_colloc < 2 || c.n_resistivity < 1 || c.n_resistivity > 4) return WT_E_INVALID_ARG;
+        double cond = 0.0;
+        for (int q = 0; q < c.n_resistivity; ++q) {
+            if (!pos_finite(c.resistivity[q])) return WT_E_INVALID_ARG;
+            cond += 1.0 / c.resistivity[q];
+        }
+        if (c.x < 0.0 || c.x >= L[0] || c.y < 0.0 || c.y >= L[1]) return WT_E_GEOMETRY;
+        if (c.z_contact < 0.0 || c.z_contact > L[2] || c.z_free < 0.0 || c.z_free > L[2] ||
+            c.z_contact == c.z_free)
+            return WT_E_GEOMETRY;
+        const double fx = c.x / h[0], fy = c.y / h[1];
+        if (std::fabs(fx - std::nearbyint(fx)) > 1e-6 || std::fabs(fy - std::nearbyint(fy)) > 1e-6)
+            return WT_E_GEOMETRY;
+        if (c.radius >= 0.5 * std::fmin(L[0], L[1])) return WT_E_GEOMETRY;
+        wt::Column& o = p.col[w];
+        o.x = c.x;
+        o.y = c.y;
+        o.radius = c.radius;
+        o.z_contact = c.z_contact;
+        o.z_free = c.z_free;
+        o.sigma = cond / c.n_resistivity;
+        o.v_applied = c.v_applied;
+        o.n = c.n_colloc;
+        o.ix = ((int)std::nearbyint(fx)) % N[0];
+        o.iy = ((int)std::nearbyint(fy)) % N[1];
+        o.offset = offset;
+        offset += c.n_colloc;
+        o.width = wt::kColWidthFraction * c.radius;
+        const double kc = std::sqrt(2.0 * wt::kCutoffExponent) / o.width;
+        for (int a = 0; a < 3; ++a) {
+            const double mm = std::floor(kc * L[a] / (2.0 * wt::kPi)) + 1.0;
+            if (mm > 4096.0) return WT_E_UNSUPPORTED_SIZE;
+            o.mmax[a] = (int)mm;
+        }
+        max_node_spacing = std::fmax(max_node_spacing, std::fabs(c.z_free - c.z_contact) / (c.n_colloc - 1));
+    }
+    // columns must not overlap: in-plane circles and z ranges both intersecting
+    for (int a = 0; a < n_cols; ++a)
+        for (int b = a + 1; b < n_cols; ++b) {
+            double dx = cols[a].x - cols[b].x, dy = cols[a].y - cols[b].y;
+            dx -= L[0] * std::nearbyint(dx / L[0]);
+            dy -= L[1] * std::nearbyint(dy / L[1]);
+            const double lo_a = std::fmin(cols[a].z_contact, cols[a].z_free), hi_a = std::fmax(cols[a].z_contact, cols[a].z_free);
+            const double lo_b = std::fmin(cols[b].z_contact, cols[b].z_free), hi_b = std::fmax(cols[b].z_contact, cols[b].z_free);
+            if (std::hypot(dx, dy) < cols[a].radius + cols[b].radius && lo_a <= hi_b && lo_b <= hi_a)
+                return WT_E_GEOMETRY;
+        }
+    p.n_q = offset;
+    p.n = offset + 1;
+    if (p.n > kMaxUnknowns) return WT_E_UNSUPPORTED_SIZE;
+
+    p.n_freq = sp->n_freq;
+    p.n_time = sp->n_time;
+    p.df = sp->df;
+    p.dt = sp->dt;
+    const double nyq = 0.5 / sp->dt;
+    p.last_weight_one = (sp->n_freq > 1 && std::fabs(sp->df * (sp->n_freq - 1) - nyq) <= 1e-9 * nyq) ? 1 : 0;
+    p.precision = opt->precision;
+    p.ir_max_iter = opt->ir_max_iter;
+    p.ir_tol = opt->ir_tol;
+    p.s_bulk[0] = 1.5 * h[0];
+    p.s_bulk[1] = 1.5 * h[1];
+    p.s_bulk[2] = std::fmax(1.5 * h[2], max_node_spacing);
+    p.nkz_tab = 0;
+    for (int w = 0; w < n_cols; ++w) p.nkz_tab = p.nkz_tab > p.col[w].mmax[2] + 1 ? p.nkz_tab : p.col[w].mmax[2] + 1;
+    p.nzh = N[2] / 2;
+
+    const size_t re = p.precision == WT_F64 ? sizeof(double) : sizeof(float);
+    const size_t cx = 2 * re;
+    // time block of the H layout: the synthesis stages a whole block in LDS
+    int tb = sp->n_time < 32 ? sp->n_time : 32;
+    const size_t lds_budget = 160 * 1024;
+    auto lds_need = [&](int t) {
+        return (size_t)n_cols * p.nzh * 3 * cx + (size_t)N[2] * t * 3 * re + (size_t)2 * N[2] * cx;
+    };
+    while (tb > 1 && lds_need(tb) > lds_budget) tb = (tb + 1) / 2;
+    if (lds_need(tb) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
+    p.tb = tb;
+
+    size_t off = 0;
+    for (int a = 0; a < 3; ++a) {
+        p.off_tw[a] = off;
+        off = align256(off + (size_t)N[a] * cx);
+    }
+    p.off_g = off;
+    off = align256(off + (size_t)n_cols * n_cols * p.nkz_tab * sizeof(double));
+    p.off_A = off;
+    off = align256(off + (size_t)p.n_q * p.n_q * sizeof(double));
+    p.off_lu = off;
+    off = align256(off + (size_t)p.n_freq * p.n * p.n * 16);
+    p.off_piv = off;
+    off = align256(off + (size_t)p.n_freq * p.n * sizeof(int));
+    p.off_qw = off;
+    off = align256(off + (size_t)p.n_freq * p.n * 16);
+    p.off_rep = off;
+    off = align256(off + (size_t)p.n_freq * sizeof(wt::SolveReport));
+    p.off_qt = off;
+    off = align256(off + (size_t)p.n_time * p.n_q * sizeof(double));
+    p.off_qhat = off;
+    off = align256(off + (size_t)p.n_time * n_cols * p.nzh * cx);
+    p.off_ehat = off;
+    off = align256(off + (size_t)N[0] * N[1] * p.nzh * 3 * cx);
+    p.ws_bytes = off;
+    p.h_bytes = (size_t)N[0] * N[1] * N[2] * p.n_time * 3 * re;
+    return WT_OK;
+}
+
+void fill_layout(const Plan& p, wt_h_layout* l) {
+    l->workspace_bytes = p.ws_bytes;
+    l->h_bytes = p.h_bytes;
+    l->h_time_block = p.tb;
+    l->n_q = p.n_q;
+    l->off_A = p.off_A;
+    l->off_qw = p.off_qw;
+    l->off_qt = p.off_qt;
+    l->off_qhat = p.off_qhat;
+    l->off_ehat = p.off_ehat;
+}
+
+wt_status bind(wt_context* ctx) {
+    WT_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    return WT_OK;
+}
+
+wt_status mark(wt_context* ctx, int stage) {
+    if (!ctx->timing) return WT_OK;
+    if (ctx->n_events >= 8) return WT_OK;
+    WT_HIP(ctx, hipEventRecord(ctx->ev[ctx->n_events], ctx->stream), "hipEventRecord");
+    if (ctx->n_events > 0) ctx->stage_ids[ctx->n_events - 1] = stage;
+    ++ctx->n_events;
+    return WT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wt_status_string(wt_status s) {
+    switch (s) {
+        case WT_OK: return "ok";
+        case WT_E_INVALID_ARG: return "invalid argument";
+        case WT_E_GEOMETRY: return "invalid geometry";
+        case WT_E_UNSUPPORTED_SIZE: return "unsupported size";
+        case WT_E_WORKSPACE: return "buffer too small";
+        case WT_E_SINGULAR: return "singular collocation system";
+        case WT_E_NOT_CONVERGED: return "refinement did not converge";
+        case WT_E_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char* wt_stage_name(int id) {
+    return (id >= 0 && id < (int)(sizeof(kStageNames) / sizeof(kStageNames[0]))) ? kStageNames[id] : "";
+}
+
+wt_status wt_context_create(wt_context** out, int hip_device, void* hip_stream) {
+    if (!out) return WT_E_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count) return WT_E_HIP;
+    wt_context* ctx = new (std::nothrow) wt_context();
+    if (!ctx) return WT_E_INVALID_ARG;
+    ctx->device = hip_device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->timing = false;
+    ctx->n_events = 0;
+    for (auto& e : ctx->ev) e = nullptr;
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        delete ctx;
+        return WT_E_HIP;
+    }
+    *out = ctx;
+    return WT_OK;
+}
+
+wt_status wt_context_destroy(wt_context* ctx) {
+    if (!ctx) return WT_E_INVALID_ARG;
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return WT_OK;
+}
+
+const char* wt_context_last_error(const wt_context* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+wt_status wt_context_enable_timing(wt_context* ctx, int enable) {
+    if (!ctx) return WT_E_INVALID_ARG;
+    if (enable && !ctx->ev[0]) {
+        wt_status st = bind(ctx);
+        if (st != WT_OK) return st;
+        for (auto& e : ctx->ev) WT_HIP(ctx, hipEventCreate(&e), "hipEventCreate");
+    }
+    ctx->timing = enable != 0;
+    ctx->n_events = 0;
+    return WT_OK;
+}
+
+wt_status wt_context_stage_times(wt_context* ctx, double* ms, int max_stages, int* stage_ids, int* n_out) {
+    if (!ctx || !n_out || (max_stages > 0 && (!ms || !stage_ids))) return WT_E_INVALID_ARG;
+    *n_out = 0;
+    if (!ctx->timing || ctx->n_events < 2) return WT_OK;
+    WT_HIP(ctx, hipEventSynchronize(ctx->ev[ctx->n_events - 1]), "hipEventSynchronize");
+    int k = 0;
+    for (int i = 0; i + 1 < ctx->n_events && k < max_stages; ++i, ++k) {
+        float t = 0.0f;
+        WT_HIP(ctx, hipEventElapsedTime(&t, ctx->ev[i], ctx->ev[i + 1]), "hipEventElapsedTime");
+        ms[k] = t;
+        stage_ids[k] = ctx->stage_ids[i];
+    }
+    *n_out = k;
+    return WT_OK;
+}
+
+wt_status wt_h_plan_create(const wt_cell* cell, const wt_column* cols, int n_cols, const wt_spectrum* spectrum,
+                           const wt_h_options* options, wt_h_plan** plan, wt_h_layout* layout) {
+    if (!plan || !layout) return WT_E_INVALID_ARG;
+    *plan = nullptr;
+    wt_h_plan* h = new (std::nothrow) wt_h_plan();
+    if (!h) return WT_E_INVALID_ARG;
+    const wt_status st = validate_and_build(cell, cols, n_cols, spectrum, options, h->p);
+    if (st != WT_OK) {
+        delete h;
+        return st;
+    }
+    fill_layout(h->p, layout);
+    *plan = h;
+    return WT_OK;
+}
+
+wt_status wt_h_plan_destroy(wt_h_plan* plan) {
+    if (!plan) return WT_E_INVALID_ARG;
+    delete plan;
+    return WT_OK;
+}
+
+wt_status wt_h_plan_layout(const wt_h_plan* plan, wt_h_layout* layout) {
+    if (!plan || !layout) return WT_E_INVALID_ARG;
+    fill_layout(plan->p, layout);
+    return WT_OK;
+}
+
+wt_status wt_h_solve(wt_context* ctx, const wt_h_plan* plan, void* d_workspace, size_t workspace_bytes, void* d_h,
+                     size_t h_bytes, wt_h_report* report) {
+    if (!ctx || !plan || !d_workspace || !d_h) return WT_E_INVALID_ARG;
+    const Plan& p = plan->p;
+    if (workspace_bytes < p.ws_bytes || h_bytes < p.h_bytes) return WT_E_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) || (reinterpret_cast<uintptr_t>(d_h) & 15))
+        return WT_E_INVALID_ARG;
+    wt_status st = bind(ctx);
+    if (st != WT_OK) return st;
+    ctx->n_events = 0;
+    hipStream_t s = ctx->stream;
+    if ((st = mark(ctx, -1)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_twiddles(p, d_workspace, s), "twiddles");
+    WT_HIP(ctx, wt::launch_green_tables(p, d_workspace, s), "green_tables");
+    if ((st = mark(ctx, kStageTables)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_collocation_solve(p, d_workspace, s), "collocation_solve");
+    if ((st = mark(ctx, kStageSolve)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_time_transform(p, d_workspace, s), "time_transform");
+    if ((st = mark(ctx, kStageTime)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_field_table(p, d_workspace, s), "field_table");
+    if ((st = mark(ctx, kStageFieldTable)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_synthesis(p, d_workspace, d_h, s), "synthesis");
+    if ((st = mark(ctx, kStageSynthesis)) != WT_OK) return st;
+    if (!report) return WT_OK;
+
+    std::vector<wt::SolveReport> rep(p.n_freq);
+    WT_HIP(ctx, hipMemcpyAsync(rep.data(), static_cast<char*>(d_workspace) + p.off_rep,
+                               rep.size() * sizeof(wt::SolveReport), hipMemcpyDeviceToHost, s),
+           "report copy");
+    WT_HIP(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+    report->backward_error_max = 0.0;
+    report->pivot_ratio_max = 0.0;
+    report->ir_iters_max = 0;
+    report->singular_count = 0;
+    for (const auto& r : rep) {
+        report->backward_error_max = std::fmax(report->backward_error_max, r.backward_error);
+        report->pivot_ratio_max = std::fmax(report->pivot_ratio_max, r.pivot_ratio);
+        report->ir_iters_max = report->ir_iters_max > r.iters ? report->ir_iters_max : r.iters;
+        report->singular_count += r.singular ? 1 : 0;
+    }
+    if (report->singular_count > 0) return WT_E_SINGULAR;
+    if (!(report->backward_error_max <= p.ir_tol)) return WT_E_NOT_CONVERGED;
+    return WT_OK;
+}
+
+wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, const wt_carriers* car,
+                     void* d_workspace, size_t workspace_bytes, void* d_i_out) {
+    (void)d_workspace;
+    (void)workspace_bytes;
+    if (!ctx || !plan || !d_h || !car || !d_i_out) return WT_E_INVALID_ARG;
+    if (car->n_carriers < 0 || car->n_tracks < 1) return WT_E_INVALID_ARG;
+    if (car->n_carriers > 0 && (!car->d_pos || !car->d_charge || !car->d_track)) return WT_E_INVALID_ARG;
+    const Plan& p = plan->p;
+    wt_status st = bind(ctx);
+    if (st != WT_OK) return st;
+    ctx->n_events = 0;
+    if ((st = mark(ctx, -1)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_current(p, d_h, car->n_carriers, car->n_tracks, car->d_pos, car->d_charge, car->d_track,
+                                   d_i_out, ctx->stream),
+           "current");
+    if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
+    return WT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal definitions shared by the HIP sources of the library (not part of
+// the C ABI).  Complex arithmetic, the validated plan, and the kernel
+// launchers that the ABI layer calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace wt {
+
+constexpr double kEps0 = 8.8541878128e-12;   // vacuum permittivity, F/m (CODATA 2018)
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxCols = 8;
+constexpr int kMaxRadices = 16;
+constexpr int kMaxTime = 512;
+constexpr double kCutoffExponent = 40.0;       // converged Green's sum: k^2 s^2 / 2 <= 40
+constexpr double kColWidthFraction = 0.25;     // boundary-fit source width = radius / 4
+
+template <typename T>
+struct cplx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ inline cplx<T> mk(T r, T i) { return cplx<T>{r, i}; }
+template <typename T>
+__host__ __device__ inline cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ inline cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ inline cplx<T> operator*(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__host__ __device__ inline cplx<T> scale(cplx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__host__ __device__ inline cplx<T> conj(cplx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__host__ __device__ inline cplx<T> mul_i(cplx<T> a) { return {-a.im, a.re}; }   // i * a
+
+struct Column {
+    double x, y, radius, z_contact, z_free;
+    double sigma;        // mean conductivity of the quarter-columns, S/m
+    double v_applied;
+    int n;               // nodes
+    int ix, iy;          // axis grid node
+    int offset;          // first unknown of this column
+    double width;        // boundary-fit source width
+    int mmax[3];         // converged mode box |m_a| <= mmax[a]
+};
+
+struct Plan {
+    double L[3];
+    int N[3];
+    double eps;            // eps_r * eps0
+    int n_cols;
+    Column col[kMaxCols];
+    int n_q;               // source charges
+    int n;                 // n_q + 1 (gauge)
+    int n_freq, n_time;
+    double df, dt;
+    int last_weight_one;   // last frequency is the Nyquist frequency 1/(2 dt)
+    int precision;         // 0 double, 1 float
+    int ir_max_iter;
+    double ir_tol;
+    double s_bulk[3];
+    int nkz_tab;           // k_z >= 0 entries per Green's table row (max over columns)
+    int tb;                // time block of the H layout
+    int nzh;               // Nz / 2
+    int nrad[3];
+    int rad[3][kMaxRadices];
+    // workspace layout (bytes)
+    size_t off_tw[3], off_g, off_A, off_lu, off_piv, off_qw, off_rep, off_qt, off_qhat, off_ehat;
+    size_t ws_bytes, h_bytes;
+};
+
+// Per-frequency solve diagnostics written by the solve kernel.
+struct SolveReport {
+    double backward_error;
+    double pivot_ratio;
+    int iters;
+    int singular;
+};
+
+// Kernel launchers (each returns the HIP error of its launch).
+hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s);
+hipError_t launch_green_tables(const Plan& p, void* ws, hipStream_t s);
+hipError_t launch_collocation_solve(const Plan& p, void* ws, hipStream_t s);
+hipError_t launch_time_transform(const Plan& p, void* ws, hipStream_t s);
+hipError_t launch_field_table(const Plan& p, void* ws, hipStream_t s);
+hipError_t launch_synthesis(const Plan& p, void* ws, void* h, hipStream_t s);
+hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks,
+                          const void* pos, const void* charge, const int* track,
+                          void* out, hipStream_t s);
+
+// Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.
+inline int factorize(int n, int* rad) {
+    int k = 0;
+    while (n % 4 == 0) { rad[k++] = 4; n /= 4; }
+    while (n % 2 == 0) { rad[k++] = 2; n /= 2; }
+    while (n % 3 == 0) { rad[k++] = 3; n /= 3; }
+    while (n % 5 == 0) { rad[k++] = 5; n /= 5; }
+    return n == 1 ? k : -1;
+}
+
+}  // namespace wt

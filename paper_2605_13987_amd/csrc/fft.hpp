@@ -1,0 +1,106 @@
+// Workgroup-cooperative inverse complex FFTs in LDS (unnormalised,
+// exp(+2 pi i k n / N)), mixed radix 2/3/4/5, Stockham autosort.
+//
+// A length-N transform is done in passes; a pass of radix r with p = product
+// of the radices already applied maps, for every i < N/r with k = i mod p,
+//   x_q = a[i + q N/r] * w^(q k N/(p r)),  q < r,      w = exp(+2 pi i / N)
+//   y_s = sum_q x_q exp(+2 pi i q s / r)
+//   b[(i - k) r + k + s p] = y_s
+// which leaves the result in natural order after the last pass.
+#pragma once
+
+#include "common.hpp"
+
+namespace wt {
+
+template <typename T>
+struct Rad {
+    static constexpr T c5_1 = (T)0.30901699437494742410;    // cos(2 pi/5)
+    static constexpr T s5_1 = (T)0.95105651629515357212;    // sin(2 pi/5)
+    static constexpr T c5_2 = (T)-0.80901699437494742410;   // cos(4 pi/5)
+    static constexpr T s5_2 = (T)0.58778525229247312917;    // sin(4 pi/5)
+    static constexpr T s3 = (T)0.86602540378443864676;      // sin(2 pi/3)
+};
+
+template <typename T, int R>
+__device__ inline void butterfly(cplx<T>* x) {
+    if constexpr (R == 2) {
+        const cplx<T> a = x[0], b = x[1];
+        x[0] = a + b;
+        x[1] = a - b;
+    } else if constexpr (R == 3) {
+        const cplx<T> t = x[1] + x[2], u = x[1] - x[2];
+        const cplx<T> m = x[0] - scale(t, (T)0.5);
+        const cplx<T> iu = mul_i(scale(u, Rad<T>::s3));
+        x[0] = x[0] + t;
+        x[1] = m + iu;
+        x[2] = m - iu;
+    } else if constexpr (R == 4) {
+        const cplx<T> a = x[0] + x[2], b = x[0] - x[2], c = x[1] + x[3], d = x[1] - x[3];
+        x[0] = a + c;
+        x[2] = a - c;
+        x[1] = b + mul_i(d);
+        x[3] = b - mul_i(d);
+    } else {
+        const cplx<T> t1 = x[1] + x[4], t2 = x[2] + x[3], t3 = x[1] - x[4], t4 = x[2] - x[3];
+        const cplx<T> a1 = x[0] + scale(t1, Rad<T>::c5_1) + scale(t2, Rad<T>::c5_2);
+        const cplx<T> a2 = x[0] + scale(t1, Rad<T>::c5_2) + scale(t2, Rad<T>::c5_1);
+        const cplx<T> b1 = mul_i(scale(t3, Rad<T>::s5_1) + scale(t4, Rad<T>::s5_2));
+        const cplx<T> b2 = mul_i(scale(t3, Rad<T>::s5_2) - scale(t4, Rad<T>::s5_1));
+        x[0] = x[0] + t1 + t2;
+        x[1] = a1 + b1;
+        x[4] = a1 - b1;
+        x[2] = a2 + b2;
+        x[3] = a2 - b2;
+    }
+}
+
+template <typename T, int R>
+__device__ inline void stockham_pass(const cplx<T>* a, cplx<T>* b, int N, int nfft, int p,
+                                     const cplx<T>* tw, int tid, int nthr) {
+    const int m = N / R;
+    const int tws = N / (p * R);
+    for (int idx = tid; idx < nfft * m; idx += nthr) {
+        const int f = idx / m;
+        const int i = idx - f * m;
+        const int k = i % p;
+        const cplx<T>* src = a + f * N;
+        cplx<T> x[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) x[q] = src[i + q * m];
+        if (k != 0) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) x[q] = x[q] * tw[q * k * tws];
+        }
+        butterfly<T, R>(x);
+        cplx<T>* dst = b + f * N + (i - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst[q * p] = x[q];
+    }
+}
+
+// nfft transforms of length N stored back to back in a; b is scratch of the
+// same size.  Returns the buffer holding the result.  Ends with a barrier.
+template <typename T>
+__device__ cplx<T>* fft_inverse_lds(cplx<T>* a, cplx<T>* b, int N, int nfft, const int* rad, int nrad,
+                                    const cplx<T>* tw) {
+    int p = 1;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int s = 0; s < nrad; ++s) {
+        const int r = rad[s];
+        switch (r) {
+            case 4: stockham_pass<T, 4>(a, b, N, nfft, p, tw, tid, nthr); break;
+            case 2: stockham_pass<T, 2>(a, b, N, nfft, p, tw, tid, nthr); break;
+            case 3: stockham_pass<T, 3>(a, b, N, nfft, p, tw, tid, nthr); break;
+            default: stockham_pass<T, 5>(a, b, N, nfft, p, tw, tid, nthr); break;
+        }
+        __syncthreads();
+        cplx<T>* t = a;
+        a = b;
+        b = t;
+        p *= r;
+    }
+    return a;
+}
+
+}  // namespace wt

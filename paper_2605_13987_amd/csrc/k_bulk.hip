@@ -1,0 +1,222 @@
+// Spectral extension of the boundary solution to the bulk (paper, abstract:
+// spectral methods extend the solution to the bulk; Section 3: spectra are
+// multiplied by the wave-vector terms in a custom kernel).
+//
+// H(x, t_n) = sum_k M(k) exp(i k.x) sum_i q_i(t_n) exp(-i k.y_i) over the grid's
+// modes (|m_a| < N_a/2, k != 0), with
+//   M(k) = -i k S(k) / (eps |k|^2 V),  S(k) = exp(-sum_a k_a^2 s_a^2 / 2).
+// Every source sits on a column axis (X_w, Y_w) on a grid node, so the sum
+// factors into an in-plane table, built once per geometry,
+//   Ehat_a(X, Y, m_z) = sum_{m_x, m_y} M_a(k) exp(i (k_x X + k_y Y))
+// (a 2D inverse FFT per (m_z, a)), and a per-column synthesis along z,
+//   H_a(X, Y, z, t) = sum_{m_z} exp(i k_z z) sum_w Ehat_a(X - X_w, Y - Y_w, m_z) Qhat_w(m_z, t),
+// a Hermitian (complex-to-real) inverse FFT of length N_z per (X, Y, t, a).
+// Two real outputs share one complex FFT: Z = F_1 + i F_2, Re -> 1, Im -> 2.
+#include "fft.hpp"
+
+namespace wt {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr size_t kLineLds = 64 * 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_multiplier(Plan p, cplx<T>* e) {
+    const int Nx = p.N[0], Ny = p.N[1], nzh = p.nzh;
+    const size_t total = (size_t)Nx * Ny * nzh;
+    const double vol = p.L[0] * p.L[1] * p.L[2];
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int mz = (int)(idx % nzh);
+        const int iy = (int)((idx / nzh) % Ny);
+        const int ix = (int)(idx / ((size_t)nzh * Ny));
+        const int mx = ix < Nx / 2 ? ix : ix - Nx;
+        const int my = iy < Ny / 2 ? iy : iy - Ny;
+        cplx<T>* out = e + idx * 3;
+        if (ix == Nx / 2 || iy == Ny / 2 || (mx == 0 && my == 0 && mz == 0)) {
+            out[0] = out[1] = out[2] = cplx<T>{(T)0, (T)0};
+            continue;
+        }
+        const double kx = 2.0 * kPi * mx / p.L[0];
+        const double ky = 2.0 * kPi * my / p.L[1];
+        const double kz = 2.0 * kPi * mz / p.L[2];
+        const double k2 = kx * kx + ky * ky + kz * kz;
+        const double ax = kx * p.s_bulk[0], ay = ky * p.s_bulk[1], az = kz * p.s_bulk[2];
+        const double w = exp(-0.5 * (ax * ax + ay * ay + az * az)) / (k2 * p.eps * vol);
+        out[0] = cplx<T>{(T)0, (T)(-kx * w)};
+        out[1] = cplx<T>{(T)0, (T)(-ky * w)};
+        out[2] = cplx<T>{(T)0, (T)(-kz * w)};
+    }
+}
+
+// In-place inverse FFTs along one grid axis of a strided array.  Line l has
+// its first element at (l / n_inner) * outer_stride + (l % n_inner) and its
+// elements elem_stride apart; a block transforms lpb lines with consecutive
+// inner index so that loads and stores touch contiguous runs.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_fft_lines(Plan p, int axis, cplx<T>* data, int n_inner, int n_lines, size_t outer_stride,
+            size_t elem_stride, int lpb, const cplx<T>* tw) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = p.N[axis];
+    cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* b = a + (size_t)lpb * N;
+    const int l0 = blockIdx.x * lpb;
+    const int nl = min(lpb, n_lines - l0);
+    for (int idx = threadIdx.x; idx < nl * N; idx += blockDim.x) {
+        const int e = idx / nl, f = idx - e * nl;
+        const int l = l0 + f;
+        const size_t base = (size_t)(l / n_inner) * outer_stride + (size_t)(l % n_inner);
+        a[f * N + e] = data[base + e * elem_stride];
+    }
+    __syncthreads();
+    const cplx<T>* res = fft_inverse_lds<T>(a, b, N, nl, p.rad[axis], p.nrad[axis], tw);
+    for (int idx = threadIdx.x; idx < nl * N; idx += blockDim.x) {
+        const int e = idx / nl, f = idx - e * nl;
+        const int l = l0 + f;
+        const size_t base = (size_t)(l / n_inner) * outer_stride + (size_t)(l % n_inner);
+        data[base + e * elem_stride] = res[f * N + e];
+    }
+}
+
+// Spectrum of real signal s (= 3 * time-in-block + component) at z-frequency
+// index k in [0, N_z): F(k) for k < N_z/2, conj(F(N_z - k)) above, 0 at N_z/2.
+template <typename T>
+__device__ inline cplx<T> column_spectrum(const Plan& p, const cplx<T>* etab, const cplx<T>* qhat,
+                                          int t0, int nsig, int s, int k) {
+    const int nzh = p.nzh;
+    if (s >= nsig || k == nzh) return cplx<T>{(T)0, (T)0};
+    const int t = t0 + s / 3, a = s % 3;
+    const bool upper = k > nzh;
+    const int kk = upper ? p.N[2] - k : k;
+    cplx<T> acc{(T)0, (T)0};
+    const cplx<T>* q = qhat + (size_t)t * p.n_cols * nzh + kk;
+    for (int w = 0; w < p.n_cols; ++w) acc = acc + etab[(w * nzh + kk) * 3 + a] * q[(size_t)w * nzh];
+    return upper ? conj(acc) : acc;
+}
+
+// One block per (X, Y) column: H for every z node and time sample, written
+// one time block at a time as a contiguous run [z][t in block][component].
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_synthesis(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* tw, T* H, int fb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Nx = p.N[0], Ny = p.N[1], Nz = p.N[2], nzh = p.nzh, W = p.n_cols;
+    const int nt = p.n_time, TB = p.tb;
+    cplx<T>* etab = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* fa = etab + W * nzh * 3;
+    cplx<T>* fbuf = fa + (size_t)fb * Nz;
+    T* stage = reinterpret_cast<T*>(fbuf + (size_t)fb * Nz);
+
+    const int col = blockIdx.x;
+    const int ix = col / Ny, iy = col - (col / Ny) * Ny;
+    for (int idx = threadIdx.x; idx < W * nzh * 3; idx += blockDim.x) {
+        const int w = idx / (nzh * 3), r = idx - w * (nzh * 3);
+        const int sx = (ix - p.col[w].ix + Nx) % Nx;
+        const int sy = (iy - p.col[w].iy + Ny) % Ny;
+        etab[idx] = ehat[((size_t)sx * Ny + sy) * nzh * 3 + r];
+    }
+    __syncthreads();
+
+    T* hcol = H + (size_t)col * Nz * nt * 3;
+    for (int t0 = 0; t0 < nt; t0 += TB) {
+        const int tbl = min(TB, nt - t0);
+        const int nsig = 3 * tbl;
+        const int npair = (nsig + 1) / 2;
+        for (int pb = 0; pb < npair; pb += fb) {
+            const int nf = min(fb, npair - pb);
+            for (int idx = threadIdx.x; idx < nf * Nz; idx += blockDim.x) {
+                const int f = idx / Nz, k = idx - f * Nz;
+                const int s0 = 2 * (pb + f);
+                const cplx<T> z0 = column_spectrum<T>(p, etab, qhat, t0, nsig, s0, k);
+                const cplx<T> z1 = column_spectrum<T>(p, etab, qhat, t0, nsig, s0 + 1, k);
+                fa[idx] = z0 + mul_i(z1);
+            }
+            __syncthreads();
+            const cplx<T>* res = fft_inverse_lds<T>(fa, fbuf, Nz, nf, p.rad[2], p.nrad[2], tw);
+            for (int idx = threadIdx.x; idx < nf * Nz; idx += blockDim.x) {
+                const int f = idx / Nz, z = idx - f * Nz;
+                const int s0 = 2 * (pb + f);
+                const cplx<T> v = res[idx];
+                stage[(z * tbl + s0 / 3) * 3 + s0 % 3] = v.re;
+                if (s0 + 1 < nsig) stage[(z * tbl + (s0 + 1) / 3) * 3 + (s0 + 1) % 3] = v.im;
+            }
+            __syncthreads();
+        }
+        T* dst = hcol + (size_t)t0 * Nz * 3;
+        for (int idx = threadIdx.x; idx < Nz * nsig; idx += blockDim.x) dst[idx] = stage[idx];
+        __syncthreads();
+    }
+}
+
+template <typename T>
+int lines_per_block(int N) {
+    int lpb = 64;
+    while (lpb > 1 && (size_t)2 * lpb * N * sizeof(cplx<T>) > kLineLds) lpb >>= 1;
+    return lpb;
+}
+
+template <typename T>
+hipError_t field_table(const Plan& p, char* b, hipStream_t s) {
+    cplx<T>* e = reinterpret_cast<cplx<T>*>(b + p.off_ehat);
+    const size_t total = (size_t)p.N[0] * p.N[1] * p.nzh;
+    const int grid = (int)((total + kBlock - 1) / kBlock < 65536 ? (total + kBlock - 1) / kBlock : 65536);
+    hipLaunchKernelGGL(k_multiplier<T>, dim3(grid), dim3(kBlock), 0, s, p, e);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int C = p.nzh * 3;
+    for (int axis = 1; axis >= 0; --axis) {
+        const int N = p.N[axis];
+        const int lpb = lines_per_block<T>(N);
+        const size_t lds = (size_t)2 * lpb * N * sizeof(cplx<T>);
+        int n_lines;
+        size_t outer, elem;
+        if (axis == 1) {          // along y: lines (x, c)
+            n_lines = p.N[0] * C;
+            outer = (size_t)p.N[1] * C;
+            elem = C;
+        } else {                  // along x: lines (y, c)
+            n_lines = p.N[1] * C;
+            outer = C;
+            elem = (size_t)p.N[1] * C;
+        }
+        const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(b + p.off_tw[axis]);
+        hipLaunchKernelGGL(k_fft_lines<T>, dim3((n_lines + lpb - 1) / lpb), dim3(kBlock), lds, s, p, axis, e, C,
+                           n_lines, outer, elem, lpb, tw);
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t synthesis(const Plan& p, char* b, void* h, hipStream_t s) {
+    const size_t fixed = (size_t)p.n_cols * p.nzh * 3 * sizeof(cplx<T>) + (size_t)p.N[2] * p.tb * 3 * sizeof(T);
+    const size_t budget = 160 * 1024;
+    int fb = 16;
+    while (fb > 1 && fixed + (size_t)2 * fb * p.N[2] * sizeof(cplx<T>) > budget) fb >>= 1;
+    const size_t lds = fixed + (size_t)2 * fb * p.N[2] * sizeof(cplx<T>);
+    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_synthesis<T>, dim3(p.N[0] * p.N[1]), dim3(kBlock), lds, s, p,
+                       reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
+                       reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
+                       reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]), static_cast<T*>(h), fb);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_field_table(const Plan& p, void* ws, hipStream_t s) {
+    char* b = static_cast<char*>(ws);
+    return p.precision == 0 ? field_table<double>(p, b, s) : field_table<float>(p, b, s);
+}
+
+hipError_t launch_synthesis(const Plan& p, void* ws, void* h, hipStream_t s) {
+    char* b = static_cast<char*>(ws);
+    return p.precision == 0 ? synthesis<double>(p, b, h, s) : synthesis<float>(p, b, h, s);
+}
+
+}  // namespace wt

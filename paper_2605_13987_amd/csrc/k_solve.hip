@@ -1,0 +1,264 @@
+// Fundamental-solution boundary fit: one bordered complex system per
+// frequency, solved in FP64 by LU with partial pivoting and refined with an
+// FP64 residual (paper, abstract and Section 3: point charges at the
+// electrode boundaries whose magnitudes enforce the boundary conditions).
+//
+// Unknowns q (column node charges, C/V) and the gauge c.  For node i = (w,m):
+//   sum_j A_ij q_j + i w sum_{m'} R_w(min(m, m')) q_{w,m'} + c = V_app(w)
+//   sum_j q_j = 0
+// with R_w(m) = m D_w / (pi r_w^2 (sigma_w + i w eps)) the cumulative
+// resistance of the column's RC line (contact node m = 0 at V_app).  The
+// system is equilibrated: unknowns q' = a q with a = max |A_ii| and the
+// neutrality row multiplied by a, so that every block is of order one.
+//
+// One workgroup per frequency; the LU factors live in the workspace and the
+// matrix entries are regenerated from A for the refinement residual.
+#include "common.hpp"
+
+namespace wt {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxN = 528;
+
+using c64 = cplx<double>;
+
+__device__ inline double cabs1(c64 a) { return fabs(a.re) + fabs(a.im); }
+__device__ inline double cmod(c64 a) { return sqrt(a.re * a.re + a.im * a.im); }
+
+__device__ inline c64 cinv(c64 a) {
+    const double d = a.re * a.re + a.im * a.im;
+    return d == 0.0 ? c64{0.0, 0.0} : c64{a.re / d, -a.im / d};
+}
+
+struct NodeMap {
+    int col;
+    int m;
+};
+
+__device__ inline NodeMap node_of(const Plan& p, int i) {
+    int col = 0;
+    while (col + 1 < p.n_cols && i >= p.col[col + 1].offset) ++col;
+    return NodeMap{col, i - p.col[col].offset};
+}
+
+// Entry (i, j) of the equilibrated system matrix.
+__device__ inline c64 s_entry(const Plan& p, const double* A, double inv_a, const c64* zc, int i, int j) {
+    const int nq = p.n_q;
+    if (i < nq && j < nq) {
+        c64 v{A[(size_t)i * nq + j], 0.0};
+        const NodeMap a = node_of(p, i), b = node_of(p, j);
+        if (a.col == b.col) {
+            const double mm = (double)(a.m < b.m ? a.m : b.m);
+            v = v + scale(zc[a.col], mm);
+        }
+        return scale(v, inv_a);
+    }
+    if (i == nq && j == nq) return c64{0.0, 0.0};
+    return c64{1.0, 0.0};
+}
+
+__device__ inline double block_max(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) s = fmax(s, red[i]);
+    return s;   // valid in every thread
+}
+
+// x <- (LU)^-1 P x, with LU and the pivots of one frequency.
+__device__ void lu_solve(int n, const c64* lu, const int* piv, c64* x) {
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 0; k < n; ++k) {
+            const int q = piv[k];
+            if (q != k) {
+                const c64 t = x[k];
+                x[k] = x[q];
+                x[q] = t;
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < n - 1; ++k) {            // unit lower triangle
+        const c64 yk = x[k];
+        for (int i = k + 1 + tid; i < n; i += blockDim.x) x[i] = x[i] - lu[(size_t)i * n + k] * yk;
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {           // upper triangle
+        if (tid == 0) x[k] = x[k] * cinv(lu[(size_t)k * n + k]);
+        __syncthreads();
+        const c64 yk = x[k];
+        for (int i = tid; i < k; i += blockDim.x) x[i] = x[i] - lu[(size_t)i * n + k] * yk;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_solve(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveReport* rep) {
+    __shared__ c64 rowk[kMaxN];
+    __shared__ c64 colk[kMaxN];
+    __shared__ c64 xs[kMaxN];
+    __shared__ c64 rs[kMaxN];
+    __shared__ int pivs[kMaxN];
+    __shared__ c64 zc[kMaxCols];
+    __shared__ double red[kBlock / 64];
+    __shared__ int red_i[kBlock / 64];
+    __shared__ double red_v[kBlock / 64];
+    __shared__ double sh_inv_a;
+    __shared__ int sh_piv;
+    __shared__ int sh_singular;
+
+    const int f = blockIdx.x;
+    const int n = p.n, nq = p.n_q, tid = threadIdx.x;
+    const double omega = 2.0 * kPi * p.df * f;
+    c64* lu = lu_all + (size_t)f * n * n;
+    int* piv = piv_all + (size_t)f * n;
+
+    // i w R_w(m) = m * D_w/(pi r^2) * i w / (sigma + i w eps)
+    if (tid < p.n_cols) {
+        const Column& c = p.col[tid];
+        const double delta = fabs(c.z_free - c.z_contact) / (c.n - 1);
+        const double g = delta / (kPi * c.radius * c.radius);
+        const double den = c.sigma * c.sigma + omega * omega * p.eps * p.eps;
+        zc[tid] = c64{g * omega * omega * p.eps / den, g * omega * c.sigma / den};
+    }
+    double dmax = 0.0;
+    for (int i = tid; i < nq; i += blockDim.x) dmax = fmax(dmax, fabs(A[(size_t)i * nq + i]));
+    dmax = block_max(dmax, red);
+    if (tid == 0) {
+        sh_inv_a = 1.0 / dmax;
+        sh_singular = 0;
+    }
+    __syncthreads();
+    const double inv_a = sh_inv_a;
+
+    for (int idx = tid; idx < n * n; idx += blockDim.x) lu[idx] = s_entry(p, A, inv_a, zc, idx / n, idx % n);
+    __syncthreads();
+
+    double umax = 0.0, umin = 1e308;
+    for (int k = 0; k < n; ++k) {
+        // pivot: first row of maximal |re| + |im| in column k
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < n; i += blockDim.x) {
+            const double v = cabs1(lu[(size_t)i * n + k]);
+            if (v > best) { best = v; bi = i; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_down(best, o, 64);
+            const int oi = __shfl_down(bi, o, 64);
+            if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+        }
+        if ((tid & 63) == 0) { red_v[tid >> 6] = best; red_i[tid >> 6] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double bv = red_v[0];
+            int b = red_i[0];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+                if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < b)) { bv = red_v[w]; b = red_i[w]; }
+            sh_piv = b;
+            pivs[k] = b;
+            piv[k] = b;
+            if (bv == 0.0) sh_singular = 1;
+        }
+        __syncthreads();
+        const int pr = sh_piv;
+        if (pr != k) {
+            for (int j = tid; j < n; j += blockDim.x) {
+                const c64 t = lu[(size_t)k * n + j];
+                lu[(size_t)k * n + j] = lu[(size_t)pr * n + j];
+                lu[(size_t)pr * n + j] = t;
+            }
+        }
+        __syncthreads();
+        const c64 pivot = lu[(size_t)k * n + k];
+        const double pm = cmod(pivot);
+        umax = fmax(umax, pm);
+        umin = fmin(umin, pm);
+        const c64 ip = cinv(pivot);
+        for (int j = k + 1 + tid; j < n; j += blockDim.x) rowk[j] = lu[(size_t)k * n + j];
+        for (int i = k + 1 + tid; i < n; i += blockDim.x) {
+            const c64 l = lu[(size_t)i * n + k] * ip;
+            lu[(size_t)i * n + k] = l;
+            colk[i] = l;
+        }
+        __syncthreads();
+        const int m = n - k - 1;
+        for (int idx = tid; idx < m * m; idx += blockDim.x) {
+            const int i = k + 1 + idx / m, j = k + 1 + idx % m;
+            lu[(size_t)i * n + j] = lu[(size_t)i * n + j] - colk[i] * rowk[j];
+        }
+        __syncthreads();
+    }
+
+    // right-hand side: applied voltages, 0 for the neutrality row
+    for (int i = tid; i < n; i += blockDim.x) {
+        c64 b{0.0, 0.0};
+        if (i < nq) b.re = p.col[node_of(p, i).col].v_applied;
+        xs[i] = b;
+    }
+    lu_solve(n, lu, pivs, xs);
+
+    // infinity norms of S and b
+    double srow = 0.0, bmax = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += cmod(s_entry(p, A, inv_a, zc, i, j));
+        srow = fmax(srow, s);
+        if (i < nq) bmax = fmax(bmax, fabs(p.col[node_of(p, i).col].v_applied));
+    }
+    const double snorm = block_max(srow, red);
+    const double bnorm = block_max(bmax, red);
+
+    int iters = 0;
+    double berr = 0.0;
+    for (;;) {
+        double rmax = 0.0, xmax = 0.0;
+        for (int i = tid; i < n; i += blockDim.x) {
+            c64 acc{0.0, 0.0};
+            if (i < nq) acc.re = p.col[node_of(p, i).col].v_applied;
+            for (int j = 0; j < n; ++j) acc = acc - s_entry(p, A, inv_a, zc, i, j) * xs[j];
+            rs[i] = acc;
+            rmax = fmax(rmax, cmod(acc));
+            xmax = fmax(xmax, cmod(xs[i]));
+        }
+        rmax = block_max(rmax, red);
+        xmax = block_max(xmax, red);
+        const double den = snorm * xmax + bnorm;
+        berr = den > 0.0 ? rmax / den : 0.0;
+        if (berr <= p.ir_tol || iters >= p.ir_max_iter) break;
+        lu_solve(n, lu, pivs, rs);
+        for (int i = tid; i < n; i += blockDim.x) xs[i] = xs[i] + rs[i];
+        __syncthreads();
+        ++iters;
+    }
+
+    for (int i = tid; i < n; i += blockDim.x) {
+        const c64 v = xs[i];
+        qw[(size_t)f * n + i] = i < nq ? scale(v, inv_a) : v;
+    }
+    if (tid == 0) {
+        rep[f].backward_error = berr;
+        rep[f].pivot_ratio = umin > 0.0 ? umax / umin : 1e308;
+        rep[f].iters = iters;
+        rep[f].singular = sh_singular;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_collocation_solve(const Plan& p, void* ws, hipStream_t s) {
+    char* b = static_cast<char*>(ws);
+    hipLaunchKernelGGL(k_solve, dim3(p.n_freq), dim3(kBlock), 0, s, p, (const double*)(b + p.off_A),
+                       (c64*)(b + p.off_lu), (int*)(b + p.off_piv), (c64*)(b + p.off_qw),
+                       (SolveReport*)(b + p.off_rep));
+    return hipGetLastError();
+}
+
+}  // namespace wt

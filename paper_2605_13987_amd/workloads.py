@@ -287,7 +287,7 @@ def _pack(name, cell, columns, spectrum, pos, charge, track, n_tracks, note):
                 note=note)
 
 
-def config_c1():
+def uniform_pixel_32x32x64():
     """32x32x64 grid of a 50x50x300 um cell, 16 frequencies, 64 x 20 ps, 100 carriers."""
     rng = rng_for(1)
     cell = make_cell(50 * UM, 300 * UM, 32, 64)
@@ -296,11 +296,11 @@ def config_c1():
     starts = uniform_starts(rng, 50, cols, cell)
     pts, q = pairs_to_carriers(starts)
     pos = drift_paths(pts, q, cols, cell, spec["n_time"], spec["dt"])
-    return _pack("c1", cell, cols, spec, pos, q, np.zeros(q.size), 1,
+    return _pack("px32", cell, cols, spec, pos, q, np.zeros(q.size), 1,
                  "50 e/h pairs, uniform starts, straight drift at 1e5 m/s")
 
 
-def config_c2(n_pairs=10000):
+def mip_pixel_128x128x256(n_pairs=10000):
     """128x128x256 grid, seeded resistivities, 256 frequencies, 200 x 10 ps, one MIP track."""
     rng = rng_for(2)
     cell = make_cell(50 * UM, 300 * UM, 128, 256)
@@ -311,11 +311,11 @@ def config_c2(n_pairs=10000):
     starts = mip_track_starts(rng, cell, cols, n_pairs)
     pts, q = pairs_to_carriers(starts)
     pos = drift_paths(pts, q, cols, cell, spec["n_time"], spec["dt"])
-    return _pack("c2", cell, cols, spec, pos, q, np.zeros(q.size), 1,
+    return _pack("px128", cell, cols, spec, pos, q, np.zeros(q.size), 1,
                  f"one MIP track along z, {n_pairs} e/h pairs with Moyal weights")
 
 
-def config_small(k=11, n_xy=24, n_z=40, n_freq=12, n_time=40, n_pairs=40,
+def small_pixel(k=11, n_xy=24, n_z=40, n_freq=12, n_time=40, n_pairs=40,
                  n_colloc=16, to_nyquist=True, rho=None):
     """Small cell for full-grid parity: multi-tile, ragged sizes, a few carriers."""
     rng = rng_for(k)
@@ -330,11 +330,11 @@ def config_small(k=11, n_xy=24, n_z=40, n_freq=12, n_time=40, n_pairs=40,
     pts, q = pairs_to_carriers(starts)
     pos = drift_paths(pts, q, cols, cell, spec["n_time"], spec["dt"])
     track = (np.arange(q.size) % 3)
-    return _pack(f"small{k}", cell, cols, spec, pos, q, track, 3,
+    return _pack(f"small-{n_xy}x{n_xy}x{n_z}-seed{k}", cell, cols, spec, pos, q, track, 3,
                  "small full-grid parity case")
 
 
-CONFIGS = {"c1": config_c1, "c2": config_c2}
+CONFIGS = {"px32": uniform_pixel_32x32x64, "px128": mip_pixel_128x128x256}
 
 
 def describe(cfg):

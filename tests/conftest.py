@@ -13,12 +13,12 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def c1():
+def px32():
     from paper_2605_13987_amd import workloads
-    return workloads.config_c1()
+    return workloads.uniform_pixel_32x32x64()
 
 
 @pytest.fixture(scope="session")
-def c1_oracle(c1):
+def px32_oracle(px32):
     import oracle
-    return oracle.weighting_field(c1["cell"], c1["columns"], c1["spectrum"])
+    return oracle.weighting_field(px32["cell"], px32["columns"], px32["spectrum"])

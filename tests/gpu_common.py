@@ -1,0 +1,104 @@
+"""Helpers for the GPU tests: run the library through the C ABI on torch memory."""
+import sys
+
+import numpy as np
+import torch
+
+from paper_2605_13987_amd import layout, wt
+
+
+def say(*args):
+    print(*args, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def dtype_of(precision):
+    return torch.float64 if precision == wt.WT_F64 else torch.float32
+
+
+def context():
+    return wt.wt_context_create(0, torch.cuda.current_stream().cuda_stream)
+
+
+def solve_h(ctx, cfg, precision, ir_max_iter=2, ir_tol=1e-12):
+    say(f"  wt_h_solve {cfg['name']} grid={cfg['cell']['N']} nf={cfg['spectrum']['n_freq']} "
+        f"nt={cfg['spectrum']['n_time']} precision={precision}")
+    plan, lay = wt.wt_h_plan_create(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=precision,
+                                    ir_max_iter=ir_max_iter, ir_tol=ir_tol)
+    ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    esz = 8 if precision == wt.WT_F64 else 4
+    h = torch.empty(lay["h_bytes"] // esz, dtype=dtype_of(precision), device="cuda")
+    st, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"], report=True,
+                            raise_on_error=False)
+    torch.cuda.synchronize()
+    return dict(plan=plan, layout=lay, ws=ws, h=h, status=st, report=rep, precision=precision)
+
+
+def ws_array(ws, offset, count, np_dtype):
+    nbytes = count * np.dtype(np_dtype).itemsize
+    raw = ws[offset:offset + nbytes].cpu().numpy()
+    return raw.view(np_dtype)
+
+
+def intermediates(run, cfg):
+    lay = run["layout"]
+    nq = lay["n_q"]
+    nf = cfg["spectrum"]["n_freq"]
+    nt = cfg["spectrum"]["n_time"]
+    A = ws_array(run["ws"], lay["off_A"], nq * nq, np.float64).reshape(nq, nq)
+    qw = ws_array(run["ws"], lay["off_qw"], nf * (nq + 1), np.complex128).reshape(nf, nq + 1)
+    qt = ws_array(run["ws"], lay["off_qt"], nt * nq, np.float64).reshape(nt, nq)
+    return dict(A=A, q=qw[:, :nq], c=qw[:, nq], q_t=qt)
+
+
+def h_standard(run, cfg):
+    """Whole H on the host in [x][y][z][t][a] order (small grids)."""
+    lay = run["layout"]
+    return layout.to_standard(run["h"].cpu().numpy(), cfg["cell"]["N"], cfg["spectrum"]["n_time"],
+                              lay["h_time_block"])
+
+
+def h_columns(run, cfg, cols_ij):
+    """H on selected (x, y) columns -> (n_cols, Nz, n_time, 3) on the host."""
+    N = cfg["cell"]["N"]
+    nt = cfg["spectrum"]["n_time"]
+    per = N[2] * nt * 3
+    idx = torch.tensor([i * N[1] + j for i, j in cols_ij], device="cuda")
+    cols = run["h"].view(-1, per).index_select(0, idx).cpu().numpy()
+    return layout.to_standard(cols, N, nt, run["layout"]["h_time_block"])
+
+
+def current(ctx, run, carriers, precision=None, subset=None):
+    precision = run["precision"] if precision is None else precision
+    dt = dtype_of(precision)
+    pos = np.asarray(carriers["pos"])
+    q = np.asarray(carriers["charge"])
+    tr = np.asarray(carriers["track"], dtype=np.int32)
+    if subset is not None:
+        pos, q, tr = pos[subset], q[subset], tr[subset]
+    n_tracks = int(carriers["n_tracks"])
+    d_pos = torch.from_numpy(np.ascontiguousarray(pos)).to(device="cuda", dtype=dt)
+    d_q = torch.from_numpy(np.ascontiguousarray(q)).to(device="cuda", dtype=dt)
+    d_tr = torch.from_numpy(np.ascontiguousarray(tr)).to(device="cuda")
+    out = torch.empty((n_tracks, pos.shape[1] - 1), dtype=dt, device="cuda")
+    say(f"  wt_current n_carriers={pos.shape[0]} n_tracks={n_tracks} nt={pos.shape[1] - 1}")
+    wt.wt_current(ctx, run["plan"], run["h"].data_ptr(), pos.shape[0], n_tracks, d_pos.data_ptr(),
+                  d_q.data_ptr(), d_tr.data_ptr(), out.data_ptr())
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def rounded_carriers(carriers, precision):
+    """The carrier arrays exactly as the GPU receives them (FP32 rounding)."""
+    if precision == wt.WT_F64:
+        return carriers
+    out = dict(carriers)
+    out["pos"] = np.asarray(carriers["pos"]).astype(np.float32).astype(np.float64)
+    out["charge"] = np.asarray(carriers["charge"]).astype(np.float32).astype(np.float64)
+    return out

@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI (no GPU work): exported symbols, plan sizes,
+argument validation and status codes."""
+import copy
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2605_13987_amd import workloads, wt
+
+
+def test_library_exports_every_declared_symbol():
+    declared = wt.declared_symbols()
+    assert {"wt_h_plan_create", "wt_h_solve", "wt_current", "wt_context_create"} <= set(declared)
+    for name in declared:
+        assert hasattr(wt.LIB, name), name
+    if shutil.which("nm"):
+        out = subprocess.run(["nm", "-D", "--defined-only", wt.LIB_PATH], capture_output=True, text=True).stdout
+        exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+        assert set(declared) <= exported
+
+
+def test_status_strings():
+    for code in range(-7, 1):
+        assert wt.wt_status_string(code)
+    assert wt.wt_status_string(-99) == "unknown status"
+    assert wt.wt_stage_name(4) == "synthesis" and wt.wt_stage_name(99) == ""
+
+
+def _px32():
+    c = workloads.uniform_pixel_32x32x64()
+    return c["cell"], c["columns"], c["spectrum"]
+
+
+def test_plan_layout_32_and_128_grids():
+    cell, cols, spec = _px32()
+    plan, lay = wt.wt_h_plan_create(cell, cols, spec, precision=wt.WT_F64)
+    assert lay["n_q"] == 128
+    assert lay["h_bytes"] == 32 * 32 * 64 * 64 * 3 * 8
+    assert lay["h_time_block"] == 32
+    assert lay["workspace_bytes"] > lay["off_ehat"] + 32 * 32 * 32 * 3 * 16 - 1
+    assert wt.wt_h_plan_layout(plan) == lay
+    wt.wt_h_plan_destroy(plan)
+    px128 = workloads.make_cell(50e-6, 300e-6, 128, 256)
+    spec2 = dict(n_freq=256, df=workloads.frequency_grid_to_nyquist(256, 10e-12), n_time=200, dt=10e-12)
+    plan, lay = wt.wt_h_plan_create(px128, cols, spec2, precision=wt.WT_F32)
+    assert lay["h_bytes"] == 128 * 128 * 256 * 200 * 3 * 4
+    assert lay["h_time_block"] == 32
+    wt.wt_h_plan_destroy(plan)
+
+
+def _status(mutate, precision=wt.WT_F32, **kw):
+    cell, cols, spec = _px32()
+    cell, cols, spec = copy.deepcopy(cell), copy.deepcopy(cols), copy.deepcopy(spec)
+    mutate(cell, cols, spec)
+    return wt.wt_h_plan_create_status(cell, cols, spec, precision=precision, **kw)
+
+
+CASES = [
+    ("ok", lambda c, k, s: None, wt.WT_OK),
+    ("odd grid", lambda c, k, s: c.update(N=(33, 32, 64)), wt.WT_E_UNSUPPORTED_SIZE),
+    ("prime factor 7", lambda c, k, s: c.update(N=(28, 32, 64)), wt.WT_E_UNSUPPORTED_SIZE),
+    ("grid too large", lambda c, k, s: c.update(N=(2048, 32, 64)), wt.WT_E_UNSUPPORTED_SIZE),
+    ("3-5 smooth sizes", lambda c, k, s: c.update(N=(30, 40, 60)), wt.WT_OK),
+    ("zero length", lambda c, k, s: c.update(L=(0.0, 50e-6, 300e-6)), wt.WT_E_INVALID_ARG),
+    ("nan eps", lambda c, k, s: c.update(eps_r=float("nan")), wt.WT_E_INVALID_ARG),
+    ("conducting bulk", lambda c, k, s: c.update(sigma_bulk=1.0), wt.WT_E_INVALID_ARG),
+    ("axis off node", lambda c, k, s: k[0].update(x=25.3e-6), wt.WT_E_GEOMETRY),
+    ("axis outside", lambda c, k, s: k[0].update(x=60e-6), wt.WT_E_GEOMETRY),
+    ("overlap", lambda c, k, s: k[1].update(x=25e-6 + 6.25e-6, y=25e-6), wt.WT_E_GEOMETRY),
+    ("coincident", lambda c, k, s: k[1].update(x=25e-6, y=25e-6), wt.WT_E_GEOMETRY),
+    ("radius too big", lambda c, k, s: [col.update(radius=30e-6) for col in k], wt.WT_E_GEOMETRY),
+    ("z outside", lambda c, k, s: k[0].update(z_free=400e-6), wt.WT_E_GEOMETRY),
+    ("zero span", lambda c, k, s: k[0].update(z_free=0.0), wt.WT_E_GEOMETRY),
+    ("one node", lambda c, k, s: k[0].update(n_colloc=1), wt.WT_E_INVALID_ARG),
+    ("too many unknowns", lambda c, k, s: [col.update(n_colloc=300) for col in k], wt.WT_E_UNSUPPORTED_SIZE),
+    ("zero resistivity", lambda c, k, s: k[0].update(resistivity=[0.0]), wt.WT_E_INVALID_ARG),
+    ("five quarters", lambda c, k, s: k[1].update(resistivity=[1e-3] * 5), wt.WT_E_INVALID_ARG),
+    ("no frequencies", lambda c, k, s: s.update(n_freq=0), wt.WT_E_INVALID_ARG),
+    ("negative dt", lambda c, k, s: s.update(dt=-1e-12), wt.WT_E_INVALID_ARG),
+    ("too many samples", lambda c, k, s: s.update(n_time=513), wt.WT_E_UNSUPPORTED_SIZE),
+    ("inf df", lambda c, k, s: s.update(df=float("inf")), wt.WT_E_INVALID_ARG),
+]
+
+
+@pytest.mark.parametrize("name,mutate,expect", CASES, ids=[c[0] for c in CASES])
+def test_plan_validation(name, mutate, expect):
+    assert _status(mutate) == expect
+
+
+def test_options_validation():
+    ok = lambda c, k, s: None
+    assert _status(ok, precision=7) == wt.WT_E_INVALID_ARG
+    assert _status(ok, ir_max_iter=-1) == wt.WT_E_INVALID_ARG
+    assert _status(ok, ir_max_iter=17) == wt.WT_E_INVALID_ARG
+    assert _status(ok, ir_tol=float("nan")) == wt.WT_E_INVALID_ARG
+
+
+def test_null_arguments_are_rejected():
+    import ctypes
+    lay = wt.wt_h_layout()
+    plan = ctypes.c_void_p()
+    assert wt.LIB.wt_h_plan_create(None, None, 0, None, None, ctypes.byref(plan), ctypes.byref(lay)) \
+        == wt.WT_E_INVALID_ARG
+    assert wt.LIB.wt_h_solve(None, None, None, 0, None, 0, None) == wt.WT_E_INVALID_ARG
+    assert wt.LIB.wt_current(None, None, None, None, None, 0, None) == wt.WT_E_INVALID_ARG
+    assert wt.LIB.wt_h_plan_destroy(None) == wt.WT_E_INVALID_ARG
+    assert wt.LIB.wt_context_destroy(None) == wt.WT_E_INVALID_ARG
+
+
+def test_context_creation_reports_missing_device():
+    import ctypes
+    ctx = ctypes.c_void_p()
+    st = wt.LIB.wt_context_create(ctypes.byref(ctx), 0, None)
+    assert st in (wt.WT_OK, wt.WT_E_HIP)          # WT_OK only where a GPU is present
+    if st == wt.WT_OK:
+        assert wt.LIB.wt_context_destroy(ctx) == wt.WT_OK
+    assert wt.LIB.wt_context_create(ctypes.byref(ctx), 10 ** 6, None) == wt.WT_E_HIP

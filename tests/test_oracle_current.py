@@ -79,7 +79,7 @@ def test_trilinear_interpolation_is_exact_for_linear_fields():
 
 def _perfect_conductor_case(n_freq=33, n_xy=48, n_z=40):
     """Columns of negligible resistivity on a Nyquist frequency grid."""
-    cfg = workloads.config_small(k=31, n_xy=n_xy, n_z=n_z, n_freq=n_freq,
+    cfg = workloads.small_pixel(k=31, n_xy=n_xy, n_z=n_z, n_freq=n_freq,
                                  n_time=2 * (n_freq - 1), n_pairs=12, n_colloc=16,
                                  rho=np.full(5, 1e-25))
     return cfg

@@ -5,7 +5,7 @@ from paper_2605_13987_amd import workloads
 
 
 def _tiny():
-    cfg = workloads.config_small(k=21, n_xy=8, n_z=16, n_freq=4, n_time=5, n_pairs=2, n_colloc=6)
+    cfg = workloads.small_pixel(k=21, n_xy=8, n_z=16, n_freq=4, n_time=5, n_pairs=2, n_colloc=6)
     return cfg
 
 
@@ -27,21 +27,21 @@ def test_superposition_fft_and_column_routes_agree():
         assert np.max(np.abs(H3[c] - H2[i, j])) <= 1e-12 * scale
 
 
-def test_column_route_matches_fft_on_c1(c1, c1_oracle):
-    cell, cols = c1["cell"], c1["columns"]
+def test_column_route_matches_fft_on_32x32x64(px32, px32_oracle):
+    cell, cols = px32["cell"], px32["columns"]
     s = green.smoothing_widths(cell, cols)
     ij = [(0, 0), (16, 16), (5, 27), (31, 2)]
-    H3 = field.field_columns(cell, s, c1_oracle["src"], c1_oracle["q_t"], ij)
-    H = c1_oracle["H"]
+    H3 = field.field_columns(cell, s, px32_oracle["src"], px32_oracle["q_t"], ij)
+    H = px32_oracle["H"]
     for c, (i, j) in enumerate(ij):
         assert np.max(np.abs(H3[c] - H[i, j])) <= 1e-11 * np.max(np.abs(H))
 
 
-def test_c4_and_mirror_symmetry_about_the_readout(c1, c1_oracle):
+def test_c4_and_mirror_symmetry_about_the_readout(px32, px32_oracle):
     """Equal bias quarter-columns on a square cell: the axis charges are C4
     symmetric about the readout axis, hence so is H (as a vector field)."""
-    H = c1_oracle["H"]
-    N = c1["cell"]["N"][0]
+    H = px32_oracle["H"]
+    N = px32["cell"]["N"][0]
     i = np.arange(N)
     # rotation (u, v) -> (-v, u) about the readout axis maps node (i, j) to (N - j, i)
     I, J = np.meshgrid(i, i, indexing="ij")

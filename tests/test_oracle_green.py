@@ -59,21 +59,21 @@ def test_grid_green_matches_ewald_within_band_leakage():
     assert np.max(np.abs(e - ee)) > 1e-9 * np.max(np.abs(ee))
 
 
-def test_nested_collocation_matrix_equals_direct_sum(c1):
-    A = collocation.collocation_matrix(c1["cell"], c1["columns"])
+def test_nested_collocation_matrix_equals_direct_sum(px32):
+    A = collocation.collocation_matrix(px32["cell"], px32["columns"])
     rows = [0, 1, 31, 63, 64, 100, 127]
     cols = [0, 2, 40, 64, 65, 127]
-    Ad = collocation.collocation_matrix_direct(c1["cell"], c1["columns"], rows, cols)
+    Ad = collocation.collocation_matrix_direct(px32["cell"], px32["columns"], rows, cols)
     assert np.max(np.abs(A[np.ix_(rows, cols)] - Ad)) <= 1e-12 * np.max(np.abs(Ad))
 
 
-def test_collocation_matrix_entries_match_ewald(c1):
-    A = collocation.collocation_matrix(c1["cell"], c1["columns"])
-    x = collocation.collocation_points(c1["columns"])
-    y = collocation.sources(c1["columns"])
+def test_collocation_matrix_entries_match_ewald(px32):
+    A = collocation.collocation_matrix(px32["cell"], px32["columns"])
+    x = collocation.collocation_points(px32["columns"])
+    y = collocation.sources(px32["columns"])
     rng = np.random.default_rng(3)
     pairs = rng.integers(0, A.shape[0], size=(16, 2))
     for i, j in pairs:
-        col = c1["columns"][0 if j < 64 else 1]
-        ge = ewald.potential(x[i] - y[j], c1["cell"]["L"], c1["cell"]["eps_r"], green.collocation_width(col))
+        col = px32["columns"][0 if j < 64 else 1]
+        ge = ewald.potential(x[i] - y[j], px32["cell"]["L"], px32["cell"]["eps_r"], green.collocation_width(col))
         assert abs(A[i, j] - ge[0]) <= 1e-12 * abs(A[0, 0])

@@ -55,23 +55,23 @@ def _kirchhoff_solve(A, columns, omega, eps_c):
     return x[:nq], x[ic]
 
 
-def test_compact_rc_line_equals_kirchhoff_assembly(c1, c1_oracle):
-    A = c1_oracle["A"]
-    eps_c = green.permittivity(c1["cell"])
+def test_compact_rc_line_equals_kirchhoff_assembly(px32, px32_oracle):
+    A = px32_oracle["A"]
+    eps_c = green.permittivity(px32["cell"])
     for om in (0.0, 2 * np.pi * 1.25e9, 2 * np.pi * 18.75e9, 2 * np.pi * 400e9):
-        q, c = collocation.solve_frequency(A, c1["columns"], om, eps_c)
-        qk, ck = _kirchhoff_solve(A, c1["columns"], om, eps_c)
+        q, c = collocation.solve_frequency(A, px32["columns"], om, eps_c)
+        qk, ck = _kirchhoff_solve(A, px32["columns"], om, eps_c)
         assert np.max(np.abs(q - qk)) <= 1e-9 * np.max(np.abs(qk)), om
         assert abs(c - ck) <= 1e-9 * max(1.0, abs(ck))
 
 
-def test_lu_agrees_with_qr_and_backward_error(c1, c1_oracle):
-    A = c1_oracle["A"]
-    eps_c = green.permittivity(c1["cell"])
+def test_lu_agrees_with_qr_and_backward_error(px32, px32_oracle):
+    A = px32_oracle["A"]
+    eps_c = green.permittivity(px32["cell"])
     nq = A.shape[0]
-    for om in c1_oracle["omega"][[0, 5, 15]]:
-        S, b = collocation.frequency_system(A, c1["columns"], om, eps_c)
-        q, c = collocation.solve_frequency(A, c1["columns"], om, eps_c)
+    for om in px32_oracle["omega"][[0, 5, 15]]:
+        S, b = collocation.frequency_system(A, px32["columns"], om, eps_c)
+        q, c = collocation.solve_frequency(A, px32["columns"], om, eps_c)
         a = np.abs(np.diag(A)).max()
         colsc = np.r_[np.full(nq, 1 / a), 1.0]
         rowsc = np.r_[np.ones(nq), a]
@@ -86,51 +86,51 @@ def test_lu_agrees_with_qr_and_backward_error(c1, c1_oracle):
         assert berr <= 1e-14
 
 
-def test_static_potentials_on_column_surfaces(c1, c1_oracle):
+def test_static_potentials_on_column_surfaces(px32, px32_oracle):
     """At w = 0 the columns are equipotential: the potential of the fitted
     charges, summed with the Ewald form of the fundamental solution, equals the
     applied voltage minus the gauge at every collocation point."""
-    q = c1_oracle["q"][0].real
-    c = c1_oracle["c"][0].real
-    assert np.max(np.abs(c1_oracle["q"][0].imag)) == 0.0
-    x = collocation.collocation_points(c1["columns"])
-    y = collocation.sources(c1["columns"])
-    widths = np.concatenate([[green.collocation_width(col)] * col["n_colloc"] for col in c1["columns"]])
-    vapp = np.concatenate([[col["v_applied"]] * col["n_colloc"] for col in c1["columns"]])
+    q = px32_oracle["q"][0].real
+    c = px32_oracle["c"][0].real
+    assert np.max(np.abs(px32_oracle["q"][0].imag)) == 0.0
+    x = collocation.collocation_points(px32["columns"])
+    y = collocation.sources(px32["columns"])
+    widths = np.concatenate([[green.collocation_width(col)] * col["n_colloc"] for col in px32["columns"]])
+    vapp = np.concatenate([[col["v_applied"]] * col["n_colloc"] for col in px32["columns"]])
     rng = np.random.default_rng(4)
     for i in rng.choice(x.shape[0], 10, replace=False):
         phi = 0.0
         for wdt in np.unique(widths):
             sel = widths == wdt
-            phi += ewald.potential(x[i] - y[sel], c1["cell"]["L"], c1["cell"]["eps_r"], wdt) @ q[sel]
+            phi += ewald.potential(x[i] - y[sel], px32["cell"]["L"], px32["cell"]["eps_r"], wdt) @ q[sel]
         assert abs(phi + c - vapp[i]) <= 1e-11
 
 
-def test_electrode_sum_rule(c1, c1_oracle):
+def test_electrode_sum_rule(px32, px32_oracle):
     """Unit voltage on every column: no charge moves, the gauge is 1; hence the
     readout and bias responses sum to zero (linearity)."""
-    A = c1_oracle["A"]
-    eps_c = green.permittivity(c1["cell"])
-    cols_all = copy.deepcopy(c1["columns"])
+    A = px32_oracle["A"]
+    eps_c = green.permittivity(px32["cell"])
+    cols_all = copy.deepcopy(px32["columns"])
     for col in cols_all:
         col["v_applied"] = 1.0
-    cols_bias = copy.deepcopy(c1["columns"])
+    cols_bias = copy.deepcopy(px32["columns"])
     cols_bias[0]["v_applied"], cols_bias[1]["v_applied"] = 0.0, 1.0
-    qscale = np.max(np.abs(c1_oracle["q"]))
-    for j, om in enumerate(c1_oracle["omega"][[0, 3, 15]]):
+    qscale = np.max(np.abs(px32_oracle["q"]))
+    for j, om in enumerate(px32_oracle["omega"][[0, 3, 15]]):
         q1, c1g = collocation.solve_frequency(A, cols_all, om, eps_c)
         assert np.max(np.abs(q1)) <= 1e-12 * qscale
         assert abs(c1g - 1.0) <= 1e-12
         qb, _ = collocation.solve_frequency(A, cols_bias, om, eps_c)
-        qr, _ = collocation.solve_frequency(A, c1["columns"], om, eps_c)
+        qr, _ = collocation.solve_frequency(A, px32["columns"], om, eps_c)
         assert np.max(np.abs(qb + qr)) <= 1e-12 * qscale
 
 
-def test_readout_admittance_is_passive(c1_oracle):
+def test_readout_admittance_is_passive(px32_oracle):
     """Y(w) = i w Q_readout / V_app of the RC network must have Re Y >= 0
     (with exp(+i w t), a dissipative network absorbs power)."""
-    Q = c1_oracle["q"][:, :64].sum(axis=1)
-    Y = 1j * c1_oracle["omega"] * Q
+    Q = px32_oracle["q"][:, :64].sum(axis=1)
+    Y = 1j * px32_oracle["omega"] * Q
     assert np.all(Y.real[1:] > 0)
     # static capacitance is positive and the charge magnitude falls with frequency
     assert Q[0].real > 0 and np.all(np.diff(np.abs(Q)) < 0)
