@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-carrier-stride", type=int, default=20)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy MIB mebibytes device-to-device 3 times (counter calibration)")
     return ap.parse_args()
 
 
@@ -89,6 +91,16 @@ def main():
     import torch
 
     from paper_2605_13987_amd import layout, workloads, wt
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: 3 x {args.copy_probe} MiB read + written", file=sys.stderr, flush=True)
+        del src, dst
 
     cfg = workloads.mip_pixel_128x128x256()
     cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]

@@ -165,6 +165,10 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     while (tb > 1 && lds_need(tb) > lds_budget) tb = (tb + 1) / 2;
     if (lds_need(tb) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
     p.tb = tb;
+    // register-FFT synthesis where N_z = N1 x N2 is supported and its staging fits
+    const int rs = p.precision == WT_F64 ? wt::stage_row_stride<double>(tb) : wt::stage_row_stride<float>(tb);
+    const size_t reg_need = (size_t)3 * n_cols * p.nzh * cx + (size_t)N[2] * cx + (size_t)N[2] * rs * re;
+    p.synth_kernel = ((N[2] == 64 || N[2] == 128 || N[2] == 256 || N[2] == 512) && reg_need <= lds_budget) ? 1 : 0;
 
     size_t off = 0;
     for (int a = 0; a < 3; ++a) {

@@ -67,6 +67,7 @@ struct Plan {
     double s_bulk[3];
     int nkz_tab;           // k_z >= 0 entries per Green's table row (max over columns)
     int tb;                // time block of the H layout
+    int synth_kernel;      // 1: register-FFT synthesis (N_z = 64, 128, 256, 512), 0: LDS Stockham
     int nzh;               // Nz / 2
     int nrad[3];
     int rad[3][kMaxRadices];
@@ -93,6 +94,17 @@ hipError_t launch_synthesis(const Plan& p, void* ws, void* h, hipStream_t s);
 hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks,
                           const void* pos, const void* charge, const int* track,
                           void* out, hipStream_t s);
+
+// Row stride (elements) of the LDS staging block of the register-FFT
+// synthesis for a time block of tbl samples: room for an even number of
+// samples, and a stride whose multiples by 0..15 fall in distinct LDS banks
+// (4 mod 8 words for float, 2 mod 4 doubles for double), with 16-byte rows.
+template <typename T>
+__host__ __device__ inline int stage_row_stride(int tbl) {
+    const int base = ((tbl + 1) / 2) * 2 * 3;
+    if (sizeof(T) == 4) return base + ((4 - base % 8) + 8) % 8;
+    return base + ((2 - base % 4) + 4) % 4;
+}
 
 // Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.
 inline int factorize(int n, int* rad) {

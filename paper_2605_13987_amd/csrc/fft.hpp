@@ -104,3 +104,68 @@ __device__ cplx<T>* fft_inverse_lds(cplx<T>* a, cplx<T>* b, int N, int nfft, con
 }
 
 }  // namespace wt
+
+namespace wt {
+
+// exp(+2 pi i j / 32) from the first octant by symmetry, so that the
+// quarter-turn values are exact.
+__host__ __device__ constexpr double cos_2pi_32(int j) {
+    constexpr double c[9] = {1.0,
+                             0.98078528040323044913,   // cos(pi/16)
+                             0.92387953251128675613,   // cos(pi/8)
+                             0.83146961230254523708,   // cos(3pi/16)
+                             0.70710678118654752440,   // cos(pi/4)
+                             0.55557023301960222474,   // cos(5pi/16)
+                             0.38268343236508977173,   // cos(3pi/8)
+                             0.19509032201612826785,   // cos(7pi/16)
+                             0.0};
+    j &= 31;
+    return j <= 8 ? c[j] : (j <= 16 ? -c[16 - j] : (j <= 24 ? -c[j - 16] : c[32 - j]));
+}
+
+__host__ __device__ constexpr int bit_reverse(int i, int n) {
+    int r = 0;
+    for (int b = 1; b < n; b <<= 1) {
+        r = (r << 1) | (i & 1);
+        i >>= 1;
+    }
+    return r;
+}
+
+// In-register inverse DFT of R = 2, 4, 8, 16 or 32 points (radix-2, decimation
+// in time, natural-order output): x[n] <- sum_k x[k] exp(+2 pi i n k / R).
+template <typename T, int R>
+__device__ inline void dft_reg(cplx<T>* x) {
+    static_assert(R == 2 || R == 4 || R == 8 || R == 16 || R == 32, "register DFT size");
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int j = bit_reverse(i, R);
+        if (j > i) {
+            const cplx<T> t = x[i];
+            x[i] = x[j];
+            x[j] = t;
+        }
+    }
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int i = 0; i < R; i += len) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                const int m = j * (32 / len);              // exp(+2 pi i j / len) = w32^m
+                cplx<T> v = x[i + j + half];
+                if (m == 8) {
+                    v = mul_i(v);
+                } else if (m != 0) {
+                    v = v * cplx<T>{(T)cos_2pi_32(m), (T)cos_2pi_32(m - 8)};
+                }
+                const cplx<T> u = x[i + j];
+                x[i + j] = u + v;
+                x[i + j + half] = u - v;
+            }
+        }
+    }
+}
+
+}  // namespace wt

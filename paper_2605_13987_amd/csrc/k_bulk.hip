@@ -14,6 +14,8 @@
 // Two real outputs share one complex FFT: Z = F_1 + i F_2, Re -> 1, Im -> 2.
 #include "fft.hpp"
 
+#include <type_traits>
+
 namespace wt {
 
 namespace {
@@ -150,6 +152,131 @@ k_synthesis(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* tw,
     }
 }
 
+// Synthesis with the length-N_z transform split as N_z = N1 x N2 and done in
+// registers: a group of N1 lanes (inside one wavefront) owns one complex FFT
+// that carries two real signals, samples t and t+1 of one component.  Lane k1
+// holds Z[k1 + N1 k2] (k2 < N2), transforms over k2, applies exp(+2 pi i n2
+// k1 / N_z), and the N1 x N2 transpose goes through the FFT's own output slots
+// of the LDS staging block (rotated so every access hits distinct banks); lane
+// j then transforms over k1 for columns n2 = j + N1 c and writes sample
+// z = n2 + N2 n1.  All lanes of the group read before any writes back, in
+// program order of their wavefront.  One workgroup per (X, Y) column; each time
+// block is staged whole and written as one contiguous run.
+template <typename T, int N1, int N2>
+__global__ void __launch_bounds__(48 * N1)
+k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, T* H) {
+    constexpr int NZ = N1 * N2;
+    constexpr int NZH = NZ / 2;
+    constexpr int C = N2 / N1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Nx = p.N[0], Ny = p.N[1], W = p.n_cols, nt = p.n_time, TB = p.tb;
+    cplx<T>* etab = reinterpret_cast<cplx<T>*>(smem);          // [3][W][NZH]
+    cplx<T>* tw = etab + 3 * W * NZH;                          // [NZ]
+    T* stage = reinterpret_cast<T*>(tw + NZ);                  // [NZ][row stride]
+
+    const int col = blockIdx.x;
+    const int ix = col / Ny, iy = col - (col / Ny) * Ny;
+    for (int idx = threadIdx.x; idx < 3 * W * NZH; idx += blockDim.x) {
+        const int a = idx / (W * NZH);
+        const int w = (idx / NZH) % W;
+        const int kk = idx % NZH;
+        const int sx = (ix - p.col[w].ix + Nx) % Nx;
+        const int sy = (iy - p.col[w].iy + Ny) % Ny;
+        etab[idx] = ehat[(((size_t)sx * Ny + sy) * NZH + kk) * 3 + a];
+    }
+    for (int j = threadIdx.x; j < NZ; j += blockDim.x) tw[j] = twz[j];
+    __syncthreads();
+
+    const int g = threadIdx.x / N1;
+    const int k1 = threadIdx.x - g * N1;
+    T* hcol = H + (size_t)col * NZ * nt * 3;
+    for (int t0 = 0; t0 < nt; t0 += TB) {
+        const int tbl = min(TB, nt - t0);
+        const int RS = stage_row_stride<T>(tbl);
+        const int npairs = ((tbl + 1) / 2) * 3;
+        if (g < npairs) {
+            const int tp = g / 3, a = g - 3 * (g / 3);
+            const bool two = 2 * tp + 1 < tbl;
+            const cplx<T>* qa = qhat + (size_t)(t0 + 2 * tp) * W * NZH;
+            const cplx<T>* qb = qa + (size_t)W * NZH;
+            const cplx<T>* ea = etab + a * W * NZH;
+            cplx<T> x[N2];
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) {
+                const int k = k1 + N1 * k2;
+                cplx<T> za{(T)0, (T)0}, zb{(T)0, (T)0};
+                if (k != NZH) {
+                    const bool up = k > NZH;
+                    const int kk = up ? NZ - k : k;
+                    for (int w = 0; w < W; ++w) {
+                        const cplx<T> e = ea[w * NZH + kk];
+                        za = za + e * qa[w * NZH + kk];
+                        if (two) zb = zb + e * qb[w * NZH + kk];
+                    }
+                    if (up) {
+                        za = conj(za);
+                        zb = conj(zb);
+                    }
+                }
+                x[k2] = za + mul_i(zb);
+            }
+            dft_reg<T, N2>(x);
+            T* s0 = stage + 6 * tp + a;          // sample 2tp at s0[z*RS], sample 2tp+1 at s0[z*RS + 3]
+#pragma unroll
+            for (int n2 = 0; n2 < N2; ++n2) {
+                cplx<T> y = x[n2];
+                if (n2 != 0) y = y * tw[n2 * k1];
+                const int z = k1 * N2 + ((n2 + k1) & (N2 - 1));
+                s0[z * RS] = y.re;
+                s0[z * RS + 3] = y.im;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            cplx<T> v[C][N1];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int n2 = k1 + N1 * c;
+#pragma unroll
+                for (int j = 0; j < N1; ++j) {
+                    const int z = j * N2 + ((n2 + j) & (N2 - 1));
+                    v[c][j] = cplx<T>{s0[z * RS], s0[z * RS + 3]};
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                dft_reg<T, N1>(v[c]);
+                const int n2 = k1 + N1 * c;
+#pragma unroll
+                for (int n1 = 0; n1 < N1; ++n1) {
+                    const int z = n2 + N2 * n1;
+                    s0[z * RS] = v[c][n1].re;
+                    s0[z * RS + 3] = v[c][n1].im;
+                }
+            }
+        }
+        __syncthreads();
+        T* dst = hcol + (size_t)t0 * NZ * 3;
+        const int rowlen = tbl * 3;
+        constexpr int VEC = 16 / sizeof(T);
+        if (rowlen % VEC == 0) {
+            using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+            const int vrow = rowlen / VEC;
+            for (int idx = threadIdx.x; idx < NZ * vrow; idx += blockDim.x) {
+                const int z = idx / vrow, r = idx - z * vrow;
+                reinterpret_cast<V*>(dst)[idx] = *reinterpret_cast<const V*>(stage + z * RS + r * VEC);
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < NZ * rowlen; idx += blockDim.x) {
+                const int z = idx / rowlen, r = idx - z * rowlen;
+                dst[idx] = stage[z * RS + r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 int lines_per_block(int N) {
     int lpb = 64;
@@ -190,8 +317,32 @@ hipError_t field_table(const Plan& p, char* b, hipStream_t s) {
     return hipSuccess;
 }
 
+template <typename T, int N1, int N2>
+hipError_t synthesis_reg(const Plan& p, char* b, void* h, hipStream_t s) {
+    const size_t lds = (size_t)3 * p.n_cols * p.nzh * sizeof(cplx<T>) + (size_t)p.N[2] * sizeof(cplx<T>) +
+                       (size_t)p.N[2] * stage_row_stride<T>(p.tb) * sizeof(T);
+    const int threads = ((p.tb + 1) / 2) * 3 * N1;
+    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_reg<T, N1, N2>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_synthesis_reg<T, N1, N2>), dim3(p.N[0] * p.N[1]), dim3(threads), lds, s, p,
+                       reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
+                       reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
+                       reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]), static_cast<T*>(h));
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t synthesis(const Plan& p, char* b, void* h, hipStream_t s) {
+    if (p.synth_kernel == 1) {
+        switch (p.N[2]) {
+            case 64: return synthesis_reg<T, 8, 8>(p, b, h, s);
+            case 128: return synthesis_reg<T, 8, 16>(p, b, h, s);
+            case 256: return synthesis_reg<T, 16, 16>(p, b, h, s);
+            case 512: return synthesis_reg<T, 16, 32>(p, b, h, s);
+            default: break;
+        }
+    }
     const size_t fixed = (size_t)p.n_cols * p.nzh * 3 * sizeof(cplx<T>) + (size_t)p.N[2] * p.tb * 3 * sizeof(T);
     const size_t budget = 160 * 1024;
     int fb = 16;

@@ -99,6 +99,66 @@ __device__ void lu_solve(int n, const c64* lu, const int* piv, c64* x) {
     }
 }
 
+// Solve with the LU factors, refine with the FP64 residual of the
+// equilibrated system, and store the charges and the report of frequency f.
+__device__ void refine_and_store(const Plan& p, const double* A, double inv_a, const c64* zc, const c64* lu,
+                                 const int* pivs, c64* xs, c64* rs, double* red, int f, c64* qw,
+                                 SolveReport* rep, double umax, double umin, int singular) {
+    const int n = p.n, nq = p.n_q, tid = threadIdx.x;
+    // right-hand side: applied voltages, 0 for the neutrality row
+    for (int i = tid; i < n; i += blockDim.x) {
+        c64 b{0.0, 0.0};
+        if (i < nq) b.re = p.col[node_of(p, i).col].v_applied;
+        xs[i] = b;
+    }
+    lu_solve(n, lu, pivs, xs);
+
+    // infinity norms of S and b
+    double srow = 0.0, bmax = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += cmod(s_entry(p, A, inv_a, zc, i, j));
+        srow = fmax(srow, s);
+        if (i < nq) bmax = fmax(bmax, fabs(p.col[node_of(p, i).col].v_applied));
+    }
+    const double snorm = block_max(srow, red);
+    const double bnorm = block_max(bmax, red);
+
+    int iters = 0;
+    double berr = 0.0;
+    for (;;) {
+        double rmax = 0.0, xmax = 0.0;
+        for (int i = tid; i < n; i += blockDim.x) {
+            c64 acc{0.0, 0.0};
+            if (i < nq) acc.re = p.col[node_of(p, i).col].v_applied;
+            for (int j = 0; j < n; ++j) acc = acc - s_entry(p, A, inv_a, zc, i, j) * xs[j];
+            rs[i] = acc;
+            rmax = fmax(rmax, cmod(acc));
+            xmax = fmax(xmax, cmod(xs[i]));
+        }
+        rmax = block_max(rmax, red);
+        xmax = block_max(xmax, red);
+        const double den = snorm * xmax + bnorm;
+        berr = den > 0.0 ? rmax / den : 0.0;
+        if (berr <= p.ir_tol || iters >= p.ir_max_iter) break;
+        lu_solve(n, lu, pivs, rs);
+        for (int i = tid; i < n; i += blockDim.x) xs[i] = xs[i] + rs[i];
+        __syncthreads();
+        ++iters;
+    }
+
+    for (int i = tid; i < n; i += blockDim.x) {
+        const c64 v = xs[i];
+        qw[(size_t)f * n + i] = i < nq ? scale(v, inv_a) : v;
+    }
+    if (tid == 0) {
+        rep[f].backward_error = berr;
+        rep[f].pivot_ratio = umin > 0.0 ? umax / umin : 1e308;
+        rep[f].iters = iters;
+        rep[f].singular = singular;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_solve(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveReport* rep) {
     __shared__ c64 rowk[kMaxN];
@@ -107,9 +167,9 @@ k_solve(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveReport
     __shared__ c64 rs[kMaxN];
     __shared__ int pivs[kMaxN];
     __shared__ c64 zc[kMaxCols];
-    __shared__ double red[kBlock / 64];
-    __shared__ int red_i[kBlock / 64];
-    __shared__ double red_v[kBlock / 64];
+    __shared__ double red[16];
+    __shared__ int red_i[16];
+    __shared__ double red_v[16];
     __shared__ double sh_inv_a;
     __shared__ int sh_piv;
     __shared__ int sh_singular;
@@ -197,64 +257,207 @@ k_solve(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveReport
         __syncthreads();
     }
 
-    // right-hand side: applied voltages, 0 for the neutrality row
-    for (int i = tid; i < n; i += blockDim.x) {
-        c64 b{0.0, 0.0};
-        if (i < nq) b.re = p.col[node_of(p, i).col].v_applied;
-        xs[i] = b;
-    }
-    lu_solve(n, lu, pivs, xs);
+    refine_and_store(p, A, inv_a, zc, lu, pivs, xs, rs, red, f, qw, rep, umax, umin, sh_singular);
+}
 
-    // infinity norms of S and b
-    double srow = 0.0, bmax = 0.0;
-    for (int i = tid; i < n; i += blockDim.x) {
-        double s = 0.0;
-        for (int j = 0; j < n; ++j) s += cmod(s_entry(p, A, inv_a, zc, i, j));
-        srow = fmax(srow, s);
-        if (i < nq) bmax = fmax(bmax, fabs(p.col[node_of(p, i).col].v_applied));
-    }
-    const double snorm = block_max(srow, red);
-    const double bnorm = block_max(bmax, red);
+// Register-resident factorisation: TR x 32 threads, thread (r, c) holding rows
+// r + TR ii (ii < NBR) and columns c + 32 jj (jj < NBC), so n <= min(TR NBR,
+// 32 NBC).  Per pivot step: the TR owners of column k find the pivot (a
+// reduction inside their wavefront), the two affected rows are exchanged
+// through LDS, the pivot row and the multipliers are published in LDS, and
+// every thread updates its block.  The factors are then written to the
+// workspace for the triangular solves of the refinement.
+template <int TR, int NBR, int NBC>
+__global__ void __launch_bounds__(TR * 32)
+k_solve_reg(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveReport* rep) {
+    constexpr int NMAX = 32 * NBC;
+    __shared__ c64 ubuf[NMAX];
+    __shared__ c64 lbuf[TR * NBR];
+    __shared__ c64 row_k[NMAX];
+    __shared__ c64 row_p[NMAX];
+    __shared__ c64 xs[kMaxN];
+    __shared__ c64 rs[kMaxN];
+    __shared__ int pivs[kMaxN];
+    __shared__ c64 zc[kMaxCols];
+    __shared__ double red[16];
+    __shared__ double sh_inv_a;
+    __shared__ int sh_piv;
+    __shared__ double sh_pval;
+    __shared__ int sh_singular;
 
-    int iters = 0;
-    double berr = 0.0;
-    for (;;) {
-        double rmax = 0.0, xmax = 0.0;
-        for (int i = tid; i < n; i += blockDim.x) {
-            c64 acc{0.0, 0.0};
-            if (i < nq) acc.re = p.col[node_of(p, i).col].v_applied;
-            for (int j = 0; j < n; ++j) acc = acc - s_entry(p, A, inv_a, zc, i, j) * xs[j];
-            rs[i] = acc;
-            rmax = fmax(rmax, cmod(acc));
-            xmax = fmax(xmax, cmod(xs[i]));
-        }
-        rmax = block_max(rmax, red);
-        xmax = block_max(xmax, red);
-        const double den = snorm * xmax + bnorm;
-        berr = den > 0.0 ? rmax / den : 0.0;
-        if (berr <= p.ir_tol || iters >= p.ir_max_iter) break;
-        lu_solve(n, lu, pivs, rs);
-        for (int i = tid; i < n; i += blockDim.x) xs[i] = xs[i] + rs[i];
-        __syncthreads();
-        ++iters;
-    }
+    const int f = blockIdx.x;
+    const int n = p.n, nq = p.n_q, tid = threadIdx.x;
+    const int r = tid % TR, c = tid / TR;
+    const double omega = 2.0 * kPi * p.df * f;
+    c64* lu = lu_all + (size_t)f * n * n;
+    int* piv = piv_all + (size_t)f * n;
 
-    for (int i = tid; i < n; i += blockDim.x) {
-        const c64 v = xs[i];
-        qw[(size_t)f * n + i] = i < nq ? scale(v, inv_a) : v;
+    if (tid < p.n_cols) {
+        const Column& cl = p.col[tid];
+        const double delta = fabs(cl.z_free - cl.z_contact) / (cl.n - 1);
+        const double g = delta / (kPi * cl.radius * cl.radius);
+        const double den = cl.sigma * cl.sigma + omega * omega * p.eps * p.eps;
+        zc[tid] = c64{g * omega * omega * p.eps / den, g * omega * cl.sigma / den};
     }
+    double dmax = 0.0;
+    for (int i = tid; i < nq; i += blockDim.x) dmax = fmax(dmax, fabs(A[(size_t)i * nq + i]));
+    dmax = block_max(dmax, red);
     if (tid == 0) {
-        rep[f].backward_error = berr;
-        rep[f].pivot_ratio = umin > 0.0 ? umax / umin : 1e308;
-        rep[f].iters = iters;
-        rep[f].singular = sh_singular;
+        sh_inv_a = 1.0 / dmax;
+        sh_singular = 0;
     }
+    __syncthreads();
+    const double inv_a = sh_inv_a;
+
+    c64 a[NBR][NBC];
+#pragma unroll
+    for (int ii = 0; ii < NBR; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < NBC; ++jj) {
+            const int i = r + TR * ii, j = c + 32 * jj;
+            a[ii][jj] = (i < n && j < n) ? s_entry(p, A, inv_a, zc, i, j) : c64{0.0, 0.0};
+        }
+
+    double umax = 0.0, umin = 1e308;
+    for (int k = 0; k < n; ++k) {
+        const int kc = k & 31, kcq = k >> 5;         // owner column thread and its local column
+        const int kr = k % TR, krq = k / TR;         // owner row thread and its local row
+        if (c == kc) {                               // pivot search in column k
+            double best = -1.0;
+            int bi = n;
+#pragma unroll
+            for (int ii = 0; ii < NBR; ++ii) {
+                const int i = r + TR * ii;
+                c64 v = a[ii][0];
+#pragma unroll
+                for (int t = 1; t < NBC; ++t) if (kcq == t) v = a[ii][t];
+                if (i >= k && i < n) {
+                    const double m = cabs1(v);
+                    if (m > best) { best = m; bi = i; }
+                }
+            }
+            for (int o = TR / 2; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(best, o, TR);
+                const int oi = __shfl_xor(bi, o, TR);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if (r == 0) {
+                sh_piv = bi;
+                sh_pval = best;
+            }
+        }
+        __syncthreads();
+        const int pr = sh_piv;
+        if (tid == 0) {
+            piv[k] = pr;
+            pivs[k] = pr;
+            if (!(sh_pval > 0.0)) sh_singular = 1;
+        }
+        if (pr != k) {                               // exchange rows k and pr through LDS
+            const int pr_r = pr % TR, pr_q = pr / TR;
+            if (r == kr || r == pr_r) {
+#pragma unroll
+                for (int jj = 0; jj < NBC; ++jj) {
+                    const int j = c + 32 * jj;
+                    c64 vk = a[0][jj], vp = a[0][jj];
+#pragma unroll
+                    for (int t = 1; t < NBR; ++t) {
+                        if (krq == t) vk = a[t][jj];
+                        if (pr_q == t) vp = a[t][jj];
+                    }
+                    if (j < n) {
+                        if (r == kr) row_k[j] = vk;
+                        if (r == pr_r) row_p[j] = vp;
+                    }
+                }
+            }
+            __syncthreads();
+            if (r == kr || r == pr_r) {
+#pragma unroll
+                for (int jj = 0; jj < NBC; ++jj) {
+                    const int j = c + 32 * jj;
+                    if (j >= n) continue;
+                    const c64 nk = row_p[j], np = row_k[j];
+#pragma unroll
+                    for (int t = 0; t < NBR; ++t) {
+                        if (r == kr && krq == t) a[t][jj] = nk;
+                        if (r == pr_r && pr_q == t) a[t][jj] = np;
+                    }
+                }
+            }
+        }
+        if (r == kr) {                               // publish the pivot row (columns >= k)
+#pragma unroll
+            for (int jj = 0; jj < NBC; ++jj) {
+                const int j = c + 32 * jj;
+                c64 v = a[0][jj];
+#pragma unroll
+                for (int t = 1; t < NBR; ++t) if (krq == t) v = a[t][jj];
+                if (j >= k && j < n) ubuf[j] = v;
+            }
+        }
+        __syncthreads();
+        const c64 pivot = ubuf[k];
+        const double pm = cmod(pivot);
+        umax = fmax(umax, pm);
+        umin = fmin(umin, pm);
+        const c64 ip = cinv(pivot);
+        if (c == kc) {                               // multipliers of column k
+#pragma unroll
+            for (int ii = 0; ii < NBR; ++ii) {
+                const int i = r + TR * ii;
+                c64 v = a[ii][0];
+#pragma unroll
+                for (int t = 1; t < NBC; ++t) if (kcq == t) v = a[ii][t];
+                const c64 l = v * ip;
+                if (i > k && i < n) {
+#pragma unroll
+                    for (int t = 0; t < NBC; ++t) if (kcq == t) a[ii][t] = l;
+                    lbuf[i] = l;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < NBR; ++ii) {
+            const int i = r + TR * ii;
+            if (i <= k || i >= n) continue;
+            const c64 l = lbuf[i];
+#pragma unroll
+            for (int jj = 0; jj < NBC; ++jj) {
+                const int j = c + 32 * jj;
+                if (j > k && j < n) a[ii][jj] = a[ii][jj] - l * ubuf[j];
+            }
+        }
+    }
+#pragma unroll
+    for (int ii = 0; ii < NBR; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < NBC; ++jj) {
+            const int i = r + TR * ii, j = c + 32 * jj;
+            if (i < n && j < n) lu[(size_t)i * n + j] = a[ii][jj];
+        }
+    __syncthreads();
+    refine_and_store(p, A, inv_a, zc, lu, pivs, xs, rs, red, f, qw, rep, umax, umin, sh_singular);
 }
 
 }  // namespace
 
 hipError_t launch_collocation_solve(const Plan& p, void* ws, hipStream_t s) {
     char* b = static_cast<char*>(ws);
+    const double* A = (const double*)(b + p.off_A);
+    c64* lu = (c64*)(b + p.off_lu);
+    int* piv = (int*)(b + p.off_piv);
+    c64* qw = (c64*)(b + p.off_qw);
+    SolveReport* rep = (SolveReport*)(b + p.off_rep);
+    if (p.n <= 96) {
+        hipLaunchKernelGGL((k_solve_reg<32, 3, 3>), dim3(p.n_freq), dim3(1024), 0, s, p, A, lu, piv, qw, rep);
+        return hipGetLastError();
+    }
+    if (p.n <= 144) {
+        hipLaunchKernelGGL((k_solve_reg<16, 9, 5>), dim3(p.n_freq), dim3(512), 0, s, p, A, lu, piv, qw, rep);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_solve, dim3(p.n_freq), dim3(kBlock), 0, s, p, (const double*)(b + p.off_A),
                        (c64*)(b + p.off_lu), (int*)(b + p.off_piv), (c64*)(b + p.off_qw),
                        (SolveReport*)(b + p.off_rep));

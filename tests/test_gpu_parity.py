@@ -84,7 +84,7 @@ def test_small_grids_end_to_end(ctx, shape, precision):
 
 def test_degenerate_single_frequency_single_sample(ctx):
     cfg = workloads.small_pixel(k=43, n_xy=8, n_z=8, n_freq=2, n_time=1, n_pairs=3, n_colloc=4)
-    cfg["spectrum"] = dict(n_freq=1, df=0.0, n_time=1, dt=10e-12)
+    cfg["spectrum"] = dict(n_freq=1, df=1.25e9, n_time=1, dt=10e-12)      # static term only
     for col in cfg["columns"]:
         col["z_free"] = 0.5 * (col["z_free"] + col["z_contact"])
     say("test_degenerate_single_frequency_single_sample")
@@ -110,6 +110,20 @@ def test_three_columns_and_zero_carriers(ctx):
     empty = dict(pos=np.zeros((0, 21, 3)), charge=np.zeros(0), track=np.zeros(0, np.int32), n_tracks=2)
     out = current(ctx, run, empty)
     assert out.shape == (2, 20) and np.all(out == 0.0)
+
+
+def test_large_system_uses_the_global_memory_factorisation(ctx):
+    """Three long columns give n = 3 * 60 + 1 = 181 unknowns, beyond the
+    register-resident factorisation; the workspace LU path must agree too."""
+    cfg = workloads.small_pixel(k=48, n_xy=16, n_z=32, n_freq=5, n_time=12, n_pairs=4, n_colloc=60)
+    extra = copy.deepcopy(cfg["columns"][1])
+    extra.update(x=0.0, y=25e-6, resistivity=[0.5e-2], n_colloc=60)
+    cfg["columns"].append(extra)
+    say("test_large_system_uses_the_global_memory_factorisation")
+    ref = oracle.weighting_field(cfg["cell"], cfg["columns"], cfg["spectrum"])
+    run = solve_h(ctx, cfg, wt.WT_F64)
+    _check_stages(run, cfg, ref, wt.WT_F64)
+    assert rel_l2(h_standard(run, cfg), ref["H"]) <= 1e-9
 
 
 def _synthetic_full(cfg, seed):
