@@ -165,10 +165,15 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     while (tb > 1 && lds_need(tb) > lds_budget) tb = (tb + 1) / 2;
     if (lds_need(tb) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
     p.tb = tb;
-    // register-FFT synthesis where N_z = N1 x N2 is supported and its staging fits
-    const int rs = p.precision == WT_F64 ? wt::stage_row_stride<double>(tb) : wt::stage_row_stride<float>(tb);
-    const size_t reg_need = (size_t)3 * n_cols * p.nzh * cx + (size_t)N[2] * cx + (size_t)N[2] * rs * re;
-    p.synth_kernel = ((N[2] == 64 || N[2] == 128 || N[2] == 256 || N[2] == 512) && reg_need <= lds_budget) ? 1 : 0;
+    // register-FFT synthesis where N_z = N1 x N2 is supported, there are at
+    // most 4 columns, the thread count ((tb+1)/2 * 3 * N1) is a multiple of
+    // N_z/2 (each thread keeps one k_z), and the LDS fits
+    p.nzh = N[2] / 2;
+    const int n1 = N[2] >= 256 ? 16 : 8;
+    const int threads = ((tb + 1) / 2) * 3 * n1;
+    const bool reg_size = N[2] == 64 || N[2] == 128 || N[2] == 256 || N[2] == 512;
+    p.synth_kernel = (reg_size && n_cols <= 4 && threads % p.nzh == 0 &&
+                      wt::synthesis_reg_lds(p, re) <= lds_budget) ? 1 : 0;
 
     size_t off = 0;
     for (int a = 0; a < 3; ++a) {

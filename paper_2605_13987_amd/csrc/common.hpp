@@ -106,6 +106,13 @@ __host__ __device__ inline int stage_row_stride(int tbl) {
     return base + ((2 - base % 4) + 4) % 4;
 }
 
+// LDS bytes of the register-FFT synthesis workgroup (element size re):
+// twiddles [N_z] (complex) and the staging block [N_z][row stride].
+inline size_t synthesis_reg_lds(const Plan& p, size_t re) {
+    const int rs = re == 8 ? stage_row_stride<double>(p.tb) : stage_row_stride<float>(p.tb);
+    return 2 * re * (size_t)p.N[2] + (size_t)p.N[2] * rs * re;
+}
+
 // Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.
 inline int factorize(int n, int* rad) {
     int k = 0;

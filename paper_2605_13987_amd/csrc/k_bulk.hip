@@ -152,83 +152,114 @@ k_synthesis(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* tw,
     }
 }
 
+typedef float vec4f __attribute__((ext_vector_type(4)));
+typedef double vec2d __attribute__((ext_vector_type(2)));
+
 // Synthesis with the length-N_z transform split as N_z = N1 x N2 and done in
-// registers: a group of N1 lanes (inside one wavefront) owns one complex FFT
-// that carries two real signals, samples t and t+1 of one component.  Lane k1
-// holds Z[k1 + N1 k2] (k2 < N2), transforms over k2, applies exp(+2 pi i n2
-// k1 / N_z), and the N1 x N2 transpose goes through the FFT's own output slots
-// of the LDS staging block (rotated so every access hits distinct banks); lane
-// j then transforms over k1 for columns n2 = j + N1 c and writes sample
-// z = n2 + N2 n1.  All lanes of the group read before any writes back, in
-// program order of their wavefront.  One workgroup per (X, Y) column; each time
-// block is staged whole and written as one contiguous run.
-template <typename T, int N1, int N2>
+// registers.  One workgroup per (X, Y) column; per time block of the H layout
+// (TB samples, staged whole in LDS as [z][sample][component], row stride RS):
+//
+// 1. Spectra.  Thread i owns k_z index kk = i mod N_z/2 and keeps the field
+//    table entries Ehat_a(X - X_w, Y - Y_w, kk) of all components and columns
+//    in registers; for each sample t of the block it reads Qhat_w(kk, t) once
+//    (coalesced over kk) and writes F_a(kk, t) = sum_w Ehat_a Qhat_w into the
+//    staging slots of the transform that will carry samples (t, t+1) of
+//    component a: F_t(kk) at rows kk, F_{t+1}(kk) at rows N_z/2 + kk.
+// 2. Transforms.  A group of N1 lanes (inside one wavefront) owns one complex
+//    FFT carrying those two real signals, Z(k) = F_t(k) + i F_{t+1}(k) with
+//    Z(N_z - k) = conj F_t(k) + i conj F_{t+1}(k) and Z(N_z/2) = 0.  Lane k1
+//    reads Z[k1 + N1 k2] (k2 < N2), transforms over k2, applies exp(+2 pi i n2
+//    k1 / N_z), and the N1 x N2 transpose goes through the same slots (rotated
+//    so every access hits distinct banks); lane j then transforms over k1 for
+//    columns n2 = j + N1 c and writes sample z = n2 + N2 n1.  All lanes of a
+//    group read before any writes back, in program order of their wavefront.
+// 3. The finished block is written as one contiguous run with non-temporal
+//    stores (H is not re-read here and should not evict the tables from L2).
+template <typename T, int N1, int N2, int WC>
 __global__ void __launch_bounds__(48 * N1)
 k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, T* H) {
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
     constexpr int C = N2 / N1;
+    constexpr int NT = 48 * N1;                                // = 3 * 16 * N1 (TB <= 32)
+    using V = typename std::conditional<sizeof(T) == 4, vec4f, vec2d>::type;
+    constexpr int VEC = 16 / sizeof(T);
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Nx = p.N[0], Ny = p.N[1], W = p.n_cols, nt = p.n_time, TB = p.tb;
-    cplx<T>* etab = reinterpret_cast<cplx<T>*>(smem);          // [3][W][NZH]
-    cplx<T>* tw = etab + 3 * W * NZH;                          // [NZ]
+    const int Nx = p.N[0], Ny = p.N[1], nt = p.n_time, TB = p.tb;
+    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);            // [NZ]
     T* stage = reinterpret_cast<T*>(tw + NZ);                  // [NZ][row stride]
+    const int nthr = blockDim.x;
 
     const int col = blockIdx.x;
     const int ix = col / Ny, iy = col - (col / Ny) * Ny;
-    for (int idx = threadIdx.x; idx < 3 * W * NZH; idx += blockDim.x) {
-        const int a = idx / (W * NZH);
-        const int w = (idx / NZH) % W;
-        const int kk = idx % NZH;
+    for (int j = threadIdx.x; j < NZ; j += nthr) tw[j] = twz[j];
+
+    // field table entries of this thread's k_z (constant over the column)
+    const int kkb = threadIdx.x % NZH;
+    cplx<T> e[3][WC];
+#pragma unroll
+    for (int w = 0; w < WC; ++w) {
         const int sx = (ix - p.col[w].ix + Nx) % Nx;
         const int sy = (iy - p.col[w].iy + Ny) % Ny;
-        etab[idx] = ehat[(((size_t)sx * Ny + sy) * NZH + kk) * 3 + a];
+        const cplx<T>* src = ehat + (((size_t)sx * Ny + sy) * NZH + kkb) * 3;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) e[a][w] = src[a];
     }
-    for (int j = threadIdx.x; j < NZ; j += blockDim.x) tw[j] = twz[j];
-    __syncthreads();
 
     const int g = threadIdx.x / N1;
     const int k1 = threadIdx.x - g * N1;
+    const int tp = g / 3, a = g - 3 * (g / 3);
     T* hcol = H + (size_t)col * NZ * nt * 3;
     for (int t0 = 0; t0 < nt; t0 += TB) {
         const int tbl = min(TB, nt - t0);
+        const int tbe = (tbl + 1) & ~1;                        // even number of staged samples
         const int RS = stage_row_stride<T>(tbl);
-        const int npairs = ((tbl + 1) / 2) * 3;
-        if (g < npairs) {
-            const int tp = g / 3, a = g - 3 * (g / 3);
-            const bool two = 2 * tp + 1 < tbl;
-            const cplx<T>* qa = qhat + (size_t)(t0 + 2 * tp) * W * NZH;
-            const cplx<T>* qb = qa + (size_t)W * NZH;
-            const cplx<T>* ea = etab + a * W * NZH;
+        __syncthreads();                                       // previous block fully copied out
+        // 1. spectra of every sample of the block (zero for a padding sample)
+        for (int idx = threadIdx.x; idx < NZH * tbe; idx += nthr) {
+            const int tin = idx / NZH;                         // kk = idx % NZH = kkb (nthr % NZH == 0)
+            cplx<T> q[WC];
+#pragma unroll
+            for (int w = 0; w < WC; ++w)
+                q[w] = tin < tbl ? qhat[((size_t)(t0 + tin) * WC + w) * NZH + kkb] : cplx<T>{(T)0, (T)0};
+            const int pair = tin >> 1, odd = tin & 1;
+            const int row = (odd ? NZH : 0) + kkb;
+#pragma unroll
+            for (int aa = 0; aa < 3; ++aa) {
+                cplx<T> f{(T)0, (T)0};
+#pragma unroll
+                for (int w = 0; w < WC; ++w) f = f + e[aa][w] * q[w];
+                T* s1 = stage + row * RS + 6 * pair + aa;
+                s1[0] = f.re;
+                s1[3] = f.im;
+            }
+        }
+        __syncthreads();
+        // 2. transforms
+        if (g < (tbe / 2) * 3) {
+            T* s1 = stage + 6 * tp + a;       // slot (z, j) of this transform at s1[z*RS + 3j]
             cplx<T> x[N2];
 #pragma unroll
             for (int k2 = 0; k2 < N2; ++k2) {
                 const int k = k1 + N1 * k2;
-                cplx<T> za{(T)0, (T)0}, zb{(T)0, (T)0};
-                if (k != NZH) {
-                    const bool up = k > NZH;
-                    const int kk = up ? NZ - k : k;
-                    for (int w = 0; w < W; ++w) {
-                        const cplx<T> e = ea[w * NZH + kk];
-                        za = za + e * qa[w * NZH + kk];
-                        if (two) zb = zb + e * qb[w * NZH + kk];
-                    }
-                    if (up) {
-                        za = conj(za);
-                        zb = conj(zb);
-                    }
-                }
-                x[k2] = za + mul_i(zb);
+                const bool up = k > NZH;
+                const int kk = up ? NZ - k : (k == NZH ? 0 : k);
+                const cplx<T> ft{s1[kk * RS], s1[kk * RS + 3]};
+                const cplx<T> fu{s1[(NZH + kk) * RS], s1[(NZH + kk) * RS + 3]};
+                const cplx<T> za = up ? conj(ft) : ft;
+                const cplx<T> zb = up ? conj(fu) : fu;
+                x[k2] = k == NZH ? cplx<T>{(T)0, (T)0} : za + mul_i(zb);
             }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             dft_reg<T, N2>(x);
-            T* s0 = stage + 6 * tp + a;          // sample 2tp at s0[z*RS], sample 2tp+1 at s0[z*RS + 3]
 #pragma unroll
             for (int n2 = 0; n2 < N2; ++n2) {
                 cplx<T> y = x[n2];
                 if (n2 != 0) y = y * tw[n2 * k1];
                 const int z = k1 * N2 + ((n2 + k1) & (N2 - 1));
-                s0[z * RS] = y.re;
-                s0[z * RS + 3] = y.im;
+                s1[z * RS] = y.re;
+                s1[z * RS + 3] = y.im;
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -239,7 +270,7 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
 #pragma unroll
                 for (int j = 0; j < N1; ++j) {
                     const int z = j * N2 + ((n2 + j) & (N2 - 1));
-                    v[c][j] = cplx<T>{s0[z * RS], s0[z * RS + 3]};
+                    v[c][j] = cplx<T>{s1[z * RS], s1[z * RS + 3]};
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -251,29 +282,28 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
 #pragma unroll
                 for (int n1 = 0; n1 < N1; ++n1) {
                     const int z = n2 + N2 * n1;
-                    s0[z * RS] = v[c][n1].re;
-                    s0[z * RS + 3] = v[c][n1].im;
+                    s1[z * RS] = v[c][n1].re;
+                    s1[z * RS + 3] = v[c][n1].im;
                 }
             }
         }
         __syncthreads();
+        // 3. copy-out
         T* dst = hcol + (size_t)t0 * NZ * 3;
         const int rowlen = tbl * 3;
-        constexpr int VEC = 16 / sizeof(T);
         if (rowlen % VEC == 0) {
-            using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
             const int vrow = rowlen / VEC;
-            for (int idx = threadIdx.x; idx < NZ * vrow; idx += blockDim.x) {
+            for (int idx = threadIdx.x; idx < NZ * vrow; idx += nthr) {
                 const int z = idx / vrow, r = idx - z * vrow;
-                reinterpret_cast<V*>(dst)[idx] = *reinterpret_cast<const V*>(stage + z * RS + r * VEC);
+                __builtin_nontemporal_store(*reinterpret_cast<const V*>(stage + z * RS + r * VEC),
+                                            reinterpret_cast<V*>(dst) + idx);
             }
         } else {
-            for (int idx = threadIdx.x; idx < NZ * rowlen; idx += blockDim.x) {
+            for (int idx = threadIdx.x; idx < NZ * rowlen; idx += nthr) {
                 const int z = idx / rowlen, r = idx - z * rowlen;
-                dst[idx] = stage[z * RS + r];
+                __builtin_nontemporal_store(stage[z * RS + r], dst + idx);
             }
         }
-        __syncthreads();
     }
 }
 
@@ -317,29 +347,40 @@ hipError_t field_table(const Plan& p, char* b, hipStream_t s) {
     return hipSuccess;
 }
 
-template <typename T, int N1, int N2>
+template <typename T, int N1, int N2, int WC>
 hipError_t synthesis_reg(const Plan& p, char* b, void* h, hipStream_t s) {
-    const size_t lds = (size_t)3 * p.n_cols * p.nzh * sizeof(cplx<T>) + (size_t)p.N[2] * sizeof(cplx<T>) +
-                       (size_t)p.N[2] * stage_row_stride<T>(p.tb) * sizeof(T);
+    const size_t lds = synthesis_reg_lds(p, sizeof(T));
+    // one thread per (k_z, sample-group): a multiple of N_z/2 threads, at most
+    // one transform group per (sample pair, component) of a block
     const int threads = ((p.tb + 1) / 2) * 3 * N1;
-    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_reg<T, N1, N2>,
+    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_reg<T, N1, N2, WC>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_synthesis_reg<T, N1, N2>), dim3(p.N[0] * p.N[1]), dim3(threads), lds, s, p,
+    hipLaunchKernelGGL((k_synthesis_reg<T, N1, N2, WC>), dim3(p.N[0] * p.N[1]), dim3(threads), lds, s, p,
                        reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]), static_cast<T*>(h));
     return hipGetLastError();
 }
 
+template <typename T, int N1, int N2>
+hipError_t synthesis_reg_w(const Plan& p, char* b, void* h, hipStream_t s) {
+    switch (p.n_cols) {
+        case 1: return synthesis_reg<T, N1, N2, 1>(p, b, h, s);
+        case 2: return synthesis_reg<T, N1, N2, 2>(p, b, h, s);
+        case 3: return synthesis_reg<T, N1, N2, 3>(p, b, h, s);
+        default: return synthesis_reg<T, N1, N2, 4>(p, b, h, s);
+    }
+}
+
 template <typename T>
 hipError_t synthesis(const Plan& p, char* b, void* h, hipStream_t s) {
     if (p.synth_kernel == 1) {
         switch (p.N[2]) {
-            case 64: return synthesis_reg<T, 8, 8>(p, b, h, s);
-            case 128: return synthesis_reg<T, 8, 16>(p, b, h, s);
-            case 256: return synthesis_reg<T, 16, 16>(p, b, h, s);
-            case 512: return synthesis_reg<T, 16, 32>(p, b, h, s);
+            case 64: return synthesis_reg_w<T, 8, 8>(p, b, h, s);
+            case 128: return synthesis_reg_w<T, 8, 16>(p, b, h, s);
+            case 256: return synthesis_reg_w<T, 16, 16>(p, b, h, s);
+            case 512: return synthesis_reg_w<T, 16, 32>(p, b, h, s);
             default: break;
         }
     }
