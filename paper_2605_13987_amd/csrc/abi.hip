@@ -166,13 +166,13 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     if (lds_need(tb) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
     p.tb = tb;
     // register-FFT synthesis where N_z = N1 x N2 is supported, there are at
-    // most 4 columns, the thread count ((tb+1)/2 * 3 * N1) is a multiple of
+    // most 4 columns, the thread count (lane groups x N1) is a multiple of
     // N_z/2 (each thread keeps one k_z), and the LDS fits
     p.nzh = N[2] / 2;
     const int n1 = N[2] >= 256 ? 16 : 8;
-    const int threads = ((tb + 1) / 2) * 3 * n1;
+    const int threads = wt::synthesis_groups(tb) * n1;
     const bool reg_size = N[2] == 64 || N[2] == 128 || N[2] == 256 || N[2] == 512;
-    p.synth_kernel = (reg_size && n_cols <= 4 && threads % p.nzh == 0 &&
+    p.synth_kernel = (reg_size && n_cols <= 4 && tb == 32 && threads % p.nzh == 0 &&
                       wt::synthesis_reg_lds(p, re) <= lds_budget) ? 1 : 0;
 
     size_t off = 0;

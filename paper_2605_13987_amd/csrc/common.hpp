@@ -97,20 +97,24 @@ hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tr
 
 // Row stride (elements) of the LDS staging block of the register-FFT
 // synthesis for a time block of tbl samples: room for an even number of
-// samples, and a stride whose multiples by 0..15 fall in distinct LDS banks
-// (4 mod 8 words for float, 2 mod 4 doubles for double), with 16-byte rows.
+// samples, made odd so that any 32 consecutive rows fall in distinct banks.
 template <typename T>
 __host__ __device__ inline int stage_row_stride(int tbl) {
-    const int base = ((tbl + 1) / 2) * 2 * 3;
-    if (sizeof(T) == 4) return base + ((4 - base % 8) + 8) % 8;
-    return base + ((2 - base % 4) + 4) % 4;
+    return ((tbl + 1) / 2) * 2 * 3 + 1;
 }
 
-// LDS bytes of the register-FFT synthesis workgroup (element size re):
-// twiddles [N_z] (complex) and the staging block [N_z][row stride].
+// Lane groups of the register-FFT synthesis: 6 * ceil(ceil(tb/2)/2), so that
+// the two groups of each half-wavefront can take sample pairs D apart.
+__host__ __device__ inline int synthesis_groups(int tb) {
+    const int pairs = (tb + 1) / 2;
+    return 6 * ((pairs + 1) / 2);
+}
+
+// LDS bytes of the register-FFT synthesis workgroup (element size re): the
+// staging block [N_z][row stride].
 inline size_t synthesis_reg_lds(const Plan& p, size_t re) {
     const int rs = re == 8 ? stage_row_stride<double>(p.tb) : stage_row_stride<float>(p.tb);
-    return 2 * re * (size_t)p.N[2] + (size_t)p.N[2] * rs * re;
+    return (size_t)p.N[2] * rs * re;
 }
 
 // Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.

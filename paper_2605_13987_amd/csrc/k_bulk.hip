@@ -169,10 +169,15 @@ typedef double vec2d __attribute__((ext_vector_type(2)));
 //    FFT carrying those two real signals, Z(k) = F_t(k) + i F_{t+1}(k) with
 //    Z(N_z - k) = conj F_t(k) + i conj F_{t+1}(k) and Z(N_z/2) = 0.  Lane k1
 //    reads Z[k1 + N1 k2] (k2 < N2), transforms over k2, applies exp(+2 pi i n2
-//    k1 / N_z), and the N1 x N2 transpose goes through the same slots (rotated
-//    so every access hits distinct banks); lane j then transforms over k1 for
+//    k1 / N_z) (twiddles kept in registers), and the N1 x N2 transpose goes
+//    through the same slots, rotated; lane j then transforms over k1 for
 //    columns n2 = j + N1 c and writes sample z = n2 + N2 n1.  All lanes of a
 //    group read before any writes back, in program order of their wavefront.
+//    Bank mapping: the row stride is odd and every access of a group touches
+//    16 rows that are distinct mod 16; the two groups of a half-wavefront
+//    take the same component of sample pairs D = TB/4 apart, whose columns
+//    differ by 6 D (= 16 mod 32 for TB = 32: 32 distinct banks per
+//    half-wavefront; 24 for TB = 16: at most two-way conflicts).
 // 3. The finished block is written as one contiguous run with non-temporal
 //    stores (H is not re-read here and should not evict the tables from L2).
 template <typename T, int N1, int N2, int WC>
@@ -181,18 +186,17 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
     constexpr int C = N2 / N1;
-    constexpr int NT = 48 * N1;                                // = 3 * 16 * N1 (TB <= 32)
-    using V = typename std::conditional<sizeof(T) == 4, vec4f, vec2d>::type;
-    constexpr int VEC = 16 / sizeof(T);
+    constexpr int TBC = 32;                                    // time block (plan guarantees p.tb == 32)
+    constexpr int NT = 48 * N1;
+    constexpr int PFI = (NZH * TBC + NT - 1) / NT;             // spectra items per thread per block
+    constexpr int STORES = NZ * 3 * TBC / NT;                  // stores per thread per full block
+    constexpr int RS = 3 * TBC + 1;                            // LDS row stride (odd: rows in distinct banks)
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Nx = p.N[0], Ny = p.N[1], nt = p.n_time, TB = p.tb;
-    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);            // [NZ]
-    T* stage = reinterpret_cast<T*>(tw + NZ);                  // [NZ][row stride]
-    const int nthr = blockDim.x;
+    const int Nx = p.N[0], Ny = p.N[1], nt = p.n_time;
+    T* stage = reinterpret_cast<T*>(smem);                     // [NZ][row stride]
 
     const int col = blockIdx.x;
     const int ix = col / Ny, iy = col - (col / Ny) * Ny;
-    for (int j = threadIdx.x; j < NZ; j += nthr) tw[j] = twz[j];
 
     // field table entries of this thread's k_z (constant over the column)
     const int kkb = threadIdx.x % NZH;
@@ -206,103 +210,173 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
         for (int a = 0; a < 3; ++a) e[a][w] = src[a];
     }
 
+    // transform group: half-wavefront pair (h, s) -> component a, sample pair tp
     const int g = threadIdx.x / N1;
     const int k1 = threadIdx.x - g * N1;
-    const int tp = g / 3, a = g - 3 * (g / 3);
+    const int hg = g >> 1, sg = g & 1;
+    constexpr int D = TBC / 4;
+    const int a = hg % 3, tp = hg / 3 + sg * D;
+    cplx<T> twr[N2];                                           // exp(+2 pi i n2 k1 / N_z)
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) twr[n2] = twz[n2 * k1];
+    // Values loaded ahead of the block loop are used here once, so they are
+    // complete on entry and no wait inside the loop (which would also wait
+    // for the block stores still in flight) is needed for them.
+    auto settle = [](const cplx<T>& v) { asm volatile("" ::"v"(v.re), "v"(v.im)); };
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) settle(twr[n2]);
+#pragma unroll
+    for (int w = 0; w < WC; ++w)
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa) settle(e[aa][w]);
+
+    // Column spectra Qhat_w(kkb, t0 + tin) of this thread's items (tin = (i +
+    // k NT) / NZH) of the block at t0.  Addresses are clamped into the table
+    // and values past the block zeroed, so the loads are unconditional.
+    cplx<T> pq[PFI][WC];
+    auto fetch = [&](int t0) {
+        const int tbl = min(TBC, nt - t0);
+#pragma unroll
+        for (int k = 0; k < PFI; ++k) {
+            const int tin = (threadIdx.x + k * NT) / NZH;
+            const int t = min(t0 + tin, nt - 1);
+#pragma unroll
+            for (int w = 0; w < WC; ++w) {
+                const cplx<T> v = qhat[((size_t)t * WC + w) * NZH + kkb];
+                pq[k][w] = tin < tbl ? v : cplx<T>{(T)0, (T)0};
+            }
+        }
+    };
+    // 1. spectra of the tbe (even) staged samples of a block
+    auto build = [&](int tbe) {
+#pragma unroll
+        for (int k = 0; k < PFI; ++k)
+#pragma unroll
+            for (int w = 0; w < WC; ++w) settle(pq[k][w]);
+#pragma unroll
+        for (int k = 0; k < PFI; ++k) {
+            const int tin = (threadIdx.x + k * NT) / NZH;
+            if (tin < tbe) {
+                const int pair = tin >> 1, odd = tin & 1;
+                T* s1 = stage + ((odd ? NZH : 0) + kkb) * RS + 6 * pair;
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa) {
+                    cplx<T> f{(T)0, (T)0};
+#pragma unroll
+                    for (int w = 0; w < WC; ++w) f = f + e[aa][w] * pq[k][w];
+                    s1[aa] = f.re;
+                    s1[aa + 3] = f.im;
+                }
+            }
+        }
+    };
+    // 2. transforms of the tbe / 2 sample pairs of a block
+    auto transform = [&](int tbe) {
+        if (tp >= tbe / 2) return;
+        // lane indices re-derived per block (opaque to the optimiser) so that
+        // the per-lane LDS addresses are not hoisted out of the block loop and
+        // kept live across it
+        int k1 = threadIdx.x % N1, slot = 6 * tp + a;
+        asm volatile("" : "+v"(k1), "+v"(slot));
+        T* s1 = stage + slot;                 // slot (z, j) of this transform at s1[z*RS + 3j]
+        cplx<T> x[N2];
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+            const int k = k1 + N1 * k2;
+            const bool up = k > NZH;
+            const int kk = up ? NZ - k : (k == NZH ? 0 : k);
+            const cplx<T> ft{s1[kk * RS], s1[kk * RS + 3]};
+            const cplx<T> fu{s1[(NZH + kk) * RS], s1[(NZH + kk) * RS + 3]};
+            const cplx<T> za = up ? conj(ft) : ft;
+            const cplx<T> zb = up ? conj(fu) : fu;
+            x[k2] = k == NZH ? cplx<T>{(T)0, (T)0} : za + mul_i(zb);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        dft_reg<T, N2>(x);
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) {
+            cplx<T> y = x[n2];
+            if (n2 != 0) y = y * twr[n2];
+            const int z = k1 * N2 + ((n2 + k1) & (N2 - 1));
+            s1[z * RS] = y.re;
+            s1[z * RS + 3] = y.im;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        cplx<T> v[C][N1];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int n2 = k1 + N1 * c;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) {
+                const int z = j * N2 + ((n2 + j) & (N2 - 1));
+                v[c][j] = cplx<T>{s1[z * RS], s1[z * RS + 3]};
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            dft_reg<T, N1>(v[c]);
+            const int n2 = k1 + N1 * c;
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) {
+                const int z = n2 + N2 * n1;
+                s1[z * RS] = v[c][n1].re;
+                s1[z * RS + 3] = v[c][n1].im;
+            }
+        }
+    };
+
+    // 3. copy-out: the block is one contiguous run of H, written with
+    // consecutive lanes on consecutive values.  A full block takes a fixed
+    // number of stores per thread (a pass of NT threads covers whole rows),
+    // so the next block's spectra, loaded just before, are waited for without
+    // waiting for these stores.  Only the last block can be partial.
+    static_assert(NT % (3 * TBC) == 0, "copy-out rows per pass");
+    constexpr int ROWS = NT / (3 * TBC);
     T* hcol = H + (size_t)col * NZ * nt * 3;
-    for (int t0 = 0; t0 < nt; t0 += TB) {
-        const int tbl = min(TB, nt - t0);
-        const int tbe = (tbl + 1) & ~1;                        // even number of staged samples
-        const int RS = stage_row_stride<T>(tbl);
-        __syncthreads();                                       // previous block fully copied out
-        // 1. spectra of every sample of the block (zero for a padding sample)
-        for (int idx = threadIdx.x; idx < NZH * tbe; idx += nthr) {
-            const int tin = idx / NZH;                         // kk = idx % NZH = kkb (nthr % NZH == 0)
-            cplx<T> q[WC];
-#pragma unroll
-            for (int w = 0; w < WC; ++w)
-                q[w] = tin < tbl ? qhat[((size_t)(t0 + tin) * WC + w) * NZH + kkb] : cplx<T>{(T)0, (T)0};
-            const int pair = tin >> 1, odd = tin & 1;
-            const int row = (odd ? NZH : 0) + kkb;
-#pragma unroll
-            for (int aa = 0; aa < 3; ++aa) {
-                cplx<T> f{(T)0, (T)0};
-#pragma unroll
-                for (int w = 0; w < WC; ++w) f = f + e[aa][w] * q[w];
-                T* s1 = stage + row * RS + 6 * pair + aa;
-                s1[0] = f.re;
-                s1[3] = f.im;
-            }
-        }
-        __syncthreads();
-        // 2. transforms
-        if (g < (tbe / 2) * 3) {
-            T* s1 = stage + 6 * tp + a;       // slot (z, j) of this transform at s1[z*RS + 3j]
-            cplx<T> x[N2];
-#pragma unroll
-            for (int k2 = 0; k2 < N2; ++k2) {
-                const int k = k1 + N1 * k2;
-                const bool up = k > NZH;
-                const int kk = up ? NZ - k : (k == NZH ? 0 : k);
-                const cplx<T> ft{s1[kk * RS], s1[kk * RS + 3]};
-                const cplx<T> fu{s1[(NZH + kk) * RS], s1[(NZH + kk) * RS + 3]};
-                const cplx<T> za = up ? conj(ft) : ft;
-                const cplx<T> zb = up ? conj(fu) : fu;
-                x[k2] = k == NZH ? cplx<T>{(T)0, (T)0} : za + mul_i(zb);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            dft_reg<T, N2>(x);
-#pragma unroll
-            for (int n2 = 0; n2 < N2; ++n2) {
-                cplx<T> y = x[n2];
-                if (n2 != 0) y = y * tw[n2 * k1];
-                const int z = k1 * N2 + ((n2 + k1) & (N2 - 1));
-                s1[z * RS] = y.re;
-                s1[z * RS + 3] = y.im;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            cplx<T> v[C][N1];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int n2 = k1 + N1 * c;
-#pragma unroll
-                for (int j = 0; j < N1; ++j) {
-                    const int z = j * N2 + ((n2 + j) & (N2 - 1));
-                    v[c][j] = cplx<T>{s1[z * RS], s1[z * RS + 3]};
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                dft_reg<T, N1>(v[c]);
-                const int n2 = k1 + N1 * c;
-#pragma unroll
-                for (int n1 = 0; n1 < N1; ++n1) {
-                    const int z = n2 + N2 * n1;
-                    s1[z * RS] = v[c][n1].re;
-                    s1[z * RS + 3] = v[c][n1].im;
-                }
-            }
-        }
-        __syncthreads();
-        // 3. copy-out
+    fetch(0);
+    build((min(TBC, nt) + 1) & ~1);
+    for (int t0 = 0; t0 < nt; t0 += TBC) {
+        const int tbl = min(TBC, nt - t0);
+        const int tn = t0 + TBC;
+        __syncthreads();                                       // spectra staged
+        transform((tbl + 1) & ~1);
+        __syncthreads();                                       // block transformed
         T* dst = hcol + (size_t)t0 * NZ * 3;
-        const int rowlen = tbl * 3;
-        if (rowlen % VEC == 0) {
-            const int vrow = rowlen / VEC;
-            for (int idx = threadIdx.x; idx < NZ * vrow; idx += nthr) {
-                const int z = idx / vrow, r = idx - z * vrow;
-                __builtin_nontemporal_store(*reinterpret_cast<const V*>(stage + z * RS + r * VEC),
-                                            reinterpret_cast<V*>(dst) + idx);
-            }
+        if (tbl == TBC) {
+            if (tn < nt) fetch(tn);
+            int lane = threadIdx.x;
+            asm volatile("" : "+v"(lane));
+            const T* src = stage + (lane / (3 * TBC)) * RS + lane % (3 * TBC);
+            T* d = dst + lane;
+#pragma unroll
+            for (int k = 0; k < STORES; ++k) __builtin_nontemporal_store(src[k * ROWS * RS], d + k * NT);
+            // the spectra loads went out before the stores: waiting for them
+            // leaves the stores in flight
+#pragma unroll
+            for (int k = 0; k < PFI; ++k)
+#pragma unroll
+                for (int w = 0; w < WC; ++w) settle(pq[k][w]);
         } else {
-            for (int idx = threadIdx.x; idx < NZ * rowlen; idx += nthr) {
-                const int z = idx / rowlen, r = idx - z * rowlen;
+            const int rowlen = tbl * 3;
+            const int dz = NT / rowlen, dr = NT - dz * rowlen;
+            int z = threadIdx.x / rowlen, r = threadIdx.x - (threadIdx.x / rowlen) * rowlen;
+            for (int idx = threadIdx.x; idx < NZ * rowlen; idx += NT) {
                 __builtin_nontemporal_store(stage[z * RS + r], dst + idx);
+                z += dz;
+                r += dr;
+                if (r >= rowlen) {
+                    r -= rowlen;
+                    ++z;
+                }
             }
+        }
+        if (tn < nt) {
+            __syncthreads();                                   // block copied out of the staging slots
+            build((min(TBC, nt - tn) + 1) & ~1);
         }
     }
 }
@@ -350,9 +424,8 @@ hipError_t field_table(const Plan& p, char* b, hipStream_t s) {
 template <typename T, int N1, int N2, int WC>
 hipError_t synthesis_reg(const Plan& p, char* b, void* h, hipStream_t s) {
     const size_t lds = synthesis_reg_lds(p, sizeof(T));
-    // one thread per (k_z, sample-group): a multiple of N_z/2 threads, at most
-    // one transform group per (sample pair, component) of a block
-    const int threads = ((p.tb + 1) / 2) * 3 * N1;
+    // lane groups of N1 threads; the plan guarantees a multiple of N_z/2 threads
+    const int threads = synthesis_groups(p.tb) * N1;
     hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_reg<T, N1, N2, WC>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;

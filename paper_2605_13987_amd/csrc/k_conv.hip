@@ -5,9 +5,9 @@
 // field at the step midpoint and lag n - m projected on dx; the field between
 // nodes is the trilinear interpolation of the nodal H with periodic wrap.
 // Section 3 of the paper computes the whole correlation of one carrier per
-// GPU thread; here one 64-lane wavefront owns a few carriers and its lanes
-// own output samples n = lane + 64 j, so the 8 corner lag series of a step
-// are read as contiguous runs and the sum over steps stays in registers.
+// GPU thread; here one 64-lane wavefront owns a carrier and its lanes own
+// output samples n = lane + 64 j, so the 8 corner lag series of a step are
+// read as contiguous runs and the sum over steps stays in registers.
 #include "common.hpp"
 
 namespace wt {
@@ -41,84 +41,156 @@ __device__ inline void flush(T* out, int track, int nt, int lane, T* acc) {
     }
 }
 
+// Field of one moving step projected on its displacement, at lag tau, for
+// the 8 trilinear corners (weights already carry -q / V_w).
+template <typename T>
+struct Step {
+    size_t b00, b01, b10, b11;     // column bases of the 4 (x, y) corners
+    int z0, z1;
+    T w[8];
+    T dx, dy, dz;
+};
+
+template <typename T>
+__device__ inline T step_value(const T* H, const Step<T>& s, int tau, int TB, int Nz, int last_block, int last_len) {
+    const int tb = tau / TB;
+    const int tin = tau - tb * TB;
+    const int len = tb == last_block ? last_len : TB;
+    const size_t toff = (size_t)tb * TB * Nz * 3 + (size_t)tin * 3;
+    const size_t o0 = toff + (size_t)s.z0 * len * 3, o1 = toff + (size_t)s.z1 * len * 3;
+    const T* h;
+    T v = (T)0;
+    h = H + s.b00 + o0; v += s.w[0] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
+    h = H + s.b00 + o1; v += s.w[1] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
+    h = H + s.b01 + o0; v += s.w[2] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
+    h = H + s.b01 + o1; v += s.w[3] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
+    h = H + s.b10 + o0; v += s.w[4] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
+    h = H + s.b10 + o1; v += s.w[5] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
+    h = H + s.b11 + o0; v += s.w[6] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
+    h = H + s.b11 + o1; v += s.w[7] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
+    return v;
+}
+
+template <typename T>
+__device__ inline bool make_step(const Plan& p, const T* P, int m, T q, Step<T>& s) {
+    const int Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
+    const size_t col_stride = (size_t)Nz * p.n_time * 3;
+    s.dx = P[3 * m + 3] - P[3 * m + 0];
+    s.dy = P[3 * m + 4] - P[3 * m + 1];
+    s.dz = P[3 * m + 5] - P[3 * m + 2];
+    const T ux = (P[3 * m + 0] + P[3 * m + 3]) * (T)0.5 * (T)(Nx / p.L[0]);
+    const T uy = (P[3 * m + 1] + P[3 * m + 4]) * (T)0.5 * (T)(Ny / p.L[1]);
+    const T uz = (P[3 * m + 2] + P[3 * m + 5]) * (T)0.5 * (T)(Nz / p.L[2]);
+    if (!(isfinite(ux) && isfinite(uy) && isfinite(uz))) return false;
+    const T flx = floor(ux), fly = floor(uy), flz = floor(uz);
+    const T fx = ux - flx, fy = uy - fly, fz = uz - flz;
+    // periodic wrap of the lower corner, clamped so every index is in range
+    const int x0 = wrap_index(flx, Nx), y0 = wrap_index(fly, Ny), z0 = wrap_index(flz, Nz);
+    const int x1 = x0 + 1 == Nx ? 0 : x0 + 1;
+    const int y1 = y0 + 1 == Ny ? 0 : y0 + 1;
+    s.z0 = z0;
+    s.z1 = z0 + 1 == Nz ? 0 : z0 + 1;
+    s.b00 = ((size_t)x0 * Ny + y0) * col_stride;
+    s.b01 = ((size_t)x0 * Ny + y1) * col_stride;
+    s.b10 = ((size_t)x1 * Ny + y0) * col_stride;
+    s.b11 = ((size_t)x1 * Ny + y1) * col_stride;
+    const T gx = (T)1 - fx, gy = (T)1 - fy, gz = (T)1 - fz;
+    // -q folded into the weights (V_w = 1 V)
+    s.w[0] = -q * gx * gy * gz;
+    s.w[1] = -q * gx * gy * fz;
+    s.w[2] = -q * gx * fy * gz;
+    s.w[3] = -q * gx * fy * fz;
+    s.w[4] = -q * fx * gy * gz;
+    s.w[5] = -q * fx * gy * fz;
+    s.w[6] = -q * fx * fy * gz;
+    s.w[7] = -q * fx * fy * fz;
+    return true;
+}
+
+// One wavefront per carrier (grid-stride over carriers).  Lanes first find the
+// carrier's moving steps (64 at a time, compacted in LDS by ballot), then run
+// over output samples n = lane + 64 j while the wavefront walks the moving
+// steps two at a time.  The four wavefronts of a workgroup add their partial
+// currents in LDS before one atomic flush when they carry the same track.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_current(Plan p, const T* H, int n_carriers, int n_tracks, const T* pos, const T* charge,
-          const int* track, T* out, int per_wave) {
+          const int* track, T* out) {
+    __shared__ short steps[kBlock / kWave][kMaxTime];
+    __shared__ T part[kBlock / kWave][kMaxTime];
+    __shared__ int wtrack[kBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
-    const int c_begin = wave * per_wave;
-    const int c_end = min(c_begin + per_wave, n_carriers);
-    const int nt = p.n_time, TB = p.tb;
-    const int Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
+    const int wv = threadIdx.x / kWave;
+    const int nt = p.n_time, TB = p.tb, Nz = p.N[2];
     const int last_block = (nt - 1) / TB;
     const int last_len = nt - last_block * TB;
-    const size_t col_stride = (size_t)Nz * nt * 3;
-    const T ihx = (T)(Nx / p.L[0]), ihy = (T)(Ny / p.L[1]), ihz = (T)(Nz / p.L[2]);
+    const int c = blockIdx.x * (kBlock / kWave) + wv;
 
     T acc[kMaxJ];
 #pragma unroll
     for (int j = 0; j < kMaxJ; ++j) acc[j] = (T)0;
-    int cur = -1;
-
-    for (int c = c_begin; c < c_end; ++c) {
-        const int tr = track[c];
-        if (tr < 0 || tr >= n_tracks) continue;
-        if (tr != cur) {
-            if (cur >= 0) flush(out, cur, nt, lane, acc);
-            cur = tr;
-        }
+    int tr = -1;
+    if (c < n_carriers) {
+        tr = track[c];
+        if (tr < 0 || tr >= n_tracks) tr = -1;
+    }
+    if (tr >= 0) {
         const T q = charge[c];
         const T* P = pos + (size_t)c * (nt + 1) * 3;
-        for (int m = 0; m < nt; ++m) {
-            const T dx = P[3 * m + 3] - P[3 * m + 0];
-            const T dy = P[3 * m + 4] - P[3 * m + 1];
-            const T dz = P[3 * m + 5] - P[3 * m + 2];
-            if (dx == (T)0 && dy == (T)0 && dz == (T)0) continue;
-            const T ux = (P[3 * m + 0] + P[3 * m + 3]) * (T)0.5 * ihx;
-            const T uy = (P[3 * m + 1] + P[3 * m + 4]) * (T)0.5 * ihy;
-            const T uz = (P[3 * m + 2] + P[3 * m + 5]) * (T)0.5 * ihz;
-            if (!(isfinite(ux) && isfinite(uy) && isfinite(uz))) continue;
-            const T flx = floor(ux), fly = floor(uy), flz = floor(uz);
-            const T fx = ux - flx, fy = uy - fly, fz = uz - flz;
-            // periodic wrap of the lower corner, clamped so every index is in range
-            const int x0 = wrap_index(flx, Nx), y0 = wrap_index(fly, Ny), z0 = wrap_index(flz, Nz);
-            const int x1 = x0 + 1 == Nx ? 0 : x0 + 1;
-            const int y1 = y0 + 1 == Ny ? 0 : y0 + 1;
-            const int z1 = z0 + 1 == Nz ? 0 : z0 + 1;
-            const size_t b00 = ((size_t)x0 * Ny + y0) * col_stride, b01 = ((size_t)x0 * Ny + y1) * col_stride;
-            const size_t b10 = ((size_t)x1 * Ny + y0) * col_stride, b11 = ((size_t)x1 * Ny + y1) * col_stride;
-            const T gx0 = (T)1 - fx, gy0 = (T)1 - fy, gz0 = (T)1 - fz;
-            // -q folded into the weights (V_w = 1 V)
-            const T w000 = -q * gx0 * gy0 * gz0, w001 = -q * gx0 * gy0 * fz;
-            const T w010 = -q * gx0 * fy * gz0, w011 = -q * gx0 * fy * fz;
-            const T w100 = -q * fx * gy0 * gz0, w101 = -q * fx * gy0 * fz;
-            const T w110 = -q * fx * fy * gz0, w111 = -q * fx * fy * fz;
+        // moving steps of this carrier, in order
+        int nmov = 0;
+        for (int m0 = 0; m0 < nt; m0 += kWave) {
+            const int m = m0 + lane;
+            bool mv = false;
+            if (m < nt) {
+                const T dx = P[3 * m + 3] - P[3 * m + 0];
+                const T dy = P[3 * m + 4] - P[3 * m + 1];
+                const T dz = P[3 * m + 5] - P[3 * m + 2];
+                mv = !(dx == (T)0 && dy == (T)0 && dz == (T)0);
+            }
+            const unsigned long long bal = __ballot(mv);
+            if (mv) steps[wv][nmov + __popcll(bal & ((1ull << lane) - 1ull))] = (short)m;
+            nmov += __popcll(bal);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int e = 0; e < nmov; e += 2) {
+            const int ma = steps[wv][e];
+            const int mb = e + 1 < nmov ? steps[wv][e + 1] : -1;
+            Step<T> sa, sb;
+            const bool va = make_step(p, P, ma, q, sa);
+            const bool vb = mb >= 0 && make_step(p, P, mb, q, sb);
 #pragma unroll
             for (int j = 0; j < kMaxJ; ++j) {
                 const int n = lane + kWave * j;
-                const int tau = n - m;
-                if (n >= nt || tau < 0) continue;
-                const int tb = tau / TB;
-                const int tin = tau - tb * TB;
-                const int len = tb == last_block ? last_len : TB;
-                const size_t toff = (size_t)tb * TB * Nz * 3 + (size_t)tin * 3;
-                const size_t o0 = toff + (size_t)z0 * len * 3, o1 = toff + (size_t)z1 * len * 3;
-                const T* h;
+                if (n >= nt) continue;
                 T v = (T)0;
-                h = H + b00 + o0; v += w000 * (h[0] * dx + h[1] * dy + h[2] * dz);
-                h = H + b00 + o1; v += w001 * (h[0] * dx + h[1] * dy + h[2] * dz);
-                h = H + b01 + o0; v += w010 * (h[0] * dx + h[1] * dy + h[2] * dz);
-                h = H + b01 + o1; v += w011 * (h[0] * dx + h[1] * dy + h[2] * dz);
-                h = H + b10 + o0; v += w100 * (h[0] * dx + h[1] * dy + h[2] * dz);
-                h = H + b10 + o1; v += w101 * (h[0] * dx + h[1] * dy + h[2] * dz);
-                h = H + b11 + o0; v += w110 * (h[0] * dx + h[1] * dy + h[2] * dz);
-                h = H + b11 + o1; v += w111 * (h[0] * dx + h[1] * dy + h[2] * dz);
+                if (va && n >= ma) v += step_value(H, sa, n - ma, TB, Nz, last_block, last_len);
+                if (vb && n >= mb) v += step_value(H, sb, n - mb, TB, Nz, last_block, last_len);
                 acc[j] += v;
             }
         }
     }
-    if (cur >= 0) flush(out, cur, nt, lane, acc);
+    // workgroup reduction when all four wavefronts carry the same track
+    if (lane == 0) wtrack[wv] = tr;
+    __syncthreads();
+    bool same = true;
+    for (int w = 1; w < kBlock / kWave; ++w) same = same && (wtrack[w] == wtrack[0]);
+    if (same && wtrack[0] >= 0) {
+#pragma unroll
+        for (int j = 0; j < kMaxJ; ++j) {
+            const int n = lane + kWave * j;
+            if (n < nt) part[wv][n] = acc[j];
+        }
+        __syncthreads();
+        for (int n = threadIdx.x; n < nt; n += kBlock) {
+            T v = (T)0;
+            for (int w = 0; w < kBlock / kWave; ++w) v += part[w][n];
+            if (v != (T)0) atomicAdd(out + (size_t)wtrack[0] * nt + n, v);
+        }
+    } else if (tr >= 0) {
+        flush(out, tr, nt, lane, acc);
+    }
 }
 
 template <typename T>
@@ -129,12 +201,10 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
     hipLaunchKernelGGL(k_fill_zero<T>, dim3(zgrid > 0 ? zgrid : 1), dim3(kBlock), 0, s, static_cast<T*>(out), n_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n_carriers == 0) return e;
-    const int per_wave = 4;
-    const int waves = (n_carriers + per_wave - 1) / per_wave;
-    const int blocks = (waves * kWave + kBlock - 1) / kBlock;
+    const int blocks = (n_carriers + kBlock / kWave - 1) / (kBlock / kWave);
     hipLaunchKernelGGL(k_current<T>, dim3(blocks), dim3(kBlock), 0, s, p, static_cast<const T*>(h), n_carriers,
                        n_tracks, static_cast<const T*>(pos), static_cast<const T*>(charge), track,
-                       static_cast<T*>(out), per_wave);
+                       static_cast<T*>(out));
     return hipGetLastError();
 }
 

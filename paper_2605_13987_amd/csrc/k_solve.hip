@@ -70,6 +70,20 @@ __device__ inline double block_max(double v, double* red) {
     return s;   // valid in every thread
 }
 
+__device__ inline c64 block_csum(c64 v, c64* red) {
+    for (int o = 32; o > 0; o >>= 1) {
+        v.re += __shfl_xor(v.re, o, 64);
+        v.im += __shfl_xor(v.im, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    c64 s = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) s = s + red[i];
+    return s;   // valid in every thread
+}
+
 // x <- (LU)^-1 P x, with LU and the pivots of one frequency.
 __device__ void lu_solve(int n, const c64* lu, const int* piv, c64* x) {
     const int tid = threadIdx.x;
@@ -441,6 +455,337 @@ k_solve_reg(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveRe
     refine_and_store(p, A, inv_a, zc, lu, pivs, xs, rs, red, f, qw, rep, umax, umin, sh_singular);
 }
 
+// y1 <- St^-1 y1 (and y2 <- St^-1 y2 when two), right-hand sides already
+// permuted, with the factors held in registers by the 32 x 32 thread grid.
+template <int NB>
+__device__ __forceinline__ void solve_in_registers(const c64 (&a)[NB][NB], int m, int r, int cc, const c64* diag,
+                                                   c64* y1, c64* y2, bool two) {
+#pragma unroll
+    for (int kq = 0; kq < NB; ++kq)                        // unit lower triangle
+    for (int k32 = 0; k32 < 32; ++k32) {
+        const int k = 32 * kq + k32;
+        if (k >= m - 1) break;
+        __syncthreads();
+        if (cc == k32) {
+            const c64 b1 = y1[k], b2 = two ? y2[k] : c64{0.0, 0.0};
+#pragma unroll
+            for (int ii = 0; ii < NB; ++ii) {
+                const int i = r + 32 * ii;
+                if (i > k && i < m) {
+                    const c64 l = a[ii][kq];
+                    y1[i] = y1[i] - l * b1;
+                    if (two) y2[i] = y2[i] - l * b2;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int kq = NB - 1; kq >= 0; --kq)                   // upper triangle
+    for (int k32 = 31; k32 >= 0; --k32) {
+        const int k = 32 * kq + k32;
+        if (k >= m) continue;
+        __syncthreads();
+        if (cc == k32) {
+            const c64 id = cinv(diag[k]);
+            const c64 b1 = y1[k] * id, b2 = two ? y2[k] * id : c64{0.0, 0.0};
+#pragma unroll
+            for (int ii = 0; ii < NB; ++ii) {
+                const int i = r + 32 * ii;
+                if (i < k) {
+                    const c64 u = a[ii][kq];
+                    y1[i] = y1[i] - u * b1;
+                    if (two) y2[i] = y2[i] - u * b2;
+                }
+            }
+            if (r == k32) {           // owner of row k; its half-wavefront read y1[k] above
+                y1[k] = b1;
+                if (two) y2[k] = b2;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Schur-complement form for n_q <= 32 NB: only the n_q x n_q block
+// St = (A + i w R) / a is factored; with St x1 = b and St x2 = 1 the bordered
+// system gives c = (1'x1) / (1'x2) and q' = x1 - c x2 (exact in exact
+// arithmetic).  1024 threads in a 32 x 32 grid, thread (r, c) holding rows
+// r + 32 ii and columns c + 32 jj of St; the factors stay in registers for
+// the triangular solves (one barrier per step: the owners of column k update
+// the rows below or above k).  Refinement uses the residual of the bordered
+// system, computed with one wavefront per row (coalesced reads of A).
+template <int NB>
+__global__ void __launch_bounds__(1024)
+k_solve_schur(Plan p, const double* A, c64* qw, SolveReport* rep) {
+    constexpr int NM = 32 * NB;
+    __shared__ c64 ubuf[NM];
+    __shared__ c64 lbuf[NM];
+    __shared__ c64 row_k[NM];
+    __shared__ c64 row_p[NM];
+    __shared__ c64 diag[NM];
+    __shared__ c64 y1[NM];
+    __shared__ c64 y2[NM];
+    __shared__ c64 xq[NM];
+    __shared__ c64 rr[NM];
+    __shared__ int perm[NM];
+    __shared__ int pivs[NM];
+    __shared__ unsigned char colof[NM];
+    __shared__ short mof[NM];
+    __shared__ c64 zc[kMaxCols];
+    __shared__ double vapp[kMaxCols];
+    __shared__ double red[16];
+    __shared__ c64 redc[16];
+    __shared__ double sh_inv_a;
+    __shared__ int sh_piv;
+    __shared__ double sh_pval;
+    __shared__ int sh_singular;
+    __shared__ c64 sh_c;
+
+    const int f = blockIdx.x;
+    const int m = p.n_q, tid = threadIdx.x;
+    const int r = tid & 31, cc = tid >> 5;
+    const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const double omega = 2.0 * kPi * p.df * f;
+
+    if (tid < p.n_cols) {
+        const Column& cl = p.col[tid];
+        const double delta = fabs(cl.z_free - cl.z_contact) / (cl.n - 1);
+        const double g = delta / (kPi * cl.radius * cl.radius);
+        const double den = cl.sigma * cl.sigma + omega * omega * p.eps * p.eps;
+        zc[tid] = c64{g * omega * omega * p.eps / den, g * omega * cl.sigma / den};
+        vapp[tid] = cl.v_applied;
+    }
+    for (int i = tid; i < m; i += blockDim.x) {
+        const NodeMap nm = node_of(p, i);
+        colof[i] = (unsigned char)nm.col;
+        mof[i] = (short)nm.m;
+    }
+    double dmax = 0.0;
+    for (int i = tid; i < m; i += blockDim.x) dmax = fmax(dmax, fabs(A[(size_t)i * m + i]));
+    dmax = block_max(dmax, red);
+    if (tid == 0) {
+        sh_inv_a = 1.0 / dmax;
+        sh_singular = 0;
+    }
+    __syncthreads();
+    const double inv_a = sh_inv_a;
+    auto st = [&](int i, int j) -> c64 {                 // entry of St
+        c64 v{A[(size_t)i * m + j], 0.0};
+        if (colof[i] == colof[j]) v = v + scale(zc[colof[i]], (double)(mof[i] < mof[j] ? mof[i] : mof[j]));
+        return scale(v, inv_a);
+    };
+
+    c64 a[NB][NB];
+#pragma unroll
+    for (int ii = 0; ii < NB; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) {
+            const int i = r + 32 * ii, j = cc + 32 * jj;
+            a[ii][jj] = (i < m && j < m) ? st(i, j) : c64{0.0, 0.0};
+        }
+
+    double umax = 0.0, umin = 1e308;
+#pragma unroll
+    for (int kq = 0; kq < NB; ++kq)                        // local index of column k: compile-time
+    for (int k32 = 0; k32 < 32; ++k32) {
+        const int k = 32 * kq + k32;
+        if (k >= m) break;
+        if (cc == k32) {                                   // pivot search in column k
+            double best = -1.0;
+            int bi = m;
+#pragma unroll
+            for (int ii = 0; ii < NB; ++ii) {
+                const int i = r + 32 * ii;
+                const c64 v = a[ii][kq];
+                if (i >= k && i < m) {
+                    const double mm = cabs1(v);
+                    if (mm > best) { best = mm; bi = i; }
+                }
+            }
+            for (int o = 16; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(best, o, 32);
+                const int oi = __shfl_xor(bi, o, 32);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if (r == 0) {
+                sh_piv = bi;
+                sh_pval = best;
+            }
+        }
+        __syncthreads();
+        const int pr = sh_piv;
+        if (tid == 0) {
+            pivs[k] = pr;
+            if (!(sh_pval > 0.0)) sh_singular = 1;
+        }
+        if (pr != k) {
+            const int p32 = pr & 31, pq = pr >> 5;
+            if (r == k32 || r == p32) {
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) {
+                    const int j = cc + 32 * jj;
+                    const c64 vk = a[kq][jj];
+                    c64 vp = a[0][jj];
+#pragma unroll
+                    for (int t = 1; t < NB; ++t)
+                        if (pq == t) vp = a[t][jj];
+                    if (j < m) {
+                        if (r == k32) row_k[j] = vk;
+                        if (r == p32) row_p[j] = vp;
+                    }
+                }
+            }
+            __syncthreads();
+            if (r == k32 || r == p32) {
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) {
+                    const int j = cc + 32 * jj;
+                    if (j >= m) continue;
+                    const c64 nk = row_p[j], np = row_k[j];
+                    if (r == k32) a[kq][jj] = nk;
+#pragma unroll
+                    for (int t = 0; t < NB; ++t)
+                        if (r == p32 && pq == t) a[t][jj] = np;
+                }
+            }
+        }
+        if (r == k32) {                                    // publish the pivot row (columns >= k)
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+                const int j = cc + 32 * jj;
+                if (j >= k && j < m) ubuf[j] = a[kq][jj];
+            }
+        }
+        __syncthreads();
+        const c64 pivot = ubuf[k];
+        if (tid == 0) diag[k] = pivot;
+        const double pm = cmod(pivot);
+        umax = fmax(umax, pm);
+        umin = fmin(umin, pm);
+        const c64 ip = cinv(pivot);
+        if (cc == k32) {                                   // multipliers of column k
+#pragma unroll
+            for (int ii = 0; ii < NB; ++ii) {
+                const int i = r + 32 * ii;
+                const c64 l = a[ii][kq] * ip;
+                if (i > k && i < m) {
+                    a[ii][kq] = l;
+                    lbuf[i] = l;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < NB; ++ii) {
+            const int i = r + 32 * ii;
+            if (i <= k || i >= m) continue;
+            const c64 l = lbuf[i];
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+                const int j = cc + 32 * jj;
+                if (j > k && j < m) a[ii][jj] = a[ii][jj] - l * ubuf[j];
+            }
+        }
+    }
+    if (tid == 0) {                                        // row permutation of the factorisation
+        for (int i = 0; i < m; ++i) perm[i] = i;
+        for (int k = 0; k < m; ++k) {
+            const int q = pivs[k];
+            const int t = perm[k];
+            perm[k] = perm[q];
+            perm[q] = t;
+        }
+    }
+    __syncthreads();
+
+    // right-hand sides: applied voltages and ones, permuted
+    for (int i = tid; i < m; i += blockDim.x) {
+        y1[i] = c64{vapp[colof[perm[i]]], 0.0};
+        y2[i] = c64{1.0, 0.0};
+    }
+    solve_in_registers<NB>(a, m, r, cc, diag, y1, y2, true);
+    // c = (1' x1) / (1' x2);  q' = x1 - c x2
+    c64 s1{0.0, 0.0}, s2{0.0, 0.0};
+    for (int i = tid; i < m; i += blockDim.x) {
+        s1 = s1 + y1[i];
+        s2 = s2 + y2[i];
+    }
+    const c64 t1 = block_csum(s1, redc), t2 = block_csum(s2, redc);
+    const c64 cg = t1 * cinv(t2);
+    for (int i = tid; i < m; i += blockDim.x) {
+        xq[i] = y1[i] - cg * y2[i];
+        rr[i] = y2[i];                                     // keep St^-1 1 for the corrections
+    }
+    if (tid == 0) sh_c = cg;
+    __syncthreads();
+
+    // infinity norms of the bordered system and of b
+    double srow = 0.0;
+    for (int i = wave; i < m; i += nwave) {
+        double sacc = 0.0;
+        for (int j = lane; j < m; j += 64) sacc += cmod(st(i, j));
+        for (int o = 32; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 64);
+        srow = fmax(srow, sacc + 1.0);
+    }
+    const double snorm = fmax(block_max(srow, red), (double)m);
+    double bmax = 0.0;
+    for (int w = 0; w < p.n_cols; ++w) bmax = fmax(bmax, fabs(vapp[w]));
+    const c64 s2_all = t2;
+
+    int iters = 0;
+    double berr = 0.0;
+    for (;;) {
+        // residual of the bordered system: rows i < m into y1, neutrality into redc-sum
+        const c64 cur_c = sh_c;
+        double rmax = 0.0;
+        for (int i = wave; i < m; i += nwave) {
+            c64 acc{0.0, 0.0};
+            for (int j = lane; j < m; j += 64) acc = acc + st(i, j) * xq[j];
+            for (int o = 32; o > 0; o >>= 1) {
+                acc.re += __shfl_xor(acc.re, o, 64);
+                acc.im += __shfl_xor(acc.im, o, 64);
+            }
+            const c64 ri = c64{vapp[colof[i]], 0.0} - acc - cur_c;
+            if (lane == 0) y1[i] = ri;
+            rmax = fmax(rmax, cmod(ri));
+        }
+        c64 qs{0.0, 0.0};
+        double xmax = 0.0;
+        for (int i = tid; i < m; i += blockDim.x) {
+            qs = qs + xq[i];
+            xmax = fmax(xmax, cmod(xq[i]));
+        }
+        const c64 r2 = c64{0.0, 0.0} - block_csum(qs, redc);
+        rmax = fmax(block_max(rmax, red), cmod(r2));
+        xmax = fmax(block_max(xmax, red), cmod(cur_c));
+        const double den = snorm * xmax + bmax;
+        berr = den > 0.0 ? rmax / den : 0.0;
+        if (berr <= p.ir_tol || iters >= p.ir_max_iter) break;
+        // correction: d = St^-1 r1 - dc x2,  dc = (1' St^-1 r1 - r2) / (1' x2)
+        for (int i = tid; i < m; i += blockDim.x) y2[i] = y1[perm[i]];
+        __syncthreads();
+        for (int i = tid; i < m; i += blockDim.x) y1[i] = y2[i];
+        solve_in_registers<NB>(a, m, r, cc, diag, y1, y2, false);
+        c64 sd{0.0, 0.0};
+        for (int i = tid; i < m; i += blockDim.x) sd = sd + y1[i];
+        const c64 dc = (block_csum(sd, redc) - r2) * cinv(s2_all);
+        for (int i = tid; i < m; i += blockDim.x) xq[i] = xq[i] + y1[i] - dc * rr[i];
+        if (tid == 0) sh_c = cur_c + dc;
+        __syncthreads();
+        ++iters;
+    }
+
+    const int n = p.n;
+    for (int i = tid; i < m; i += blockDim.x) qw[(size_t)f * n + i] = scale(xq[i], inv_a);
+    if (tid == 0) {
+        qw[(size_t)f * n + m] = sh_c;
+        rep[f].backward_error = berr;
+        rep[f].pivot_ratio = umin > 0.0 ? umax / umin : 1e308;
+        rep[f].iters = iters;
+        rep[f].singular = sh_singular;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_collocation_solve(const Plan& p, void* ws, hipStream_t s) {
@@ -450,8 +795,16 @@ hipError_t launch_collocation_solve(const Plan& p, void* ws, hipStream_t s) {
     int* piv = (int*)(b + p.off_piv);
     c64* qw = (c64*)(b + p.off_qw);
     SolveReport* rep = (SolveReport*)(b + p.off_rep);
-    if (p.n <= 96) {
-        hipLaunchKernelGGL((k_solve_reg<32, 3, 3>), dim3(p.n_freq), dim3(1024), 0, s, p, A, lu, piv, qw, rep);
+    if (p.n_q <= 64) {
+        hipLaunchKernelGGL(k_solve_schur<2>, dim3(p.n_freq), dim3(1024), 0, s, p, A, qw, rep);
+        return hipGetLastError();
+    }
+    if (p.n_q <= 96) {
+        hipLaunchKernelGGL(k_solve_schur<3>, dim3(p.n_freq), dim3(1024), 0, s, p, A, qw, rep);
+        return hipGetLastError();
+    }
+    if (p.n_q <= 128) {
+        hipLaunchKernelGGL(k_solve_schur<4>, dim3(p.n_freq), dim3(1024), 0, s, p, A, qw, rep);
         return hipGetLastError();
     }
     if (p.n <= 144) {
