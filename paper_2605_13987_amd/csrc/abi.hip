@@ -165,15 +165,11 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     while (tb > 1 && lds_need(tb) > lds_budget) tb = (tb + 1) / 2;
     if (lds_need(tb) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
     p.tb = tb;
-    // register-FFT synthesis where N_z = N1 x N2 is supported, there are at
-    // most 4 columns, the thread count (lane groups x N1) is a multiple of
-    // N_z/2 (each thread keeps one k_z), and the LDS fits
-    p.nzh = N[2] / 2;
-    const int n1 = N[2] >= 256 ? 16 : 8;
-    const int threads = wt::synthesis_groups(tb) * n1;
+    // register-FFT synthesis where N_z = N1 x N2 is supported, the time block
+    // is whole, there are at most 4 columns, and the LDS fits
     const bool reg_size = N[2] == 64 || N[2] == 128 || N[2] == 256 || N[2] == 512;
-    p.synth_kernel = (reg_size && n_cols <= 4 && tb == 32 && threads % p.nzh == 0 &&
-                      wt::synthesis_reg_lds(p, re) <= lds_budget) ? 1 : 0;
+    p.synth_kernel = (reg_size && n_cols <= 4 && tb == wt::kSynthBlock &&
+                      wt::synthesis_reg_lds(N[2], re) <= lds_budget) ? 1 : 0;
 
     size_t off = 0;
     for (int a = 0; a < 3; ++a) {

@@ -95,26 +95,22 @@ hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tr
                           const void* pos, const void* charge, const int* track,
                           void* out, hipStream_t s);
 
-// Row stride (elements) of the LDS staging block of the register-FFT
-// synthesis for a time block of tbl samples: room for an even number of
-// samples, made odd so that any 32 consecutive rows fall in distinct banks.
-template <typename T>
-__host__ __device__ inline int stage_row_stride(int tbl) {
-    return ((tbl + 1) / 2) * 2 * 3 + 1;
+// Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256, 512}): time block
+// of 32 samples staged in LDS as rows of 3 x 32 values, row stride 97 (= 1
+// mod 32 banks) and row z at z * 97 + floor(z / N2).
+constexpr int kSynthBlock = 32;
+constexpr int kSynthRowStride = 3 * kSynthBlock + 1;
+
+__host__ __device__ constexpr int synthesis_n2(int nz) {
+    return nz == 64 ? 8 : (nz == 128 ? 16 : (nz == 256 ? 16 : 32));
 }
 
-// Lane groups of the register-FFT synthesis: 6 * ceil(ceil(tb/2)/2), so that
-// the two groups of each half-wavefront can take sample pairs D apart.
-__host__ __device__ inline int synthesis_groups(int tb) {
-    const int pairs = (tb + 1) / 2;
-    return 6 * ((pairs + 1) / 2);
-}
+// Threads of the register-FFT synthesis workgroup: 48 groups of N1 lanes.
+__host__ __device__ constexpr int synthesis_threads(int nz) { return 48 * (nz / synthesis_n2(nz)); }
 
-// LDS bytes of the register-FFT synthesis workgroup (element size re): the
-// staging block [N_z][row stride].
-inline size_t synthesis_reg_lds(const Plan& p, size_t re) {
-    const int rs = re == 8 ? stage_row_stride<double>(p.tb) : stage_row_stride<float>(p.tb);
-    return (size_t)p.N[2] * rs * re;
+// LDS bytes of the register-FFT synthesis workgroup (element size re).
+inline size_t synthesis_reg_lds(int nz, size_t re) {
+    return ((size_t)nz * kSynthRowStride + nz / synthesis_n2(nz)) * re;
 }
 
 // Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.

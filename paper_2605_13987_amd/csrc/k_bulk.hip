@@ -156,28 +156,30 @@ typedef float vec4f __attribute__((ext_vector_type(4)));
 typedef double vec2d __attribute__((ext_vector_type(2)));
 
 // Synthesis with the length-N_z transform split as N_z = N1 x N2 and done in
-// registers.  One workgroup per (X, Y) column; per time block of the H layout
-// (TB samples, staged whole in LDS as [z][sample][component], row stride RS):
+// registers.  One workgroup per (X, Y) column; per time block of 32 samples of
+// the H layout, staged whole in LDS as [z][sample][component] (row z at
+// z RS + floor(z / N2), RS = 97):
 //
 // 1. Spectra.  Thread i owns k_z index kk = i mod N_z/2 and keeps the field
 //    table entries Ehat_a(X - X_w, Y - Y_w, kk) of all components and columns
-//    in registers; for each sample t of the block it reads Qhat_w(kk, t) once
-//    (coalesced over kk) and writes F_a(kk, t) = sum_w Ehat_a Qhat_w into the
-//    staging slots of the transform that will carry samples (t, t+1) of
-//    component a: F_t(kk) at rows kk, F_{t+1}(kk) at rows N_z/2 + kk.
+//    in registers.  For a pair of samples (t, t+1) it forms F_a(kk, t) =
+//    sum_w Ehat_a Qhat_w(kk, t) and F_a(kk, t+1), and writes the spectrum of
+//    the complex signal that carries both, Z(kk) = F_t(kk) + i F_{t+1}(kk) to
+//    row kk and Z(N_z - kk) = conj F_t(kk) + i conj F_{t+1}(kk) to row
+//    N_z - kk (Z(N_z/2) = 0), in the columns of that pair and component.
 // 2. Transforms.  A group of N1 lanes (inside one wavefront) owns one complex
-//    FFT carrying those two real signals, Z(k) = F_t(k) + i F_{t+1}(k) with
-//    Z(N_z - k) = conj F_t(k) + i conj F_{t+1}(k) and Z(N_z/2) = 0.  Lane k1
-//    reads Z[k1 + N1 k2] (k2 < N2), transforms over k2, applies exp(+2 pi i n2
-//    k1 / N_z) (twiddles kept in registers), and the N1 x N2 transpose goes
-//    through the same slots, rotated; lane j then transforms over k1 for
-//    columns n2 = j + N1 c and writes sample z = n2 + N2 n1.  All lanes of a
-//    group read before any writes back, in program order of their wavefront.
-//    Bank mapping: the row stride is odd and every access of a group touches
-//    16 rows that are distinct mod 16; the two groups of a half-wavefront
-//    take the same component of sample pairs D = TB/4 apart, whose columns
-//    differ by 6 D (= 16 mod 32 for TB = 32: 32 distinct banks per
-//    half-wavefront; 24 for TB = 16: at most two-way conflicts).
+//    FFT of length N_z.  Lane k1 reads Z[k1 + N1 k2] (k2 < N2), transforms
+//    over k2, applies exp(+2 pi i n2 k1 / N_z) (twiddles kept in registers)
+//    and writes element (k1, n2) to row k1 N2 + n2; lane j then transforms
+//    over k1 for the columns n2 = j + N1 c and writes sample z = n2 + N2 n1.
+//    The real and imaginary parts are samples t and t+1 of H_a(z).  All
+//    lanes of a group read before any writes back, in program order of their
+//    wavefront.  Every LDS access is a per-lane base plus a compile-time
+//    offset.  Banks (32, one dword each): RS = 1 mod 32 puts consecutive rows
+//    in consecutive banks, and the row padding puts the pass-1 writes of a
+//    group at banks k1 (N2 + 1) + n2, distinct over its lanes; the two groups
+//    of a half-wavefront take the same component of sample pairs 8 apart,
+//    whose columns differ by 48 = 16 mod 32 banks.
 // 3. The finished block is written as one contiguous run with non-temporal
 //    stores (H is not re-read here and should not evict the tables from L2).
 template <typename T, int N1, int N2, int WC>
@@ -186,20 +188,26 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
     constexpr int C = N2 / N1;
-    constexpr int TBC = 32;                                    // time block (plan guarantees p.tb == 32)
+    constexpr int TBC = kSynthBlock;                           // time block (the plan requires p.tb == 32)
+    constexpr int NP = TBC / 2;                                // sample pairs per block
     constexpr int NT = 48 * N1;
-    constexpr int PFI = (NZH * TBC + NT - 1) / NT;             // spectra items per thread per block
+    constexpr int PPT = NT / NZH;                              // pairs covered by one pass of the workgroup
+    constexpr int PFI = (NP + PPT - 1) / PPT;                  // (kk, pair) items per thread
+    constexpr int RS = kSynthRowStride;
     constexpr int STORES = NZ * 3 * TBC / NT;                  // stores per thread per full block
-    constexpr int RS = 3 * TBC + 1;                            // LDS row stride (odd: rows in distinct banks)
+    constexpr int ROWS = NT / (3 * TBC);                       // rows per copy-out pass
+    static_assert(N2 == synthesis_n2(NZ) && NT == synthesis_threads(NZ), "synthesis split");
+    static_assert(NT % NZH == 0 && NT % (3 * TBC) == 0 && N2 % ROWS == 0, "synthesis thread mapping");
     extern __shared__ __align__(16) unsigned char smem[];
     const int Nx = p.N[0], Ny = p.N[1], nt = p.n_time;
-    T* stage = reinterpret_cast<T*>(smem);                     // [NZ][row stride]
+    T* stage = reinterpret_cast<T*>(smem);
 
     const int col = blockIdx.x;
     const int ix = col / Ny, iy = col - (col / Ny) * Ny;
 
     // field table entries of this thread's k_z (constant over the column)
     const int kkb = threadIdx.x % NZH;
+    const int pb = threadIdx.x / NZH;                          // first sample pair of this thread
     cplx<T> e[3][WC];
 #pragma unroll
     for (int w = 0; w < WC; ++w) {
@@ -214,8 +222,7 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
     const int g = threadIdx.x / N1;
     const int k1 = threadIdx.x - g * N1;
     const int hg = g >> 1, sg = g & 1;
-    constexpr int D = TBC / 4;
-    const int a = hg % 3, tp = hg / 3 + sg * D;
+    const int a = hg % 3, tp = hg / 3 + sg * (NP / 2);
     cplx<T> twr[N2];                                           // exp(+2 pi i n2 k1 / N_z)
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) twr[n2] = twz[n2 * k1];
@@ -230,120 +237,127 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
 #pragma unroll
         for (int aa = 0; aa < 3; ++aa) settle(e[aa][w]);
 
-    // Column spectra Qhat_w(kkb, t0 + tin) of this thread's items (tin = (i +
-    // k NT) / NZH) of the block at t0.  Addresses are clamped into the table
+    // Column spectra Qhat_w(kkb, t) of both samples of this thread's pairs
+    // (pb + k PPT) of the block at t0.  Addresses are clamped into the table
     // and values past the block zeroed, so the loads are unconditional.
-    cplx<T> pq[PFI][WC];
+    cplx<T> pq[PFI][WC][2];
     auto fetch = [&](int t0) {
         const int tbl = min(TBC, nt - t0);
 #pragma unroll
-        for (int k = 0; k < PFI; ++k) {
-            const int tin = (threadIdx.x + k * NT) / NZH;
-            const int t = min(t0 + tin, nt - 1);
+        for (int k = 0; k < PFI; ++k)
 #pragma unroll
-            for (int w = 0; w < WC; ++w) {
-                const cplx<T> v = qhat[((size_t)t * WC + w) * NZH + kkb];
-                pq[k][w] = tin < tbl ? v : cplx<T>{(T)0, (T)0};
+            for (int sm = 0; sm < 2; ++sm) {
+                const int tin = 2 * (pb + k * PPT) + sm;
+                const int t = min(t0 + tin, nt - 1);
+#pragma unroll
+                for (int w = 0; w < WC; ++w) {
+                    const cplx<T> v = qhat[((size_t)t * WC + w) * NZH + kkb];
+                    pq[k][w][sm] = tin < tbl ? v : cplx<T>{(T)0, (T)0};
+                }
             }
-        }
     };
-    // 1. spectra of the tbe (even) staged samples of a block
-    auto build = [&](int tbe) {
+    // 1. spectra Z of the npair staged sample pairs of a block
+    auto build = [&](int npair) {
 #pragma unroll
         for (int k = 0; k < PFI; ++k)
 #pragma unroll
-            for (int w = 0; w < WC; ++w) settle(pq[k][w]);
+            for (int w = 0; w < WC; ++w) {
+                settle(pq[k][w][0]);
+                settle(pq[k][w][1]);
+            }
+        const bool dc = kkb == 0;                              // its mirror row is N_z/2, where Z = 0
+        const int zm = dc ? NZH : NZ - kkb;
+        T* r0 = stage + kkb * RS + kkb / N2 + 6 * pb;
+        T* r1 = stage + zm * RS + zm / N2 + 6 * pb;
 #pragma unroll
         for (int k = 0; k < PFI; ++k) {
-            const int tin = (threadIdx.x + k * NT) / NZH;
-            if (tin < tbe) {
-                const int pair = tin >> 1, odd = tin & 1;
-                T* s1 = stage + ((odd ? NZH : 0) + kkb) * RS + 6 * pair;
+            if (pb + k * PPT < npair) {
 #pragma unroll
                 for (int aa = 0; aa < 3; ++aa) {
-                    cplx<T> f{(T)0, (T)0};
+                    cplx<T> f0{(T)0, (T)0}, f1{(T)0, (T)0};
 #pragma unroll
-                    for (int w = 0; w < WC; ++w) f = f + e[aa][w] * pq[k][w];
-                    s1[aa] = f.re;
-                    s1[aa + 3] = f.im;
+                    for (int w = 0; w < WC; ++w) {
+                        f0 = f0 + e[aa][w] * pq[k][w][0];
+                        f1 = f1 + e[aa][w] * pq[k][w][1];
+                    }
+                    const int c = 6 * k * PPT + aa;
+                    r0[c] = f0.re - f1.im;
+                    r0[c + 3] = f0.im + f1.re;
+                    r1[c] = dc ? (T)0 : f0.re + f1.im;
+                    r1[c + 3] = dc ? (T)0 : f1.re - f0.im;
                 }
             }
         }
     };
-    // 2. transforms of the tbe / 2 sample pairs of a block
-    auto transform = [&](int tbe) {
-        if (tp >= tbe / 2) return;
+    // 2. transforms of the npair sample pairs of a block
+    auto transform = [&](int npair) {
+        if (tp >= npair) return;
         // lane indices re-derived per block (opaque to the optimiser) so that
         // the per-lane LDS addresses are not hoisted out of the block loop and
         // kept live across it
-        int k1 = threadIdx.x % N1, slot = 6 * tp + a;
-        asm volatile("" : "+v"(k1), "+v"(slot));
-        T* s1 = stage + slot;                 // slot (z, j) of this transform at s1[z*RS + 3j]
+        int kl = threadIdx.x % N1, slot = 6 * tp + a;
+        asm volatile("" : "+v"(kl), "+v"(slot));
+        // pass 1: Z[k1 + N1 k2] is row k1 + N1 k2, at k1 RS + N1 k2 RS + k2 / C
+        const T* rd = stage + slot + kl * RS;
         cplx<T> x[N2];
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
-            const int k = k1 + N1 * k2;
-            const bool up = k > NZH;
-            const int kk = up ? NZ - k : (k == NZH ? 0 : k);
-            const cplx<T> ft{s1[kk * RS], s1[kk * RS + 3]};
-            const cplx<T> fu{s1[(NZH + kk) * RS], s1[(NZH + kk) * RS + 3]};
-            const cplx<T> za = up ? conj(ft) : ft;
-            const cplx<T> zb = up ? conj(fu) : fu;
-            x[k2] = k == NZH ? cplx<T>{(T)0, (T)0} : za + mul_i(zb);
+            const int o = N1 * k2 * RS + k2 / C;
+            x[k2] = cplx<T>{rd[o], rd[o + 3]};
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         dft_reg<T, N2>(x);
+        // element (k1, n2) to row k1 N2 + n2, at k1 (N2 RS + 1) + n2 RS
+        T* wr = stage + slot + kl * (N2 * RS + 1);
 #pragma unroll
         for (int n2 = 0; n2 < N2; ++n2) {
             cplx<T> y = x[n2];
             if (n2 != 0) y = y * twr[n2];
-            const int z = k1 * N2 + ((n2 + k1) & (N2 - 1));
-            s1[z * RS] = y.re;
-            s1[z * RS + 3] = y.im;
+            wr[n2 * RS] = y.re;
+            wr[n2 * RS + 3] = y.im;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        // pass 2: lane j takes columns n2 = j + N1 c; element (k1', n2) is at
+        // k1' (N2 RS + 1) + N1 c RS + j RS, and sample z = n2 + N2 n1 goes to
+        // row z, at j RS + (N1 c + N2 n1) RS + n1
+        T* rw = stage + slot + kl * RS;
         cplx<T> v[C][N1];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int n2 = k1 + N1 * c;
+        for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int j = 0; j < N1; ++j) {
-                const int z = j * N2 + ((n2 + j) & (N2 - 1));
-                v[c][j] = cplx<T>{s1[z * RS], s1[z * RS + 3]};
+                const int o = j * (N2 * RS + 1) + N1 * c * RS;
+                v[c][j] = cplx<T>{rw[o], rw[o + 3]};
             }
-        }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             dft_reg<T, N1>(v[c]);
-            const int n2 = k1 + N1 * c;
 #pragma unroll
             for (int n1 = 0; n1 < N1; ++n1) {
-                const int z = n2 + N2 * n1;
-                s1[z * RS] = v[c][n1].re;
-                s1[z * RS + 3] = v[c][n1].im;
+                const int o = (N1 * c + N2 * n1) * RS + n1;
+                rw[o] = v[c][n1].re;
+                rw[o + 3] = v[c][n1].im;
             }
         }
     };
 
     // 3. copy-out: the block is one contiguous run of H, written with
     // consecutive lanes on consecutive values.  A full block takes a fixed
-    // number of stores per thread (a pass of NT threads covers whole rows),
-    // so the next block's spectra, loaded just before, are waited for without
-    // waiting for these stores.  Only the last block can be partial.
-    static_assert(NT % (3 * TBC) == 0, "copy-out rows per pass");
-    constexpr int ROWS = NT / (3 * TBC);
+    // number of stores per thread (a pass of NT threads covers ROWS whole
+    // rows), so the next block's spectra, loaded just before, are waited for
+    // without waiting for these stores.  Only the last block can be partial.
     T* hcol = H + (size_t)col * NZ * nt * 3;
     fetch(0);
-    build((min(TBC, nt) + 1) & ~1);
+    build((min(TBC, nt) + 1) / 2);
     for (int t0 = 0; t0 < nt; t0 += TBC) {
         const int tbl = min(TBC, nt - t0);
         const int tn = t0 + TBC;
         __syncthreads();                                       // spectra staged
-        transform((tbl + 1) & ~1);
+        transform((tbl + 1) / 2);
         __syncthreads();                                       // block transformed
         T* dst = hcol + (size_t)t0 * NZ * 3;
         if (tbl == TBC) {
@@ -353,19 +367,23 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
             const T* src = stage + (lane / (3 * TBC)) * RS + lane % (3 * TBC);
             T* d = dst + lane;
 #pragma unroll
-            for (int k = 0; k < STORES; ++k) __builtin_nontemporal_store(src[k * ROWS * RS], d + k * NT);
+            for (int k = 0; k < STORES; ++k)
+                __builtin_nontemporal_store(src[k * ROWS * RS + k * ROWS / N2], d + k * NT);
             // the spectra loads went out before the stores: waiting for them
             // leaves the stores in flight
 #pragma unroll
             for (int k = 0; k < PFI; ++k)
 #pragma unroll
-                for (int w = 0; w < WC; ++w) settle(pq[k][w]);
+                for (int w = 0; w < WC; ++w) {
+                    settle(pq[k][w][0]);
+                    settle(pq[k][w][1]);
+                }
         } else {
             const int rowlen = tbl * 3;
             const int dz = NT / rowlen, dr = NT - dz * rowlen;
             int z = threadIdx.x / rowlen, r = threadIdx.x - (threadIdx.x / rowlen) * rowlen;
             for (int idx = threadIdx.x; idx < NZ * rowlen; idx += NT) {
-                __builtin_nontemporal_store(stage[z * RS + r], dst + idx);
+                __builtin_nontemporal_store(stage[z * RS + z / N2 + r], dst + idx);
                 z += dz;
                 r += dr;
                 if (r >= rowlen) {
@@ -376,7 +394,7 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
         }
         if (tn < nt) {
             __syncthreads();                                   // block copied out of the staging slots
-            build((min(TBC, nt - tn) + 1) & ~1);
+            build((min(TBC, nt - tn) + 1) / 2);
         }
     }
 }
@@ -423,9 +441,8 @@ hipError_t field_table(const Plan& p, char* b, hipStream_t s) {
 
 template <typename T, int N1, int N2, int WC>
 hipError_t synthesis_reg(const Plan& p, char* b, void* h, hipStream_t s) {
-    const size_t lds = synthesis_reg_lds(p, sizeof(T));
-    // lane groups of N1 threads; the plan guarantees a multiple of N_z/2 threads
-    const int threads = synthesis_groups(p.tb) * N1;
+    const size_t lds = synthesis_reg_lds(p.N[2], sizeof(T));
+    const int threads = synthesis_threads(p.N[2]);
     hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_reg<T, N1, N2, WC>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
