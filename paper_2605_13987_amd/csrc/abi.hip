@@ -2,6 +2,7 @@
 // and workspace layout, and the order of the kernel launches.
 #include "wt.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -156,20 +157,27 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
 
     const size_t re = p.precision == WT_F64 ? sizeof(double) : sizeof(float);
     const size_t cx = 2 * re;
-    // time block of the H layout: the synthesis stages a whole block in LDS
-    int tb = sp->n_time < 32 ? sp->n_time : 32;
+    // Time block of the H layout (the synthesis stages a whole block in LDS).
+    // The register-FFT synthesis serves N_z = N1 x N2 in {64, 128, 256, 512}
+    // with at most 4 columns when its staging block fits; otherwise the LDS
+    // Stockham synthesis, whose block is halved until its tables fit.
     const size_t lds_budget = 160 * 1024;
-    auto lds_need = [&](int t) {
-        return (size_t)n_cols * p.nzh * 3 * cx + (size_t)N[2] * t * 3 * re + (size_t)2 * N[2] * cx;
-    };
-    while (tb > 1 && lds_need(tb) > lds_budget) tb = (tb + 1) / 2;
-    if (lds_need(tb) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
-    p.tb = tb;
-    // register-FFT synthesis where N_z = N1 x N2 is supported, the time block
-    // is whole, there are at most 4 columns, and the LDS fits
     const bool reg_size = N[2] == 64 || N[2] == 128 || N[2] == 256 || N[2] == 512;
-    p.synth_kernel = (reg_size && n_cols <= 4 && tb == wt::kSynthBlock &&
-                      wt::synthesis_reg_lds(N[2], re) <= lds_budget) ? 1 : 0;
+    int tb;
+    if (reg_size && n_cols <= 4 &&
+        wt::synthesis_reg_lds(N[2], wt::synthesis_block(N[2]), re) <= lds_budget) {
+        p.synth_kernel = 1;
+        tb = std::min(sp->n_time, wt::synthesis_block(N[2]));
+    } else {
+        p.synth_kernel = 0;
+        tb = std::min(sp->n_time, 32);
+        auto lds_need = [&](int t) {
+            return (size_t)n_cols * p.nzh * 3 * cx + (size_t)N[2] * t * 3 * re + (size_t)2 * N[2] * cx;
+        };
+        while (tb > 1 && lds_need(tb) > lds_budget) tb = (tb + 1) / 2;
+        if (lds_need(tb) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
+    }
+    p.tb = tb;
 
     size_t off = 0;
     for (int a = 0; a < 3; ++a) {

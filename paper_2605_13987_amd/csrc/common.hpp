@@ -95,22 +95,30 @@ hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tr
                           const void* pos, const void* charge, const int* track,
                           void* out, hipStream_t s);
 
-// Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256, 512}): time block
-// of 32 samples staged in LDS as rows of 3 x 32 values, row stride 97 (= 1
-// mod 32 banks) and row z at z * 97 + floor(z / N2).
-constexpr int kSynthBlock = 32;
-constexpr int kSynthRowStride = 3 * kSynthBlock + 1;
-
+// Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256, 512}).
 __host__ __device__ constexpr int synthesis_n2(int nz) {
     return nz == 64 ? 8 : (nz == 128 ? 16 : (nz == 256 ? 16 : 32));
 }
 
-// Threads of the register-FFT synthesis workgroup: 48 groups of N1 lanes.
-__host__ __device__ constexpr int synthesis_threads(int nz) { return 48 * (nz / synthesis_n2(nz)); }
+// Time block: 32 samples (one workgroup per compute unit; the 16-sample form
+// with two workgroups per unit measured slower).
+__host__ __device__ constexpr int synthesis_block(int /*nz*/) { return 32; }
+
+// The block is staged in LDS as rows of 3 x tb values.  A gap of this many
+// columns after the first half of a row puts the sample pairs tb/4 apart
+// 16 banks apart (columns 6 pair + component).
+__host__ __device__ constexpr int synthesis_gap(int tb) { return ((16 - 3 * tb / 2) % 32 + 32) % 32; }
+
+// Row stride: the row, its gap, and one more element so that the stride is
+// odd; row z starts at z * stride + floor(z / N2).
+__host__ __device__ constexpr int synthesis_row_stride(int tb) { return 3 * tb + synthesis_gap(tb) + 1; }
+
+// Threads of the register-FFT synthesis workgroup: 3 tb / 2 groups of N1 lanes.
+__host__ __device__ constexpr int synthesis_threads(int nz, int tb) { return 3 * tb / 2 * (nz / synthesis_n2(nz)); }
 
 // LDS bytes of the register-FFT synthesis workgroup (element size re).
-inline size_t synthesis_reg_lds(int nz, size_t re) {
-    return ((size_t)nz * kSynthRowStride + nz / synthesis_n2(nz)) * re;
+inline size_t synthesis_reg_lds(int nz, int tb, size_t re) {
+    return ((size_t)nz * synthesis_row_stride(tb) + nz / synthesis_n2(nz)) * re;
 }
 
 // Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.

@@ -152,13 +152,25 @@ k_synthesis(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* tw,
     }
 }
 
+// p advanced by a 32-bit byte offset: with p uniform over the wavefront this
+// is the scalar-base + lane-offset form of global memory access.
+template <typename T>
+__device__ inline T* byte_offset(T* p, unsigned off) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off);
+}
+template <typename T>
+__device__ inline const T* byte_offset(const T* p, unsigned off) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off);
+}
+
 typedef float vec4f __attribute__((ext_vector_type(4)));
 typedef double vec2d __attribute__((ext_vector_type(2)));
 
 // Synthesis with the length-N_z transform split as N_z = N1 x N2 and done in
-// registers.  One workgroup per (X, Y) column; per time block of 32 samples of
-// the H layout, staged whole in LDS as [z][sample][component] (row z at
-// z RS + floor(z / N2), RS = 97):
+// registers.  One workgroup per (X, Y) column; per time block of TB (16 or
+// 32) samples of the H layout, staged whole in LDS as [z][sample][component]
+// (row z at z RS + floor(z / N2), RS odd, a gap in the middle of the row for
+// TB = 16):
 //
 // 1. Spectra.  Thread i owns k_z index kk = i mod N_z/2 and keeps the field
 //    table entries Ehat_a(X - X_w, Y - Y_w, kk) of all components and columns
@@ -175,28 +187,31 @@ typedef double vec2d __attribute__((ext_vector_type(2)));
 //    The real and imaginary parts are samples t and t+1 of H_a(z).  All
 //    lanes of a group read before any writes back, in program order of their
 //    wavefront.  Every LDS access is a per-lane base plus a compile-time
-//    offset.  Banks (32, one dword each): RS = 1 mod 32 puts consecutive rows
-//    in consecutive banks, and the row padding puts the pass-1 writes of a
-//    group at banks k1 (N2 + 1) + n2, distinct over its lanes; the two groups
-//    of a half-wavefront take the same component of sample pairs 8 apart,
-//    whose columns differ by 48 = 16 mod 32 banks.
+//    offset.  Banks (32, one dword each): with RS odd, consecutive rows fall
+//    in distinct banks, and the row padding puts the pass-1 writes of a group
+//    at banks k1 (N2 RS + 1) + n2 RS, distinct over its lanes; the two groups
+//    of a half-wavefront take the same component of sample pairs TB/4 apart,
+//    whose columns differ by 16 mod 32 banks (48 for TB = 32, 24 + the gap of
+//    24 for TB = 16), so that together they cover all 32 banks.
 // 3. The finished block is written as one contiguous run with non-temporal
 //    stores (H is not re-read here and should not evict the tables from L2).
-template <typename T, int N1, int N2, int WC>
-__global__ void __launch_bounds__(48 * N1)
+template <typename T, int N1, int N2, int WC, int TBC>
+__global__ void __launch_bounds__(3 * TBC / 2 * N1)
 k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, T* H) {
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
     constexpr int C = N2 / N1;
-    constexpr int TBC = kSynthBlock;                           // time block (the plan requires p.tb == 32)
     constexpr int NP = TBC / 2;                                // sample pairs per block
-    constexpr int NT = 48 * N1;
+    constexpr int NG = 3 * NP;                                 // transforms (lane groups) per block
+    constexpr int NT = NG * N1;
+    constexpr int GAP = synthesis_gap(TBC);                    // columns skipped after pair NP/2 - 1
     constexpr int PPT = NT / NZH;                              // pairs covered by one pass of the workgroup
     constexpr int PFI = (NP + PPT - 1) / PPT;                  // (kk, pair) items per thread
-    constexpr int RS = kSynthRowStride;
+    constexpr int RS = synthesis_row_stride(TBC);
     constexpr int STORES = NZ * 3 * TBC / NT;                  // stores per thread per full block
     constexpr int ROWS = NT / (3 * TBC);                       // rows per copy-out pass
-    static_assert(N2 == synthesis_n2(NZ) && NT == synthesis_threads(NZ), "synthesis split");
+    static_assert(N2 == synthesis_n2(NZ) && NT == synthesis_threads(NZ, TBC) && TBC == synthesis_block(NZ),
+                  "synthesis split");
     static_assert(NT % NZH == 0 && NT % (3 * TBC) == 0 && N2 % ROWS == 0, "synthesis thread mapping");
     extern __shared__ __align__(16) unsigned char smem[];
     const int Nx = p.N[0], Ny = p.N[1], nt = p.n_time;
@@ -207,7 +222,10 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
 
     // field table entries of this thread's k_z (constant over the column)
     const int kkb = threadIdx.x % NZH;
-    const int pb = threadIdx.x / NZH;                          // first sample pair of this thread
+    // first sample pair of this thread; uniform over its wavefront when N_z/2
+    // is a multiple of the wavefront size, and then kept in a scalar register
+    int pb = threadIdx.x / NZH;
+    if constexpr (NZH % 64 == 0) pb = __builtin_amdgcn_readfirstlane(pb);
     cplx<T> e[3][WC];
 #pragma unroll
     for (int w = 0; w < WC; ++w) {
@@ -223,6 +241,8 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
     const int k1 = threadIdx.x - g * N1;
     const int hg = g >> 1, sg = g & 1;
     const int a = hg % 3, tp = hg / 3 + sg * (NP / 2);
+    // column of sample pair q, component c: 6 q + c (+ the gap in the second half)
+    auto pcol = [](int q) { return 6 * q + (q >= NP / 2 ? GAP : 0); };
     cplx<T> twr[N2];                                           // exp(+2 pi i n2 k1 / N_z)
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) twr[n2] = twz[n2 * k1];
@@ -238,8 +258,7 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
         for (int aa = 0; aa < 3; ++aa) settle(e[aa][w]);
 
     // Column spectra Qhat_w(kkb, t) of both samples of this thread's pairs
-    // (pb + k PPT) of the block at t0.  Addresses are clamped into the table
-    // and values past the block zeroed, so the loads are unconditional.
+    // (pb + k PPT) of the block at t0; zero past the block.
     cplx<T> pq[PFI][WC][2];
     auto fetch = [&](int t0) {
         const int tbl = min(TBC, nt - t0);
@@ -248,11 +267,13 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
 #pragma unroll
             for (int sm = 0; sm < 2; ++sm) {
                 const int tin = 2 * (pb + k * PPT) + sm;
-                const int t = min(t0 + tin, nt - 1);
+                if (tin < tbl) {
+                    const cplx<T>* q = qhat + (size_t)(t0 + tin) * WC * NZH;
 #pragma unroll
-                for (int w = 0; w < WC; ++w) {
-                    const cplx<T> v = qhat[((size_t)t * WC + w) * NZH + kkb];
-                    pq[k][w][sm] = tin < tbl ? v : cplx<T>{(T)0, (T)0};
+                    for (int w = 0; w < WC; ++w) pq[k][w][sm] = *byte_offset(q + w * NZH, kkb * sizeof(cplx<T>));
+                } else {
+#pragma unroll
+                    for (int w = 0; w < WC; ++w) pq[k][w][sm] = cplx<T>{(T)0, (T)0};
                 }
             }
     };
@@ -265,26 +286,37 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
                 settle(pq[k][w][0]);
                 settle(pq[k][w][1]);
             }
-        const bool dc = kkb == 0;                              // its mirror row is N_z/2, where Z = 0
-        const int zm = dc ? NZH : NZ - kkb;
-        T* r0 = stage + kkb * RS + kkb / N2 + 6 * pb;
-        T* r1 = stage + zm * RS + zm / N2 + 6 * pb;
+        // Rows kkb and N_z - kkb.  For kk = 0 the mirror would be row N_z,
+        // i.e. row 0; it goes to row N_z/2 instead, which pass 1 does not read
+        // (it takes Z(N_z/2) = 0).
+        const int zm = kkb == 0 ? NZH : NZ - kkb;
+        T* r0 = stage + kkb * RS + kkb / N2;
+        T* r1 = stage + zm * RS + zm / N2;
 #pragma unroll
         for (int k = 0; k < PFI; ++k) {
             if (pb + k * PPT < npair) {
+                // Z(kk) = sum_w Ehat_w (Qhat_w(t) + i Qhat_w(t+1)) and
+                // Z(N_z - kk) = sum_w conj(Ehat_w) (conj Qhat_w(t) + i conj Qhat_w(t+1))
+                cplx<T> u[WC], v[WC];
+#pragma unroll
+                for (int w = 0; w < WC; ++w) {
+                    const cplx<T> q0 = pq[k][w][0], q1 = pq[k][w][1];
+                    u[w] = cplx<T>{q0.re - q1.im, q0.im + q1.re};
+                    v[w] = cplx<T>{q0.re + q1.im, q1.re - q0.im};
+                }
 #pragma unroll
                 for (int aa = 0; aa < 3; ++aa) {
-                    cplx<T> f0{(T)0, (T)0}, f1{(T)0, (T)0};
+                    cplx<T> z = e[aa][0] * u[0], zr = conj(e[aa][0]) * v[0];
 #pragma unroll
-                    for (int w = 0; w < WC; ++w) {
-                        f0 = f0 + e[aa][w] * pq[k][w][0];
-                        f1 = f1 + e[aa][w] * pq[k][w][1];
+                    for (int w = 1; w < WC; ++w) {
+                        z = z + e[aa][w] * u[w];
+                        zr = zr + conj(e[aa][w]) * v[w];
                     }
-                    const int c = 6 * k * PPT + aa;
-                    r0[c] = f0.re - f1.im;
-                    r0[c + 3] = f0.im + f1.re;
-                    r1[c] = dc ? (T)0 : f0.re + f1.im;
-                    r1[c + 3] = dc ? (T)0 : f1.re - f0.im;
+                    const int c = pcol(pb + k * PPT) + aa;
+                    r0[c] = z.re;
+                    r0[c + 3] = z.im;
+                    r1[c] = zr.re;
+                    r1[c + 3] = zr.im;
                 }
             }
         }
@@ -295,7 +327,7 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
         // lane indices re-derived per block (opaque to the optimiser) so that
         // the per-lane LDS addresses are not hoisted out of the block loop and
         // kept live across it
-        int kl = threadIdx.x % N1, slot = 6 * tp + a;
+        int kl = threadIdx.x % N1, slot = pcol(tp) + a;
         asm volatile("" : "+v"(kl), "+v"(slot));
         // pass 1: Z[k1 + N1 k2] is row k1 + N1 k2, at k1 RS + N1 k2 RS + k2 / C
         const T* rd = stage + slot + kl * RS;
@@ -305,6 +337,8 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
             const int o = N1 * k2 * RS + k2 / C;
             x[k2] = cplx<T>{rd[o], rd[o + 3]};
         }
+        // Z(N_z/2) = 0 (row N_z/2, lane 0 at k2 = N2/2, holds no spectrum)
+        if (kl == 0) x[N2 / 2] = cplx<T>{(T)0, (T)0};
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         dft_reg<T, N2>(x);
@@ -364,11 +398,12 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
             if (tn < nt) fetch(tn);
             int lane = threadIdx.x;
             asm volatile("" : "+v"(lane));
-            const T* src = stage + (lane / (3 * TBC)) * RS + lane % (3 * TBC);
-            T* d = dst + lane;
+            const int rr = lane % (3 * TBC);
+            const T* src = stage + (lane / (3 * TBC)) * RS + rr + (rr >= 3 * TBC / 2 ? GAP : 0);
 #pragma unroll
             for (int k = 0; k < STORES; ++k)
-                __builtin_nontemporal_store(src[k * ROWS * RS + k * ROWS / N2], d + k * NT);
+                __builtin_nontemporal_store(src[k * ROWS * RS + k * ROWS / N2],
+                                            byte_offset(dst + k * NT, lane * sizeof(T)));
             // the spectra loads went out before the stores: waiting for them
             // leaves the stores in flight
 #pragma unroll
@@ -383,7 +418,7 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
             const int dz = NT / rowlen, dr = NT - dz * rowlen;
             int z = threadIdx.x / rowlen, r = threadIdx.x - (threadIdx.x / rowlen) * rowlen;
             for (int idx = threadIdx.x; idx < NZ * rowlen; idx += NT) {
-                __builtin_nontemporal_store(stage[z * RS + z / N2 + r], dst + idx);
+                __builtin_nontemporal_store(stage[z * RS + z / N2 + r + (r >= 3 * TBC / 2 ? GAP : 0)], dst + idx);
                 z += dz;
                 r += dr;
                 if (r >= rowlen) {
@@ -441,12 +476,14 @@ hipError_t field_table(const Plan& p, char* b, hipStream_t s) {
 
 template <typename T, int N1, int N2, int WC>
 hipError_t synthesis_reg(const Plan& p, char* b, void* h, hipStream_t s) {
-    const size_t lds = synthesis_reg_lds(p.N[2], sizeof(T));
-    const int threads = synthesis_threads(p.N[2]);
-    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_reg<T, N1, N2, WC>,
+    constexpr int NZ = N1 * N2;
+    constexpr int TBC = synthesis_block(NZ);
+    const size_t lds = synthesis_reg_lds(NZ, TBC, sizeof(T));
+    const int threads = synthesis_threads(NZ, TBC);
+    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_reg<T, N1, N2, WC, TBC>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_synthesis_reg<T, N1, N2, WC>), dim3(p.N[0] * p.N[1]), dim3(threads), lds, s, p,
+    hipLaunchKernelGGL((k_synthesis_reg<T, N1, N2, WC, TBC>), dim3(p.N[0] * p.N[1]), dim3(threads), lds, s, p,
                        reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]), static_cast<T*>(h));
