@@ -25,9 +25,23 @@ if ROOT not in sys.path:
 
 METRIC = "H(x,t) grid·freq pts/s + carrier tracks/s, mixed vs plain FP64 at stated rel err"
 HBM_PEAK_GBS = 8000.0
-# grid columns (ix, iy) on which the oracle recomputes H for the CPU timing and
-# the error figure: a 16 x 16 lattice off the column axes
-CPU_SAMPLE_COLUMNS = [(i, j) for i in range(3, 128, 8) for j in range(5, 128, 8)]
+
+# HBM bytes per launch of k_synthesis_reg on this workload: rocprofv3
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB device-to-device
+# copy gives for the same counters), in profiles/k_synthesis_reg_128x128x256_f32.md.
+# Reported only while the kernel's sources are the ones it was measured on.
+SYNTH_TRAFFIC_BYTES = 10170317389
+SYNTH_TRAFFIC_SOURCES_SHA256 = "a4ffdb59a581108b1eb0c23474b58c308a023168c7f86cb296da28032145f7de"
+SYNTH_SOURCES = ("k_bulk.hip", "fft.hpp", "common.hpp")
+
+
+def synthesis_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in SYNTH_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_13987_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -36,7 +50,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-carrier-stride", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="approximate CPU time of the oracle baseline sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB mebibytes device-to-device 3 times (counter calibration)")
     return ap.parse_args()
@@ -51,13 +66,16 @@ def blas_threads():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(cfg, h_cols_gpu, stride):
+def cpu_baseline(cfg, gpu_columns, budget_s):
     """The FP64 oracle on a bounded sample of the same workload.
 
     Timed parts: the boundary fit for every frequency and the time transform
-    (whole-step work), the field on the sampled grid columns, and Eq. 1 on
-    every stride-th carrier.  The whole-step rate is extrapolated from them:
-    fit + per-column time x all columns + per-carrier time x all carriers.
+    (whole-step work), the field on lattices of 256 grid columns added until
+    about half the time budget is spent, and Eq. 1 on strided subsets of the
+    carriers until about a third of it is.  The whole-step rate is
+    extrapolated from them: fit + per-column time x all columns + per-carrier
+    time x all carriers.  gpu_columns(cols) returns the GPU's H on those
+    columns, for the error figure.
     """
     import numpy as np
 
@@ -70,31 +88,49 @@ def cpu_baseline(cfg, h_cols_gpu, stride):
     sol = collocation.solve_spectrum(cell, cols, spec)
     q_t = timegrid.to_time(sol["q"], spec)
     t_fit = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ref = field.field_columns(cell, green.smoothing_widths(cell, cols), collocation.sources(cols), q_t,
-                              CPU_SAMPLE_COLUMNS)
-    t_cols = time.perf_counter() - t0
-    err = float(np.linalg.norm(h_cols_gpu - ref) / np.linalg.norm(ref))
-    # convolution: every stride-th carrier on a synthetic field of the same grid
+    s, src = green.smoothing_widths(cell, cols), collocation.sources(cols)
+    sample, t_cols, err_num, err_den = [], 0.0, 0.0, 0.0
+    for shift in range(64):                       # 16 x 16 lattices off the column axes
+        lattice = [((i + 3 + shift) % N[0], (j + 5 + 3 * shift) % N[1])
+                   for i in range(0, N[0], N[0] // 16) for j in range(0, N[1], N[1] // 16)]
+        seen = set(sample)
+        lattice = [c for c in lattice if c not in seen]
+        t0 = time.perf_counter()
+        ref = field.field_columns(cell, s, src, q_t, lattice)
+        t_cols += time.perf_counter() - t0
+        got = gpu_columns(lattice)
+        err_num += float(np.sum((got - ref) ** 2))
+        err_den += float(np.sum(ref ** 2))
+        sample += lattice
+        if t_cols > 0.5 * budget_s:
+            break
+    err = (err_num / err_den) ** 0.5
+    # convolution: strided carrier subsets on a synthetic field of the same grid
     car = cfg["carriers"]
     n_car = car["pos"].shape[0]
-    sub = np.arange(0, n_car, stride)
     f = workloads.synthetic_h_factors(workloads.rng_for(99), N, spec["n_time"])
-    t0 = time.perf_counter()
-    convolution.induced_current(lambda ix, iy, iz: workloads.synthetic_h_values(f, ix, iy, iz), cell,
-                                car["pos"][sub], car["charge"][sub], car["track"][sub], car["n_tracks"])
-    t_conv = time.perf_counter() - t0
+    h_at = lambda ix, iy, iz: workloads.synthetic_h_values(f, ix, iy, iz)
+    stride, n_done, t_conv = 50, 0, 0.0
+    for off in range(stride):
+        sub = np.arange(off, n_car, stride)
+        t0 = time.perf_counter()
+        convolution.induced_current(h_at, cell, car["pos"][sub], car["charge"][sub], car["track"][sub],
+                                    car["n_tracks"])
+        t_conv += time.perf_counter() - t0
+        n_done += sub.size
+        if t_conv > budget_s / 3:
+            break
     n_cols_all = N[0] * N[1]
-    t_step = t_fit + t_cols * n_cols_all / len(CPU_SAMPLE_COLUMNS) + t_conv * n_car / sub.size
+    t_step = t_fit + t_cols * n_cols_all / len(sample) + t_conv * n_car / n_done
     return dict(value=N[0] * N[1] * N[2] * spec["n_freq"] / t_step, unit="grid*freq pts/s",
                 cores=blas_threads(), kind="oracle",
                 sample=(f"boundary fit for all {spec['n_freq']} frequencies + time transform ({t_fit:.1f} s), "
-                        f"field on {len(CPU_SAMPLE_COLUMNS)} of {n_cols_all} grid columns, all z and t "
-                        f"({t_cols:.1f} s), Eq. 1 on {sub.size} of {n_car} carriers ({t_conv:.1f} s); "
-                        f"whole step extrapolated from these parts: {t_step:.0f} s"),
+                        f"field on {len(sample)} of {n_cols_all} grid columns, all z and t ({t_cols:.1f} s), "
+                        f"Eq. 1 on {n_done} of {n_car} carriers ({t_conv:.1f} s); whole step extrapolated "
+                        f"from these parts: {t_step:.0f} s"),
                 step_s_extrapolated=t_step,
-                tracks_per_s=car["n_tracks"] / (t_conv * n_car / sub.size),
-                carriers_per_s=sub.size / t_conv), err
+                tracks_per_s=car["n_tracks"] / (t_conv * n_car / n_done),
+                carriers_per_s=n_done / t_conv), err
 
 
 def main():
@@ -175,11 +211,15 @@ def main():
     w = len(cfg["columns"])
     synth_bytes = lay["h_bytes"] + N[0] * N[1] * w * (N[2] // 2) * 3 * 8
     achieved = synth_bytes / (stage["synthesis"] * 1e-3) / 1e9
+    traffic = (SYNTH_TRAFFIC_BYTES if list(N) == [128, 128, 256] and spec["n_time"] == 200 and w == 2
+               and synthesis_sources_sha256() == SYNTH_TRAFFIC_SOURCES_SHA256 else None)
 
     per_col = N[2] * spec["n_time"] * 3
-    idx = torch.tensor([i * N[1] + j for i, j in CPU_SAMPLE_COLUMNS], device="cuda")
-    h_cols = layout.to_standard(h.view(-1, per_col).index_select(0, idx).cpu().numpy().astype(np.float64),
-                                N, spec["n_time"], lay["h_time_block"])
+
+    def gpu_columns(cols):
+        idx = torch.tensor([i * N[1] + j for i, j in cols], device="cuda")
+        return layout.to_standard(h.view(-1, per_col).index_select(0, idx).cpu().numpy().astype(np.float64),
+                                  N, spec["n_time"], lay["h_time_block"])
 
     line = {
         "metric": METRIC,
@@ -208,12 +248,12 @@ def main():
         "h_grid_time_pts_per_s": n_pts * spec["n_time"] / t_h,
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "roofline": {"kernel": "k_synthesis_reg", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": synth_bytes},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes/launch", "bytes_per_launch": synth_bytes},
         "solve_report": rep,
     }
     if not args.no_cpu_baseline:
-        base, err = cpu_baseline(cfg, h_cols, args.cpu_carrier_stride)
+        base, err = cpu_baseline(cfg, gpu_columns, args.cpu_seconds)
         line["cpu_baseline"] = base
         line["rel_err"] = {"H_sampled_columns_vs_fp64_oracle": err}
     print(json.dumps(line), flush=True)

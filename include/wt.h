@@ -148,10 +148,14 @@ typedef struct {
 
 /* Create a context bound to HIP device `hip_device` and the HIP stream
  * `hip_stream` (a hipStream_t; NULL = the default stream).  Fails with
- * WT_E_HIP when no such device exists. */
+ * WT_E_HIP when no such device exists or the runtime cannot reach it.  The
+ * library calls the HIP runtime it was loaded with: device memory and the
+ * stream must belong to that same runtime (one HIP runtime per process). */
 wt_status wt_context_create(wt_context** ctx, int hip_device, void* hip_stream);
 wt_status wt_context_destroy(wt_context* ctx);
-/* Last HIP error message of the context ("" if none); owned by the context. */
+/* Last HIP error message of the context ("" if none); owned by the context.
+ * With ctx = NULL: the message of this thread's last failed
+ * wt_context_create, owned by the library. */
 const char* wt_context_last_error(const wt_context* ctx);
 
 /* Per-stage timing (HIP events on the context's stream).  When enabled,

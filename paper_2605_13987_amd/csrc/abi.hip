@@ -255,11 +255,29 @@ const char* wt_stage_name(int id) {
     return (id >= 0 && id < (int)(sizeof(kStageNames) / sizeof(kStageNames[0]))) ? kStageNames[id] : "";
 }
 
+// Message of the last failed wt_context_create of this thread (no context
+// exists to hold it).
+static thread_local std::string g_create_error;
+
 wt_status wt_context_create(wt_context** out, int hip_device, void* hip_stream) {
     if (!out) return WT_E_INVALID_ARG;
     *out = nullptr;
+    g_create_error.clear();
     int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count) return WT_E_HIP;
+    hipError_t err = hipGetDeviceCount(&count);
+    if (err != hipSuccess) {
+        g_create_error = std::string("hipGetDeviceCount: ") + hipGetErrorString(err);
+        return WT_E_HIP;
+    }
+    if (hip_device < 0 || hip_device >= count) {
+        g_create_error = "no HIP device " + std::to_string(hip_device) + " (" + std::to_string(count) + " visible)";
+        return WT_E_HIP;
+    }
+    err = hipSetDevice(hip_device);
+    if (err != hipSuccess) {
+        g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(err);
+        return WT_E_HIP;
+    }
     wt_context* ctx = new (std::nothrow) wt_context();
     if (!ctx) return WT_E_INVALID_ARG;
     ctx->device = hip_device;
@@ -267,10 +285,6 @@ wt_status wt_context_create(wt_context** out, int hip_device, void* hip_stream) 
     ctx->timing = false;
     ctx->n_events = 0;
     for (auto& e : ctx->ev) e = nullptr;
-    if (hipSetDevice(hip_device) != hipSuccess) {
-        delete ctx;
-        return WT_E_HIP;
-    }
     *out = ctx;
     return WT_OK;
 }
@@ -283,7 +297,9 @@ wt_status wt_context_destroy(wt_context* ctx) {
     return WT_OK;
 }
 
-const char* wt_context_last_error(const wt_context* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+const char* wt_context_last_error(const wt_context* ctx) {
+    return ctx ? ctx->last_error.c_str() : g_create_error.c_str();
+}
 
 wt_status wt_context_enable_timing(wt_context* ctx, int enable) {
     if (!ctx) return WT_E_INVALID_ARG;

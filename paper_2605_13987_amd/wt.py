@@ -80,6 +80,14 @@ class wt_carriers(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_13987_amd.build`")
+    # One HIP runtime per process.  The callers' device memory and streams come
+    # from PyTorch, whose wheel ships its own HIP runtime; with torch loaded
+    # first, libwt.so binds to that runtime.  Loaded the other way round, the
+    # process would hold two runtimes and the second cannot use the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     sig = {
@@ -125,7 +133,7 @@ def wt_stage_name(stage: int) -> str:
 
 def _check(status, where, ctx=None):
     if status != WT_OK:
-        detail = LIB.wt_context_last_error(ctx).decode() if (ctx and status == WT_E_HIP) else ""
+        detail = LIB.wt_context_last_error(ctx).decode() if status == WT_E_HIP else ""
         raise WtError(status, where, detail)
 
 

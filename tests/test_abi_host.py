@@ -1,12 +1,16 @@
 """Host-side checks of the C ABI (no GPU work): exported symbols, plan sizes,
 argument validation and status codes."""
 import copy
+import os
 import shutil
 import subprocess
+import sys
 
 import pytest
 
 from paper_2605_13987_amd import workloads, wt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -116,3 +120,15 @@ def test_context_creation_reports_missing_device():
     if st == wt.WT_OK:
         assert wt.LIB.wt_context_destroy(ctx) == wt.WT_OK
     assert wt.LIB.wt_context_create(ctypes.byref(ctx), 10 ** 6, None) == wt.WT_E_HIP
+
+
+def test_binding_leaves_one_hip_runtime_in_the_process():
+    """Importing the binding alone must not map a second HIP runtime next to
+    PyTorch's (two runtimes in one process cannot share the device)."""
+    code = ("from paper_2605_13987_amd import wt\n"
+            "import torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"
