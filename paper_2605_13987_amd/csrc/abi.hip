@@ -157,17 +157,17 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
 
     const size_t re = p.precision == WT_F64 ? sizeof(double) : sizeof(float);
     const size_t cx = 2 * re;
-    // Time block of the H layout (the synthesis stages a whole block in LDS).
-    // The register-FFT synthesis serves N_z = N1 x N2 in {64, 128, 256, 512}
-    // with at most 4 columns when its staging block fits; otherwise the LDS
-    // Stockham synthesis, whose block is halved until its tables fit.
+    // Time block of the H layout (the synthesis stages a whole block in LDS):
+    // the pipelined register-FFT synthesis for N_z in {64, 128, 256} with at
+    // most 4 columns when its two staging buffers fit (blocks of 16 samples);
+    // otherwise the LDS Stockham synthesis, whose block is halved until its
+    // tables fit.
     const size_t lds_budget = 160 * 1024;
-    const bool reg_size = N[2] == 64 || N[2] == 128 || N[2] == 256 || N[2] == 512;
+    const bool pipe_size = N[2] == 64 || N[2] == 128 || N[2] == 256;
     int tb;
-    if (reg_size && n_cols <= 4 &&
-        wt::synthesis_reg_lds(N[2], wt::synthesis_block(N[2]), re) <= lds_budget) {
-        p.synth_kernel = 1;
-        tb = std::min(sp->n_time, wt::synthesis_block(N[2]));
+    if (pipe_size && n_cols <= 4 && wt::synthesis_pipe_lds(N[2], re) <= lds_budget) {
+        p.synth_kernel = 2;
+        tb = std::min(sp->n_time, wt::kPipeBlock);
     } else {
         p.synth_kernel = 0;
         tb = std::min(sp->n_time, 32);

@@ -67,7 +67,7 @@ struct Plan {
     double s_bulk[3];
     int nkz_tab;           // k_z >= 0 entries per Green's table row (max over columns)
     int tb;                // time block of the H layout
-    int synth_kernel;      // 1: register-FFT synthesis (N_z = 64, 128, 256, 512), 0: LDS Stockham
+    int synth_kernel;      // 2: pipelined register FFTs (N_z = 64, 128, 256), 0: LDS Stockham
     int nzh;               // Nz / 2
     int nrad[3];
     int rad[3][kMaxRadices];
@@ -95,31 +95,25 @@ hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tr
                           const void* pos, const void* charge, const int* track,
                           void* out, hipStream_t s);
 
-// Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256, 512}).
-__host__ __device__ constexpr int synthesis_n2(int nz) {
-    return nz == 64 ? 8 : (nz == 128 ? 16 : (nz == 256 ? 16 : 32));
+// Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256}).
+__host__ __device__ constexpr int synthesis_n2(int nz) { return nz == 64 ? 8 : 16; }
+
+// Blocks of 16 samples, staged in LDS as rows of 3 x 16 values (sample pair
+// q, component c, real/imaginary part at column 6 q + c (+3), plus a gap of
+// 24 columns from pair 4 on), row stride 73, and row z at
+// 73 z + 3 floor(z / N2).  The gap and the padding keep the transforms'
+// LDS accesses free of bank conflicts (two groups of a half-wavefront take
+// sample pairs 4 apart, 16 banks apart).
+constexpr int kPipeBlock = 16;
+constexpr int kPipeGap = 24;
+constexpr int kPipeRowStride = 3 * kPipeBlock + kPipeGap + 1;
+constexpr int kPipeRowPad = 3;
+
+// Elements of one staging buffer, and LDS bytes of the workgroup (two buffers).
+__host__ __device__ constexpr int synthesis_buffer(int nz) {
+    return nz * kPipeRowStride + nz / synthesis_n2(nz) * kPipeRowPad;
 }
-
-// Time block: 32 samples (one workgroup per compute unit; the 16-sample form
-// with two workgroups per unit measured slower).
-__host__ __device__ constexpr int synthesis_block(int /*nz*/) { return 32; }
-
-// The block is staged in LDS as rows of 3 x tb values.  A gap of this many
-// columns after the first half of a row puts the sample pairs tb/4 apart
-// 16 banks apart (columns 6 pair + component).
-__host__ __device__ constexpr int synthesis_gap(int tb) { return ((16 - 3 * tb / 2) % 32 + 32) % 32; }
-
-// Row stride: the row, its gap, and one more element so that the stride is
-// odd; row z starts at z * stride + floor(z / N2).
-__host__ __device__ constexpr int synthesis_row_stride(int tb) { return 3 * tb + synthesis_gap(tb) + 1; }
-
-// Threads of the register-FFT synthesis workgroup: 3 tb / 2 groups of N1 lanes.
-__host__ __device__ constexpr int synthesis_threads(int nz, int tb) { return 3 * tb / 2 * (nz / synthesis_n2(nz)); }
-
-// LDS bytes of the register-FFT synthesis workgroup (element size re).
-inline size_t synthesis_reg_lds(int nz, int tb, size_t re) {
-    return ((size_t)nz * synthesis_row_stride(tb) + nz / synthesis_n2(nz)) * re;
-}
+inline size_t synthesis_pipe_lds(int nz, size_t re) { return 2 * (size_t)synthesis_buffer(nz) * re; }
 
 // Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.
 inline int factorize(int n, int* rad) {

@@ -154,15 +154,21 @@ __device__ inline void dft_reg(cplx<T>* x) {
 #pragma unroll
             for (int j = 0; j < half; ++j) {
                 const int m = j * (32 / len);              // exp(+2 pi i j / len) = w32^m
-                cplx<T> v = x[i + j + half];
-                if (m == 8) {
-                    v = mul_i(v);
-                } else if (m != 0) {
-                    v = v * cplx<T>{(T)cos_2pi_32(m), (T)cos_2pi_32(m - 8)};
+                const cplx<T> u = x[i + j], v = x[i + j + half];
+                if (m == 0) {
+                    x[i + j] = u + v;
+                    x[i + j + half] = u - v;
+                } else if (m == 8) {
+                    x[i + j] = u + mul_i(v);
+                    x[i + j + half] = u - mul_i(v);
+                } else {
+                    // a = u + w v with the products fused into the sums, and
+                    // u - w v = 2u - a
+                    const T c = (T)cos_2pi_32(m), s = (T)cos_2pi_32(m - 8);
+                    const cplx<T> a{fma(v.re, c, fma(-v.im, s, u.re)), fma(v.re, s, fma(v.im, c, u.im))};
+                    x[i + j] = a;
+                    x[i + j + half] = cplx<T>{fma((T)2, u.re, -a.re), fma((T)2, u.im, -a.im)};
                 }
-                const cplx<T> u = x[i + j];
-                x[i + j] = u + v;
-                x[i + j + half] = u - v;
             }
         }
     }

@@ -164,248 +164,170 @@ __device__ inline const T* byte_offset(const T* p, unsigned off) {
 }
 
 typedef float vec4f __attribute__((ext_vector_type(4)));
+typedef float vec2f __attribute__((ext_vector_type(2)));
 typedef double vec2d __attribute__((ext_vector_type(2)));
 
-// Synthesis with the length-N_z transform split as N_z = N1 x N2 and done in
-// registers.  One workgroup per (X, Y) column; per time block of TB (16 or
-// 32) samples of the H layout, staged whole in LDS as [z][sample][component]
-// (row z at z RS + floor(z / N2), RS odd, a gap in the middle of the row for
-// TB = 16):
+// Synthesis of H(X, Y, z, t) for N_z = N1 x N2 in {64, 128, 256}, with the
+// length-N_z transforms done in registers.  One workgroup per (X, Y) column;
+// H is produced in blocks of 16 samples, each staged whole in LDS as
+// [z][sample][component] (the row layout is described at kPipeBlock):
 //
-// 1. Spectra.  Thread i owns k_z index kk = i mod N_z/2 and keeps the field
+// 1. Spectra.  A memory-team thread owns k_z index kk and keeps the field
 //    table entries Ehat_a(X - X_w, Y - Y_w, kk) of all components and columns
-//    in registers.  For a pair of samples (t, t+1) it forms F_a(kk, t) =
-//    sum_w Ehat_a Qhat_w(kk, t) and F_a(kk, t+1), and writes the spectrum of
-//    the complex signal that carries both, Z(kk) = F_t(kk) + i F_{t+1}(kk) to
-//    row kk and Z(N_z - kk) = conj F_t(kk) + i conj F_{t+1}(kk) to row
-//    N_z - kk (Z(N_z/2) = 0), in the columns of that pair and component.
-// 2. Transforms.  A group of N1 lanes (inside one wavefront) owns one complex
-//    FFT of length N_z.  Lane k1 reads Z[k1 + N1 k2] (k2 < N2), transforms
-//    over k2, applies exp(+2 pi i n2 k1 / N_z) (twiddles kept in registers)
-//    and writes element (k1, n2) to row k1 N2 + n2; lane j then transforms
-//    over k1 for the columns n2 = j + N1 c and writes sample z = n2 + N2 n1.
-//    The real and imaginary parts are samples t and t+1 of H_a(z).  All
-//    lanes of a group read before any writes back, in program order of their
-//    wavefront.  Every LDS access is a per-lane base plus a compile-time
-//    offset.  Banks (32, one dword each): with RS odd, consecutive rows fall
-//    in distinct banks, and the row padding puts the pass-1 writes of a group
-//    at banks k1 (N2 RS + 1) + n2 RS, distinct over its lanes; the two groups
-//    of a half-wavefront take the same component of sample pairs TB/4 apart,
-//    whose columns differ by 16 mod 32 banks (48 for TB = 32, 24 + the gap of
-//    24 for TB = 16), so that together they cover all 32 banks.
-// 3. The finished block is written as one contiguous run with non-temporal
-//    stores (H is not re-read here and should not evict the tables from L2).
-template <typename T, int N1, int N2, int WC, int TBC>
-__global__ void __launch_bounds__(3 * TBC / 2 * N1)
-k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, T* H) {
+//    in registers.  For a pair of samples (t, t+1) it writes the spectrum of
+//    the complex signal that carries both, Z(kk) = F_t(kk) + i F_{t+1}(kk)
+//    with F_t(kk) = sum_w Ehat_w Qhat_w(kk, t), to row kk, and
+//    Z(N_z - kk) = conj F_t(kk) + i conj F_{t+1}(kk) to row N_z - kk.
+// 2. Transforms.  A group of N1 lanes of the transform team (inside one
+//    wavefront) owns one complex FFT of length N_z.  Pass 1: lane k1 reads
+//    Z[k1 + N1 k2] (k2 < N2; Z(N_z/2) = 0), transforms over k2, applies
+//    exp(+2 pi i n2 k1 / N_z) (twiddles kept in registers) and writes
+//    element (k1, n2) to row k1 N2 + n2.  Pass 2: lane j transforms over k1
+//    for the columns n2 = j + N1 c and writes sample z = n2 + N2 n1.  The
+//    real and imaginary parts are samples t and t+1 of H_a(z).  All lanes of
+//    a group read before any writes back, in program order of their
+//    wavefront.  Every LDS address is a per-lane base plus a constant.
+// 3. Copy-out.  The finished block is one contiguous run of H, written by
+//    the memory team with non-temporal stores (H is not re-read here and
+//    should not evict the tables from L2).
+//
+// Two staging buffers and two teams of wavefronts overlap the steps: while
+// the transform team runs pass 1 and then pass 2 of block s in buffer
+// s mod 2, the memory team loads the column spectra of block s+1 and copies
+// block s-1 out of the other buffer (phase 1), then builds block s+1's
+// spectra into it (phase 2).  A workgroup barrier ends each phase; within a
+// phase the teams touch different buffers.
+template <typename T, int N1, int N2, int WC>
+__global__ void __launch_bounds__(48 * N1)
+k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, T* H) {
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
     constexpr int C = N2 / N1;
+    constexpr int TBC = kPipeBlock;                            // 16 samples per block
     constexpr int NP = TBC / 2;                                // sample pairs per block
-    constexpr int NG = 3 * NP;                                 // transforms (lane groups) per block
-    constexpr int NT = NG * N1;
-    constexpr int GAP = synthesis_gap(TBC);                    // columns skipped after pair NP/2 - 1
-    constexpr int PPT = NT / NZH;                              // pairs covered by one pass of the workgroup
+    constexpr int NG = 3 * NP;                                 // transforms per block
+    constexpr int NTT = NG * N1;                               // transform team
+    constexpr int NTM = NTT;                                   // memory team
+    constexpr int GAP = kPipeGap;
+    constexpr int RS = kPipeRowStride;
+    constexpr int PAD = kPipeRowPad;                           // row z at z RS + (z / N2) PAD
+    constexpr int BUF = synthesis_buffer(NZ);                  // elements per staging buffer
+    constexpr int PPT = NTM / NZH;                             // pairs covered by one pass of the team
     constexpr int PFI = (NP + PPT - 1) / PPT;                  // (kk, pair) items per thread
-    constexpr int RS = synthesis_row_stride(TBC);
-    constexpr int STORES = NZ * 3 * TBC / NT;                  // stores per thread per full block
-    constexpr int ROWS = NT / (3 * TBC);                       // rows per copy-out pass
-    static_assert(N2 == synthesis_n2(NZ) && NT == synthesis_threads(NZ, TBC) && TBC == synthesis_block(NZ),
-                  "synthesis split");
-    static_assert(NT % NZH == 0 && NT % (3 * TBC) == 0 && N2 % ROWS == 0, "synthesis thread mapping");
+    constexpr int LW = 3 * TBC / 2;                            // copy-out lanes per row (2 values each)
+    constexpr int STORES = NZ * LW / NTM;                      // paired stores per thread per full block
+    constexpr int ROWS = NTM / LW;                             // rows per copy-out pass
+    static_assert(N2 == synthesis_n2(NZ) && NTT % 64 == 0 && N2 % N1 == 0, "synthesis split");
+    static_assert(NTM % NZH == 0 && NTM % LW == 0 && N2 % ROWS == 0 && GAP % 2 == 0, "synthesis thread mapping");
     extern __shared__ __align__(16) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
     const int Nx = p.N[0], Ny = p.N[1], nt = p.n_time;
-    T* stage = reinterpret_cast<T*>(smem);
-
     const int col = blockIdx.x;
     const int ix = col / Ny, iy = col - (col / Ny) * Ny;
-
-    // field table entries of this thread's k_z (constant over the column)
-    const int kkb = threadIdx.x % NZH;
-    // first sample pair of this thread; uniform over its wavefront when N_z/2
-    // is a multiple of the wavefront size, and then kept in a scalar register
-    int pb = threadIdx.x / NZH;
-    if constexpr (NZH % 64 == 0) pb = __builtin_amdgcn_readfirstlane(pb);
-    cplx<T> e[3][WC];
-#pragma unroll
-    for (int w = 0; w < WC; ++w) {
-        const int sx = (ix - p.col[w].ix + Nx) % Nx;
-        const int sy = (iy - p.col[w].iy + Ny) % Ny;
-        const cplx<T>* src = ehat + (((size_t)sx * Ny + sy) * NZH + kkb) * 3;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) e[a][w] = src[a];
-    }
-
-    // transform group: half-wavefront pair (h, s) -> component a, sample pair tp
-    const int g = threadIdx.x / N1;
-    const int k1 = threadIdx.x - g * N1;
-    const int hg = g >> 1, sg = g & 1;
-    const int a = hg % 3, tp = hg / 3 + sg * (NP / 2);
-    // column of sample pair q, component c: 6 q + c (+ the gap in the second half)
-    auto pcol = [](int q) { return 6 * q + (q >= NP / 2 ? GAP : 0); };
-    cplx<T> twr[N2];                                           // exp(+2 pi i n2 k1 / N_z)
-#pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) twr[n2] = twz[n2 * k1];
-    // Values loaded ahead of the block loop are used here once, so they are
-    // complete on entry and no wait inside the loop (which would also wait
-    // for the block stores still in flight) is needed for them.
-    auto settle = [](const cplx<T>& v) { asm volatile("" ::"v"(v.re), "v"(v.im)); };
-#pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) settle(twr[n2]);
-#pragma unroll
-    for (int w = 0; w < WC; ++w)
-#pragma unroll
-        for (int aa = 0; aa < 3; ++aa) settle(e[aa][w]);
-
-    // Column spectra Qhat_w(kkb, t) of both samples of this thread's pairs
-    // (pb + k PPT) of the block at t0; zero past the block.
-    cplx<T> pq[PFI][WC][2];
-    auto fetch = [&](int t0) {
-        const int tbl = min(TBC, nt - t0);
-#pragma unroll
-        for (int k = 0; k < PFI; ++k)
-#pragma unroll
-            for (int sm = 0; sm < 2; ++sm) {
-                const int tin = 2 * (pb + k * PPT) + sm;
-                if (tin < tbl) {
-                    const cplx<T>* q = qhat + (size_t)(t0 + tin) * WC * NZH;
-#pragma unroll
-                    for (int w = 0; w < WC; ++w) pq[k][w][sm] = *byte_offset(q + w * NZH, kkb * sizeof(cplx<T>));
-                } else {
-#pragma unroll
-                    for (int w = 0; w < WC; ++w) pq[k][w][sm] = cplx<T>{(T)0, (T)0};
-                }
-            }
-    };
-    // 1. spectra Z of the npair staged sample pairs of a block
-    auto build = [&](int npair) {
-#pragma unroll
-        for (int k = 0; k < PFI; ++k)
-#pragma unroll
-            for (int w = 0; w < WC; ++w) {
-                settle(pq[k][w][0]);
-                settle(pq[k][w][1]);
-            }
-        // Rows kkb and N_z - kkb.  For kk = 0 the mirror would be row N_z,
-        // i.e. row 0; it goes to row N_z/2 instead, which pass 1 does not read
-        // (it takes Z(N_z/2) = 0).
-        const int zm = kkb == 0 ? NZH : NZ - kkb;
-        T* r0 = stage + kkb * RS + kkb / N2;
-        T* r1 = stage + zm * RS + zm / N2;
-#pragma unroll
-        for (int k = 0; k < PFI; ++k) {
-            if (pb + k * PPT < npair) {
-                // Z(kk) = sum_w Ehat_w (Qhat_w(t) + i Qhat_w(t+1)) and
-                // Z(N_z - kk) = sum_w conj(Ehat_w) (conj Qhat_w(t) + i conj Qhat_w(t+1))
-                cplx<T> u[WC], v[WC];
-#pragma unroll
-                for (int w = 0; w < WC; ++w) {
-                    const cplx<T> q0 = pq[k][w][0], q1 = pq[k][w][1];
-                    u[w] = cplx<T>{q0.re - q1.im, q0.im + q1.re};
-                    v[w] = cplx<T>{q0.re + q1.im, q1.re - q0.im};
-                }
-#pragma unroll
-                for (int aa = 0; aa < 3; ++aa) {
-                    cplx<T> z = e[aa][0] * u[0], zr = conj(e[aa][0]) * v[0];
-#pragma unroll
-                    for (int w = 1; w < WC; ++w) {
-                        z = z + e[aa][w] * u[w];
-                        zr = zr + conj(e[aa][w]) * v[w];
-                    }
-                    const int c = pcol(pb + k * PPT) + aa;
-                    r0[c] = z.re;
-                    r0[c + 3] = z.im;
-                    r1[c] = zr.re;
-                    r1[c + 3] = zr.im;
-                }
-            }
-        }
-    };
-    // 2. transforms of the npair sample pairs of a block
-    auto transform = [&](int npair) {
-        if (tp >= npair) return;
-        // lane indices re-derived per block (opaque to the optimiser) so that
-        // the per-lane LDS addresses are not hoisted out of the block loop and
-        // kept live across it
-        int kl = threadIdx.x % N1, slot = pcol(tp) + a;
-        asm volatile("" : "+v"(kl), "+v"(slot));
-        // pass 1: Z[k1 + N1 k2] is row k1 + N1 k2, at k1 RS + N1 k2 RS + k2 / C
-        const T* rd = stage + slot + kl * RS;
-        cplx<T> x[N2];
-#pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) {
-            const int o = N1 * k2 * RS + k2 / C;
-            x[k2] = cplx<T>{rd[o], rd[o + 3]};
-        }
-        // Z(N_z/2) = 0 (row N_z/2, lane 0 at k2 = N2/2, holds no spectrum)
-        if (kl == 0) x[N2 / 2] = cplx<T>{(T)0, (T)0};
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        dft_reg<T, N2>(x);
-        // element (k1, n2) to row k1 N2 + n2, at k1 (N2 RS + 1) + n2 RS
-        T* wr = stage + slot + kl * (N2 * RS + 1);
-#pragma unroll
-        for (int n2 = 0; n2 < N2; ++n2) {
-            cplx<T> y = x[n2];
-            if (n2 != 0) y = y * twr[n2];
-            wr[n2 * RS] = y.re;
-            wr[n2 * RS + 3] = y.im;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        // pass 2: lane j takes columns n2 = j + N1 c; element (k1', n2) is at
-        // k1' (N2 RS + 1) + N1 c RS + j RS, and sample z = n2 + N2 n1 goes to
-        // row z, at j RS + (N1 c + N2 n1) RS + n1
-        T* rw = stage + slot + kl * RS;
-        cplx<T> v[C][N1];
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int j = 0; j < N1; ++j) {
-                const int o = j * (N2 * RS + 1) + N1 * c * RS;
-                v[c][j] = cplx<T>{rw[o], rw[o + 3]};
-            }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            dft_reg<T, N1>(v[c]);
-#pragma unroll
-            for (int n1 = 0; n1 < N1; ++n1) {
-                const int o = (N1 * c + N2 * n1) * RS + n1;
-                rw[o] = v[c][n1].re;
-                rw[o + 3] = v[c][n1].im;
-            }
-        }
-    };
-
-    // 3. copy-out: the block is one contiguous run of H, written with
-    // consecutive lanes on consecutive values.  A full block takes a fixed
-    // number of stores per thread (a pass of NT threads covers ROWS whole
-    // rows), so the next block's spectra, loaded just before, are waited for
-    // without waiting for these stores.  Only the last block can be partial.
     T* hcol = H + (size_t)col * NZ * nt * 3;
-    fetch(0);
-    build((min(TBC, nt) + 1) / 2);
-    for (int t0 = 0; t0 < nt; t0 += TBC) {
-        const int tbl = min(TBC, nt - t0);
-        const int tn = t0 + TBC;
-        __syncthreads();                                       // spectra staged
-        transform((tbl + 1) / 2);
-        __syncthreads();                                       // block transformed
-        T* dst = hcol + (size_t)t0 * NZ * 3;
-        if (tbl == TBC) {
-            if (tn < nt) fetch(tn);
-            int lane = threadIdx.x;
-            asm volatile("" : "+v"(lane));
-            const int rr = lane % (3 * TBC);
-            const T* src = stage + (lane / (3 * TBC)) * RS + rr + (rr >= 3 * TBC / 2 ? GAP : 0);
+    const int nblk = (nt + TBC - 1) / TBC;
+    // column of sample pair q (component 0, real part): 6 q, plus the gap in the second half
+    auto pcol = [](int q) { return 6 * q + (q >= NP / 2 ? GAP : 0); };
+    auto settle = [](const cplx<T>& v) { asm volatile("" ::"v"(v.re), "v"(v.im)); };
+
+    if (threadIdx.x < NTT) {
+        // ------------------------------------------------ transform team
+        const int g = threadIdx.x / N1;
+        const int k1 = threadIdx.x - g * N1;
+        const int hg = g >> 1, sg = g & 1;
+        const int a = hg % 3, tp = hg / 3 + sg * (NP / 2);
+        cplx<T> twr[N2];                                       // exp(+2 pi i n2 k1 / N_z)
 #pragma unroll
-            for (int k = 0; k < STORES; ++k)
-                __builtin_nontemporal_store(src[k * ROWS * RS + k * ROWS / N2],
-                                            byte_offset(dst + k * NT, lane * sizeof(T)));
-            // the spectra loads went out before the stores: waiting for them
-            // leaves the stores in flight
+        for (int n2 = 0; n2 < N2; ++n2) twr[n2] = twz[n2 * k1];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) settle(twr[n2]);
+        // pass 1: Z[k1 + N1 k2] is row k1 + N1 k2, at k1 RS + N1 k2 RS + (k2 / C) PAD;
+        // element (k1, n2) goes to row k1 N2 + n2, at k1 (N2 RS + PAD) + n2 RS
+        auto pass1 = [&](T* stage, int npair) {
+            if (tp >= npair) return;
+            // lane indices re-derived per block (opaque to the optimiser) so that
+            // the per-lane LDS addresses are not hoisted out of the block loop
+            int kl = threadIdx.x % N1, slot = pcol(tp) + a;
+            asm volatile("" : "+v"(kl), "+v"(slot));
+            const T* rd = stage + slot + kl * RS;
+            cplx<T> x[N2];
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) {
+                const int o = N1 * k2 * RS + (k2 / C) * PAD;
+                x[k2] = cplx<T>{rd[o], rd[o + 3]};
+            }
+            if (kl == 0) x[N2 / 2] = cplx<T>{(T)0, (T)0};       // Z(N_z/2) = 0
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            dft_reg<T, N2>(x);
+            T* wr = stage + slot + kl * (N2 * RS + PAD);
+#pragma unroll
+            for (int n2 = 0; n2 < N2; ++n2) {
+                cplx<T> y = x[n2];
+                if (n2 != 0) y = y * twr[n2];
+                wr[n2 * RS] = y.re;
+                wr[n2 * RS + 3] = y.im;
+            }
+        };
+        // pass 2: lane j takes the columns n2 = j + N1 c; element (k1', n2) is at
+        // k1' (N2 RS + PAD) + N1 c RS + j RS, and sample z = n2 + N2 n1 goes to
+        // row z, at j RS + (N1 c + N2 n1) RS + n1 PAD
+        auto pass2 = [&](T* stage, int npair) {
+            if (tp >= npair) return;
+            int kl = threadIdx.x % N1, slot = pcol(tp) + a;
+            asm volatile("" : "+v"(kl), "+v"(slot));
+            T* rw = stage + slot + kl * RS;
+            cplx<T> v[C][N1];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int j = 0; j < N1; ++j) {
+                    const int o = j * (N2 * RS + PAD) + N1 * c * RS;
+                    v[c][j] = cplx<T>{rw[o], rw[o + 3]};
+                }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                dft_reg<T, N1>(v[c]);
+#pragma unroll
+                for (int n1 = 0; n1 < N1; ++n1) {
+                    const int o = (N1 * c + N2 * n1) * RS + n1 * PAD;
+                    rw[o] = v[c][n1].re;
+                    rw[o + 3] = v[c][n1].im;
+                }
+            }
+        };
+        __syncthreads();                                       // block 0 staged
+        for (int s = 0; s < nblk; ++s) {
+            const int npair = (min(TBC, nt - s * TBC) + 1) / 2;
+            T* stage = lds + (s & 1) * BUF;
+            pass1(stage, npair);
+            __syncthreads();
+            pass2(stage, npair);
+            __syncthreads();
+        }
+    } else {
+        // --------------------------------------------------- memory team
+        const int m = threadIdx.x - NTT;
+        const int kkb = m % NZH;
+        int pb = m / NZH;                                      // first sample pair of this thread
+        if constexpr (NZH % 64 == 0) pb = __builtin_amdgcn_readfirstlane(pb);
+        cplx<T> e[3][WC];
+#pragma unroll
+        for (int w = 0; w < WC; ++w) {
+            const int sx = (ix - p.col[w].ix + Nx) % Nx;
+            const int sy = (iy - p.col[w].iy + Ny) % Ny;
+            const cplx<T>* src = ehat + (((size_t)sx * Ny + sy) * NZH + kkb) * 3;
+#pragma unroll
+            for (int aa = 0; aa < 3; ++aa) e[aa][w] = src[aa];
+        }
+#pragma unroll
+        for (int w = 0; w < WC; ++w)
+#pragma unroll
+            for (int aa = 0; aa < 3; ++aa) settle(e[aa][w]);
+        cplx<T> pq[PFI][WC][2];
+        auto settle_all = [&]() {
 #pragma unroll
             for (int k = 0; k < PFI; ++k)
 #pragma unroll
@@ -413,24 +335,130 @@ k_synthesis_reg(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>*
                     settle(pq[k][w][0]);
                     settle(pq[k][w][1]);
                 }
-        } else {
-            const int rowlen = tbl * 3;
-            const int dz = NT / rowlen, dr = NT - dz * rowlen;
-            int z = threadIdx.x / rowlen, r = threadIdx.x - (threadIdx.x / rowlen) * rowlen;
-            for (int idx = threadIdx.x; idx < NZ * rowlen; idx += NT) {
-                __builtin_nontemporal_store(stage[z * RS + z / N2 + r + (r >= 3 * TBC / 2 ? GAP : 0)], dst + idx);
-                z += dz;
-                r += dr;
-                if (r >= rowlen) {
-                    r -= rowlen;
-                    ++z;
+        };
+        // Column spectra Qhat_w(kkb, t) of both samples of this thread's pairs
+        // of the block at t0.  A sample past the block is zero when it pairs
+        // with the last one (odd block length); pairs wholly past the block
+        // are not used.
+        auto fetch = [&](int t0) {
+            const int tbl = min(TBC, nt - t0);
+#pragma unroll
+            for (int k = 0; k < PFI; ++k)
+#pragma unroll
+                for (int sm = 0; sm < 2; ++sm) {
+                    const int tin = 2 * (pb + k * PPT) + sm;
+                    if (tin < tbl) {
+                        const cplx<T>* q = qhat + (size_t)(t0 + tin) * WC * NZH;
+#pragma unroll
+                        for (int w = 0; w < WC; ++w)
+                            pq[k][w][sm] = *byte_offset(q + w * NZH, kkb * sizeof(cplx<T>));
+                    } else if (tin == tbl) {
+#pragma unroll
+                        for (int w = 0; w < WC; ++w) pq[k][w][sm] = cplx<T>{(T)0, (T)0};
+                    }
+                }
+        };
+        // spectra Z of the npair sample pairs of a block: rows kkb and
+        // N_z - kkb (row N_z/2 for kk = 0, which pass 1 does not read)
+        auto build = [&](T* stage, int npair) {
+            settle_all();
+            const int zm = kkb == 0 ? NZH : NZ - kkb;
+            T* r0 = stage + kkb * RS + (kkb / N2) * PAD;
+            T* r1 = stage + zm * RS + (zm / N2) * PAD;
+#pragma unroll
+            for (int k = 0; k < PFI; ++k) {
+                if (pb + k * PPT < npair) {
+                    // Z(kk) = sum_w Ehat_w (Qhat_w(t) + i Qhat_w(t+1)),
+                    // Z(N_z - kk) = sum_w conj(Ehat_w) (conj Qhat_w(t) + i conj Qhat_w(t+1))
+                    cplx<T> u[WC], v[WC];
+#pragma unroll
+                    for (int w = 0; w < WC; ++w) {
+                        const cplx<T> q0 = pq[k][w][0], q1 = pq[k][w][1];
+                        u[w] = cplx<T>{q0.re - q1.im, q0.im + q1.re};
+                        v[w] = cplx<T>{q0.re + q1.im, q1.re - q0.im};
+                    }
+#pragma unroll
+                    for (int aa = 0; aa < 3; ++aa) {
+                        cplx<T> z = e[aa][0] * u[0], zr = conj(e[aa][0]) * v[0];
+#pragma unroll
+                        for (int w = 1; w < WC; ++w) {
+                            z = z + e[aa][w] * u[w];
+                            zr = zr + conj(e[aa][w]) * v[w];
+                        }
+                        const int c = pcol(pb + k * PPT) + aa;
+                        r0[c] = z.re;
+                        r0[c + 3] = z.im;
+                        r1[c] = zr.re;
+                        r1[c + 3] = zr.im;
+                    }
                 }
             }
+        };
+        // A full block: each lane writes two consecutive values of a row per
+        // store (rows are 3 x 16 values, the gap falls between value pairs);
+        // a fixed number of stores per thread, so that the spectra loads
+        // issued just before are waited for without waiting for the stores.
+        auto copyout_full = [&](const T* stage, int t0) {
+            T* dst = hcol + (size_t)t0 * NZ * 3;
+            int lane = m;
+            asm volatile("" : "+v"(lane));
+            const int rr = 2 * (lane % LW);
+            const T* src = stage + (lane / LW) * RS + rr + (rr >= 3 * TBC / 2 ? GAP : 0);
+#pragma unroll
+            for (int k = 0; k < STORES; ++k) {
+                const T* sk = src + k * ROWS * RS + (k * ROWS / N2) * PAD;
+                T* dk = byte_offset(dst + k * NTM * 2, lane * 2 * (unsigned)sizeof(T));
+                if constexpr (sizeof(T) == 4) {
+                    __builtin_nontemporal_store(vec2f{sk[0], sk[1]}, reinterpret_cast<vec2f*>(dk));
+                } else {
+                    __builtin_nontemporal_store(vec2d{sk[0], sk[1]}, reinterpret_cast<vec2d*>(dk));
+                }
+            }
+            settle_all();
+        };
+        auto copyout = [&](const T* stage, int t0) {
+            const int tbl = min(TBC, nt - t0);
+            T* dst = hcol + (size_t)t0 * NZ * 3;
+            if (tbl == TBC) {
+                copyout_full(stage, t0);
+            } else {
+                const int rowlen = tbl * 3;
+                const int dz = NTM / rowlen, dr = NTM - dz * rowlen;
+                int z = m / rowlen, r = m - (m / rowlen) * rowlen;
+                for (int idx = m; idx < NZ * rowlen; idx += NTM) {
+                    __builtin_nontemporal_store(stage[z * RS + (z / N2) * PAD + r + (r >= 3 * TBC / 2 ? GAP : 0)],
+                                                dst + idx);
+                    z += dz;
+                    r += dr;
+                    if (r >= rowlen) {
+                        r -= rowlen;
+                        ++z;
+                    }
+                }
+            }
+        };
+        // Block s (>= 1) of the loop copies out block s-1, which is full (only
+        // the last block can be partial), after issuing the loads of block
+        // s+1: every spectra load is followed by the same number of stores
+        // and waited for right after them, and nothing left pending crosses
+        // a loop iteration.
+        fetch(0);
+        build(lds, (min(TBC, nt) + 1) / 2);
+        __syncthreads();                                       // block 0 staged
+        if (TBC < nt) fetch(TBC);
+        __syncthreads();                                       // pass 1 of block 0 done
+        if (TBC < nt) build(lds + BUF, (min(TBC, nt - TBC) + 1) / 2);
+        settle_all();
+        __syncthreads();                                       // block 0 transformed
+        for (int s = 1; s < nblk; ++s) {
+            const int tn = (s + 1) * TBC;
+            if (tn < nt) fetch(tn);
+            copyout_full(lds + ((s - 1) & 1) * BUF, (s - 1) * TBC);
+            __syncthreads();                                   // pass 1 of block s done
+            if (tn < nt) build(lds + ((s + 1) & 1) * BUF, (min(TBC, nt - tn) + 1) / 2);
+            __syncthreads();                                   // block s transformed
         }
-        if (tn < nt) {
-            __syncthreads();                                   // block copied out of the staging slots
-            build((min(TBC, nt - tn) + 1) / 2);
-        }
+        copyout(lds + ((nblk - 1) & 1) * BUF, (nblk - 1) * TBC);
     }
 }
 
@@ -475,15 +503,13 @@ hipError_t field_table(const Plan& p, char* b, hipStream_t s) {
 }
 
 template <typename T, int N1, int N2, int WC>
-hipError_t synthesis_reg(const Plan& p, char* b, void* h, hipStream_t s) {
+hipError_t synthesis_pipe(const Plan& p, char* b, void* h, hipStream_t s) {
     constexpr int NZ = N1 * N2;
-    constexpr int TBC = synthesis_block(NZ);
-    const size_t lds = synthesis_reg_lds(NZ, TBC, sizeof(T));
-    const int threads = synthesis_threads(NZ, TBC);
-    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_reg<T, N1, N2, WC, TBC>,
+    const size_t lds = synthesis_pipe_lds(NZ, sizeof(T));
+    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_pipe<T, N1, N2, WC>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_synthesis_reg<T, N1, N2, WC, TBC>), dim3(p.N[0] * p.N[1]), dim3(threads), lds, s, p,
+    hipLaunchKernelGGL((k_synthesis_pipe<T, N1, N2, WC>), dim3(p.N[0] * p.N[1]), dim3(48 * N1), lds, s, p,
                        reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]), static_cast<T*>(h));
@@ -491,23 +517,22 @@ hipError_t synthesis_reg(const Plan& p, char* b, void* h, hipStream_t s) {
 }
 
 template <typename T, int N1, int N2>
-hipError_t synthesis_reg_w(const Plan& p, char* b, void* h, hipStream_t s) {
+hipError_t synthesis_pipe_w(const Plan& p, char* b, void* h, hipStream_t s) {
     switch (p.n_cols) {
-        case 1: return synthesis_reg<T, N1, N2, 1>(p, b, h, s);
-        case 2: return synthesis_reg<T, N1, N2, 2>(p, b, h, s);
-        case 3: return synthesis_reg<T, N1, N2, 3>(p, b, h, s);
-        default: return synthesis_reg<T, N1, N2, 4>(p, b, h, s);
+        case 1: return synthesis_pipe<T, N1, N2, 1>(p, b, h, s);
+        case 2: return synthesis_pipe<T, N1, N2, 2>(p, b, h, s);
+        case 3: return synthesis_pipe<T, N1, N2, 3>(p, b, h, s);
+        default: return synthesis_pipe<T, N1, N2, 4>(p, b, h, s);
     }
 }
 
 template <typename T>
 hipError_t synthesis(const Plan& p, char* b, void* h, hipStream_t s) {
-    if (p.synth_kernel == 1) {
+    if (p.synth_kernel == 2) {
         switch (p.N[2]) {
-            case 64: return synthesis_reg_w<T, 8, 8>(p, b, h, s);
-            case 128: return synthesis_reg_w<T, 8, 16>(p, b, h, s);
-            case 256: return synthesis_reg_w<T, 16, 16>(p, b, h, s);
-            case 512: return synthesis_reg_w<T, 16, 32>(p, b, h, s);
+            case 64: return synthesis_pipe_w<T, 8, 8>(p, b, h, s);
+            case 128: return synthesis_pipe_w<T, 8, 16>(p, b, h, s);
+            case 256: return synthesis_pipe_w<T, 16, 16>(p, b, h, s);
             default: break;
         }
     }

@@ -41,7 +41,7 @@ def test_plan_layout_32_and_128_grids():
     plan, lay = wt.wt_h_plan_create(cell, cols, spec, precision=wt.WT_F64)
     assert lay["n_q"] == 128
     assert lay["h_bytes"] == 32 * 32 * 64 * 64 * 3 * 8
-    assert lay["h_time_block"] == 32
+    assert lay["h_time_block"] == 16
     assert lay["workspace_bytes"] > lay["off_ehat"] + 32 * 32 * 32 * 3 * 16 - 1
     assert wt.wt_h_plan_layout(plan) == lay
     wt.wt_h_plan_destroy(plan)
@@ -49,7 +49,7 @@ def test_plan_layout_32_and_128_grids():
     spec2 = dict(n_freq=256, df=workloads.frequency_grid_to_nyquist(256, 10e-12), n_time=200, dt=10e-12)
     plan, lay = wt.wt_h_plan_create(px128, cols, spec2, precision=wt.WT_F32)
     assert lay["h_bytes"] == 128 * 128 * 256 * 200 * 3 * 4
-    assert lay["h_time_block"] == 32
+    assert lay["h_time_block"] == 16
     wt.wt_h_plan_destroy(plan)
 
 
