@@ -12,6 +12,9 @@ and time transform in float64.  Inputs are resident on the GPU before timing.
 
 Prints one JSON line.  value = grid points x frequencies per second of the
 whole step; tracks/s and carriers/s of the current stage are extra fields.
+The same step with H stored as scaled float16 (the mixed-precision path) is
+timed after it and reported under "mixed", with its errors against the FP64
+oracle (H) and the float32 path (the current).
 """
 import argparse
 import json
@@ -74,8 +77,8 @@ def cpu_baseline(cfg, gpu_columns, budget_s):
     about half the time budget is spent, and Eq. 1 on strided subsets of the
     carriers until about a third of it is.  The whole-step rate is
     extrapolated from them: fit + per-column time x all columns + per-carrier
-    time x all carriers.  gpu_columns(cols) returns the GPU's H on those
-    columns, for the error figure.
+    time x all carriers.  gpu_columns maps a path name to a function that
+    returns the GPU's H on given columns, for the error figures.
     """
     import numpy as np
 
@@ -89,7 +92,9 @@ def cpu_baseline(cfg, gpu_columns, budget_s):
     q_t = timegrid.to_time(sol["q"], spec)
     t_fit = time.perf_counter() - t0
     s, src = green.smoothing_widths(cell, cols), collocation.sources(cols)
-    sample, t_cols, err_num, err_den = [], 0.0, 0.0, 0.0
+    sample, t_cols = [], 0.0
+    err_num = {name: 0.0 for name in gpu_columns}
+    err_den = 0.0
     for shift in range(64):                       # 16 x 16 lattices off the column axes
         lattice = [((i + 3 + shift) % N[0], (j + 5 + 3 * shift) % N[1])
                    for i in range(0, N[0], N[0] // 16) for j in range(0, N[1], N[1] // 16)]
@@ -98,13 +103,13 @@ def cpu_baseline(cfg, gpu_columns, budget_s):
         t0 = time.perf_counter()
         ref = field.field_columns(cell, s, src, q_t, lattice)
         t_cols += time.perf_counter() - t0
-        got = gpu_columns(lattice)
-        err_num += float(np.sum((got - ref) ** 2))
+        for name, fn in gpu_columns.items():
+            err_num[name] += float(np.sum((fn(lattice) - ref) ** 2))
         err_den += float(np.sum(ref ** 2))
         sample += lattice
         if t_cols > 0.5 * budget_s:
             break
-    err = (err_num / err_den) ** 0.5
+    err = {name: (v / err_den) ** 0.5 for name, v in err_num.items()}
     # convolution: strided carrier subsets on a synthetic field of the same grid
     car = cfg["carriers"]
     n_car = car["pos"].shape[0]
@@ -157,70 +162,90 @@ def main():
     cfg = workloads.mip_pixel_128x128x256()
     cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
     N = cell["N"]
+    n_pts = N[0] * N[1] * N[2]
+    per_col = N[2] * spec["n_time"] * 3
+    w = len(cfg["columns"])
     stream = torch.cuda.current_stream()
     ctx = wt.wt_context_create(0, stream.cuda_stream)
-    plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2, ir_tol=1e-12)
-    ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
-    h = torch.empty(lay["h_bytes"] // 4, dtype=torch.float32, device="cuda")
     pos = torch.from_numpy(car["pos"]).to("cuda", torch.float32)
     q = torch.from_numpy(car["charge"]).to("cuda", torch.float32)
     tr = torch.from_numpy(car["track"]).to("cuda")
     n_c, n_tr = pos.shape[0], car["n_tracks"]
-    out = torch.empty((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
 
-    def step():
-        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"])
-        wt.wt_current(ctx, plan, h.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
-                      out.data_ptr())
+    def run_path(h_format):
+        """Time the whole step with H stored in h_format; returns the figures and buffers."""
+        plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2,
+                                        ir_tol=1e-12, h_format=h_format)
+        ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
+        hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
+        out = torch.empty((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
 
-    st, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"], report=True)
-    print(f"# solve report: {rep}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    ms = e0.elapsed_time(e1) / args.steps
-    print(f"# timed {args.steps} steps: {ms:.3f} ms/step (wall {1e3 * t_wall / args.steps:.3f} ms)",
-          file=sys.stderr, flush=True)
+        def step():
+            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
+            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
+                          out.data_ptr())
 
-    # per-stage durations from HIP events recorded by the library on the same stream
-    wt.wt_context_enable_timing(ctx, True)
-    stage = {}
-    reps = max(3, min(args.steps, 10))
-    for _ in range(reps):
-        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"])
-        for name, t in wt.wt_context_stage_times(ctx):
-            stage[name] = stage.get(name, 0.0) + t / reps
-        wt.wt_current(ctx, plan, h.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
-                      out.data_ptr())
-        for name, t in wt.wt_context_stage_times(ctx):
-            stage[name] = stage.get(name, 0.0) + t / reps
-    wt.wt_context_enable_timing(ctx, False)
+        st, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True)
+        print(f"# h_format {h_format}: solve report {rep}", file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t_wall = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter() - t_wall
+        ms = e0.elapsed_time(e1) / args.steps
+        print(f"# h_format {h_format}: timed {args.steps} steps: {ms:.3f} ms/step "
+              f"(wall {1e3 * t_wall / args.steps:.3f} ms)", file=sys.stderr, flush=True)
+        # per-stage durations from HIP events recorded by the library on the same stream
+        wt.wt_context_enable_timing(ctx, True)
+        stage = {}
+        reps = max(3, min(args.steps, 10))
+        for _ in range(reps):
+            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
+            for name, t in wt.wt_context_stage_times(ctx):
+                stage[name] = stage.get(name, 0.0) + t / reps
+            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
+                          out.data_ptr())
+            for name, t in wt.wt_context_stage_times(ctx):
+                stage[name] = stage.get(name, 0.0) + t / reps
+        wt.wt_context_enable_timing(ctx, False)
+        torch.cuda.synchronize()
+        wt.wt_h_plan_destroy(plan)
+        if h_format == wt.WT_H_F16_SCALED:
+            h = hbuf[:n_pts * spec["n_time"] * 3 * 2].view(torch.float16)
+            off = lay["h_decode_offset"]
+            decode = float(hbuf[off:off + 4].view(torch.float32).item())
+        else:
+            h, decode = hbuf.view(torch.float32), 1.0
+        t_h = sum(v for k, v in stage.items() if k != "current") * 1e-3
+        t_cur = stage["current"] * 1e-3
+        # synthesis kernel: algorithmic bytes = write of H + read of the field table per column
+        synth_bytes = h.numel() * h.element_size() + N[0] * N[1] * w * (N[2] // 2) * 3 * 8
+        achieved = synth_bytes / (stage["synthesis"] * 1e-3) / 1e9
+        return dict(ms=ms, stage=stage, t_h=t_h, t_cur=t_cur, rep=rep, h=h, decode=decode, out=out,
+                    synth_bytes=synth_bytes, achieved=achieved, lay=lay)
 
-    n_pts = N[0] * N[1] * N[2]
-    t_h = sum(v for k, v in stage.items() if k != "current") * 1e-3
-    t_cur = stage["current"] * 1e-3
-    # synthesis kernel: algorithmic bytes = write of H + read of the field table per column
-    w = len(cfg["columns"])
-    synth_bytes = lay["h_bytes"] + N[0] * N[1] * w * (N[2] // 2) * 3 * 8
-    achieved = synth_bytes / (stage["synthesis"] * 1e-3) / 1e9
+    def columns_of(r):
+        def fn(cols):
+            idx = torch.tensor([i * N[1] + j for i, j in cols], device="cuda")
+            vals = r["h"].view(-1, per_col).index_select(0, idx).cpu().numpy().astype(np.float64) * r["decode"]
+            return layout.to_standard(vals, N, spec["n_time"], r["lay"]["h_time_block"])
+        return fn
+
+    plain = run_path(wt.WT_H_PLAIN)
+    mixed = run_path(wt.WT_H_F16_SCALED)
+    i_plain = plain["out"].double().cpu().numpy()
+    i_mixed = mixed["out"].double().cpu().numpy()
+    i_err_mixed = float(np.linalg.norm(i_mixed - i_plain) / np.linalg.norm(i_plain))
+
+    stage, ms = plain["stage"], plain["ms"]
     traffic = (SYNTH_TRAFFIC_BYTES if list(N) == [128, 128, 256] and spec["n_time"] == 200 and w == 2
                and synthesis_sources_sha256() == SYNTH_TRAFFIC_SOURCES_SHA256 else None)
-
-    per_col = N[2] * spec["n_time"] * 3
-
-    def gpu_columns(cols):
-        idx = torch.tensor([i * N[1] + j for i, j in cols], device="cuda")
-        return layout.to_standard(h.view(-1, per_col).index_select(0, idx).cpu().numpy().astype(np.float64),
-                                  N, spec["n_time"], lay["h_time_block"])
-
     line = {
         "metric": METRIC,
         "value": n_pts * spec["n_freq"] / (ms * 1e-3),
@@ -238,26 +263,39 @@ def main():
             "workload": (f"plain path: {N[0]}x{N[1]}x{N[2]} grid of a 50x50x300 um pixel, readout + bias "
                          f"columns (r = 5 um, 5 seeded resistivities), {spec['n_freq']} frequencies to 50 GHz, "
                          f"{spec['n_time']} x 10 ps, one MIP track with {n_c // 2} e/h pairs ({n_c} carriers); "
-                         f"f32 field/FFT/convolution, f64 boundary fit"),
+                         f"f32 field/FFT/convolution and H, f64 boundary fit"),
             "grid": list(N), "n_freq": spec["n_freq"], "n_time": spec["n_time"], "n_carriers": n_c,
             "n_tracks": n_tr, "parallelism": "single GPU",
         },
-        "tracks_per_s": n_tr / t_cur,
-        "carriers_per_s": n_c / t_cur,
-        "h_grid_freq_pts_per_s": n_pts * spec["n_freq"] / t_h,
-        "h_grid_time_pts_per_s": n_pts * spec["n_time"] / t_h,
+        "tracks_per_s": n_tr / plain["t_cur"],
+        "carriers_per_s": n_c / plain["t_cur"],
+        "h_grid_freq_pts_per_s": n_pts * spec["n_freq"] / plain["t_h"],
+        "h_grid_time_pts_per_s": n_pts * spec["n_time"] / plain["t_h"],
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
-        "roofline": {"kernel": "k_synthesis_reg", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_unit": "bytes/launch", "bytes_per_launch": synth_bytes},
-        "solve_report": rep,
+        "roofline": {"kernel": "k_synthesis_pipe", "bound": "hbm", "achieved": plain["achieved"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": plain["achieved"] / HBM_PEAK_GBS,
+                     "traffic": traffic, "traffic_unit": "bytes/launch", "bytes_per_launch": plain["synth_bytes"]},
+        "solve_report": plain["rep"],
+        "mixed": {
+            "h_storage": "float16 holding H * h_scale (h_scale a power of two), decoded in float32",
+            "h_scale": mixed["rep"]["h_scale"],
+            "value": n_pts * spec["n_freq"] / (mixed["ms"] * 1e-3),
+            "ms_per_step": mixed["ms"],
+            "tracks_per_s": n_tr / mixed["t_cur"],
+            "h_grid_freq_pts_per_s": n_pts * spec["n_freq"] / mixed["t_h"],
+            "stage_ms": {k: round(v, 4) for k, v in mixed["stage"].items()},
+            "roofline": {"kernel": "k_synthesis_pipe (float16 H)", "bound": "hbm", "achieved": mixed["achieved"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": mixed["achieved"] / HBM_PEAK_GBS,
+                         "bytes_per_launch": mixed["synth_bytes"]},
+            "rel_err": {"i_vs_float32_path": i_err_mixed},
+        },
     }
     if not args.no_cpu_baseline:
-        base, err = cpu_baseline(cfg, gpu_columns, args.cpu_seconds)
+        base, err = cpu_baseline(cfg, {"plain": columns_of(plain), "mixed": columns_of(mixed)}, args.cpu_seconds)
         line["cpu_baseline"] = base
-        line["rel_err"] = {"H_sampled_columns_vs_fp64_oracle": err}
+        line["rel_err"] = {"H_sampled_columns_vs_fp64_oracle": err["plain"]}
+        line["mixed"]["rel_err"]["H_sampled_columns_vs_fp64_oracle"] = err["mixed"]
     print(json.dumps(line), flush=True)
-    wt.wt_h_plan_destroy(plan)
     wt.wt_context_destroy(ctx)
 
 

@@ -92,10 +92,21 @@ typedef struct {
     double dt;
 } wt_spectrum;
 
+typedef enum {
+    WT_H_PLAIN = 0,        /* H stored in the path's precision (double or float) */
+    WT_H_F16_SCALED = 1    /* H stored as float16 values of H * h_scale, with
+                              h_scale = 2^s chosen from a bound on |H| so that
+                              every stored magnitude is <= 16384 (requires
+                              WT_F32 and N_z in {64, 128, 256} with at most 4
+                              columns); the synthesis and the convolution
+                              compute in float */
+} wt_h_format;
+
 typedef struct {
     int precision;      /* wt_precision */
     int ir_max_iter;    /* refinement sweeps after the LU solve, 0..16 */
     double ir_tol;      /* target normwise backward error (>= 0) */
+    int h_format;       /* wt_h_format */
 } wt_h_options;
 
 /* Filled by wt_h_solve when a report pointer is given (that call then
@@ -105,6 +116,7 @@ typedef struct {
     double pivot_ratio_max;     /* max over frequencies of max|U_ii| / min|U_ii| */
     int ir_iters_max;           /* refinement sweeps used (max over frequencies) */
     int singular_count;         /* frequencies whose LU met a zero pivot */
+    double h_scale;             /* stored value = H * h_scale (1 for WT_H_PLAIN) */
 } wt_h_report;
 
 /* Sizes and byte offsets of a plan.  H is stored time-blocked:
@@ -113,7 +125,10 @@ typedef struct {
  * (x, y, z), time t and component a the element index is
  *   (x*Ny + y)*Nz*n_time*3 + tb*h_time_block*Nz*3 + z*Tb*3 + tin*3 + a
  * with Tb the length of block tb.  Each node's lag series is contiguous
- * within a block.  The element type is double (WT_F64) or float (WT_F32).
+ * within a block.  The element type is double (WT_F64), float (WT_F32) or,
+ * for WT_H_F16_SCALED, float16 holding H * h_scale; the buffer then ends
+ * with a float 1 / h_scale at byte offset h_decode_offset (written by
+ * wt_h_solve, read by wt_current), so that H carries its own scale.
  * The workspace offsets locate intermediate results (for inspection):
  *   A      double  [n_q][n_q]        collocation matrix, V/C
  *   qw     double2 [n_freq][n_q+1]   charges q(w_j) (C/V) then the gauge c
@@ -126,6 +141,8 @@ typedef struct {
     int h_time_block;
     int n_q;
     size_t off_A, off_qw, off_qt, off_qhat, off_ehat;
+    int h_format;               /* wt_h_format of the plan */
+    size_t h_decode_offset;     /* WT_H_F16_SCALED: byte offset of 1/h_scale in H; else 0 */
 } wt_h_layout;
 
 typedef struct wt_context wt_context;

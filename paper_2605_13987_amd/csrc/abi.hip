@@ -73,6 +73,7 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     if (sp->n_freq < 1 || sp->n_freq > 65535 || sp->n_time < 1) return WT_E_INVALID_ARG;
     if (sp->n_time > wt::kMaxTime) return WT_E_UNSUPPORTED_SIZE;
     if (!pos_finite(sp->dt)) return WT_E_INVALID_ARG;
+    if (opt->h_format != WT_H_PLAIN && opt->h_format != WT_H_F16_SCALED) return WT_E_INVALID_ARG;
     if (sp->n_freq > 1 ? !pos_finite(sp->df) : !(std::isfinite(sp->df) && sp->df >= 0.0)) return WT_E_INVALID_ARG;
     if (opt->precision != WT_F64 && opt->precision != WT_F32) return WT_E_INVALID_ARG;
     if (opt->ir_max_iter < 0 || opt->ir_max_iter > 16) return WT_E_INVALID_ARG;
@@ -178,6 +179,10 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
         if (lds_need(tb) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
     }
     p.tb = tb;
+    p.h_format = opt->h_format;
+    // float16 H is written by the pipelined synthesis only, from the float path
+    if (p.h_format == WT_H_F16_SCALED && p.precision != WT_F32) return WT_E_INVALID_ARG;
+    if (p.h_format == WT_H_F16_SCALED && p.synth_kernel != 2) return WT_E_UNSUPPORTED_SIZE;
 
     size_t off = 0;
     for (int a = 0; a < 3; ++a) {
@@ -202,8 +207,17 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     off = align256(off + (size_t)p.n_time * n_cols * p.nzh * cx);
     p.off_ehat = off;
     off = align256(off + (size_t)N[0] * N[1] * p.nzh * 3 * cx);
+    p.off_hscale = off;
+    off = align256(off + 64 + (size_t)p.nzh * (sizeof(unsigned) + sizeof(float)));
     p.ws_bytes = off;
-    p.h_bytes = (size_t)N[0] * N[1] * N[2] * p.n_time * 3 * re;
+    const size_t n_h = (size_t)N[0] * N[1] * N[2] * p.n_time * 3;
+    if (p.h_format == WT_H_F16_SCALED) {
+        p.h_values_bytes = align256(n_h * 2);
+        p.h_bytes = p.h_values_bytes + 256;
+    } else {
+        p.h_values_bytes = n_h * re;
+        p.h_bytes = p.h_values_bytes;
+    }
     return WT_OK;
 }
 
@@ -217,6 +231,8 @@ void fill_layout(const Plan& p, wt_h_layout* l) {
     l->off_qt = p.off_qt;
     l->off_qhat = p.off_qhat;
     l->off_ehat = p.off_ehat;
+    l->h_format = p.h_format;
+    l->h_decode_offset = p.h_format == WT_H_F16_SCALED ? p.h_values_bytes : 0;
 }
 
 wt_status bind(wt_context* ctx) {
@@ -377,6 +393,7 @@ wt_status wt_h_solve(wt_context* ctx, const wt_h_plan* plan, void* d_workspace, 
     WT_HIP(ctx, wt::launch_time_transform(p, d_workspace, s), "time_transform");
     if ((st = mark(ctx, kStageTime)) != WT_OK) return st;
     WT_HIP(ctx, wt::launch_field_table(p, d_workspace, s), "field_table");
+    if (p.h_format == WT_H_F16_SCALED) WT_HIP(ctx, wt::launch_h_scale(p, d_workspace, d_h, s), "h_scale");
     if ((st = mark(ctx, kStageFieldTable)) != WT_OK) return st;
     WT_HIP(ctx, wt::launch_synthesis(p, d_workspace, d_h, s), "synthesis");
     if ((st = mark(ctx, kStageSynthesis)) != WT_OK) return st;
@@ -386,7 +403,13 @@ wt_status wt_h_solve(wt_context* ctx, const wt_h_plan* plan, void* d_workspace, 
     WT_HIP(ctx, hipMemcpyAsync(rep.data(), static_cast<char*>(d_workspace) + p.off_rep,
                                rep.size() * sizeof(wt::SolveReport), hipMemcpyDeviceToHost, s),
            "report copy");
+    float h_scale = 1.0f;
+    if (p.h_format == WT_H_F16_SCALED)
+        WT_HIP(ctx, hipMemcpyAsync(&h_scale, static_cast<char*>(d_workspace) + p.off_hscale, sizeof(float),
+                                   hipMemcpyDeviceToHost, s),
+               "scale copy");
     WT_HIP(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+    report->h_scale = h_scale;
     report->backward_error_max = 0.0;
     report->pivot_ratio_max = 0.0;
     report->ir_iters_max = 0;

@@ -62,6 +62,7 @@ struct Plan {
     double df, dt;
     int last_weight_one;   // last frequency is the Nyquist frequency 1/(2 dt)
     int precision;         // 0 double, 1 float
+    int h_format;          // 0 H in the path's precision, 1 float16 holding H * h_scale
     int ir_max_iter;
     double ir_tol;
     double s_bulk[3];
@@ -73,7 +74,9 @@ struct Plan {
     int rad[3][kMaxRadices];
     // workspace layout (bytes)
     size_t off_tw[3], off_g, off_A, off_lu, off_piv, off_qw, off_rep, off_qt, off_qhat, off_ehat;
+    size_t off_hscale;     // float16 H: [0] float h_scale, [64 B on] uint32 max |Ehat| per k_z, then float qsum per k_z
     size_t ws_bytes, h_bytes;
+    size_t h_values_bytes; // bytes of the values of H; for float16 H the float 1/h_scale follows
 };
 
 // Per-frequency solve diagnostics written by the solve kernel.
@@ -90,6 +93,7 @@ hipError_t launch_green_tables(const Plan& p, void* ws, hipStream_t s);
 hipError_t launch_collocation_solve(const Plan& p, void* ws, hipStream_t s);
 hipError_t launch_time_transform(const Plan& p, void* ws, hipStream_t s);
 hipError_t launch_field_table(const Plan& p, void* ws, hipStream_t s);
+hipError_t launch_h_scale(const Plan& p, void* ws, void* h, hipStream_t s);
 hipError_t launch_synthesis(const Plan& p, void* ws, void* h, hipStream_t s);
 hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks,
                           const void* pos, const void* charge, const int* track,

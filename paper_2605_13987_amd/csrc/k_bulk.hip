@@ -14,6 +14,7 @@
 // Two real outputs share one complex FFT: Z = F_1 + i F_2, Re -> 1, Im -> 2.
 #include "fft.hpp"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace wt {
@@ -165,6 +166,7 @@ __device__ inline const T* byte_offset(const T* p, unsigned off) {
 
 typedef float vec4f __attribute__((ext_vector_type(4)));
 typedef float vec2f __attribute__((ext_vector_type(2)));
+typedef _Float16 vec2h __attribute__((ext_vector_type(2)));
 typedef double vec2d __attribute__((ext_vector_type(2)));
 
 // Synthesis of H(X, Y, z, t) for N_z = N1 x N2 in {64, 128, 256}, with the
@@ -197,9 +199,10 @@ typedef double vec2d __attribute__((ext_vector_type(2)));
 // block s-1 out of the other buffer (phase 1), then builds block s+1's
 // spectra into it (phase 2).  A workgroup barrier ends each phase; within a
 // phase the teams touch different buffers.
-template <typename T, int N1, int N2, int WC>
+template <typename T, int N1, int N2, int WC, typename TO>
 __global__ void __launch_bounds__(48 * N1)
-k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, T* H) {
+k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, const float* h_scale,
+                 TO* H) {
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
     constexpr int C = N2 / N1;
@@ -224,8 +227,10 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
     const int Nx = p.N[0], Ny = p.N[1], nt = p.n_time;
     const int col = blockIdx.x;
     const int ix = col / Ny, iy = col - (col / Ny) * Ny;
-    T* hcol = H + (size_t)col * NZ * nt * 3;
+    TO* hcol = H + (size_t)col * NZ * nt * 3;
     const int nblk = (nt + TBC - 1) / TBC;
+    // stored value = H * enc (float16 H), else H
+    constexpr bool kScaled = !std::is_same<TO, T>::value;
     // column of sample pair q (component 0, real part): 6 q, plus the gap in the second half
     auto pcol = [](int q) { return 6 * q + (q >= NP / 2 ? GAP : 0); };
     auto settle = [](const cplx<T>& v) { asm volatile("" ::"v"(v.re), "v"(v.im)); };
@@ -310,6 +315,7 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
     } else {
         // --------------------------------------------------- memory team
         const int m = threadIdx.x - NTT;
+        const T enc = kScaled ? (T)h_scale[0] : (T)1;
         const int kkb = m % NZH;
         int pb = m / NZH;                                      // first sample pair of this thread
         if constexpr (NZH % 64 == 0) pb = __builtin_amdgcn_readfirstlane(pb);
@@ -399,7 +405,7 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
         // a fixed number of stores per thread, so that the spectra loads
         // issued just before are waited for without waiting for the stores.
         auto copyout_full = [&](const T* stage, int t0) {
-            T* dst = hcol + (size_t)t0 * NZ * 3;
+            TO* dst = hcol + (size_t)t0 * NZ * 3;
             int lane = m;
             asm volatile("" : "+v"(lane));
             const int rr = 2 * (lane % LW);
@@ -407,8 +413,11 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
 #pragma unroll
             for (int k = 0; k < STORES; ++k) {
                 const T* sk = src + k * ROWS * RS + (k * ROWS / N2) * PAD;
-                T* dk = byte_offset(dst + k * NTM * 2, lane * 2 * (unsigned)sizeof(T));
-                if constexpr (sizeof(T) == 4) {
+                TO* dk = byte_offset(dst + k * NTM * 2, lane * 2 * (unsigned)sizeof(TO));
+                if constexpr (kScaled) {
+                    __builtin_nontemporal_store(vec2h{(_Float16)(sk[0] * enc), (_Float16)(sk[1] * enc)},
+                                                reinterpret_cast<vec2h*>(dk));
+                } else if constexpr (sizeof(T) == 4) {
                     __builtin_nontemporal_store(vec2f{sk[0], sk[1]}, reinterpret_cast<vec2f*>(dk));
                 } else {
                     __builtin_nontemporal_store(vec2d{sk[0], sk[1]}, reinterpret_cast<vec2d*>(dk));
@@ -418,7 +427,7 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
         };
         auto copyout = [&](const T* stage, int t0) {
             const int tbl = min(TBC, nt - t0);
-            T* dst = hcol + (size_t)t0 * NZ * 3;
+            TO* dst = hcol + (size_t)t0 * NZ * 3;
             if (tbl == TBC) {
                 copyout_full(stage, t0);
             } else {
@@ -426,8 +435,8 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
                 const int dz = NTM / rowlen, dr = NTM - dz * rowlen;
                 int z = m / rowlen, r = m - (m / rowlen) * rowlen;
                 for (int idx = m; idx < NZ * rowlen; idx += NTM) {
-                    __builtin_nontemporal_store(stage[z * RS + (z / N2) * PAD + r + (r >= 3 * TBC / 2 ? GAP : 0)],
-                                                dst + idx);
+                    const T v = stage[z * RS + (z / N2) * PAD + r + (r >= 3 * TBC / 2 ? GAP : 0)];
+                    __builtin_nontemporal_store(kScaled ? (TO)(v * enc) : (TO)v, dst + idx);
                     z += dz;
                     r += dr;
                     if (r >= rowlen) {
@@ -459,6 +468,92 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
             __syncthreads();                                   // block s transformed
         }
         copyout(lds + ((nblk - 1) & 1) * BUF, (nblk - 1) * TBC);
+    }
+}
+
+// Scale of float16 H (stored value = H * h_scale).  H_a(X, Y, z, t) is the
+// sum over k_z in (-N_z/2, N_z/2) of e^{i k_z z} sum_w Ehat_a(X - X_w,
+// Y - Y_w, k_z) Qhat_w(k_z, t) (negative k_z as conjugates), so
+//   |H| <= B = sum_{k >= 0} m_k max_{X,Y,a} |Ehat_a(X,Y,k)| sum_w max_t |Qhat_w(k,t)|
+// with m_0 = 1 and m_k = 2 otherwise.  h_scale = 2^s with s the largest
+// integer such that B h_scale <= 16384, a quarter of the float16 range: a
+// power of two, so that scaling and unscaling are exact.
+//
+// k_hscale_emax: max over (X, Y, a) of |Ehat| per k_z, as the bits of a
+// non-negative float (their integer order is the float order).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_hscale_emax(Plan p, const cplx<T>* ehat, unsigned* emax) {
+    // the grid stride is a multiple of N_z/2 (which divides the block size),
+    // so each thread stays on one k_z; threads of a block with the same k_z
+    // combine in LDS before one atomic per k_z
+    __shared__ float m_lds[kBlock];
+    const size_t n = (size_t)p.N[0] * p.N[1] * p.nzh;
+    float m = 0.0f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const cplx<T>* e = ehat + i * 3;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) m = fmaxf(m, (float)sqrt(e[a].re * e[a].re + e[a].im * e[a].im));
+    }
+    m_lds[threadIdx.x] = m;
+    __syncthreads();
+    if ((int)threadIdx.x < p.nzh) {
+        for (int j = threadIdx.x + p.nzh; j < kBlock; j += p.nzh) m = fmaxf(m, m_lds[j]);
+        atomicMax(emax + threadIdx.x, __float_as_uint(m));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_hscale_clear(unsigned* emax, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) emax[i] = 0u;
+}
+
+// One workgroup per k_z: qsum[k] = sum_w max_t |Qhat_w(k, t)|.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_hscale_qmax(Plan p, const cplx<T>* qhat, float* qsum) {
+    __shared__ float part[kBlock];
+    const int k = blockIdx.x, nzh = p.nzh, W = p.n_cols, nt = p.n_time;
+    float acc = 0.0f;
+    for (int w = 0; w < W; ++w) {
+        float m = 0.0f;
+        for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+            const cplx<T> q = qhat[((size_t)t * W + w) * nzh + k];
+            m = fmaxf(m, (float)sqrt(q.re * q.re + q.im * q.im));
+        }
+        part[threadIdx.x] = m;
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) part[threadIdx.x] = fmaxf(part[threadIdx.x], part[threadIdx.x + h]);
+            __syncthreads();
+        }
+        acc += part[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) qsum[k] = acc;
+}
+
+// One workgroup: the bound B, then h_scale (workspace) and 1/h_scale (the
+// float after the values of H).
+__global__ void __launch_bounds__(kBlock)
+k_hscale_finish(int nzh, const unsigned* emax, const float* qsum, float* scale, float* decode) {
+    __shared__ double part[kBlock];
+    double b = 0.0;
+    for (int k = threadIdx.x; k < nzh; k += blockDim.x)
+        b += (k == 0 ? 1.0 : 2.0) * (double)__uint_as_float(emax[k]) * (double)qsum[k];
+    part[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double B = part[0];
+        int sc = 0;
+        if (B > 0.0 && isfinite(B)) {
+            sc = (int)floor(log2(16384.0 / B));
+            while (ldexp(B, sc) > 16384.0) --sc;          // guard the rounding of log2
+            sc = sc < -120 ? -120 : (sc > 120 ? 120 : sc);
+        }
+        scale[0] = ldexpf(1.0f, sc);
+        decode[0] = ldexpf(1.0f, -sc);
     }
 }
 
@@ -502,39 +597,46 @@ hipError_t field_table(const Plan& p, char* b, hipStream_t s) {
     return hipSuccess;
 }
 
-template <typename T, int N1, int N2, int WC>
+template <typename T, int N1, int N2, int WC, typename TO>
 hipError_t synthesis_pipe(const Plan& p, char* b, void* h, hipStream_t s) {
     constexpr int NZ = N1 * N2;
     const size_t lds = synthesis_pipe_lds(NZ, sizeof(T));
-    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_pipe<T, N1, N2, WC>,
+    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_pipe<T, N1, N2, WC, TO>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_synthesis_pipe<T, N1, N2, WC>), dim3(p.N[0] * p.N[1]), dim3(48 * N1), lds, s, p,
+    hipLaunchKernelGGL((k_synthesis_pipe<T, N1, N2, WC, TO>), dim3(p.N[0] * p.N[1]), dim3(48 * N1), lds, s, p,
                        reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
-                       reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]), static_cast<T*>(h));
+                       reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]),
+                       reinterpret_cast<const float*>(b + p.off_hscale), static_cast<TO*>(h));
     return hipGetLastError();
 }
 
-template <typename T, int N1, int N2>
+template <typename T, int N1, int N2, typename TO>
 hipError_t synthesis_pipe_w(const Plan& p, char* b, void* h, hipStream_t s) {
     switch (p.n_cols) {
-        case 1: return synthesis_pipe<T, N1, N2, 1>(p, b, h, s);
-        case 2: return synthesis_pipe<T, N1, N2, 2>(p, b, h, s);
-        case 3: return synthesis_pipe<T, N1, N2, 3>(p, b, h, s);
-        default: return synthesis_pipe<T, N1, N2, 4>(p, b, h, s);
+        case 1: return synthesis_pipe<T, N1, N2, 1, TO>(p, b, h, s);
+        case 2: return synthesis_pipe<T, N1, N2, 2, TO>(p, b, h, s);
+        case 3: return synthesis_pipe<T, N1, N2, 3, TO>(p, b, h, s);
+        default: return synthesis_pipe<T, N1, N2, 4, TO>(p, b, h, s);
+    }
+}
+
+template <typename T, typename TO>
+hipError_t synthesis_pipe_n(const Plan& p, char* b, void* h, hipStream_t s) {
+    switch (p.N[2]) {
+        case 64: return synthesis_pipe_w<T, 8, 8, TO>(p, b, h, s);
+        case 128: return synthesis_pipe_w<T, 8, 16, TO>(p, b, h, s);
+        default: return synthesis_pipe_w<T, 16, 16, TO>(p, b, h, s);
     }
 }
 
 template <typename T>
 hipError_t synthesis(const Plan& p, char* b, void* h, hipStream_t s) {
     if (p.synth_kernel == 2) {
-        switch (p.N[2]) {
-            case 64: return synthesis_pipe_w<T, 8, 8>(p, b, h, s);
-            case 128: return synthesis_pipe_w<T, 8, 16>(p, b, h, s);
-            case 256: return synthesis_pipe_w<T, 16, 16>(p, b, h, s);
-            default: break;
-        }
+        if constexpr (std::is_same<T, float>::value)
+            if (p.h_format == 1) return synthesis_pipe_n<T, _Float16>(p, b, h, s);
+        return synthesis_pipe_n<T, T>(p, b, h, s);
     }
     const size_t fixed = (size_t)p.n_cols * p.nzh * 3 * sizeof(cplx<T>) + (size_t)p.N[2] * p.tb * 3 * sizeof(T);
     const size_t budget = 160 * 1024;
@@ -556,6 +658,29 @@ hipError_t synthesis(const Plan& p, char* b, void* h, hipStream_t s) {
 hipError_t launch_field_table(const Plan& p, void* ws, hipStream_t s) {
     char* b = static_cast<char*>(ws);
     return p.precision == 0 ? field_table<double>(p, b, s) : field_table<float>(p, b, s);
+}
+
+hipError_t launch_h_scale(const Plan& p, void* ws, void* h, hipStream_t s) {
+    if (p.precision != 1) return hipErrorInvalidValue;
+    char* b = static_cast<char*>(ws);
+    float* scale = reinterpret_cast<float*>(b + p.off_hscale);
+    unsigned* emax = reinterpret_cast<unsigned*>(b + p.off_hscale + 64);
+    hipLaunchKernelGGL(k_hscale_clear, dim3(1), dim3(kBlock), 0, s, emax, p.nzh);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (kBlock % p.nzh != 0) return hipErrorInvalidValue;
+    const size_t n = (size_t)p.N[0] * p.N[1] * p.nzh;
+    const int grid = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 256);
+    hipLaunchKernelGGL(k_hscale_emax<float>, dim3(grid), dim3(kBlock), 0, s, p,
+                       reinterpret_cast<const cplx<float>*>(b + p.off_ehat), emax);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    float* qsum = reinterpret_cast<float*>(b + p.off_hscale + 64 + (size_t)p.nzh * sizeof(unsigned));
+    hipLaunchKernelGGL(k_hscale_qmax<float>, dim3(p.nzh), dim3(kBlock), 0, s, p,
+                       reinterpret_cast<const cplx<float>*>(b + p.off_qhat), qsum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hscale_finish, dim3(1), dim3(kBlock), 0, s, p.nzh, emax, qsum, scale,
+                       reinterpret_cast<float*>(static_cast<char*>(h) + p.h_values_bytes));
+    return hipGetLastError();
 }
 
 hipError_t launch_synthesis(const Plan& p, void* ws, void* h, hipStream_t s) {

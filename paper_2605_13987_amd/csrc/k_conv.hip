@@ -10,6 +10,8 @@
 // read as contiguous runs and the sum over steps stays in registers.
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace wt {
 
 namespace {
@@ -51,23 +53,38 @@ struct Step {
     T dx, dy, dz;
 };
 
-template <typename T>
-__device__ inline T step_value(const T* H, const Step<T>& s, int tau, int TB, int Nz, int last_block, int last_len) {
+template <typename T, typename TH>
+__device__ inline T step_value(const TH* H, const Step<T>& s, int tau, int TB, int Nz, int last_block, int last_len) {
     const int tb = tau / TB;
     const int tin = tau - tb * TB;
     const int len = tb == last_block ? last_len : TB;
     const size_t toff = (size_t)tb * TB * Nz * 3 + (size_t)tin * 3;
     const size_t o0 = toff + (size_t)s.z0 * len * 3, o1 = toff + (size_t)s.z1 * len * 3;
-    const T* h;
+    auto proj = [&](const TH* h) {
+        if constexpr (std::is_same<TH, _Float16>::value) {
+            // the three float16 components with one 8-byte load from the 4-byte
+            // aligned word below them (the buffer has at least 2 bytes after
+            // its last value)
+            const uintptr_t a = reinterpret_cast<uintptr_t>(h);
+            const unsigned long long w = *reinterpret_cast<const unsigned long long*>(a & ~(uintptr_t)3);
+            const unsigned long long v = w >> ((a & 2) * 8);
+            const T hx = (T)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu));
+            const T hy = (T)__builtin_bit_cast(_Float16, (unsigned short)((v >> 16) & 0xffffu));
+            const T hz = (T)__builtin_bit_cast(_Float16, (unsigned short)((v >> 32) & 0xffffu));
+            return hx * s.dx + hy * s.dy + hz * s.dz;
+        } else {
+            return (T)h[0] * s.dx + (T)h[1] * s.dy + (T)h[2] * s.dz;
+        }
+    };
     T v = (T)0;
-    h = H + s.b00 + o0; v += s.w[0] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
-    h = H + s.b00 + o1; v += s.w[1] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
-    h = H + s.b01 + o0; v += s.w[2] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
-    h = H + s.b01 + o1; v += s.w[3] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
-    h = H + s.b10 + o0; v += s.w[4] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
-    h = H + s.b10 + o1; v += s.w[5] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
-    h = H + s.b11 + o0; v += s.w[6] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
-    h = H + s.b11 + o1; v += s.w[7] * (h[0] * s.dx + h[1] * s.dy + h[2] * s.dz);
+    v += s.w[0] * proj(H + s.b00 + o0);
+    v += s.w[1] * proj(H + s.b00 + o1);
+    v += s.w[2] * proj(H + s.b01 + o0);
+    v += s.w[3] * proj(H + s.b01 + o1);
+    v += s.w[4] * proj(H + s.b10 + o0);
+    v += s.w[5] * proj(H + s.b10 + o1);
+    v += s.w[6] * proj(H + s.b11 + o0);
+    v += s.w[7] * proj(H + s.b11 + o1);
     return v;
 }
 
@@ -112,9 +129,11 @@ __device__ inline bool make_step(const Plan& p, const T* P, int m, T q, Step<T>&
 // over output samples n = lane + 64 j while the wavefront walks the moving
 // steps two at a time.  The four wavefronts of a workgroup add their partial
 // currents in LDS before one atomic flush when they carry the same track.
-template <typename T>
+// H is stored as TH: T, or float16 holding H * h_scale, whose sums are scaled
+// by decode = 1 / h_scale once per output sample.
+template <typename T, typename TH>
 __global__ void __launch_bounds__(kBlock)
-k_current(Plan p, const T* H, int n_carriers, int n_tracks, const T* pos, const T* charge,
+k_current(Plan p, const TH* H, const float* decode, int n_carriers, int n_tracks, const T* pos, const T* charge,
           const int* track, T* out) {
     __shared__ short steps[kBlock / kWave][kMaxTime];
     __shared__ T part[kBlock / kWave][kMaxTime];
@@ -171,6 +190,11 @@ k_current(Plan p, const T* H, int n_carriers, int n_tracks, const T* pos, const 
             }
         }
     }
+    if constexpr (!std::is_same<T, TH>::value) {
+        const T dec = (T)decode[0];
+#pragma unroll
+        for (int j = 0; j < kMaxJ; ++j) acc[j] *= dec;
+    }
     // workgroup reduction when all four wavefronts carry the same track
     if (lane == 0) wtrack[wv] = tr;
     __syncthreads();
@@ -193,7 +217,7 @@ k_current(Plan p, const T* H, int n_carriers, int n_tracks, const T* pos, const 
     }
 }
 
-template <typename T>
+template <typename T, typename TH>
 hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, const void* pos,
                    const void* charge, const int* track, void* out, hipStream_t s) {
     const size_t n_out = (size_t)n_tracks * p.n_time;
@@ -202,8 +226,9 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n_carriers == 0) return e;
     const int blocks = (n_carriers + kBlock / kWave - 1) / (kBlock / kWave);
-    hipLaunchKernelGGL(k_current<T>, dim3(blocks), dim3(kBlock), 0, s, p, static_cast<const T*>(h), n_carriers,
-                       n_tracks, static_cast<const T*>(pos), static_cast<const T*>(charge), track,
+    const float* decode = reinterpret_cast<const float*>(static_cast<const char*>(h) + p.h_values_bytes);
+    hipLaunchKernelGGL((k_current<T, TH>), dim3(blocks), dim3(kBlock), 0, s, p, static_cast<const TH*>(h), decode,
+                       n_carriers, n_tracks, static_cast<const T*>(pos), static_cast<const T*>(charge), track,
                        static_cast<T*>(out));
     return hipGetLastError();
 }
@@ -212,8 +237,9 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
 
 hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks, const void* pos,
                           const void* charge, const int* track, void* out, hipStream_t s) {
-    return p.precision == 0 ? current<double>(p, h, n_carriers, n_tracks, pos, charge, track, out, s)
-                            : current<float>(p, h, n_carriers, n_tracks, pos, charge, track, out, s);
+    if (p.precision == 0) return current<double, double>(p, h, n_carriers, n_tracks, pos, charge, track, out, s);
+    if (p.h_format == 1) return current<float, _Float16>(p, h, n_carriers, n_tracks, pos, charge, track, out, s);
+    return current<float, float>(p, h, n_carriers, n_tracks, pos, charge, track, out, s);
 }
 
 }  // namespace wt

@@ -29,6 +29,8 @@ WT_E_NOT_CONVERGED = -6
 WT_E_HIP = -7
 WT_F64 = 0
 WT_F32 = 1
+WT_H_PLAIN = 0
+WT_H_F16_SCALED = 1
 
 
 class WtError(RuntimeError):
@@ -58,18 +60,19 @@ class wt_spectrum(ctypes.Structure):
 
 
 class wt_h_options(ctypes.Structure):
-    _fields_ = [("precision", c_int), ("ir_max_iter", c_int), ("ir_tol", c_double)]
+    _fields_ = [("precision", c_int), ("ir_max_iter", c_int), ("ir_tol", c_double), ("h_format", c_int)]
 
 
 class wt_h_report(ctypes.Structure):
     _fields_ = [("backward_error_max", c_double), ("pivot_ratio_max", c_double),
-                ("ir_iters_max", c_int), ("singular_count", c_int)]
+                ("ir_iters_max", c_int), ("singular_count", c_int), ("h_scale", c_double)]
 
 
 class wt_h_layout(ctypes.Structure):
     _fields_ = [("workspace_bytes", c_size_t), ("h_bytes", c_size_t), ("h_time_block", c_int),
                 ("n_q", c_int), ("off_A", c_size_t), ("off_qw", c_size_t), ("off_qt", c_size_t),
-                ("off_qhat", c_size_t), ("off_ehat", c_size_t)]
+                ("off_qhat", c_size_t), ("off_ehat", c_size_t), ("h_format", c_int),
+                ("h_decode_offset", c_size_t)]
 
 
 class wt_carriers(ctypes.Structure):
@@ -188,12 +191,12 @@ def layout_dict(layout: wt_h_layout) -> dict:
 
 
 def wt_h_plan_create(cell: dict, columns, spectrum: dict, precision: int = WT_F32,
-                     ir_max_iter: int = 2, ir_tol: float = 1e-12):
+                     ir_max_iter: int = 2, ir_tol: float = 1e-12, h_format: int = WT_H_PLAIN):
     """Returns (plan handle, layout dict)."""
     plan = c_void_p()
     lay = wt_h_layout()
     sp = wt_spectrum(spectrum["n_freq"], spectrum["df"], spectrum["n_time"], spectrum["dt"])
-    opt = wt_h_options(int(precision), int(ir_max_iter), float(ir_tol))
+    opt = wt_h_options(int(precision), int(ir_max_iter), float(ir_tol), int(h_format))
     cols = make_columns(columns)
     _check(LIB.wt_h_plan_create(ctypes.byref(make_cell(cell)), cols, len(columns), ctypes.byref(sp),
                                 ctypes.byref(opt), ctypes.byref(plan), ctypes.byref(lay)), "wt_h_plan_create")
@@ -201,12 +204,12 @@ def wt_h_plan_create(cell: dict, columns, spectrum: dict, precision: int = WT_F3
 
 
 def wt_h_plan_create_status(cell: dict, columns, spectrum: dict, precision: int = WT_F32,
-                            ir_max_iter: int = 2, ir_tol: float = 1e-12) -> int:
+                            ir_max_iter: int = 2, ir_tol: float = 1e-12, h_format: int = WT_H_PLAIN) -> int:
     """Status code of plan creation (the plan, if any, is destroyed)."""
     plan = c_void_p()
     lay = wt_h_layout()
     sp = wt_spectrum(spectrum["n_freq"], spectrum["df"], spectrum["n_time"], spectrum["dt"])
-    opt = wt_h_options(int(precision), int(ir_max_iter), float(ir_tol))
+    opt = wt_h_options(int(precision), int(ir_max_iter), float(ir_tol), int(h_format))
     cols = make_columns(columns)
     st = LIB.wt_h_plan_create(ctypes.byref(make_cell(cell)), cols, len(columns), ctypes.byref(sp),
                               ctypes.byref(opt), ctypes.byref(plan), ctypes.byref(lay))

@@ -26,18 +26,27 @@ def context():
     return wt.wt_context_create(0, torch.cuda.current_stream().cuda_stream)
 
 
-def solve_h(ctx, cfg, precision, ir_max_iter=2, ir_tol=1e-12):
+def solve_h(ctx, cfg, precision, ir_max_iter=2, ir_tol=1e-12, h_format=wt.WT_H_PLAIN):
     say(f"  wt_h_solve {cfg['name']} grid={cfg['cell']['N']} nf={cfg['spectrum']['n_freq']} "
-        f"nt={cfg['spectrum']['n_time']} precision={precision}")
+        f"nt={cfg['spectrum']['n_time']} precision={precision} h_format={h_format}")
     plan, lay = wt.wt_h_plan_create(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=precision,
-                                    ir_max_iter=ir_max_iter, ir_tol=ir_tol)
+                                    ir_max_iter=ir_max_iter, ir_tol=ir_tol, h_format=h_format)
     ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
-    esz = 8 if precision == wt.WT_F64 else 4
-    h = torch.empty(lay["h_bytes"] // esz, dtype=dtype_of(precision), device="cuda")
-    st, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"], report=True,
+    hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
+    st, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True,
                             raise_on_error=False)
     torch.cuda.synchronize()
-    return dict(plan=plan, layout=lay, ws=ws, h=h, status=st, report=rep, precision=precision)
+    N = cfg["cell"]["N"]
+    n_values = N[0] * N[1] * N[2] * cfg["spectrum"]["n_time"] * 3
+    if h_format == wt.WT_H_F16_SCALED:
+        h = hbuf[:n_values * 2].view(torch.float16)
+        off = lay["h_decode_offset"]
+        decode = float(hbuf[off:off + 4].view(torch.float32).item())
+    else:
+        h = hbuf.view(dtype_of(precision))
+        decode = 1.0
+    return dict(plan=plan, layout=lay, ws=ws, h=h, hbuf=hbuf, decode=decode, h_format=h_format, status=st,
+                report=rep, precision=precision)
 
 
 def ws_array(ws, offset, count, np_dtype):
@@ -60,8 +69,8 @@ def intermediates(run, cfg):
 def h_standard(run, cfg):
     """Whole H on the host in [x][y][z][t][a] order (small grids)."""
     lay = run["layout"]
-    return layout.to_standard(run["h"].cpu().numpy(), cfg["cell"]["N"], cfg["spectrum"]["n_time"],
-                              lay["h_time_block"])
+    vals = run["h"].cpu().numpy().astype(np.float64) * run["decode"]
+    return layout.to_standard(vals, cfg["cell"]["N"], cfg["spectrum"]["n_time"], lay["h_time_block"])
 
 
 def h_columns(run, cfg, cols_ij):
@@ -70,7 +79,7 @@ def h_columns(run, cfg, cols_ij):
     nt = cfg["spectrum"]["n_time"]
     per = N[2] * nt * 3
     idx = torch.tensor([i * N[1] + j for i, j in cols_ij], device="cuda")
-    cols = run["h"].view(-1, per).index_select(0, idx).cpu().numpy()
+    cols = run["h"].view(-1, per).index_select(0, idx).cpu().numpy().astype(np.float64) * run["decode"]
     return layout.to_standard(cols, N, nt, run["layout"]["h_time_block"])
 
 

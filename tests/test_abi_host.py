@@ -132,3 +132,26 @@ def test_binding_leaves_one_hip_runtime_in_the_process():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_f16_scaled_layout_and_validation():
+    cfg = workloads.uniform_pixel_32x32x64()
+    plan, lay = wt.wt_h_plan_create(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=wt.WT_F32,
+                                    h_format=wt.WT_H_F16_SCALED)
+    wt.wt_h_plan_destroy(plan)
+    n = 32 * 32 * 64 * 64 * 3
+    assert lay["h_format"] == wt.WT_H_F16_SCALED
+    assert lay["h_decode_offset"] == (n * 2 + 255) // 256 * 256
+    assert lay["h_bytes"] == lay["h_decode_offset"] + 256
+    plain = wt.wt_h_plan_create(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=wt.WT_F32)
+    wt.wt_h_plan_destroy(plain[0])
+    assert plain[1]["h_decode_offset"] == 0 and plain[1]["h_bytes"] == n * 4
+    # float16 H needs the float path
+    assert wt.wt_h_plan_create_status(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=wt.WT_F64,
+                                      h_format=wt.WT_H_F16_SCALED) == wt.WT_E_INVALID_ARG
+    assert wt.wt_h_plan_create_status(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=wt.WT_F32,
+                                      h_format=7) == wt.WT_E_INVALID_ARG
+    # and the register-FFT synthesis sizes
+    small = workloads.small_pixel(k=41, n_xy=24, n_z=40, n_freq=4, n_time=10, n_pairs=5, n_colloc=8)
+    assert wt.wt_h_plan_create_status(small["cell"], small["columns"], small["spectrum"], precision=wt.WT_F32,
+                                      h_format=wt.WT_H_F16_SCALED) == wt.WT_E_UNSUPPORTED_SIZE

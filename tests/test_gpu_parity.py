@@ -62,6 +62,7 @@ SMALL = [
     (24, 40, 12, 40, 16),
     (30, 60, 9, 37, 20),
     (20, 20, 5, 70, 8),
+    (16, 128, 6, 37, 12),     # register-FFT synthesis with N_z = 8 x 16 and a ragged last block
 ]
 
 
