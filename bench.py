@@ -29,12 +29,13 @@ if ROOT not in sys.path:
 METRIC = "H(x,t) grid·freq pts/s + carrier tracks/s, mixed vs plain FP64 at stated rel err"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of k_synthesis_reg on this workload: rocprofv3
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB device-to-device
-# copy gives for the same counters), in profiles/k_synthesis_reg_128x128x256_f32.md.
-# Reported only while the kernel's sources are the ones it was measured on.
-SYNTH_TRAFFIC_BYTES = 10170317389
-SYNTH_TRAFFIC_SOURCES_SHA256 = "a4ffdb59a581108b1eb0c23474b58c308a023168c7f86cb296da28032145f7de"
+# HBM bytes per launch of k_synthesis_pipe on this workload (float32 H, float16
+# H): rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB
+# device-to-device copy gives for the same counters), in
+# profiles/k_synthesis_pipe_128x128x256.md.  Reported only while the kernel's
+# sources are the ones they were measured on.
+SYNTH_TRAFFIC_BYTES = {"plain": 10170298291, "mixed": 5136785203}
+SYNTH_TRAFFIC_SOURCES_SHA256 = "b1896e1a8dbf3d1e06b2308116171e51f0c2183416b2dc76cda4eba630dac943"
 SYNTH_SOURCES = ("k_bulk.hip", "fft.hpp", "common.hpp")
 
 
@@ -244,8 +245,9 @@ def main():
     i_err_mixed = float(np.linalg.norm(i_mixed - i_plain) / np.linalg.norm(i_plain))
 
     stage, ms = plain["stage"], plain["ms"]
-    traffic = (SYNTH_TRAFFIC_BYTES if list(N) == [128, 128, 256] and spec["n_time"] == 200 and w == 2
-               and synthesis_sources_sha256() == SYNTH_TRAFFIC_SOURCES_SHA256 else None)
+    measured = (list(N) == [128, 128, 256] and spec["n_time"] == 200 and w == 2
+                and synthesis_sources_sha256() == SYNTH_TRAFFIC_SOURCES_SHA256)
+    traffic = SYNTH_TRAFFIC_BYTES["plain"] if measured else None
     line = {
         "metric": METRIC,
         "value": n_pts * spec["n_freq"] / (ms * 1e-3),
@@ -286,7 +288,8 @@ def main():
             "stage_ms": {k: round(v, 4) for k, v in mixed["stage"].items()},
             "roofline": {"kernel": "k_synthesis_pipe (float16 H)", "bound": "hbm", "achieved": mixed["achieved"],
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": mixed["achieved"] / HBM_PEAK_GBS,
-                         "bytes_per_launch": mixed["synth_bytes"]},
+                         "traffic": SYNTH_TRAFFIC_BYTES["mixed"] if measured else None,
+                         "traffic_unit": "bytes/launch", "bytes_per_launch": mixed["synth_bytes"]},
             "rel_err": {"i_vs_float32_path": i_err_mixed},
         },
     }
