@@ -139,6 +139,41 @@ def cpu_baseline(cfg, gpu_columns, budget_s):
                 carriers_per_s=n_done / t_conv), err
 
 
+def current_compulsory_bytes(cfg, elem_bytes):
+    """Compulsory HBM bytes of the Eq. 1 convolution: every node that is a
+    trilinear corner of some moving step, times the lags it is read for (a
+    step at m reads lags 0..N_t-1-m), times 3 components, plus 24 B per step
+    (midpoint and displacement) and the output.  Returns (bytes, steps)."""
+    import numpy as np
+
+    cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
+    N, L, nt = cell["N"], cell["L"], spec["n_time"]
+    P = np.asarray(car["pos"], dtype=np.float32).astype(np.float64)
+    d = P[:, 1:, :] - P[:, :-1, :]
+    moving = np.any(d != 0, axis=2)
+    c_idx, m_idx = np.nonzero(moving)
+    mid = 0.5 * (P[c_idx, m_idx, :] + P[c_idx, m_idx + 1, :]) * (np.asarray(N) / np.asarray(L))
+    lo = np.floor(mid).astype(np.int64)
+    lags = nt - m_idx
+    node = np.empty(0, dtype=np.int64)
+    need = np.empty(0, dtype=np.int64)
+    for ox in (0, 1):
+        for oy in (0, 1):
+            for oz in (0, 1):
+                x = (lo[:, 0] + ox) % N[0]
+                y = (lo[:, 1] + oy) % N[1]
+                z = (lo[:, 2] + oz) % N[2]
+                node = np.concatenate([node, (x * N[1] + y) * N[2] + z])
+                need = np.concatenate([need, lags])
+    order = np.lexsort((-need, node))
+    node, need = node[order], need[order]
+    first = np.ones(node.size, dtype=bool)
+    first[1:] = node[1:] != node[:-1]
+    h_bytes = int(need[first].sum()) * 3 * elem_bytes
+    n_steps = int(c_idx.size)
+    return h_bytes + 24 * n_steps + car["n_tracks"] * nt * 4, n_steps
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -240,6 +275,30 @@ def main():
 
     plain = run_path(wt.WT_H_PLAIN)
     mixed = run_path(wt.WT_H_F16_SCALED)
+    cur_bytes, n_steps = current_compulsory_bytes(cfg, 4)
+    cur_bytes16, _ = current_compulsory_bytes(cfg, 2)
+    # FP64 boundary fit with M = 256 nodes per column (n = 513) at 512
+    # frequencies to 50 GHz: the solve of the 50x50x300 um cell does not depend
+    # on the grid (converged Green's function), so a small grid carries it
+    m256 = workloads.small_pixel(k=48, n_xy=32, n_z=64, n_freq=512, n_time=16, n_pairs=1, n_colloc=256)
+    plan_m, lay_m = wt.wt_h_plan_create(m256["cell"], m256["columns"], m256["spectrum"], precision=wt.WT_F32,
+                                        ir_max_iter=2, ir_tol=1e-12)
+    ws_m = torch.empty(lay_m["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    h_m = torch.empty(lay_m["h_bytes"], dtype=torch.uint8, device="cuda")
+    _, rep_m = wt.wt_h_solve(ctx, plan_m, ws_m.data_ptr(), ws_m.numel(), h_m.data_ptr(), lay_m["h_bytes"],
+                             report=True, raise_on_error=False)
+    wt.wt_context_enable_timing(ctx, True)
+    t_m = []
+    for _ in range(3):
+        wt.wt_h_solve(ctx, plan_m, ws_m.data_ptr(), ws_m.numel(), h_m.data_ptr(), lay_m["h_bytes"])
+        t_m.append(dict(wt.wt_context_stage_times(ctx))["collocation_solve"])
+    wt.wt_context_enable_timing(ctx, False)
+    wt.wt_h_plan_destroy(plan_m)
+    del ws_m, h_m
+    solve_m256 = {"n_unknowns": lay_m["n_q"] + 1, "n_freq": 512, "ms": float(np.median(t_m)),
+                  "backward_error_max": rep_m["backward_error_max"], "ir_iters_max": rep_m["ir_iters_max"]}
+    print(f"# M = 256 solve: {solve_m256}", file=sys.stderr, flush=True)
+
     i_plain = plain["out"].double().cpu().numpy()
     i_mixed = mixed["out"].double().cpu().numpy()
     i_err_mixed = float(np.linalg.norm(i_mixed - i_plain) / np.linalg.norm(i_plain))
@@ -271,6 +330,10 @@ def main():
         },
         "tracks_per_s": n_tr / plain["t_cur"],
         "carriers_per_s": n_c / plain["t_cur"],
+        "events_per_s": n_steps / plain["t_cur"],
+        "current_roofline": {"kernel": "k_current", "bound": "hbm", "compulsory_bytes": cur_bytes,
+                             "achieved": cur_bytes / plain["t_cur"] / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": cur_bytes / plain["t_cur"] / 1e9 / HBM_PEAK_GBS, "moving_steps": n_steps},
         "h_grid_freq_pts_per_s": n_pts * spec["n_freq"] / plain["t_h"],
         "h_grid_time_pts_per_s": n_pts * spec["n_time"] / plain["t_h"],
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
@@ -278,12 +341,15 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": plain["achieved"] / HBM_PEAK_GBS,
                      "traffic": traffic, "traffic_unit": "bytes/launch", "bytes_per_launch": plain["synth_bytes"]},
         "solve_report": plain["rep"],
+        "solve_m256": solve_m256,
         "mixed": {
             "h_storage": "float16 holding H * h_scale (h_scale a power of two), decoded in float32",
             "h_scale": mixed["rep"]["h_scale"],
             "value": n_pts * spec["n_freq"] / (mixed["ms"] * 1e-3),
             "ms_per_step": mixed["ms"],
             "tracks_per_s": n_tr / mixed["t_cur"],
+            "events_per_s": n_steps / mixed["t_cur"],
+            "current_compulsory_gbs": cur_bytes16 / mixed["t_cur"] / 1e9,
             "h_grid_freq_pts_per_s": n_pts * spec["n_freq"] / mixed["t_h"],
             "stage_ms": {k: round(v, 4) for k, v in mixed["stage"].items()},
             "roofline": {"kernel": "k_synthesis_pipe (float16 H)", "bound": "hbm", "achieved": mixed["achieved"],

@@ -194,3 +194,33 @@ def test_stage_timing(ctx, px32):
         assert [n for n, _ in st] == ["current"] and st[0][1] > 0
     finally:
         wt.wt_context_enable_timing(ctx, False)
+
+
+def test_m256_collocation_global_lu(ctx):
+    """M = 256 collocation nodes per column (n = 513 unknowns): the global-memory
+    LU path.  cond(A) is ~1e8 here, so the charges are held to the backward
+    error (<= 1e-13) and to 50 cond(S) eps against the oracle, H to the float32
+    bar."""
+    cfg = workloads.small_pixel(k=47, n_xy=16, n_z=64, n_freq=4, n_time=16, n_pairs=10, n_colloc=256)
+    say("test_m256_collocation_global_lu")
+    ref = oracle.weighting_field(cfg["cell"], cfg["columns"], cfg["spectrum"])
+    run = solve_h(ctx, cfg, wt.WT_F32)
+    assert run["status"] == wt.WT_OK, run["report"]
+    assert run["layout"]["n_q"] == 512
+    assert run["report"]["backward_error_max"] <= 1e-13
+    im = intermediates(run, cfg)
+    assert np.max(np.abs(im["A"] - ref["A"])) <= 1e-12 * np.max(np.abs(ref["A"]))
+    from oracle import collocation, green
+    eps_c = green.permittivity(cfg["cell"])
+    nq = ref["A"].shape[0]
+    a = np.max(np.abs(np.diag(ref["A"])))
+    cond = 0.0
+    for wj in collocation.angular_frequencies(cfg["spectrum"]):
+        S = collocation.frequency_system(ref["A"], cfg["columns"], wj, eps_c)[0]
+        S[:, :nq] /= a                      # the equilibrated system that is solved
+        S[nq, :] *= a
+        cond = max(cond, np.linalg.cond(S))
+    err_q = rel_l2(im["q"], ref["q"])
+    say(f"  cond(S) {cond:.2e}, q rel L2 {err_q:.2e}")
+    assert err_q <= max(1e-10, 50 * cond * np.finfo(float).eps)
+    assert rel_l2(h_standard(run, cfg), ref["H"]) <= H_TOL[wt.WT_F32]
