@@ -25,6 +25,9 @@ What it computes (paper: abstract, Eq. 1 in the introduction, Section 3):
 * ``convolution`` Eq. 1 discretised per carrier step: midpoint position,
                   displacement for v dt', rectangle rule in the lag, trilinear
                   interpolation of the grid field with periodic wrap.
+* ``electronics`` the currents convolved with a front-end impulse response,
+                  plus noise, and per-track timing features (amplitude, peak
+                  time, constant-fraction time).
 
 Pins (tests marked "not gpu"): Ewald sums for G and E_G; the direct G against
 the nested collocation sums; the compact RC-line system against a Kirchhoff
@@ -32,11 +35,14 @@ the nested collocation sums; the compact RC-line system against a Kirchhoff
 zero frequency; the electrode-sum rule; the full-period identity of the time
 quadrature; the textbook Ramo-Shockley limit for perfectly conducting columns;
 passivity and causality; the three field routes against each other; charge
-conservation of the convolution; brute-force loops for the convolution.
+conservation of the convolution; brute-force loops for the convolution; the
+closed-form convolution of two sampled exponentials, the identity response,
+a sampled parabola's vertex and a linear ramp's constant-fraction crossing for
+the electronics.
 
 Parity unpinned: none of the computed quantities.  The modelling readings
 themselves (thin-wire columns, smoothing widths, periodic z, collocation
 azimuth, column permittivity) are choices, not results, and are not pinned.
 """
-from . import green, collocation, timegrid, field, convolution  # noqa: F401
+from . import green, collocation, timegrid, field, convolution, electronics  # noqa: F401
 from .pipeline import weighting_field, induced_current  # noqa: F401
