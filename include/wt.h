@@ -218,6 +218,29 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h,
                      const wt_carriers* carriers, void* d_workspace, size_t workspace_bytes,
                      void* d_i_out);
 
+/* Readout electronics and timing features (the workflow's last step,
+ * Section 2: the induced signals convolved with the transfer function of the
+ * readout electronics, plus noise; the front-end model is the caller's).
+ * For every track k and sample n < n_time:
+ *   v[k][n] = dt * sum_{m<=n} g[n-m] i[k][m] + noise_sigma * noise[k][n]
+ * and features[k] = {A, t_peak, t_cfd}:
+ *   n_p = the first index of max_n |v[k][n]|, A = v[k][n_p] (signed);
+ *   with u = sign(A) v: t_peak = (n_p + d) dt, d the vertex offset of the
+ *     parabola through u[n_p-1], u[n_p], u[n_p+1] (0 at the ends of the
+ *     record or where those samples are not concave);
+ *   t_cfd = the last upward crossing of cfd_fraction * |A| by u before n_p,
+ *     interpolated linearly between samples (NaN if none, or if A = 0).
+ * Device arrays: d_current [n_tracks][n_time] (as written by wt_current),
+ * d_response [n_time] (the sampled impulse response g, 1/s), d_noise
+ * [n_tracks][n_time] (e.g. standard normal samples; NULL for none),
+ * d_signal [n_tracks][n_time] and d_features [n_tracks][3] (overwritten).
+ * Element type double (WT_F64) or float (WT_F32).  n_tracks >= 1, n_time
+ * 1..512, dt > 0, noise_sigma >= 0, 0 < cfd_fraction < 1; otherwise
+ * WT_E_INVALID_ARG (n_time > 512: WT_E_UNSUPPORTED_SIZE). */
+wt_status wt_electronics(wt_context* ctx, int precision, int n_tracks, int n_time, double dt,
+                         const void* d_current, const void* d_response, const void* d_noise, double noise_sigma,
+                         double cfd_fraction, void* d_signal, void* d_features);
+
 const char* wt_status_string(wt_status status);
 
 #ifdef __cplusplus

@@ -444,4 +444,22 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, co
     return WT_OK;
 }
 
+wt_status wt_electronics(wt_context* ctx, int precision, int n_tracks, int n_time, double dt, const void* d_current,
+                         const void* d_response, const void* d_noise, double noise_sigma, double cfd_fraction,
+                         void* d_signal, void* d_features) {
+    if (!ctx || !d_current || !d_response || !d_signal || !d_features) return WT_E_INVALID_ARG;
+    if (precision != WT_F64 && precision != WT_F32) return WT_E_INVALID_ARG;
+    if (n_tracks < 1 || n_time < 1 || !pos_finite(dt)) return WT_E_INVALID_ARG;
+    if (!(noise_sigma >= 0.0) || !std::isfinite(noise_sigma)) return WT_E_INVALID_ARG;
+    if (!(cfd_fraction > 0.0 && cfd_fraction < 1.0)) return WT_E_INVALID_ARG;
+    if (n_time > wt::kMaxTime) return WT_E_UNSUPPORTED_SIZE;
+    wt_status st = bind(ctx);
+    if (st != WT_OK) return st;
+    ctx->n_events = 0;
+    WT_HIP(ctx, wt::launch_electronics(precision, n_tracks, n_time, dt, d_current, d_response, d_noise, noise_sigma,
+                                       cfd_fraction, d_signal, d_features, ctx->stream),
+           "electronics");
+    return WT_OK;
+}
+
 }  // extern "C"

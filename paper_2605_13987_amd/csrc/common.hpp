@@ -95,6 +95,8 @@ hipError_t launch_time_transform(const Plan& p, void* ws, hipStream_t s);
 hipError_t launch_field_table(const Plan& p, void* ws, hipStream_t s);
 hipError_t launch_h_scale(const Plan& p, void* ws, void* h, hipStream_t s);
 hipError_t launch_synthesis(const Plan& p, void* ws, void* h, hipStream_t s);
+hipError_t launch_electronics(int precision, int n_tracks, int nt, double dt, const void* cur, const void* g,
+                              const void* noise, double sigma, double frac, void* v, void* feat, hipStream_t s);
 hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks,
                           const void* pos, const void* charge, const int* track,
                           void* out, hipStream_t s);

@@ -343,3 +343,16 @@ def describe(cfg):
     return (f"{cfg['name']}: grid {c['N'][0]}x{c['N'][1]}x{c['N'][2]}, "
             f"{s['n_freq']} freq, {s['n_time']} x {s['dt'] / PS:.0f} ps, "
             f"{cfg['carriers']['pos'].shape[0]} carriers")
+
+
+def cr_rc_response(n_time, dt, tau=250 * PS, gain=1.0e3):
+    """Sampled impulse response (ohm/s) of a CR-RC front end: transimpedance
+    `gain` (ohm, the integral of the response) and shaping time tau, sampled
+    on t_n = n dt: gain * t / tau^2 * exp(-t / tau)."""
+    t = np.arange(n_time) * dt
+    return gain * t / tau ** 2 * np.exp(-t / tau)
+
+
+def noise_samples(k, n_tracks, n_time):
+    """Seeded standard normal samples for the electronics noise."""
+    return rng_for(k).standard_normal((n_tracks, n_time))

@@ -107,6 +107,8 @@ def _load():
         "wt_h_plan_layout": (c_int, [c_void_p, P(wt_h_layout)]),
         "wt_h_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_h_report)]),
         "wt_current": (c_int, [c_void_p, c_void_p, c_void_p, P(wt_carriers), c_void_p, c_size_t, c_void_p]),
+        "wt_electronics": (c_int, [c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
+                                   c_double, c_double, c_void_p, c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -250,3 +252,15 @@ def wt_current(ctx, plan, d_h: int, n_carriers: int, n_tracks: int, d_pos: int, 
     car = wt_carriers(int(n_carriers), int(n_tracks), c_void_p(d_pos), c_void_p(d_charge), c_void_p(d_track))
     _check(LIB.wt_current(ctx, plan, c_void_p(d_h), ctypes.byref(car), c_void_p(d_workspace or None),
                           int(workspace_bytes), c_void_p(d_i_out)), "wt_current", ctx)
+
+
+def wt_electronics(ctx, precision: int, n_tracks: int, n_time: int, dt: float, d_current: int, d_response: int,
+                   d_noise: int, noise_sigma: float, cfd_fraction: float, d_signal: int, d_features: int,
+                   raise_on_error: bool = True) -> int:
+    """Front-end response, noise and timing features of the currents (device arrays)."""
+    st = LIB.wt_electronics(ctx, int(precision), int(n_tracks), int(n_time), float(dt), c_void_p(d_current),
+                            c_void_p(d_response), c_void_p(d_noise or None), float(noise_sigma),
+                            float(cfd_fraction), c_void_p(d_signal), c_void_p(d_features))
+    if raise_on_error:
+        _check(st, "wt_electronics", ctx)
+    return st
