@@ -299,6 +299,30 @@ def main():
                   "backward_error_max": rep_m["backward_error_max"], "ir_iters_max": rep_m["ir_iters_max"]}
     print(f"# M = 256 solve: {solve_m256}", file=sys.stderr, flush=True)
 
+    # readout electronics on the plain path's current: CR-RC front end
+    # (tau = 250 ps, 1 kohm), seeded noise, constant fraction 0.5
+    g_e = torch.from_numpy(workloads.cr_rc_response(spec["n_time"], spec["dt"])).to("cuda", torch.float32)
+    n_e = torch.from_numpy(workloads.noise_samples(31, n_tr, spec["n_time"])).to("cuda", torch.float32)
+    v_e = torch.empty((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
+    f_e = torch.empty((n_tr, 3), dtype=torch.float32, device="cuda")
+    sigma_e = 1e-2 * float(plain["out"].abs().max().item()) * 1e3   # 1% of the peak current through 1 kohm
+
+    def elec():
+        wt.wt_electronics(ctx, wt.WT_F32, n_tr, spec["n_time"], spec["dt"], plain["out"].data_ptr(), g_e.data_ptr(),
+                          n_e.data_ptr(), sigma_e, 0.5, v_e.data_ptr(), f_e.data_ptr())
+
+    elec()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        elec()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    electronics = {"ms": e0.elapsed_time(e1) / 10, "n_tracks": n_tr,
+                   "features_first_track": {"amplitude_V": float(f_e[0, 0]), "t_peak_s": float(f_e[0, 1]),
+                                            "t_cfd_s": float(f_e[0, 2])}}
+
     i_plain = plain["out"].double().cpu().numpy()
     i_mixed = mixed["out"].double().cpu().numpy()
     i_err_mixed = float(np.linalg.norm(i_mixed - i_plain) / np.linalg.norm(i_plain))
@@ -342,6 +366,7 @@ def main():
                      "traffic": traffic, "traffic_unit": "bytes/launch", "bytes_per_launch": plain["synth_bytes"]},
         "solve_report": plain["rep"],
         "solve_m256": solve_m256,
+        "electronics": electronics,
         "mixed": {
             "h_storage": "float16 holding H * h_scale (h_scale a power of two), decoded in float32",
             "h_scale": mixed["rep"]["h_scale"],
