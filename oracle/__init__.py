@@ -28,6 +28,9 @@ What it computes (paper: abstract, Eq. 1 in the introduction, Section 3):
 * ``electronics`` the currents convolved with a front-end impulse response,
                   plus noise, and per-track timing features (amplitude, peak
                   time, constant-fraction time).
+* ``timedomain``  the paper's own forward-Euler time stepping of the boundary
+                  charges on the same RC-line model, as a cross-check of the
+                  frequency-domain solve.
 
 Pins (tests marked "not gpu"): Ewald sums for G and E_G; the direct G against
 the nested collocation sums; the compact RC-line system against a Kirchhoff
@@ -38,11 +41,13 @@ passivity and causality; the three field routes against each other; charge
 conservation of the convolution; brute-force loops for the convolution; the
 closed-form convolution of two sampled exponentials, the identity response,
 a sampled parabola's vertex and a linear ramp's constant-fraction crossing for
-the electronics.
+the electronics; for the time-domain scheme, its transfer function against
+the collocation system, its zero- and infinite-time limits, and first-order
+convergence of forward Euler to the exact step response.
 
 Parity unpinned: none of the computed quantities.  The modelling readings
 themselves (thin-wire columns, smoothing widths, periodic z, collocation
 azimuth, column permittivity) are choices, not results, and are not pinned.
 """
-from . import green, collocation, timegrid, field, convolution, electronics  # noqa: F401
+from . import green, collocation, timegrid, field, convolution, electronics, timedomain  # noqa: F401
 from .pipeline import weighting_field, induced_current  # noqa: F401
