@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", type=int, default=64,
+                    help="geometry variants in the batched (graph-captured) measurement; 0 skips it")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="approximate CPU time of the oracle baseline sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -172,6 +174,76 @@ def current_compulsory_bytes(cfg, elem_bytes):
     h_bytes = int(need[first].sum()) * 3 * elem_bytes
     n_steps = int(c_idx.size)
     return h_bytes + 24 * n_steps + car["n_tracks"] * nt * 4, n_steps
+
+
+def batched_variants(wt, workloads, torch, n_variants, replays):
+    """The geometry-variant batch: n_variants seeded cells of uneven grids and
+    frequency counts, each a full step (H solve + current of its track), run
+    eagerly and as one captured HIP graph on one stream, sharing one workspace
+    and one H buffer sized for the largest variant."""
+    import numpy as np
+
+    variants = [workloads.geometry_variant(k) for k in range(n_variants)]
+    stream = torch.cuda.Stream()
+    ctx = wt.wt_context_create(0, stream.cuda_stream)
+    items, ws_bytes, h_bytes, pts = [], 0, 0, 0
+    for v in variants:
+        plan, lay = wt.wt_h_plan_create(v["cell"], v["columns"], v["spectrum"], precision=wt.WT_F32)
+        car = v["carriers"]
+        N = v["cell"]["N"]
+        items.append(dict(plan=plan, lay=lay,
+                          pos=torch.from_numpy(car["pos"]).to("cuda", torch.float32),
+                          q=torch.from_numpy(car["charge"]).to("cuda", torch.float32),
+                          tr=torch.from_numpy(car["track"]).to("cuda"),
+                          out=torch.empty((car["n_tracks"], v["spectrum"]["n_time"]), dtype=torch.float32,
+                                          device="cuda"),
+                          n_tr=car["n_tracks"]))
+        ws_bytes = max(ws_bytes, lay["workspace_bytes"])
+        h_bytes = max(h_bytes, lay["h_bytes"])
+        pts += N[0] * N[1] * N[2] * v["spectrum"]["n_freq"]
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    h = torch.empty(h_bytes, dtype=torch.uint8, device="cuda")
+
+    def batch():
+        for it in items:
+            wt.wt_h_solve(ctx, it["plan"], ws.data_ptr(), ws.numel(), h.data_ptr(), h.numel())
+            wt.wt_current(ctx, it["plan"], h.data_ptr(), it["pos"].shape[0], it["n_tr"], it["pos"].data_ptr(),
+                          it["q"].data_ptr(), it["tr"].data_ptr(), it["out"].data_ptr())
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    with torch.cuda.stream(stream):
+        batch()                                                   # warm-up, kernel attributes
+        t_eager = timed(batch)
+    ref = [it["out"].clone() for it in items]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        batch()
+    t_graph = []
+    err = 0.0
+    for _ in range(replays):
+        with torch.cuda.stream(stream):                           # a replay runs on the current stream
+            t_graph.append(timed(graph.replay))
+        err = max(err, max(float((it["out"] - r).abs().max() / r.abs().max().clamp_min(1e-30))
+                           for it, r in zip(items, ref)))
+    del graph
+    for it in items:
+        wt.wt_h_plan_destroy(it["plan"])
+    wt.wt_context_destroy(ctx)
+    n_pipe = sum(1 for v in variants if v["cell"]["N"][2] in (64, 128, 256))
+    return {"n_variants": n_variants, "grid_freq_pts": pts, "ms_eager": t_eager, "ms_graph": float(np.median(t_graph)),
+            "value_graph": pts / (np.median(t_graph) * 1e-3), "unit": "grid*freq pts/s",
+            "replay_vs_eager_current_max_rel_diff": err, "variants_on_register_fft_synthesis": n_pipe,
+            "workload": ("seeded geometry variants: pitch 25-100 um, radius 3-10 um, five resistivities "
+                         "0.01-1 ohm cm, grids 64..160 x 64..160 x 64..320 (even 2*3*5-smooth), 64-256 frequencies, "
+                         "200 x 10 ps, one 1e3-pair MIP track each; float32 H, one shared workspace and H buffer")}
 
 
 def main():
@@ -323,6 +395,47 @@ def main():
                    "features_first_track": {"amplitude_V": float(f_e[0, 0]), "t_peak_s": float(f_e[0, 1]),
                                             "t_cfd_s": float(f_e[0, 2])}}
 
+    # the whole step captured once as a HIP graph and replayed
+    g_stream = torch.cuda.Stream()
+    g_ctx = wt.wt_context_create(0, g_stream.cuda_stream)
+    g_plan, g_lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2, ir_tol=1e-12)
+    g_ws = torch.empty(g_lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    g_h = torch.empty(g_lay["h_bytes"], dtype=torch.uint8, device="cuda")
+    g_out = torch.empty((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
+
+    def g_step():
+        wt.wt_h_solve(g_ctx, g_plan, g_ws.data_ptr(), g_ws.numel(), g_h.data_ptr(), g_lay["h_bytes"])
+        wt.wt_current(g_ctx, g_plan, g_h.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
+                      g_out.data_ptr())
+
+    with torch.cuda.stream(g_stream):
+        g_step()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=g_stream):
+        g_step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(g_stream):                             # a replay runs on the current stream
+        for _ in range(args.warmup):
+            graph.replay()
+        e0.record(g_stream)
+        for _ in range(args.steps):
+            graph.replay()
+        e1.record(g_stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / args.steps
+    del graph, g_ws, g_h
+    wt.wt_h_plan_destroy(g_plan)
+    wt.wt_context_destroy(g_ctx)
+    torch.cuda.empty_cache()
+    print(f"# captured step replayed: {graph_ms:.3f} ms/step", file=sys.stderr, flush=True)
+    batch = None
+    if args.variants > 0:
+        batch = batched_variants(wt, workloads, torch, args.variants, 3)
+        print(f"# batch of {args.variants} variants: eager {batch['ms_eager']:.1f} ms, graph {batch['ms_graph']:.1f} ms",
+              file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+
     i_plain = plain["out"].double().cpu().numpy()
     i_mixed = mixed["out"].double().cpu().numpy()
     i_err_mixed = float(np.linalg.norm(i_mixed - i_plain) / np.linalg.norm(i_plain))
@@ -367,6 +480,8 @@ def main():
         "solve_report": plain["rep"],
         "solve_m256": solve_m256,
         "electronics": electronics,
+        "graph": {"ms_per_step": graph_ms, "note": "the same step captured once as a HIP graph and replayed"},
+        "batched_variants": batch,
         "mixed": {
             "h_storage": "float16 holding H * h_scale (h_scale a power of two), decoded in float32",
             "h_scale": mixed["rep"]["h_scale"],

@@ -356,3 +356,40 @@ def cr_rc_response(n_time, dt, tau=250 * PS, gain=1.0e3):
 def noise_samples(k, n_tracks, n_time):
     """Seeded standard normal samples for the electronics noise."""
     return rng_for(k).standard_normal((n_tracks, n_time))
+
+
+def smooth_sizes(lo, hi):
+    """Even 2*3*5-smooth integers in [lo, hi]."""
+    out = []
+    for n in range(lo + (lo & 1), hi + 1, 2):
+        m = n
+        for p in (2, 3, 5):
+            while m % p == 0:
+                m //= p
+        if m == 1:
+            out.append(n)
+    return out
+
+
+def geometry_variant(k, n_pairs=1000, n_time=200):
+    """One seeded geometry variant of the batched workload: pitch U(25, 100)
+    um, column radius U(3, 10) um clamped to 0.2 pitch, five resistivities
+    U(0.01, 1) ohm cm, N_xy an even 2*3*5-smooth size in [64, 160], N_z in
+    {N_xy, 2 N_xy} up to 320, N_f in {64, 96, ..., 256} to Nyquist, 200
+    samples of 10 ps, one MIP track of n_pairs e/h pairs."""
+    rng = rng_for(1000 + k)
+    pitch = rng.uniform(25.0, 100.0) * UM
+    radius = min(rng.uniform(3.0, 10.0) * UM, 0.2 * pitch)
+    rho = rng.uniform(0.01, 1.0, size=5) * OHM_CM
+    n_xy = int(rng.choice(smooth_sizes(64, 160)))
+    n_z = int(rng.choice([n for n in (n_xy, 2 * n_xy) if n <= 320]))
+    n_freq = int(rng.choice(np.arange(64, 257, 32)))
+    cell = make_cell(pitch, 300 * UM, n_xy, n_z)
+    cols = standard_columns(pitch, 300 * UM, radius, rho[0], rho[1:], 64)
+    dt = 10 * PS
+    spec = dict(n_freq=n_freq, df=frequency_grid_to_nyquist(n_freq, dt), n_time=n_time, dt=dt)
+    starts = mip_track_starts(rng, cell, cols, n_pairs)
+    pts, q = pairs_to_carriers(starts)
+    pos = drift_paths(pts, q, cols, cell, spec["n_time"], spec["dt"])
+    return _pack(f"variant-{k}", cell, cols, spec, pos, q, np.zeros(q.size), 1,
+                 f"pitch {pitch / UM:.1f} um, r {radius / UM:.2f} um, {n_pairs} e/h pairs")
