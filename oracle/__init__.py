@@ -31,6 +31,10 @@ What it computes (paper: abstract, Eq. 1 in the introduction, Section 3):
 * ``timedomain``  the paper's own forward-Euler time stepping of the boundary
                   charges on the same RC-line model, as a cross-check of the
                   frequency-domain solve.
+* ``gradient``    forward-mode derivatives of the currents with respect to each
+                  column's quarter-column resistivities and radius: the
+                  derivative of the boundary-fit system, solved per frequency,
+                  pushed through the linear rest of the path.
 
 Pins (tests marked "not gpu"): Ewald sums for G and E_G; the direct G against
 the nested collocation sums; the compact RC-line system against a Kirchhoff
@@ -43,11 +47,13 @@ closed-form convolution of two sampled exponentials, the identity response,
 a sampled parabola's vertex and a linear ramp's constant-fraction crossing for
 the electronics; for the time-domain scheme, its transfer function against
 the collocation system, its zero- and infinite-time limits, and first-order
-convergence of forward Euler to the exact step response.
+convergence of forward Euler to the exact step response; for the derivatives,
+central differences of the whole forward pipeline and of the collocation
+matrix, and the common conductivity derivative of parallel quarter-columns.
 
 Parity unpinned: none of the computed quantities.  The modelling readings
 themselves (thin-wire columns, smoothing widths, periodic z, collocation
 azimuth, column permittivity) are choices, not results, and are not pinned.
 """
-from . import green, collocation, timegrid, field, convolution, electronics, timedomain  # noqa: F401
+from . import green, collocation, timegrid, field, convolution, electronics, timedomain, gradient  # noqa: F401
 from .pipeline import weighting_field, induced_current  # noqa: F401
