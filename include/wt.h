@@ -17,6 +17,9 @@
  *   wt_current  H + carrier polylines -> i_track(t)   (Eq. 1, introduction;
  *               Section 3: the convolution of every carrier's velocity with H)
  *
+ * and wt_h_gradient gives dL/d(column resistivities, radii) of a loss of the
+ * currents by the adjoint of both calls.
+ *
  * Conventions shared by every call:
  *  - SI units (m, s, ohm*m, C, V).  V_w = 1 V.
  *  - All device buffers are caller-owned (e.g. torch tensors); the library
@@ -240,6 +243,40 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h,
 wt_status wt_electronics(wt_context* ctx, int precision, int n_tracks, int n_time, double dt,
                          const void* d_current, const void* d_response, const void* d_noise, double noise_sigma,
                          double cfd_fraction, void* d_signal, void* d_features);
+
+/* Bytes of the gradient workspace of wt_h_gradient for a plan and n_tracks
+ * tracks (WT_E_UNSUPPORTED_SIZE when the plan has more than 128 charges). */
+wt_status wt_h_gradient_workspace(const wt_h_plan* plan, int n_tracks, size_t* bytes);
+
+/* Gradient of a loss L of the currents with respect to every column's
+ * quarter-column resistivities and radius (the electrode parameters of the
+ * paper's Section 4 studies: resistance R = 4 rho L / (pi d^2) through the
+ * resistivity and the diameter), by the adjoint of the whole path.
+ *   d_grad_current [n_tracks][n_time]: dL/di, element type of the plan's
+ *     precision;
+ *   d_grad_params  [n_cols][5] double (overwritten): dL/d resistivity[p]
+ *     (ohm*m) for p < n_resistivity (0 in the unused slots), then dL/d radius
+ *     (m).
+ * The carriers are those given to wt_current; their polylines are held fixed.
+ * d_workspace must hold what wt_h_solve wrote for this plan (the collocation
+ * matrix, the charges q(w) of every frequency and the field table); it is
+ * only read.  H itself is not needed: the adjoint projects every moving step
+ * of the carriers on the column spectra, correlates with dL/di over the lags,
+ * transposes the z-transform and the time quadrature, solves the transposed
+ * boundary-fit system S(w)^T lambda = dL/dq(w) at every frequency (FP64,
+ * LU with partial pivoting and refinement) and contracts lambda with
+ * dS/dtheta: the RC-line block through the column conductivity and radius,
+ * the collocation matrix through the collocation offset r and the source
+ * width r/4.
+ * d_grad_workspace: >= wt_h_gradient_workspace bytes, 256-byte aligned,
+ * overwritten.  Plans with more than 128 charges: WT_E_UNSUPPORTED_SIZE.
+ * With report != NULL the call synchronises and reports the transposed
+ * solves (WT_E_SINGULAR / WT_E_NOT_CONVERGED as for wt_h_solve; h_scale 1). */
+wt_status wt_h_gradient(wt_context* ctx, const wt_h_plan* plan,
+                        const void* d_workspace, size_t workspace_bytes,
+                        const wt_carriers* carriers, const void* d_grad_current,
+                        void* d_grad_workspace, size_t grad_workspace_bytes,
+                        double* d_grad_params, wt_h_report* report);
 
 const char* wt_status_string(wt_status status);
 

@@ -31,9 +31,12 @@ using wt::Plan;
 
 constexpr int kMaxUnknowns = 528;
 constexpr int kStageTables = 0, kStageSolve = 1, kStageTime = 2, kStageFieldTable = 3, kStageSynthesis = 4,
-              kStageCurrent = 5;
+              kStageCurrent = 5, kStageAdjointProjection = 6, kStageAdjointSolve = 7, kStageAdjointParams = 8;
 const char* const kStageNames[] = {"green_tables", "collocation_solve", "time_transform",
-                                   "field_table",  "synthesis",         "current"};
+                                   "field_table",  "synthesis",         "current",
+                                   "adjoint_projection", "adjoint_solve", "adjoint_params"};
+// The adjoint's transposed solves use the Schur-complement form of the boundary fit.
+constexpr int kMaxGradientCharges = 128;
 
 bool pos_finite(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -110,6 +113,8 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
         o.z_contact = c.z_contact;
         o.z_free = c.z_free;
         o.sigma = cond / c.n_resistivity;
+        o.n_res = c.n_resistivity;
+        for (int q = 0; q < 4; ++q) o.resistivity[q] = q < c.n_resistivity ? c.resistivity[q] : 0.0;
         o.v_applied = c.v_applied;
         o.n = c.n_colloc;
         o.ix = ((int)std::nearbyint(fx)) % N[0];
@@ -219,6 +224,35 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
         p.h_bytes = p.h_values_bytes;
     }
     return WT_OK;
+}
+
+wt::GradLayout grad_layout(const Plan& p, int n_tracks) {
+    wt::GradLayout g{};
+    const size_t cx = p.precision == WT_F64 ? 16 : 8;
+    g.n_tracks = n_tracks;
+    size_t off = 0;
+    g.off_phi = off;
+    off = align256(off + (size_t)n_tracks * p.n_time * p.n_cols * p.nzh * cx);
+    g.off_gamma = off;
+    off = align256(off + (size_t)p.n_time * p.n_cols * p.nzh * 16);
+    g.off_gbar = off;
+    off = align256(off + (size_t)p.n_time * p.n_q * 8);
+    g.off_rhs = off;
+    off = align256(off + (size_t)p.n_freq * p.n * 16);
+    g.off_lam = off;
+    off = align256(off + (size_t)p.n_freq * p.n * 16);
+    g.off_rep = off;
+    off = align256(off + (size_t)p.n_freq * sizeof(wt::SolveReport));
+    g.off_part = off;
+    off = align256(off + (size_t)p.n_freq * p.n_cols * 2 * 8);
+    g.off_K = off;
+    off = align256(off + (size_t)p.n_q * p.n_q * 8);
+    g.off_gd = off;
+    off = align256(off + (size_t)2 * p.n_cols * p.n_cols * p.nkz_tab * 8);
+    g.off_prod = off;
+    off = align256(off + (size_t)2 * p.n_q * p.n_q * 8);
+    g.bytes = off;
+    return g;
 }
 
 void fill_layout(const Plan& p, wt_h_layout* l) {
@@ -441,6 +475,66 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, co
                                    d_i_out, ctx->stream),
            "current");
     if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
+    return WT_OK;
+}
+
+wt_status wt_h_gradient_workspace(const wt_h_plan* plan, int n_tracks, size_t* bytes) {
+    if (!plan || !bytes || n_tracks < 1) return WT_E_INVALID_ARG;
+    *bytes = 0;
+    if (plan->p.n_q > kMaxGradientCharges) return WT_E_UNSUPPORTED_SIZE;
+    *bytes = grad_layout(plan->p, n_tracks).bytes;
+    return WT_OK;
+}
+
+wt_status wt_h_gradient(wt_context* ctx, const wt_h_plan* plan, const void* d_workspace, size_t workspace_bytes,
+                        const wt_carriers* car, const void* d_grad_current, void* d_grad_workspace,
+                        size_t grad_workspace_bytes, double* d_grad_params, wt_h_report* report) {
+    if (!ctx || !plan || !d_workspace || !car || !d_grad_current || !d_grad_workspace || !d_grad_params)
+        return WT_E_INVALID_ARG;
+    if (car->n_carriers < 0 || car->n_tracks < 1) return WT_E_INVALID_ARG;
+    if (car->n_carriers > 0 && (!car->d_pos || !car->d_charge || !car->d_track)) return WT_E_INVALID_ARG;
+    const Plan& p = plan->p;
+    if (p.n_q > kMaxGradientCharges) return WT_E_UNSUPPORTED_SIZE;
+    if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) || (reinterpret_cast<uintptr_t>(d_grad_workspace) & 255))
+        return WT_E_INVALID_ARG;
+    const wt::GradLayout g = grad_layout(p, car->n_tracks);
+    if (workspace_bytes < p.ws_bytes || grad_workspace_bytes < g.bytes) return WT_E_WORKSPACE;
+    wt_status st = bind(ctx);
+    if (st != WT_OK) return st;
+    ctx->n_events = 0;
+    hipStream_t s = ctx->stream;
+    char* gb = static_cast<char*>(d_grad_workspace);
+    if ((st = mark(ctx, -1)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_lattice_derivatives(p, reinterpret_cast<double*>(gb + g.off_gd), s), "lattice_derivatives");
+    WT_HIP(ctx, wt::launch_adjoint_rhs(p, g, d_workspace, car->n_carriers, car->d_pos, car->d_charge, car->d_track,
+                                       d_grad_current, d_grad_workspace, s),
+           "adjoint_projection");
+    if ((st = mark(ctx, kStageAdjointProjection)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_adjoint_solve(p, d_workspace, gb + g.off_rhs, gb + g.off_lam, gb + g.off_rep, s),
+           "adjoint_solve");
+    if ((st = mark(ctx, kStageAdjointSolve)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_adjoint_params(p, g, d_workspace, d_grad_workspace, d_grad_params, s), "adjoint_params");
+    if ((st = mark(ctx, kStageAdjointParams)) != WT_OK) return st;
+    if (!report) return WT_OK;
+
+    std::vector<wt::SolveReport> rep(p.n_freq);
+    WT_HIP(ctx, hipMemcpyAsync(rep.data(), gb + g.off_rep, rep.size() * sizeof(wt::SolveReport),
+                               hipMemcpyDeviceToHost, s),
+           "report copy");
+    WT_HIP(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+    report->h_scale = 1.0;
+    report->backward_error_max = 0.0;
+    report->pivot_ratio_max = 0.0;
+    report->ir_iters_max = 0;
+    report->singular_count = 0;
+    for (const auto& r : rep) {
+        report->backward_error_max = std::fmax(report->backward_error_max, r.backward_error);
+        report->pivot_ratio_max = std::fmax(report->pivot_ratio_max, r.pivot_ratio);
+        report->ir_iters_max = report->ir_iters_max > r.iters ? report->ir_iters_max : r.iters;
+        report->singular_count += r.singular ? 1 : 0;
+    }
+    if (report->singular_count > 0) return WT_E_SINGULAR;
+    if (!(report->backward_error_max <= p.ir_tol)) return WT_E_NOT_CONVERGED;
     return WT_OK;
 }
 

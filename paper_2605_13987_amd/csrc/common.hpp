@@ -42,6 +42,8 @@ __host__ __device__ inline cplx<T> mul_i(cplx<T> a) { return {-a.im, a.re}; }   
 struct Column {
     double x, y, radius, z_contact, z_free;
     double sigma;        // mean conductivity of the quarter-columns, S/m
+    double resistivity[4];   // the quarter-columns' resistivities, ohm m
+    int n_res;
     double v_applied;
     int n;               // nodes
     int ix, iy;          // axis grid node
@@ -79,6 +81,23 @@ struct Plan {
     size_t h_values_bytes; // bytes of the values of H; for float16 H the float 1/h_scale follows
 };
 
+// Buffers of the adjoint (gradient) computation, byte offsets into the
+// caller's gradient workspace.
+struct GradLayout {
+    int n_tracks;
+    size_t off_phi;      // [n_tracks][n_time][n_cols][nzh] complex, path precision: event projections
+    size_t off_gamma;    // [n_time][n_cols][nzh] complex double: dL/d(column spectra)
+    size_t off_gbar;     // [n_time][n_q] double: dL/dq(t)
+    size_t off_rhs;      // [n_freq][n] complex double: right-hand sides of the transposed solves
+    size_t off_lam;      // [n_freq][n] complex double: adjoint charges
+    size_t off_rep;      // [n_freq] SolveReport of the transposed solves
+    size_t off_part;     // [n_freq][n_cols][2] double: per-frequency RC-line terms
+    size_t off_K;        // [n_q][n_q] double: sum over frequencies of Re(lambda_i q_j)
+    size_t off_gd;       // [2][n_cols][n_cols][nkz_tab] double: lattice-sum derivatives
+    size_t off_prod;     // [2][n_q][n_q] double: collocation-matrix derivative terms
+    size_t bytes;
+};
+
 // Per-frequency solve diagnostics written by the solve kernel.
 struct SolveReport {
     double backward_error;
@@ -100,6 +119,18 @@ hipError_t launch_electronics(int precision, int n_tracks, int nt, double dt, co
 hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks,
                           const void* pos, const void* charge, const int* track,
                           void* out, hipStream_t s);
+// Adjoint: lattice-sum derivatives (d/d collocation offset, d/d source width)
+// into gd; transposed boundary-fit solves with right-hand sides rhs into lam;
+// the event projection to dL/dq(w) (right-hand sides) and the final
+// contraction to the parameter gradient.
+hipError_t launch_lattice_derivatives(const Plan& p, double* gd, hipStream_t s);
+hipError_t launch_adjoint_solve(const Plan& p, const void* ws, const void* rhs, void* lam, void* rep,
+                                hipStream_t s);
+hipError_t launch_adjoint_rhs(const Plan& p, const GradLayout& g, const void* ws, int n_carriers,
+                              const void* pos, const void* charge, const int* track, const void* grad_i,
+                              void* gws, hipStream_t s);
+hipError_t launch_adjoint_params(const Plan& p, const GradLayout& g, const void* ws, void* gws, double* out,
+                                 hipStream_t s);
 
 // Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256}).
 __host__ __device__ constexpr int synthesis_n2(int nz) { return nz == 64 ? 8 : 16; }

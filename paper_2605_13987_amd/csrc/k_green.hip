@@ -42,8 +42,12 @@ __global__ void k_twiddles(int n0, int n1, int n2, cplx<T>* t0, cplx<T>* t1, cpl
     }
 }
 
-// One block per (k_z >= 0, source column v, collocation column w).
-__global__ void __launch_bounds__(kBlock) k_lattice(Plan p, double* g) {
+// One block per (k_z >= 0, source column v, collocation column w).  kind 0:
+// g_vw(k_z); kind 1: its derivative in the in-plane offset dx (collocation
+// column's radius), sum exp(-k^2 s^2/2)/k^2 (-k_x sin(k_x dx + k_y dy));
+// kind 2: its derivative in the source width s, sum -s exp(-k^2 s^2/2)
+// cos(k_x dx + k_y dy).
+__global__ void __launch_bounds__(kBlock) k_lattice(Plan p, int kind, double* g) {
     __shared__ double red[kBlock / 64];
     const int iz = blockIdx.x;
     const int v = blockIdx.y / p.n_cols, w = blockIdx.y % p.n_cols;
@@ -71,7 +75,13 @@ __global__ void __launch_bounds__(kBlock) k_lattice(Plan p, double* g) {
         const double k2 = kx * kx + ky * ky + kz * kz;
         double u = mx * ax + my * ay;
         u -= rint(u);
-        acc += exp(-0.5 * k2 * sc * sc) / k2 * cospi(2.0 * u);
+        const double e = exp(-0.5 * k2 * sc * sc);
+        if (kind == 0)
+            acc += e / k2 * cospi(2.0 * u);
+        else if (kind == 1)
+            acc -= e / k2 * kx * sinpi(2.0 * u);
+        else
+            acc -= sc * e * cospi(2.0 * u);
     }
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) out[iz] = s;
@@ -130,12 +140,23 @@ hipError_t launch_green_tables(const Plan& p, void* ws, hipStream_t s) {
     char* b = static_cast<char*>(ws);
     double* g = (double*)(b + p.off_g);
     double* A = (double*)(b + p.off_A);
-    hipLaunchKernelGGL(k_lattice, dim3(p.nkz_tab, p.n_cols * p.n_cols), dim3(kBlock), 0, s, p, g);
+    hipLaunchKernelGGL(k_lattice, dim3(p.nkz_tab, p.n_cols * p.n_cols), dim3(kBlock), 0, s, p, 0, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_collocation_matrix, dim3((p.n_q + kBlock - 1) / kBlock, p.n_q), dim3(kBlock), 0, s,
                        p, (const double*)g, A);
     return hipGetLastError();
+}
+
+hipError_t launch_lattice_derivatives(const Plan& p, double* gd, hipStream_t s) {
+    const size_t table = (size_t)p.n_cols * p.n_cols * p.nkz_tab;
+    for (int kind = 1; kind <= 2; ++kind) {
+        hipLaunchKernelGGL(k_lattice, dim3(p.nkz_tab, p.n_cols * p.n_cols), dim3(kBlock), 0, s, p, kind,
+                           gd + (kind - 1) * table);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace wt

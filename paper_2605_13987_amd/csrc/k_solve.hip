@@ -509,14 +509,16 @@ __device__ __forceinline__ void solve_in_registers(const c64 (&a)[NB][NB], int m
 // Schur-complement form for n_q <= 32 NB: only the n_q x n_q block
 // St = (A + i w R) / a is factored; with St x1 = b and St x2 = 1 the bordered
 // system gives c = (1'x1) / (1'x2) and q' = x1 - c x2 (exact in exact
-// arithmetic).  1024 threads in a 32 x 32 grid, thread (r, c) holding rows
+// arithmetic).  ADJ: the transposed system of the adjoint, S^T [l; c] =
+// [rhs; 0] with rhs per frequency from the workspace; R is symmetric and the
+// border is the same row and column of ones, so only A is read transposed.  1024 threads in a 32 x 32 grid, thread (r, c) holding rows
 // r + 32 ii and columns c + 32 jj of St; the factors stay in registers for
 // the triangular solves (one barrier per step: the owners of column k update
 // the rows below or above k).  Refinement uses the residual of the bordered
 // system, computed with one wavefront per row (coalesced reads of A).
-template <int NB>
+template <int NB, bool ADJ>
 __global__ void __launch_bounds__(1024)
-k_solve_schur(Plan p, const double* A, c64* qw, SolveReport* rep) {
+k_solve_schur(Plan p, const double* A, const c64* rhs, c64* qw, SolveReport* rep) {
     constexpr int NM = 32 * NB;
     __shared__ c64 ubuf[NM];
     __shared__ c64 lbuf[NM];
@@ -569,8 +571,8 @@ k_solve_schur(Plan p, const double* A, c64* qw, SolveReport* rep) {
     }
     __syncthreads();
     const double inv_a = sh_inv_a;
-    auto st = [&](int i, int j) -> c64 {                 // entry of St
-        c64 v{A[(size_t)i * m + j], 0.0};
+    auto st = [&](int i, int j) -> c64 {                 // entry of St (of St^T for ADJ)
+        c64 v{ADJ ? A[(size_t)j * m + i] : A[(size_t)i * m + j], 0.0};
         if (colof[i] == colof[j]) v = v + scale(zc[colof[i]], (double)(mof[i] < mof[j] ? mof[i] : mof[j]));
         return scale(v, inv_a);
     };
@@ -698,9 +700,11 @@ k_solve_schur(Plan p, const double* A, c64* qw, SolveReport* rep) {
     }
     __syncthreads();
 
-    // right-hand sides: applied voltages and ones, permuted
+    // right-hand sides: applied voltages (ADJ: the given ones) and ones, permuted
+    const c64* bf = ADJ ? rhs + (size_t)f * p.n : nullptr;
+    auto bval = [&](int i) -> c64 { return ADJ ? bf[i] : c64{vapp[colof[i]], 0.0}; };
     for (int i = tid; i < m; i += blockDim.x) {
-        y1[i] = c64{vapp[colof[perm[i]]], 0.0};
+        y1[i] = bval(perm[i]);
         y2[i] = c64{1.0, 0.0};
     }
     solve_in_registers<NB>(a, m, r, cc, diag, y1, y2, true);
@@ -729,7 +733,12 @@ k_solve_schur(Plan p, const double* A, c64* qw, SolveReport* rep) {
     }
     const double snorm = fmax(block_max(srow, red), (double)m);
     double bmax = 0.0;
-    for (int w = 0; w < p.n_cols; ++w) bmax = fmax(bmax, fabs(vapp[w]));
+    if constexpr (ADJ) {
+        for (int i = tid; i < m; i += blockDim.x) bmax = fmax(bmax, cmod(bf[i]));
+        bmax = block_max(bmax, red);
+    } else {
+        for (int w = 0; w < p.n_cols; ++w) bmax = fmax(bmax, fabs(vapp[w]));
+    }
     const c64 s2_all = t2;
 
     int iters = 0;
@@ -745,7 +754,7 @@ k_solve_schur(Plan p, const double* A, c64* qw, SolveReport* rep) {
                 acc.re += __shfl_xor(acc.re, o, 64);
                 acc.im += __shfl_xor(acc.im, o, 64);
             }
-            const c64 ri = c64{vapp[colof[i]], 0.0} - acc - cur_c;
+            const c64 ri = bval(i) - acc - cur_c;
             if (lane == 0) y1[i] = ri;
             rmax = fmax(rmax, cmod(ri));
         }
@@ -796,15 +805,15 @@ hipError_t launch_collocation_solve(const Plan& p, void* ws, hipStream_t s) {
     c64* qw = (c64*)(b + p.off_qw);
     SolveReport* rep = (SolveReport*)(b + p.off_rep);
     if (p.n_q <= 64) {
-        hipLaunchKernelGGL(k_solve_schur<2>, dim3(p.n_freq), dim3(1024), 0, s, p, A, qw, rep);
+        hipLaunchKernelGGL((k_solve_schur<2, false>), dim3(p.n_freq), dim3(1024), 0, s, p, A, nullptr, qw, rep);
         return hipGetLastError();
     }
     if (p.n_q <= 96) {
-        hipLaunchKernelGGL(k_solve_schur<3>, dim3(p.n_freq), dim3(1024), 0, s, p, A, qw, rep);
+        hipLaunchKernelGGL((k_solve_schur<3, false>), dim3(p.n_freq), dim3(1024), 0, s, p, A, nullptr, qw, rep);
         return hipGetLastError();
     }
     if (p.n_q <= 128) {
-        hipLaunchKernelGGL(k_solve_schur<4>, dim3(p.n_freq), dim3(1024), 0, s, p, A, qw, rep);
+        hipLaunchKernelGGL((k_solve_schur<4, false>), dim3(p.n_freq), dim3(1024), 0, s, p, A, nullptr, qw, rep);
         return hipGetLastError();
     }
     if (p.n <= 144) {
@@ -814,6 +823,24 @@ hipError_t launch_collocation_solve(const Plan& p, void* ws, hipStream_t s) {
     hipLaunchKernelGGL(k_solve, dim3(p.n_freq), dim3(kBlock), 0, s, p, (const double*)(b + p.off_A),
                        (c64*)(b + p.off_lu), (int*)(b + p.off_piv), (c64*)(b + p.off_qw),
                        (SolveReport*)(b + p.off_rep));
+    return hipGetLastError();
+}
+
+// Transposed systems of the adjoint (Schur form only: n_q <= 128).
+hipError_t launch_adjoint_solve(const Plan& p, const void* ws, const void* rhs, void* lam, void* rep,
+                                hipStream_t s) {
+    const double* A = (const double*)(static_cast<const char*>(ws) + p.off_A);
+    const c64* b = static_cast<const c64*>(rhs);
+    c64* x = static_cast<c64*>(lam);
+    SolveReport* r = static_cast<SolveReport*>(rep);
+    if (p.n_q <= 64)
+        hipLaunchKernelGGL((k_solve_schur<2, true>), dim3(p.n_freq), dim3(1024), 0, s, p, A, b, x, r);
+    else if (p.n_q <= 96)
+        hipLaunchKernelGGL((k_solve_schur<3, true>), dim3(p.n_freq), dim3(1024), 0, s, p, A, b, x, r);
+    else if (p.n_q <= 128)
+        hipLaunchKernelGGL((k_solve_schur<4, true>), dim3(p.n_freq), dim3(1024), 0, s, p, A, b, x, r);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

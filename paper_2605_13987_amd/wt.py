@@ -109,6 +109,9 @@ def _load():
         "wt_current": (c_int, [c_void_p, c_void_p, c_void_p, P(wt_carriers), c_void_p, c_size_t, c_void_p]),
         "wt_electronics": (c_int, [c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                    c_double, c_double, c_void_p, c_void_p]),
+        "wt_h_gradient_workspace": (c_int, [c_void_p, c_int, P(c_size_t)]),
+        "wt_h_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, P(wt_carriers), c_void_p, c_void_p,
+                                  c_size_t, c_void_p, P(wt_h_report)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -264,3 +267,32 @@ def wt_electronics(ctx, precision: int, n_tracks: int, n_time: int, dt: float, d
     if raise_on_error:
         _check(st, "wt_electronics", ctx)
     return st
+
+
+# ---------------------------------------------------------------- gradient
+
+def wt_h_gradient_workspace(plan, n_tracks: int) -> int:
+    """Bytes of the gradient workspace for n_tracks tracks."""
+    n = c_size_t()
+    _check(LIB.wt_h_gradient_workspace(plan, int(n_tracks), ctypes.byref(n)), "wt_h_gradient_workspace")
+    return n.value
+
+
+def wt_h_gradient(ctx, plan, d_workspace: int, workspace_bytes: int, n_carriers: int, n_tracks: int, d_pos: int,
+                  d_charge: int, d_track: int, d_grad_current: int, d_grad_workspace: int,
+                  grad_workspace_bytes: int, d_grad_params: int, report: bool = False,
+                  raise_on_error: bool = True):
+    """Enqueue the adjoint: dL/d(resistivities, radius) per column into
+    d_grad_params ([n_cols][5] double).  Returns (status, report dict or None)."""
+    car = wt_carriers(int(n_carriers), int(n_tracks), c_void_p(d_pos), c_void_p(d_charge), c_void_p(d_track))
+    rep = wt_h_report() if report else None
+    st = LIB.wt_h_gradient(ctx, plan, c_void_p(d_workspace), int(workspace_bytes), ctypes.byref(car),
+                           c_void_p(d_grad_current), c_void_p(d_grad_workspace), int(grad_workspace_bytes),
+                           c_void_p(d_grad_params), ctypes.byref(rep) if report else None)
+    if raise_on_error and st != WT_OK:
+        _check(st, "wt_h_gradient", ctx)
+    out = None
+    if report:
+        out = {name: getattr(rep, name) for name, _ in wt_h_report._fields_}
+    return st, out
+

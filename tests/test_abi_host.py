@@ -155,3 +155,33 @@ def test_f16_scaled_layout_and_validation():
     small = workloads.small_pixel(k=41, n_xy=24, n_z=40, n_freq=4, n_time=10, n_pairs=5, n_colloc=8)
     assert wt.wt_h_plan_create_status(small["cell"], small["columns"], small["spectrum"], precision=wt.WT_F32,
                                       h_format=wt.WT_H_F16_SCALED) == wt.WT_E_UNSUPPORTED_SIZE
+
+
+def test_gradient_workspace_and_validation():
+    import ctypes
+    cell, cols, spec = _px32()
+    plan, lay = wt.wt_h_plan_create(cell, cols, spec, precision=wt.WT_F32)
+    try:
+        n1 = wt.wt_h_gradient_workspace(plan, 1)
+        n100 = wt.wt_h_gradient_workspace(plan, 100)
+        nq, nf, nt, nzh = lay["n_q"], spec["n_freq"], spec["n_time"], cell["N"][2] // 2
+        # per extra track: one [n_time][n_cols][N_z/2] complex float block of event projections
+        assert n100 - n1 >= 99 * nt * 2 * nzh * 8 and n100 - n1 <= 99 * nt * 2 * nzh * 8 + 512
+        assert n1 >= nq * nq * 8 * 3 + 2 * nf * (nq + 1) * 16
+        n = ctypes.c_size_t()
+        assert wt.LIB.wt_h_gradient_workspace(plan, 0, ctypes.byref(n)) == wt.WT_E_INVALID_ARG
+        assert wt.LIB.wt_h_gradient_workspace(None, 1, ctypes.byref(n)) == wt.WT_E_INVALID_ARG
+        car = wt.wt_carriers(1, 1, None, None, None)
+        assert wt.LIB.wt_h_gradient(None, plan, None, 0, ctypes.byref(car), None, None, 0, None, None) \
+            == wt.WT_E_INVALID_ARG
+    finally:
+        wt.wt_h_plan_destroy(plan)
+    # the transposed solves use the Schur-complement form: at most 128 charges
+    big = [dict(c, n_colloc=65) for c in cols]
+    plan, _ = wt.wt_h_plan_create(cell, big, spec, precision=wt.WT_F32)
+    try:
+        n = ctypes.c_size_t()
+        assert wt.LIB.wt_h_gradient_workspace(plan, 1, ctypes.byref(n)) == wt.WT_E_UNSUPPORTED_SIZE
+    finally:
+        wt.wt_h_plan_destroy(plan)
+
