@@ -246,6 +246,68 @@ def batched_variants(wt, workloads, torch, n_variants, replays):
                          "200 x 10 ps, one 1e3-pair MIP track each; float32 H, one shared workspace and H buffer")}
 
 
+def adjoint_section(cfg, torch, wt, np, reps):
+    """Gradient of the peak time and windowed charge of the track's current with
+    respect to the 5 resistivities and the radii (adjoint), against the cost of
+    the central-difference scan it replaces and against the FP64 adjoint."""
+    from paper_2605_13987_amd.grad import ColumnModel, signal_features
+    from paper_2605_13987_amd import workloads
+
+    dt = cfg["spectrum"]["dt"]
+    rng = workloads.rng_for(63)
+    t_c, t_s = rng.uniform(0.5e-9, 1.5e-9), rng.uniform(0.1e-9, 0.4e-9)
+    out = {}
+    grads = {}
+    for prec in (wt.WT_F32, wt.WT_F64):
+        model = ColumnModel(cfg["cell"], cfg["columns"], cfg["spectrum"], cfg["carriers"], precision=prec)
+        theta = model.theta0()
+        plan, cur = model.solve(theta)
+        i = cur.detach().requires_grad_(True)
+        t_peak, q_w = signal_features(i, dt, t_c, t_s, 2e-9)
+        g_tp = torch.autograd.grad(t_peak.sum(), i)[0]
+        g_qw = torch.autograd.grad(q_w.sum(), i)[0]
+        grads[prec] = (theta.numpy(), model.gradient(plan, g_tp).numpy(), model.gradient(plan, g_qw).numpy())
+        if prec != wt.WT_F32:
+            continue
+        s = torch.cuda.current_stream()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record(s)
+        for _ in range(reps):
+            plan, cur = model.solve(theta)
+        e1.record(s)
+        for _ in range(reps):
+            model.gradient(plan, g_tp)
+        e2.record(s)
+        torch.cuda.synchronize()
+        fwd, bwd = e0.elapsed_time(e1) / reps, e1.elapsed_time(e2) / reps
+        wt.wt_context_enable_timing(model.ctx, True)
+        model.gradient(plan, g_tp)
+        stages = dict(wt.wt_context_stage_times(model.ctx))
+        wt.wt_context_enable_timing(model.ctx, False)
+        n_par = sum(len(c["resistivity"]) + 1 for c in cfg["columns"])
+        out.update({"n_params": n_par, "forward_ms": fwd, "backward_ms": bwd,
+                    "backward_stage_ms": {k: round(v, 4) for k, v in stages.items()},
+                    "central_difference_scan_ms": 2 * n_par * fwd,
+                    "note": "backward = wt_h_gradient (event projection, transposed FP64 solves, contraction); "
+                            "the scan it replaces needs 2 forward solves per parameter"})
+    th, tp32, qw32 = grads[wt.WT_F32]
+    _, tp64, qw64 = grads[wt.WT_F64]
+    slots = [(w, p) for w, c in enumerate(cfg["columns"]) for p in list(range(len(c["resistivity"]))) + [4]]
+
+    def logd(g):
+        return np.array([th[w, p] * g[w, p] for w, p in slots])
+
+    def rel(a, b):
+        return float(np.max(np.abs(logd(a) - logd(b))) / np.max(np.abs(logd(b))))
+
+    out["log_gradient_t_peak_s"] = {"readout_rho": float(logd(tp32)[0]),
+                                    "bias_rho_sum": float(sum(logd(tp32)[2:6])),
+                                    "readout_radius": float(logd(tp32)[1]), "bias_radius": float(logd(tp32)[6])}
+    out["rel_err_float32_vs_float64_adjoint"] = {"t_peak": rel(tp32, tp64), "q_w": rel(qw32, qw64)}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -395,6 +457,10 @@ def main():
                    "features_first_track": {"amplitude_V": float(f_e[0, 0]), "t_peak_s": float(f_e[0, 1]),
                                             "t_cfd_s": float(f_e[0, 2])}}
 
+    adjoint = adjoint_section(cfg, torch, wt, np, max(3, min(args.steps, 10)))
+    torch.cuda.empty_cache()
+    print(f"# adjoint: {adjoint}", file=sys.stderr, flush=True)
+
     # the whole step captured once as a HIP graph and replayed
     g_stream = torch.cuda.Stream()
     g_ctx = wt.wt_context_create(0, g_stream.cuda_stream)
@@ -480,6 +546,7 @@ def main():
         "solve_report": plain["rep"],
         "solve_m256": solve_m256,
         "electronics": electronics,
+        "adjoint": adjoint,
         "graph": {"ms_per_step": graph_ms, "note": "the same step captured once as a HIP graph and replayed"},
         "batched_variants": batch,
         "mixed": {
