@@ -100,7 +100,7 @@ typedef enum {
     WT_H_F16_SCALED = 1    /* H stored as float16 values of H * h_scale, with
                               h_scale = 2^s chosen from a bound on |H| so that
                               every stored magnitude is <= 16384 (requires
-                              WT_F32 and N_z in {64, 128, 256} with at most 4
+                              WT_F32 and N_z in {64, 128, 256, 512} with at most 4
                               columns); the synthesis and the convolution
                               compute in float */
 } wt_h_format;

@@ -164,16 +164,17 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     const size_t re = p.precision == WT_F64 ? sizeof(double) : sizeof(float);
     const size_t cx = 2 * re;
     // Time block of the H layout (the synthesis stages a whole block in LDS):
-    // the pipelined register-FFT synthesis for N_z in {64, 128, 256} with at
-    // most 4 columns when its two staging buffers fit (blocks of 16 samples);
+    // the pipelined register-FFT synthesis for N_z in {64, 128, 256, 512} with
+    // at most 4 columns when its two staging buffers fit (blocks of 16
+    // samples, 8 for N_z = 512);
     // otherwise the LDS Stockham synthesis, whose block is halved until its
     // tables fit.
     const size_t lds_budget = 160 * 1024;
-    const bool pipe_size = N[2] == 64 || N[2] == 128 || N[2] == 256;
+    const bool pipe_size = N[2] == 64 || N[2] == 128 || N[2] == 256 || N[2] == 512;
     int tb;
     if (pipe_size && n_cols <= 4 && wt::synthesis_pipe_lds(N[2], re) <= lds_budget) {
         p.synth_kernel = 2;
-        tb = std::min(sp->n_time, wt::kPipeBlock);
+        tb = std::min(sp->n_time, wt::synthesis_block(N[2]));
     } else {
         p.synth_kernel = 0;
         tb = std::min(sp->n_time, 32);

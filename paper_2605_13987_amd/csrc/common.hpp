@@ -132,23 +132,37 @@ hipError_t launch_adjoint_rhs(const Plan& p, const GradLayout& g, const void* ws
 hipError_t launch_adjoint_params(const Plan& p, const GradLayout& g, const void* ws, void* gws, double* out,
                                  hipStream_t s);
 
-// Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256}).
-__host__ __device__ constexpr int synthesis_n2(int nz) { return nz == 64 ? 8 : 16; }
+// Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256, 512}).
+__host__ __device__ constexpr int synthesis_n2(int nz) { return nz == 64 ? 8 : (nz == 512 ? 32 : 16); }
 
-// Blocks of 16 samples, staged in LDS as rows of 3 x 16 values (sample pair
-// q, component c, real/imaginary part at column 6 q + c (+3), plus a gap of
-// 24 columns from pair 4 on), row stride 73, and row z at
-// 73 z + 3 floor(z / N2).  The gap and the padding keep the transforms'
-// LDS accesses free of bank conflicts (two groups of a half-wavefront take
-// sample pairs 4 apart, 16 banks apart).
+// H is produced in blocks of kPipeBlock samples (8 for N_z = 512, so that two
+// staging buffers fit in LDS), each staged in LDS as rows of 3 x block values:
+// sample pair q, component c, real/imaginary part at column 6 q + c (+3),
+// plus a gap from pair block/4 on, row z at RS z + 3 floor(z / N2).  The gap
+// and the padding keep the transforms' LDS accesses free of bank conflicts
+// (two groups of a half-wavefront take sample pairs block/4 apart).
 constexpr int kPipeBlock = 16;
-constexpr int kPipeGap = 24;
-constexpr int kPipeRowStride = 3 * kPipeBlock + kPipeGap + 1;
 constexpr int kPipeRowPad = 3;
+__host__ __device__ constexpr int synthesis_block(int nz) { return nz == 512 ? 8 : kPipeBlock; }
+__host__ __device__ constexpr int synthesis_gap(int nz) { return nz == 512 ? 4 : 24; }
+__host__ __device__ constexpr int synthesis_row_stride(int nz) {
+    return 3 * synthesis_block(nz) + synthesis_gap(nz) + 1;
+}
+// Threads: the transform team (3 block/2 transforms x N1 lanes) and the
+// memory team (a multiple of N_z/2: each of its threads owns one k_z).
+__host__ __device__ constexpr int synthesis_transform_team(int nz) {
+    return 3 * (synthesis_block(nz) / 2) * (nz / synthesis_n2(nz));
+}
+__host__ __device__ constexpr int synthesis_memory_team(int nz) {
+    return nz == 512 ? 256 : synthesis_transform_team(nz);
+}
+__host__ __device__ constexpr int synthesis_threads(int nz) {
+    return synthesis_transform_team(nz) + synthesis_memory_team(nz);
+}
 
 // Elements of one staging buffer, and LDS bytes of the workgroup (two buffers).
 __host__ __device__ constexpr int synthesis_buffer(int nz) {
-    return nz * kPipeRowStride + nz / synthesis_n2(nz) * kPipeRowPad;
+    return nz * synthesis_row_stride(nz) + nz / synthesis_n2(nz) * kPipeRowPad;
 }
 inline size_t synthesis_pipe_lds(int nz, size_t re) { return 2 * (size_t)synthesis_buffer(nz) * re; }
 

@@ -169,10 +169,13 @@ typedef float vec2f __attribute__((ext_vector_type(2)));
 typedef _Float16 vec2h __attribute__((ext_vector_type(2)));
 typedef double vec2d __attribute__((ext_vector_type(2)));
 
-// Synthesis of H(X, Y, z, t) for N_z = N1 x N2 in {64, 128, 256}, with the
-// length-N_z transforms done in registers.  One workgroup per (X, Y) column;
-// H is produced in blocks of 16 samples, each staged whole in LDS as
-// [z][sample][component] (the row layout is described at kPipeBlock):
+constexpr int const_gcd(int a, int b) { return b == 0 ? a : const_gcd(b, a % b); }
+
+// Synthesis of H(X, Y, z, t) for N_z = N1 x N2 in {64, 128, 256, 512}, with
+// the length-N_z transforms done in registers.  One workgroup per (X, Y)
+// column; H is produced in blocks of 16 samples (8 for N_z = 512), each
+// staged whole in LDS as [z][sample][component] (the row layout is described
+// at kPipeBlock):
 //
 // 1. Spectra.  A memory-team thread owns k_z index kk and keeps the field
 //    table entries Ehat_a(X - X_w, Y - Y_w, kk) of all components and columns
@@ -200,28 +203,34 @@ typedef double vec2d __attribute__((ext_vector_type(2)));
 // spectra into it (phase 2).  A workgroup barrier ends each phase; within a
 // phase the teams touch different buffers.
 template <typename T, int N1, int N2, int WC, typename TO>
-__global__ void __launch_bounds__(48 * N1)
+__global__ void __launch_bounds__(synthesis_threads(N1 * N2))
 k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, const float* h_scale,
                  TO* H) {
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
     constexpr int C = N2 / N1;
-    constexpr int TBC = kPipeBlock;                            // 16 samples per block
+    constexpr int TBC = synthesis_block(NZ);                   // samples per block
     constexpr int NP = TBC / 2;                                // sample pairs per block
     constexpr int NG = 3 * NP;                                 // transforms per block
     constexpr int NTT = NG * N1;                               // transform team
-    constexpr int NTM = NTT;                                   // memory team
-    constexpr int GAP = kPipeGap;
-    constexpr int RS = kPipeRowStride;
+    constexpr int NTM = synthesis_memory_team(NZ);             // memory team
+    constexpr int GAP = synthesis_gap(NZ);
+    constexpr int RS = synthesis_row_stride(NZ);
     constexpr int PAD = kPipeRowPad;                           // row z at z RS + (z / N2) PAD
     constexpr int BUF = synthesis_buffer(NZ);                  // elements per staging buffer
     constexpr int PPT = NTM / NZH;                             // pairs covered by one pass of the team
     constexpr int PFI = (NP + PPT - 1) / PPT;                  // (kk, pair) items per thread
-    constexpr int LW = 3 * TBC / 2;                            // copy-out lanes per row (2 values each)
-    constexpr int STORES = NZ * LW / NTM;                      // paired stores per thread per full block
-    constexpr int ROWS = NTM / LW;                             // rows per copy-out pass
-    static_assert(N2 == synthesis_n2(NZ) && NTT % 64 == 0 && N2 % N1 == 0, "synthesis split");
-    static_assert(NTM % NZH == 0 && NTM % LW == 0 && N2 % ROWS == 0 && GAP % 2 == 0, "synthesis thread mapping");
+    constexpr int LW = 3 * TBC / 2;                            // value pairs per row
+    // Copy-out: value pair p = lane + NTM k of the block (row p / LW); with
+    // CR = LW / gcd(NTM, LW) per-lane bases, store k = CR j + r sits CROWS j
+    // rows after base r, a constant offset.
+    constexpr int CR = LW / const_gcd(NTM, LW);
+    constexpr int CROWS = NTM * CR / LW;
+    constexpr int CJ = NZ / CROWS;
+    static_assert(N2 == synthesis_n2(NZ) && NTT % 64 == 0 && NTM % 64 == 0 && N2 % N1 == 0, "synthesis split");
+    static_assert(NTT + NTM == synthesis_threads(NZ), "synthesis teams");
+    static_assert(NTM % NZH == 0 && NZ % CROWS == 0 && (N2 % CROWS == 0 || CROWS % N2 == 0) && GAP % 2 == 0,
+                  "synthesis thread mapping");
     extern __shared__ __align__(16) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
     const int Nx = p.N[0], Ny = p.N[1], nt = p.n_time;
@@ -401,18 +410,25 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
             }
         };
         // A full block: each lane writes two consecutive values of a row per
-        // store (rows are 3 x 16 values, the gap falls between value pairs);
-        // a fixed number of stores per thread, so that the spectra loads
-        // issued just before are waited for without waiting for the stores.
+        // store (rows are 3 x block values, the gap falls between value
+        // pairs); a fixed number of stores per thread, so that the spectra
+        // loads issued just before are waited for without waiting for the
+        // stores.
         auto copyout_full = [&](const T* stage, int t0) {
             TO* dst = hcol + (size_t)t0 * NZ * 3;
             int lane = m;
             asm volatile("" : "+v"(lane));
-            const int rr = 2 * (lane % LW);
-            const T* src = stage + (lane / LW) * RS + rr + (rr >= 3 * TBC / 2 ? GAP : 0);
+            const T* src[CR];
 #pragma unroll
-            for (int k = 0; k < STORES; ++k) {
-                const T* sk = src + k * ROWS * RS + (k * ROWS / N2) * PAD;
+            for (int r = 0; r < CR; ++r) {
+                const int pr = lane + NTM * r;
+                const int z = pr / LW, rr = 2 * (pr - z * LW);
+                src[r] = stage + z * RS + (z / N2) * PAD + rr + (rr >= 3 * TBC / 2 ? GAP : 0);
+            }
+#pragma unroll
+            for (int k = 0; k < CR * CJ; ++k) {
+                const int j = k / CR, r = k - j * CR;
+                const T* sk = src[r] + j * CROWS * RS + (j * CROWS / N2) * PAD;
                 TO* dk = byte_offset(dst + k * NTM * 2, lane * 2 * (unsigned)sizeof(TO));
                 if constexpr (kScaled) {
                     __builtin_nontemporal_store(vec2h{(_Float16)(sk[0] * enc), (_Float16)(sk[1] * enc)},
@@ -604,7 +620,7 @@ hipError_t synthesis_pipe(const Plan& p, char* b, void* h, hipStream_t s) {
     hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_pipe<T, N1, N2, WC, TO>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_synthesis_pipe<T, N1, N2, WC, TO>), dim3(p.N[0] * p.N[1]), dim3(48 * N1), lds, s, p,
+    hipLaunchKernelGGL((k_synthesis_pipe<T, N1, N2, WC, TO>), dim3(p.N[0] * p.N[1]), dim3(synthesis_threads(NZ)), lds, s, p,
                        reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]),
@@ -627,7 +643,8 @@ hipError_t synthesis_pipe_n(const Plan& p, char* b, void* h, hipStream_t s) {
     switch (p.N[2]) {
         case 64: return synthesis_pipe_w<T, 8, 8, TO>(p, b, h, s);
         case 128: return synthesis_pipe_w<T, 8, 16, TO>(p, b, h, s);
-        default: return synthesis_pipe_w<T, 16, 16, TO>(p, b, h, s);
+        case 256: return synthesis_pipe_w<T, 16, 16, TO>(p, b, h, s);
+        default: return synthesis_pipe_w<T, 16, 32, TO>(p, b, h, s);
     }
 }
 

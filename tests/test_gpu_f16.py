@@ -69,6 +69,22 @@ def test_16x16x128_f16_ragged(ctx):
     assert err_i <= TOL
 
 
+def test_8x8x512_f16_ragged(ctx):
+    cfg = workloads.small_pixel(k=46, n_xy=8, n_z=512, n_freq=5, n_time=21, n_pairs=20, n_colloc=8)
+    say("test_8x8x512_f16_ragged")
+    ref = oracle.weighting_field(cfg["cell"], cfg["columns"], cfg["spectrum"])
+    run = solve_h(ctx, cfg, wt.WT_F32, h_format=wt.WT_H_F16_SCALED)
+    assert run["layout"]["h_time_block"] == 8
+    _check_scale(run)
+    err_h = rel_l2(h_standard(run, cfg), ref["H"])
+    say(f"  H rel L2 {err_h:.3e}")
+    assert err_h <= TOL
+    car = rounded_carriers(cfg["carriers"], wt.WT_F32)
+    err_i = rel_l2(current(ctx, run, car), oracle.induced_current(ref["H"], cfg["cell"], car))
+    say(f"  i rel L2 {err_i:.3e}")
+    assert err_i <= TOL
+
+
 def test_128x128x256_f16_sampled_columns_and_current_vs_plain(ctx):
     cfg = workloads.mip_pixel_128x128x256()
     say("test_128x128x256_f16_sampled_columns_and_current_vs_plain")

@@ -63,6 +63,7 @@ SMALL = [
     (30, 60, 9, 37, 20),
     (20, 20, 5, 70, 8),
     (16, 128, 6, 37, 12),     # register-FFT synthesis with N_z = 8 x 16 and a ragged last block
+    (8, 512, 5, 21, 8),       # N_z = 16 x 32, blocks of 8 samples, ragged odd last block
 ]
 
 
