@@ -48,6 +48,130 @@ def synthesis_sources_sha256():
     return h.hexdigest()
 
 
+def current_compulsory_bytes_device(pos, cell, n_tracks, nt, elem_bytes, torch, chunk=1 << 17):
+    """``current_compulsory_bytes`` for carriers held on the device (torch),
+    in chunks of carriers.  Returns (bytes, moving steps)."""
+    N, L = cell["N"], cell["L"]
+    scale = torch.tensor([N[a] / L[a] for a in range(3)], dtype=torch.float64, device=pos.device)
+    nodes, needs = [], []
+    n_steps = 0
+    for c0 in range(0, pos.shape[0], chunk):
+        P = pos[c0:c0 + chunk].double()
+        moving = (P[:, 1:] != P[:, :-1]).any(dim=2)
+        ci, mi = moving.nonzero(as_tuple=True)
+        n_steps += int(ci.numel())
+        lo = torch.floor(0.5 * (P[ci, mi] + P[ci, mi + 1]) * scale).long()
+        lags = nt - mi
+        for ox in (0, 1):
+            for oy in (0, 1):
+                for oz in (0, 1):
+                    x = (lo[:, 0] + ox) % N[0]
+                    y = (lo[:, 1] + oy) % N[1]
+                    z = (lo[:, 2] + oz) % N[2]
+                    nodes.append((x * N[1] + y) * N[2] + z)
+                    needs.append(lags)
+    node = torch.cat(nodes)
+    need = torch.cat(needs)
+    uniq, inv = torch.unique(node, return_inverse=True)
+    best = torch.zeros(uniq.numel(), dtype=need.dtype, device=need.device).scatter_reduce(0, inv, need, "amax")
+    h_bytes = int(best.sum().item()) * 3 * elem_bytes
+    return h_bytes + 24 * n_steps + n_tracks * nt * 4, n_steps
+
+
+def c5_section(torch, wt, np, steps):
+    """The 256x256x512 workload (1e6 carriers in 100 tracks, 512 frequencies,
+    400 samples): float16-scaled H (80.5 GB) and float32 H (161 GB), one at a
+    time, each a whole step (solve + current) timed over ``steps`` steps."""
+    from paper_2605_13987_amd import layout, workloads
+
+    cfg = workloads.pixel_256x256x512_tracks(device="cuda", out_dtype=torch.float32)
+    cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
+    N, nt, n_tr = cell["N"], spec["n_time"], car["n_tracks"]
+    n_pts = N[0] * N[1] * N[2]
+    n_c = car["pos"].shape[0]
+    stream = torch.cuda.current_stream()
+    ctx = wt.wt_context_create(0, stream.cuda_stream)
+    res = {"workload": (f"{N[0]}x{N[1]}x{N[2]} grid of the 50x50x300 um pixel, {spec['n_freq']} frequencies to "
+                        f"50 GHz, {nt} x 10 ps, {n_tr} MIP tracks of 5e3 e/h pairs ({n_c} carriers), drift + "
+                        f"0.5 um Gaussian diffusion per step"), "n_carriers": n_c, "n_tracks": n_tr}
+    currents, cols_h = {}, {}
+    for name, fmt, eb in (("mixed", wt.WT_H_F16_SCALED, 2), ("plain", wt.WT_H_PLAIN, 4)):
+        plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2, ir_tol=1e-12,
+                                        h_format=fmt)
+        ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
+        hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
+        out = torch.empty((n_tr, nt), dtype=torch.float32, device="cuda")
+
+        def step():
+            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
+            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, car["pos"].data_ptr(), car["charge"].data_ptr(),
+                          car["track"].data_ptr(), out.data_ptr())
+
+        _, rep_s = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True)
+        step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        wt.wt_context_enable_timing(ctx, True)
+        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
+        stage = dict(wt.wt_context_stage_times(ctx))
+        wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, car["pos"].data_ptr(), car["charge"].data_ptr(),
+                      car["track"].data_ptr(), out.data_ptr())
+        stage.update(dict(wt.wt_context_stage_times(ctx)))
+        wt.wt_context_enable_timing(ctx, False)
+        synth_bytes = n_pts * nt * 3 * eb + N[0] * N[1] * len(cfg["columns"]) * (N[2] // 2) * 3 * 8
+        achieved = synth_bytes / (stage["synthesis"] * 1e-3) / 1e9
+        cur_bytes, n_steps = current_compulsory_bytes_device(car["pos"], cell, n_tr, nt, eb, torch)
+        t_cur = stage["current"] * 1e-3
+        res[name] = {"ms_per_step": ms, "value": n_pts * spec["n_freq"] / (ms * 1e-3), "unit": "grid*freq pts/s",
+                     "h_bytes": lay["h_bytes"], "h_scale": rep_s["h_scale"],
+                     "backward_error_max": rep_s["backward_error_max"],
+                     "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+                     "tracks_per_s": n_tr / t_cur, "carriers_per_s": n_c / t_cur, "events_per_s": n_steps / t_cur,
+                     "synthesis_roofline": {"kernel": "k_synthesis_pipe", "bound": "hbm", "achieved": achieved,
+                                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                            "bytes_per_launch": synth_bytes},
+                     "current_roofline": {"kernel": "k_current", "bound": "hbm", "compulsory_bytes": cur_bytes,
+                                          "achieved": cur_bytes / t_cur / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                          "frac": cur_bytes / t_cur / 1e9 / HBM_PEAK_GBS, "moving_steps": n_steps}}
+        currents[name] = out.double().cpu().numpy()
+        if name == "mixed":
+            per = N[2] * nt * 3
+            idx = torch.tensor([i * N[1] + j for i, j in C5_COLS], device="cuda")
+            h16 = hbuf[:n_pts * nt * 3 * 2].view(torch.float16).view(-1, per)
+            vals = h16.index_select(0, idx).double().cpu().numpy() / rep_s["h_scale"]
+            cols_h[name] = layout.to_standard(vals, N, nt, lay["h_time_block"])
+        print(f"# 256x256x512 {name}: {ms:.2f} ms/step, stages {res[name]['stage_ms']}", file=sys.stderr, flush=True)
+        wt.wt_h_plan_destroy(plan)
+        del ws, hbuf, out
+        torch.cuda.empty_cache()
+    wt.wt_context_destroy(ctx)
+    a, b = currents["mixed"], currents["plain"]
+    res["rel_err"] = {"i_mixed_vs_plain": float(np.linalg.norm(a - b) / np.linalg.norm(b))}
+    return res, cfg, cols_h
+
+
+C5_COLS = [(0, 0), (128, 128), (150, 128), (20, 200)]
+
+
+def c5_oracle_errors(cfg, cols_h):
+    """Errors of the 256x256x512 float16 H on sampled columns against the oracle's direct sums."""
+    import numpy as np
+
+    import oracle
+
+    ref = oracle.weighting_field(cfg["cell"], cfg["columns"], cfg["spectrum"], route="columns", cols_ij=C5_COLS)
+    out = {}
+    for name, h in cols_h.items():
+        out[name] = float(np.linalg.norm(h - ref["H_cols"]) / np.linalg.norm(ref["H_cols"]))
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +182,8 @@ def parse():
                     help="geometry variants in the batched (graph-captured) measurement; 0 skips it")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="approximate CPU time of the oracle baseline sample")
+    ap.add_argument("--c5-steps", type=int, default=3,
+                    help="timed steps of the 256x256x512 workload (1e6 carriers); 0 skips it")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB mebibytes device-to-device 3 times (counter calibration)")
     return ap.parse_args()
@@ -502,6 +628,11 @@ def main():
               file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
+    c5, c5_cfg, c5_cols = None, None, None
+    if args.c5_steps > 0:
+        c5, c5_cfg, c5_cols = c5_section(torch, wt, np, args.c5_steps)
+        torch.cuda.empty_cache()
+
     i_plain = plain["out"].double().cpu().numpy()
     i_mixed = mixed["out"].double().cpu().numpy()
     i_err_mixed = float(np.linalg.norm(i_mixed - i_plain) / np.linalg.norm(i_plain))
@@ -549,6 +680,7 @@ def main():
         "adjoint": adjoint,
         "graph": {"ms_per_step": graph_ms, "note": "the same step captured once as a HIP graph and replayed"},
         "batched_variants": batch,
+        "px256": c5,
         "mixed": {
             "h_storage": "float16 holding H * h_scale (h_scale a power of two), decoded in float32",
             "h_scale": mixed["rep"]["h_scale"],
@@ -571,6 +703,8 @@ def main():
         line["cpu_baseline"] = base
         line["rel_err"] = {"H_sampled_columns_vs_fp64_oracle": err["plain"]}
         line["mixed"]["rel_err"]["H_sampled_columns_vs_fp64_oracle"] = err["mixed"]
+        if c5 is not None:
+            c5["mixed"]["rel_err_H_sampled_columns_vs_fp64_oracle"] = c5_oracle_errors(c5_cfg, c5_cols)["mixed"]
     print(json.dumps(line), flush=True)
     wt.wt_context_destroy(ctx)
 

@@ -193,6 +193,80 @@ def drift_paths(starts, charges, columns, cell, n_time, dt, speed=DRIFT_SPEED,
     return pos
 
 
+def drift_paths_torch(starts, charges, columns, cell, n_time, dt, speed=DRIFT_SPEED, diffusion_sigma=0.0,
+                      seed=0, device="cpu", out_dtype=None):
+    """``drift_paths`` for large carrier sets, stepped with torch on ``device``.
+
+    Same model: each step moves ``speed*dt`` toward the nearest point of the
+    target column's axis segment (electrons to the readout, holes to a bias
+    column) plus an isotropic Gaussian displacement of ``diffusion_sigma`` per
+    axis from a torch generator seeded with ``seed``; a carrier stops on the
+    column surface with a fractional last step.  The nearest periodic image is
+    found by wrapping the in-plane offset and trying the segment's images at
+    z - L_z, z, z + L_z.  State in float64; the polylines are returned as
+    (n, n_time+1, 3) of ``out_dtype`` (default float64) on ``device``.
+    """
+    import torch
+
+    f64 = torch.float64
+    dev = torch.device(device)
+    out_dtype = f64 if out_dtype is None else out_dtype
+    L = [float(v) for v in cell["L"]]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    cur = torch.as_tensor(np.asarray(starts), dtype=f64, device=dev).clone()
+    neg = torch.as_tensor(np.asarray(charges) < 0, device=dev)
+    n = cur.shape[0]
+    segs = _segments(columns, cell)
+    groups = [[s for s, c in zip(segs, columns) if c["v_applied"] > 0.5],
+              [s for s, c in zip(segs, columns) if c["v_applied"] <= 0.5]]
+
+    def target(p):
+        tgt = torch.zeros_like(p)
+        dist = torch.full((n,), float("inf"), dtype=f64, device=dev)
+        rad = torch.zeros(n, dtype=f64, device=dev)
+        for gi, group in enumerate(groups):
+            sel = neg if gi == 0 else ~neg
+            for (x, y, z0, z1, r) in group:
+                dx = p[:, 0] - x
+                dx = dx - L[0] * torch.round(dx / L[0])
+                dy = p[:, 1] - y
+                dy = dy - L[1] * torch.round(dy / L[1])
+                bz = None
+                for k in (-1.0, 0.0, 1.0):
+                    cz = torch.clamp(p[:, 2], z0 + k * L[2], z1 + k * L[2])
+                    bz = cz if bz is None else torch.where((p[:, 2] - cz).abs() < (p[:, 2] - bz).abs(), cz, bz)
+                d = torch.sqrt(dx * dx + dy * dy + (p[:, 2] - bz) ** 2)
+                m = sel & (d < dist)
+                q = torch.stack([p[:, 0] - dx, p[:, 1] - dy, bz], dim=1)
+                tgt = torch.where(m[:, None], q, tgt)
+                dist = torch.where(m, d, dist)
+                rad = torch.where(m, torch.full_like(rad, r), rad)
+        return tgt, dist, rad
+
+    pos = torch.empty((n, n_time + 1, 3), dtype=out_dtype, device=dev)
+    pos[:, 0] = cur.to(out_dtype)
+    alive = torch.ones(n, dtype=torch.bool, device=dev)
+    step_len = speed * dt
+    for s in range(n_time):
+        tgt, dist, rad = target(cur)
+        u = (tgt - cur) / torch.clamp(dist, min=1e-30)[:, None]
+        move = u * step_len
+        if diffusion_sigma > 0.0:
+            move = move + diffusion_sigma * torch.randn(cur.shape, generator=gen, dtype=f64, device=dev)
+        nxt = cur + move
+        _, d_next, _ = target(nxt)
+        hit = alive & (d_next <= rad)
+        frac = torch.clamp((dist - rad) / step_len, 0.0, 1.0)
+        stop = cur + u * (frac * step_len)[:, None]
+        nxt = torch.where(hit[:, None], stop, nxt)
+        nxt = torch.where(alive[:, None], nxt, cur)
+        alive &= ~hit
+        cur = nxt
+        pos[:, s + 1] = cur.to(out_dtype)
+    return pos
+
+
 def pairs_to_carriers(starts):
     """One electron (-e) and one hole (+e) at every start point."""
     n = starts.shape[0]
@@ -313,6 +387,38 @@ def mip_pixel_128x128x256(n_pairs=10000):
     pos = drift_paths(pts, q, cols, cell, spec["n_time"], spec["dt"])
     return _pack("px128", cell, cols, spec, pos, q, np.zeros(q.size), 1,
                  f"one MIP track along z, {n_pairs} e/h pairs with Moyal weights")
+
+
+def pixel_256x256x512_tracks(device="cpu", n_tracks=100, n_pairs=5000, out_dtype=None):
+    """256x256x512 grid of the 50x50x300 um pixel, 512 frequencies to 50 GHz,
+    400 x 10 ps, ``n_tracks`` MIP tracks of ``n_pairs`` e/h pairs each, drift
+    at 1e5 m/s plus Gaussian diffusion of 0.5 um per axis per 10 ps step.
+
+    The polylines are stepped with torch on ``device`` (see
+    ``drift_paths_torch``); the returned carriers hold torch tensors there.
+    """
+    import torch
+
+    rng = rng_for(5)
+    cell = make_cell(50 * UM, 300 * UM, 256, 512)
+    rho = rng.uniform(0.05, 1.0, size=5) * OHM_CM
+    cols = standard_columns(50 * UM, 300 * UM, 5 * UM, rho[0], rho[1:], 64)
+    dt = 10 * PS
+    spec = dict(n_freq=512, df=frequency_grid_to_nyquist(512, dt), n_time=400, dt=dt)
+    starts, charge, track = [], [], []
+    for k in range(n_tracks):
+        pts, q = pairs_to_carriers(mip_track_starts(rng, cell, cols, n_pairs))
+        starts.append(pts)
+        charge.append(q)
+        track.append(np.full(q.size, k, dtype=np.int32))
+    starts = np.concatenate(starts)
+    charge = np.concatenate(charge)
+    pos = drift_paths_torch(starts, charge, cols, cell, spec["n_time"], dt, diffusion_sigma=0.5 * UM,
+                            seed=SEED_BASE + 5, device=device, out_dtype=out_dtype)
+    car = dict(pos=pos, charge=torch.as_tensor(charge, device=pos.device, dtype=pos.dtype),
+               track=torch.as_tensor(np.concatenate(track), device=pos.device), n_tracks=int(n_tracks))
+    return dict(name="px256", cell=cell, columns=cols, spectrum=spec, carriers=car,
+                note=f"{n_tracks} MIP tracks along z, {n_pairs} e/h pairs each, drift + 0.5 um diffusion per step")
 
 
 def small_pixel(k=11, n_xy=24, n_z=40, n_freq=12, n_time=40, n_pairs=40,

@@ -1,0 +1,106 @@
+"""Parity at the 256x256x512 workload: 512 frequencies to 50 GHz, 400 samples
+of 10 ps, 100 MIP tracks of 5e3 e/h pairs with drift and diffusion (1e6
+carriers), H stored as scaled float16 (80.5 GB).
+
+* H on sampled (x, y) columns against the oracle's direct mode sums (1e-3);
+* the convolution at full size on a synthetic float16 field: against the
+  oracle on every 100th carrier (1e-3, the float16 rounding of the field) and
+  through linearity over all carriers (1e-5).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import context, h_columns, rel_l2, say, solve_h
+from paper_2605_13987_amd import layout, workloads, wt
+
+pytestmark = pytest.mark.gpu
+
+COLS = [(0, 0), (128, 128), (150, 128), (128, 100), (20, 200), (255, 7)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = context()
+    yield c
+    wt.wt_context_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def c5():
+    say("generating the 256x256x512 workload: 1e6 carrier polylines on the device")
+    cfg = workloads.pixel_256x256x512_tracks(device="cuda", out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    return cfg
+
+
+def test_256x256x512_f16_field_on_sampled_columns(ctx, c5):
+    run = solve_h(ctx, c5, wt.WT_F32, h_format=wt.WT_H_F16_SCALED)
+    assert run["status"] == wt.WT_OK, run["report"]
+    assert run["layout"]["h_time_block"] == 8
+    say("oracle: boundary fit + direct sums on 6 columns")
+    ref = oracle.weighting_field(c5["cell"], c5["columns"], c5["spectrum"], route="columns", cols_ij=COLS)
+    got = h_columns(run, c5, COLS)
+    for k, ij in enumerate(COLS):
+        say(f"  column {ij}: rel L2 {rel_l2(got[k], ref['H_cols'][k]):.2e}")
+    err = rel_l2(got, ref["H_cols"])
+    say(f"  all sampled columns: rel L2 {err:.2e}")
+    assert err <= 1e-3
+    wt.wt_h_plan_destroy(run["plan"])
+    del run
+    torch.cuda.empty_cache()
+
+
+def _currents(ctx, plan, hbuf, car, idx, nt):
+    pos = car["pos"].index_select(0, idx).contiguous()
+    q = car["charge"].index_select(0, idx).contiguous()
+    tr = car["track"].index_select(0, idx).contiguous()
+    out = torch.empty((car["n_tracks"], nt), dtype=torch.float32, device="cuda")
+    wt.wt_current(ctx, plan, hbuf.data_ptr(), pos.shape[0], car["n_tracks"], pos.data_ptr(), q.data_ptr(),
+                  tr.data_ptr(), out.data_ptr())
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+def test_256x256x512_current_on_synthetic_f16_field(ctx, c5):
+    cell, spec, car = c5["cell"], c5["spectrum"], c5["carriers"]
+    N, nt = cell["N"], spec["n_time"]
+    plan, lay = wt.wt_h_plan_create(cell, c5["columns"], spec, precision=wt.WT_F32, h_format=wt.WT_H_F16_SCALED)
+    tb = lay["h_time_block"]
+    f = workloads.synthetic_h_factors(workloads.rng_for(55), N, nt, scale=1.0)
+    say("building the synthetic float16 field on the device")
+    hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
+    h16 = hbuf[:N[0] * N[1] * N[2] * nt * 3 * 2].view(torch.float16)
+    dev = dict(device="cuda", dtype=torch.float64)
+    fx, fy, fz, ft = (torch.from_numpy(f[k]).to(**dev) for k in ("fx", "fy", "fz", "ft"))
+    per_x = N[1] * N[2] * nt * 3
+    for x in range(N[0]):
+        slab = torch.zeros((1, N[1], N[2], nt, 3), **dev)
+        for r in range(fx.shape[0]):
+            slab += (fx[r, x][None, None, None, None, :] * fy[r][None, :, None, None, :]
+                     * fz[r][None, None, :, None, :] * ft[r][None, None, None, :, :])
+        h16[x * per_x:(x + 1) * per_x] = layout.from_standard(slab, tb).to(torch.float16)
+    off = lay["h_decode_offset"]
+    hbuf[off:off + 4].view(torch.float32).fill_(1.0)
+    n = car["pos"].shape[0]
+    say(f"  currents of all {n} carriers, and of the even and odd halves")
+    i_all = _currents(ctx, plan, hbuf, car, torch.arange(n, device="cuda"), nt)
+    i_even = _currents(ctx, plan, hbuf, car, torch.arange(0, n, 2, device="cuda"), nt)
+    i_odd = _currents(ctx, plan, hbuf, car, torch.arange(1, n, 2, device="cuda"), nt)
+    err_lin = rel_l2(i_even + i_odd, i_all)
+    say(f"  linearity rel L2 {err_lin:.2e}")
+    assert err_lin <= 1e-5
+    sub = torch.arange(0, n, 100, device="cuda")
+    i_sub = _currents(ctx, plan, hbuf, car, sub, nt)
+    say(f"  oracle convolution on every 100th carrier ({sub.numel()})")
+    sub_car = dict(pos=car["pos"].index_select(0, sub).double().cpu().numpy(),
+                   charge=car["charge"].index_select(0, sub).double().cpu().numpy(),
+                   track=car["track"].index_select(0, sub).cpu().numpy(), n_tracks=car["n_tracks"])
+    i_ref = oracle.induced_current(lambda ix, iy, iz: workloads.synthetic_h_values(f, ix, iy, iz), cell, sub_car)
+    err = rel_l2(i_sub, i_ref)
+    say(f"  i rel L2 {err:.2e}")
+    assert err <= 1e-3
+    wt.wt_h_plan_destroy(plan)
+    del hbuf, h16
+    torch.cuda.empty_cache()
