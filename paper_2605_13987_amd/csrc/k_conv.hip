@@ -44,22 +44,27 @@ __device__ inline void flush(T* out, int track, int nt, int lane, T* acc) {
 }
 
 // Field of one moving step projected on its displacement, at lag tau, for
-// the 8 trilinear corners (weights already carry -q / V_w).
-template <typename T>
+// the 8 trilinear corners (weights already carry -q / V_w).  The corner
+// columns are held as pointers; offsets inside a column (at most N_z n_time 3
+// elements) are 32-bit.
+template <typename T, typename TH>
 struct Step {
-    size_t b00, b01, b10, b11;     // column bases of the 4 (x, y) corners
+    const TH *c00, *c01, *c10, *c11;   // columns of the 4 (x, y) corners
     int z0, z1;
     T w[8];
     T dx, dy, dz;
 };
 
-template <typename T, typename TH>
-__device__ inline T step_value(const TH* H, const Step<T>& s, int tau, int TB, int Nz, int last_block, int last_len) {
-    const int tb = tau / TB;
-    const int tin = tau - tb * TB;
-    const int len = tb == last_block ? last_len : TB;
-    const size_t toff = (size_t)tb * TB * Nz * 3 + (size_t)tin * 3;
-    const size_t o0 = toff + (size_t)s.z0 * len * 3, o1 = toff + (size_t)s.z1 * len * 3;
+// TBC: the time block of the H layout when it is a compile-time constant
+// (a power of two), else 0 and TB at run time.
+template <int TBC, typename T, typename TH>
+__device__ inline T step_value(const Step<T, TH>& s, int tau, int TB, int Nz, int last_block, int last_len) {
+    const int tbs = TBC > 0 ? TBC : TB;
+    const int tb = TBC > 0 ? tau / TBC : tau / TB;
+    const int tin = tau - tb * tbs;
+    const int len = tb == last_block ? last_len : tbs;
+    const unsigned toff = (unsigned)(tb * tbs * Nz * 3 + tin * 3);
+    const unsigned o0 = toff + (unsigned)(s.z0 * len * 3), o1 = toff + (unsigned)(s.z1 * len * 3);
     auto proj = [&](const TH* h) {
         if constexpr (std::is_same<TH, _Float16>::value) {
             // the three float16 components with one 8-byte load from the 4-byte
@@ -77,19 +82,19 @@ __device__ inline T step_value(const TH* H, const Step<T>& s, int tau, int TB, i
         }
     };
     T v = (T)0;
-    v += s.w[0] * proj(H + s.b00 + o0);
-    v += s.w[1] * proj(H + s.b00 + o1);
-    v += s.w[2] * proj(H + s.b01 + o0);
-    v += s.w[3] * proj(H + s.b01 + o1);
-    v += s.w[4] * proj(H + s.b10 + o0);
-    v += s.w[5] * proj(H + s.b10 + o1);
-    v += s.w[6] * proj(H + s.b11 + o0);
-    v += s.w[7] * proj(H + s.b11 + o1);
+    v += s.w[0] * proj(s.c00 + o0);
+    v += s.w[1] * proj(s.c00 + o1);
+    v += s.w[2] * proj(s.c01 + o0);
+    v += s.w[3] * proj(s.c01 + o1);
+    v += s.w[4] * proj(s.c10 + o0);
+    v += s.w[5] * proj(s.c10 + o1);
+    v += s.w[6] * proj(s.c11 + o0);
+    v += s.w[7] * proj(s.c11 + o1);
     return v;
 }
 
-template <typename T>
-__device__ inline bool make_step(const Plan& p, const T* P, int m, T q, Step<T>& s) {
+template <typename T, typename TH>
+__device__ inline bool make_step(const Plan& p, const TH* H, const T* P, int m, T q, Step<T, TH>& s) {
     const int Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
     const size_t col_stride = (size_t)Nz * p.n_time * 3;
     s.dx = P[3 * m + 3] - P[3 * m + 0];
@@ -107,10 +112,10 @@ __device__ inline bool make_step(const Plan& p, const T* P, int m, T q, Step<T>&
     const int y1 = y0 + 1 == Ny ? 0 : y0 + 1;
     s.z0 = z0;
     s.z1 = z0 + 1 == Nz ? 0 : z0 + 1;
-    s.b00 = ((size_t)x0 * Ny + y0) * col_stride;
-    s.b01 = ((size_t)x0 * Ny + y1) * col_stride;
-    s.b10 = ((size_t)x1 * Ny + y0) * col_stride;
-    s.b11 = ((size_t)x1 * Ny + y1) * col_stride;
+    s.c00 = H + ((size_t)x0 * Ny + y0) * col_stride;
+    s.c01 = H + ((size_t)x0 * Ny + y1) * col_stride;
+    s.c10 = H + ((size_t)x1 * Ny + y0) * col_stride;
+    s.c11 = H + ((size_t)x1 * Ny + y1) * col_stride;
     const T gx = (T)1 - fx, gy = (T)1 - fy, gz = (T)1 - fz;
     // -q folded into the weights (V_w = 1 V)
     s.w[0] = -q * gx * gy * gz;
@@ -124,14 +129,18 @@ __device__ inline bool make_step(const Plan& p, const T* P, int m, T q, Step<T>&
     return true;
 }
 
-// One wavefront per carrier (grid-stride over carriers).  Lanes first find the
-// carrier's moving steps (64 at a time, compacted in LDS by ballot), then run
-// over output samples n = lane + 64 j while the wavefront walks the moving
-// steps two at a time.  The four wavefronts of a workgroup add their partial
-// currents in LDS before one atomic flush when they carry the same track.
-// H is stored as TH: T, or float16 holding H * h_scale, whose sums are scaled
-// by decode = 1 / h_scale once per output sample.
-template <typename T, typename TH>
+// One wavefront per carrier.  Lanes first find the carrier's moving steps (64
+// at a time, compacted in LDS by ballot), then run over output samples n =
+// lane + 64 j while the wavefront walks the moving steps two at a time.  The
+// four wavefronts of a workgroup add their partial currents in LDS before one
+// atomic flush when they carry the same track.  H is stored as TH: T, or
+// float16 holding H * h_scale, whose sums are scaled by decode = 1 / h_scale
+// once per output sample.  Neighbouring carriers read neighbouring corners,
+// and those reads are shared through the caches only while the carriers are
+// processed at the same time: workgroups are dealt to the 8 XCDs round robin,
+// so carriers are numbered such that the workgroups resident on one XCD hold
+// consecutive carriers, whose common reads its L2 then serves.
+template <int TBC, typename T, typename TH>
 __global__ void __launch_bounds__(kBlock)
 k_current(Plan p, const TH* H, const float* decode, int n_carriers, int n_tracks, const T* pos, const T* charge,
           const int* track, T* out) {
@@ -143,7 +152,8 @@ k_current(Plan p, const TH* H, const float* decode, int n_carriers, int n_tracks
     const int nt = p.n_time, TB = p.tb, Nz = p.N[2];
     const int last_block = (nt - 1) / TB;
     const int last_len = nt - last_block * TB;
-    const int c = blockIdx.x * (kBlock / kWave) + wv;
+    const int per_xcd = (gridDim.x + 7) / 8;
+    const int c = ((blockIdx.x % 8) * per_xcd + blockIdx.x / 8) * (kBlock / kWave) + wv;
 
     T acc[kMaxJ];
 #pragma unroll
@@ -176,16 +186,16 @@ k_current(Plan p, const TH* H, const float* decode, int n_carriers, int n_tracks
         for (int e = 0; e < nmov; e += 2) {
             const int ma = steps[wv][e];
             const int mb = e + 1 < nmov ? steps[wv][e + 1] : -1;
-            Step<T> sa, sb;
-            const bool va = make_step(p, P, ma, q, sa);
-            const bool vb = mb >= 0 && make_step(p, P, mb, q, sb);
+            Step<T, TH> sa, sb;
+            const bool va = make_step(p, H, P, ma, q, sa);
+            const bool vb = mb >= 0 && make_step(p, H, P, mb, q, sb);
 #pragma unroll
             for (int j = 0; j < kMaxJ; ++j) {
                 const int n = lane + kWave * j;
                 if (n >= nt) continue;
                 T v = (T)0;
-                if (va && n >= ma) v += step_value(H, sa, n - ma, TB, Nz, last_block, last_len);
-                if (vb && n >= mb) v += step_value(H, sb, n - mb, TB, Nz, last_block, last_len);
+                if (va && n >= ma) v += step_value<TBC>(sa, n - ma, TB, Nz, last_block, last_len);
+                if (vb && n >= mb) v += step_value<TBC>(sb, n - mb, TB, Nz, last_block, last_len);
                 acc[j] += v;
             }
         }
@@ -225,11 +235,22 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
     hipLaunchKernelGGL(k_fill_zero<T>, dim3(zgrid > 0 ? zgrid : 1), dim3(kBlock), 0, s, static_cast<T*>(out), n_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n_carriers == 0) return e;
+    // the carriers of workgroup b come from a permutation of [0, 8 * per_xcd)
+    // workgroups (some past the last carrier, which then do nothing)
     const int blocks = (n_carriers + kBlock / kWave - 1) / (kBlock / kWave);
+    const int grid = 8 * ((blocks + 7) / 8);
     const float* decode = reinterpret_cast<const float*>(static_cast<const char*>(h) + p.h_values_bytes);
-    hipLaunchKernelGGL((k_current<T, TH>), dim3(blocks), dim3(kBlock), 0, s, p, static_cast<const TH*>(h), decode,
-                       n_carriers, n_tracks, static_cast<const T*>(pos), static_cast<const T*>(charge), track,
-                       static_cast<T*>(out));
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, p, static_cast<const TH*>(h), decode, n_carriers,
+                           n_tracks, static_cast<const T*>(pos), static_cast<const T*>(charge), track,
+                           static_cast<T*>(out));
+    };
+    if (p.tb == 16)
+        go(k_current<16, T, TH>);
+    else if (p.tb == 8)
+        go(k_current<8, T, TH>);
+    else
+        go(k_current<0, T, TH>);
     return hipGetLastError();
 }
 
