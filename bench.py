@@ -392,7 +392,10 @@ def adjoint_section(cfg, torch, wt, np, reps):
         t_peak, q_w = signal_features(i, dt, t_c, t_s, 2e-9)
         g_tp = torch.autograd.grad(t_peak.sum(), i)[0]
         g_qw = torch.autograd.grad(q_w.sum(), i)[0]
-        grads[prec] = (theta.numpy(), model.gradient(plan, g_tp).numpy(), model.gradient(plan, g_qw).numpy())
+        (tp_th, tp_p), (qw_th, qw_p) = model.gradient(plan, g_tp), model.gradient(plan, g_qw)
+        p0 = float(cfg["cell"]["L"][0])
+        grads[prec] = (theta.numpy(), np.append(tp_th.numpy().ravel(), p0 * float(tp_p)),
+                       np.append(qw_th.numpy().ravel(), p0 * float(qw_p)))
         if prec != wt.WT_F32:
             continue
         s = torch.cuda.current_stream()
@@ -411,25 +414,28 @@ def adjoint_section(cfg, torch, wt, np, reps):
         model.gradient(plan, g_tp)
         stages = dict(wt.wt_context_stage_times(model.ctx))
         wt.wt_context_enable_timing(model.ctx, False)
-        n_par = sum(len(c["resistivity"]) + 1 for c in cfg["columns"])
+        n_par = sum(len(c["resistivity"]) + 1 for c in cfg["columns"]) + 1
         out.update({"n_params": n_par, "forward_ms": fwd, "backward_ms": bwd,
                     "backward_stage_ms": {k: round(v, 4) for k, v in stages.items()},
                     "central_difference_scan_ms": 2 * n_par * fwd,
-                    "note": "backward = wt_h_gradient (event projection, transposed FP64 solves, contraction); "
-                            "the scan it replaces needs 2 forward solves per parameter"})
+                    "note": "backward = wt_h_gradient (event projections, transposed FP64 solves, contraction) for "
+                            "5 resistivities, 2 radii and the pitch; the scan it replaces needs 2 forward solves "
+                            "per parameter"})
     th, tp32, qw32 = grads[wt.WT_F32]
     _, tp64, qw64 = grads[wt.WT_F64]
     slots = [(w, p) for w, c in enumerate(cfg["columns"]) for p in list(range(len(c["resistivity"]))) + [4]]
 
     def logd(g):
-        return np.array([th[w, p] * g[w, p] for w, p in slots])
+        # log-derivatives: theta dL/dtheta per live slot, then pitch dL/dpitch
+        return np.array([th[w, p] * g[5 * w + p] for w, p in slots] + [g[-1]])
 
     def rel(a, b):
         return float(np.max(np.abs(logd(a) - logd(b))) / np.max(np.abs(logd(b))))
 
     out["log_gradient_t_peak_s"] = {"readout_rho": float(logd(tp32)[0]),
                                     "bias_rho_sum": float(sum(logd(tp32)[2:6])),
-                                    "readout_radius": float(logd(tp32)[1]), "bias_radius": float(logd(tp32)[6])}
+                                    "readout_radius": float(logd(tp32)[1]), "bias_radius": float(logd(tp32)[6]),
+                                    "pitch": float(logd(tp32)[7])}
     out["rel_err_float32_vs_float64_adjoint"] = {"t_peak": rel(tp32, tp64), "q_w": rel(qw32, qw64)}
     return out
 

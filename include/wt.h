@@ -249,15 +249,22 @@ wt_status wt_electronics(wt_context* ctx, int precision, int n_tracks, int n_tim
 wt_status wt_h_gradient_workspace(const wt_h_plan* plan, int n_tracks, size_t* bytes);
 
 /* Gradient of a loss L of the currents with respect to every column's
- * quarter-column resistivities and radius (the electrode parameters of the
- * paper's Section 4 studies: resistance R = 4 rho L / (pi d^2) through the
- * resistivity and the diameter), by the adjoint of the whole path.
+ * quarter-column resistivities and radius and to the pixel pitch (the
+ * electrode parameters of the paper's Section 4 studies: resistance
+ * R = 4 rho L / (pi d^2) through the resistivity and the diameter, and the
+ * pixel geometry), by the adjoint of the whole path.
  *   d_grad_current [n_tracks][n_time]: dL/di, element type of the plan's
  *     precision;
- *   d_grad_params  [n_cols][5] double (overwritten): dL/d resistivity[p]
- *     (ohm*m) for p < n_resistivity (0 in the unused slots), then dL/d radius
- *     (m).
- * The carriers are those given to wt_current; their polylines are held fixed.
+ *   d_grad_params  [n_cols*5 + 1] double (overwritten): for column w,
+ *     [5w + p] = dL/d resistivity[p] (ohm*m) for p < n_resistivity (0 in the
+ *     unused slots) and [5w + 4] = dL/d radius (m); then [5 n_cols] =
+ *     dL/d pitch (m): the derivative under a uniform scaling of the in-plane
+ *     cell size L_x, L_y, the column axes and the carriers' in-plane
+ *     coordinates (the grid counts, radii and z extents held), per metre of
+ *     L_x.
+ * The carriers are those given to wt_current.  For the resistivities and
+ * radii their polylines are held fixed; for the pitch their in-plane
+ * coordinates scale with the cell (trilinear weights unchanged).
  * d_workspace must hold what wt_h_solve wrote for this plan (the collocation
  * matrix, the charges q(w) of every frequency and the field table); it is
  * only read.  H itself is not needed: the adjoint projects every moving step
@@ -267,7 +274,10 @@ wt_status wt_h_gradient_workspace(const wt_h_plan* plan, int n_tracks, size_t* b
  * LU with partial pivoting and refinement) and contracts lambda with
  * dS/dtheta: the RC-line block through the column conductivity and radius,
  * the collocation matrix through the collocation offset r and the source
- * width r/4.
+ * width r/4 (and the cell size for the pitch).  For the pitch the current also
+ * changes at fixed charges, through the field table and the in-plane
+ * displacements: a second projection of the moving steps, with the pitch
+ * derivative of the field table, is taken against the column spectra.
  * d_grad_workspace: >= wt_h_gradient_workspace bytes, 256-byte aligned,
  * overwritten.  Plans with more than 128 charges: WT_E_UNSUPPORTED_SIZE.
  * With report != NULL the call synchronises and reports the transposed

@@ -22,6 +22,12 @@ S(w) [q; c] = b of the boundary fit:
 Then dq(w) = -S(w)^-1 (dS/dtheta) [q; c] at every frequency, and the rest of
 the path is linear in the charges: the time quadrature, the bulk field and the
 convolution map dq to dH and di exactly as they map q to H and i.
+
+The pitch (a uniform scaling of the in-plane cell size, the column axes and
+the carriers' in-plane coordinates, the grid counts held) also changes the
+bulk field's mode set and the carrier displacements; its reference here is
+the central difference of the whole forward pipeline (``pitch_derivative``),
+not a forward-mode derivative.
 """
 from __future__ import annotations
 
@@ -184,3 +190,31 @@ def perturbed_columns(columns, param, value):
 def parameter_value(columns, param):
     w, kind, p = param
     return columns[w]["resistivity"][p] if kind == "rho" else columns[w]["radius"]
+
+
+def scaled_geometry(cell, columns, carriers, scale):
+    """The cell, columns and carriers with the in-plane size scaled by ``scale``."""
+    L = cell["L"]
+    c2 = dict(cell, L=(L[0] * scale, L[1] * scale, L[2]))
+    cols = [dict(c, x=c["x"] * scale, y=c["y"] * scale, resistivity=list(c["resistivity"])) for c in columns]
+    pos = np.array(carriers["pos"], dtype=np.float64, copy=True)
+    pos[..., :2] *= scale
+    car = dict(carriers, pos=pos)
+    return c2, cols, car
+
+
+def currents_at_scale(cell, columns, spectrum, carriers, scale):
+    """Currents of the whole pipeline (FFT field route) at an in-plane scale."""
+    c2, cols, car = scaled_geometry(cell, columns, carriers, scale)
+    s = green.smoothing_widths(c2, cols)
+    sol = collocation.solve_spectrum(c2, cols, spectrum)
+    H = field.field_fft(c2, s, collocation.sources(cols), timegrid.to_time(sol["q"], spectrum))
+    return pipeline.induced_current(H, c2, car)
+
+
+def pitch_derivative(cell, columns, spectrum, carriers, rel_step=1e-4):
+    """di/d(pitch) (per metre of L_x) by central differences of the pipeline."""
+    ip = currents_at_scale(cell, columns, spectrum, carriers, 1.0 + rel_step)
+    im = currents_at_scale(cell, columns, spectrum, carriers, 1.0 - rel_step)
+    return (ip - im) / (2.0 * rel_step * cell["L"][0])
+

@@ -234,8 +234,16 @@ wt::GradLayout grad_layout(const Plan& p, int n_tracks) {
     size_t off = 0;
     g.off_phi = off;
     off = align256(off + (size_t)n_tracks * p.n_time * p.n_cols * p.nzh * cx);
+    g.off_phis = off;
+    off = align256(off + (size_t)n_tracks * p.n_time * p.n_cols * p.nzh * cx);
     g.off_gamma = off;
     off = align256(off + (size_t)p.n_time * p.n_cols * p.nzh * 16);
+    g.off_gammas = off;
+    off = align256(off + (size_t)p.n_time * p.n_cols * p.nzh * 16);
+    g.off_eds = off;
+    off = align256(off + (size_t)p.N[0] * p.N[1] * p.nzh * 3 * cx);
+    g.off_pitch = off;
+    off = align256(off + (size_t)p.n_time * 8);
     g.off_gbar = off;
     off = align256(off + (size_t)p.n_time * p.n_q * 8);
     g.off_rhs = off;
@@ -249,9 +257,9 @@ wt::GradLayout grad_layout(const Plan& p, int n_tracks) {
     g.off_K = off;
     off = align256(off + (size_t)p.n_q * p.n_q * 8);
     g.off_gd = off;
-    off = align256(off + (size_t)2 * p.n_cols * p.n_cols * p.nkz_tab * 8);
+    off = align256(off + (size_t)3 * p.n_cols * p.n_cols * p.nkz_tab * 8);
     g.off_prod = off;
-    off = align256(off + (size_t)2 * p.n_q * p.n_q * 8);
+    off = align256(off + (size_t)3 * p.n_q * p.n_q * 8);
     g.bytes = off;
     return g;
 }
@@ -507,6 +515,7 @@ wt_status wt_h_gradient(wt_context* ctx, const wt_h_plan* plan, const void* d_wo
     char* gb = static_cast<char*>(d_grad_workspace);
     if ((st = mark(ctx, -1)) != WT_OK) return st;
     WT_HIP(ctx, wt::launch_lattice_derivatives(p, reinterpret_cast<double*>(gb + g.off_gd), s), "lattice_derivatives");
+    WT_HIP(ctx, wt::launch_field_table_pitch_derivative(p, d_workspace, gb + g.off_eds, s), "field_table_derivative");
     WT_HIP(ctx, wt::launch_adjoint_rhs(p, g, d_workspace, car->n_carriers, car->d_pos, car->d_charge, car->d_track,
                                        d_grad_current, d_grad_workspace, s),
            "adjoint_projection");

@@ -86,15 +86,19 @@ struct Plan {
 struct GradLayout {
     int n_tracks;
     size_t off_phi;      // [n_tracks][n_time][n_cols][nzh] complex, path precision: event projections
+    size_t off_phis;     // the same for the pitch derivative of the current at fixed charges
     size_t off_gamma;    // [n_time][n_cols][nzh] complex double: dL/d(column spectra)
+    size_t off_gammas;   // the same lag correlation of the pitch projections
+    size_t off_eds;      // [N_x][N_y][nzh][3] complex, path precision: pitch derivative of the field table
+    size_t off_pitch;    // [n_time] double: per-lag terms of the pitch derivative at fixed charges
     size_t off_gbar;     // [n_time][n_q] double: dL/dq(t)
     size_t off_rhs;      // [n_freq][n] complex double: right-hand sides of the transposed solves
     size_t off_lam;      // [n_freq][n] complex double: adjoint charges
     size_t off_rep;      // [n_freq] SolveReport of the transposed solves
     size_t off_part;     // [n_freq][n_cols][2] double: per-frequency RC-line terms
     size_t off_K;        // [n_q][n_q] double: sum over frequencies of Re(lambda_i q_j)
-    size_t off_gd;       // [2][n_cols][n_cols][nkz_tab] double: lattice-sum derivatives
-    size_t off_prod;     // [2][n_q][n_q] double: collocation-matrix derivative terms
+    size_t off_gd;       // [3][n_cols][n_cols][nkz_tab] double: lattice-sum derivatives
+    size_t off_prod;     // [3][n_q][n_q] double: collocation-matrix derivative terms
     size_t bytes;
 };
 
@@ -124,6 +128,7 @@ hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tr
 // the event projection to dL/dq(w) (right-hand sides) and the final
 // contraction to the parameter gradient.
 hipError_t launch_lattice_derivatives(const Plan& p, double* gd, hipStream_t s);
+hipError_t launch_field_table_pitch_derivative(const Plan& p, const void* ws, void* out, hipStream_t s);
 hipError_t launch_adjoint_solve(const Plan& p, const void* ws, const void* rhs, void* lam, void* rep,
                                 hipStream_t s);
 hipError_t launch_adjoint_rhs(const Plan& p, const GradLayout& g, const void* ws, int n_carriers,

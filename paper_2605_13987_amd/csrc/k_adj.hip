@@ -24,6 +24,14 @@
 //    sum_{l >= 1} (sum_{m >= l} l_m)(sum_{m >= l} q_m)), and the collocation
 //    matrix through r (collocation offset of its rows, source width r/4 of its
 //    columns), contracted with K_ij = sum_f Re[lambda_i q_j].
+// 7. Pitch: a uniform scaling by s of the in-plane cell size, the column axes
+//    and the carriers' in-plane coordinates.  The trilinear weights and the
+//    column spectra are unchanged; the current changes at fixed charges
+//    through the field table (dEhat/ds) and the in-plane displacements, i.e.
+//    by the projections phi^s = -q m_k sum_v w_v e^{...} (dx . dEhat/ds +
+//    dx_x Ehat_x + dx_y Ehat_y), which give dL/ds = sum_{t,w,k} Re[Gamma^s
+//    Qhat]; and the boundary fit through dA/ds (a third lattice-sum table and
+//    -2 A from the cell volume), taken with lambda as in step 6.
 #include "common.hpp"
 
 #include <algorithm>
@@ -72,8 +80,8 @@ __device__ inline int wrap_cell(T f, int n) {
 // changes.  The corners and weights follow the forward convolution exactly.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_adj_events(Plan p, const cplx<T>* ehat, const cplx<T>* twz, int n_carriers, int n_tracks, const T* pos,
-             const T* charge, const int* track, int chunk, cplx<T>* phi) {
+k_adj_events(Plan p, const cplx<T>* ehat, const cplx<T>* eds, const cplx<T>* twz, int n_carriers, int n_tracks,
+             const T* pos, const T* charge, const int* track, int chunk, cplx<T>* phi, cplx<T>* phis) {
     const int m = blockIdx.x;
     const int c0 = blockIdx.y * chunk;
     const int c1 = min(n_carriers, c0 + chunk);
@@ -81,25 +89,29 @@ k_adj_events(Plan p, const cplx<T>* ehat, const cplx<T>* twz, int n_carriers, in
     const int n_items = W * nzh;
     int wi[kItems], kk[kItems];
     bool ok[kItems];
-    cplx<T> acc[kItems];
+    cplx<T> acc[kItems], accs[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int it = (blockIdx.z * kItems + j) * kBlock + threadIdx.x;
         ok[j] = it < n_items;
         wi[j] = ok[j] ? it / nzh : 0;
         kk[j] = ok[j] ? it - wi[j] * nzh : 0;
-        acc[j] = cplx<T>{(T)0, (T)0};
+        acc[j] = accs[j] = cplx<T>{(T)0, (T)0};
     }
     int cur = -1;
     auto flush = [&]() {
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
+            const size_t o = (((size_t)cur * nt + m) * W + wi[j]) * nzh + kk[j];
             if (cur >= 0 && ok[j] && (acc[j].re != (T)0 || acc[j].im != (T)0)) {
-                cplx<T>* d = phi + (((size_t)cur * nt + m) * W + wi[j]) * nzh + kk[j];
-                atomicAdd(&d->re, acc[j].re);
-                atomicAdd(&d->im, acc[j].im);
+                atomicAdd(&phi[o].re, acc[j].re);
+                atomicAdd(&phi[o].im, acc[j].im);
             }
-            acc[j] = cplx<T>{(T)0, (T)0};
+            if (cur >= 0 && ok[j] && (accs[j].re != (T)0 || accs[j].im != (T)0)) {
+                atomicAdd(&phis[o].re, accs[j].re);
+                atomicAdd(&phis[o].im, accs[j].im);
+            }
+            acc[j] = accs[j] = cplx<T>{(T)0, (T)0};
         }
     };
     for (int c = c0; c < c1; ++c) {
@@ -131,16 +143,28 @@ k_adj_events(Plan p, const cplx<T>* ehat, const cplx<T>* twz, int n_carriers, in
             const int k = kk[j];
             const int sx0 = (x0 - col.ix + Nx) % Nx, sx1 = (x1 - col.ix + Nx) % Nx;
             const int sy0 = (y0 - col.iy + Ny) % Ny, sy1 = (y1 - col.iy + Ny) % Ny;
-            auto proj = [&](int sx, int sy) {
-                const cplx<T>* e = ehat + (((size_t)sx * Ny + sy) * nzh + k) * 3;
-                const cplx<T> a = e[0], b = e[1], cz = e[2];
-                return cplx<T>{a.re * dx + b.re * dy + cz.re * dz, a.im * dx + b.im * dy + cz.im * dz};
+            // dx . Ehat at one (x, y) corner into pe; dx . dEhat/ds + the
+            // in-plane part of dx . Ehat into ps
+            cplx<T> v{(T)0, (T)0}, vs{(T)0, (T)0};
+            auto proj = [&](int sx, int sy, T wxy) {
+                const size_t o = (((size_t)sx * Ny + sy) * nzh + k) * 3;
+                const cplx<T> a = ehat[o], b = ehat[o + 1], cz = ehat[o + 2];
+                const cplx<T> da = eds[o], db = eds[o + 1], dc = eds[o + 2];
+                const cplx<T> pxy{a.re * dx + b.re * dy, a.im * dx + b.im * dy};
+                const cplx<T> pe{pxy.re + cz.re * dz, pxy.im + cz.im * dz};
+                const cplx<T> ps{pxy.re + da.re * dx + db.re * dy + dc.re * dz,
+                                 pxy.im + da.im * dx + db.im * dy + dc.im * dz};
+                v = v + scale(pe, wxy);
+                vs = vs + scale(ps, wxy);
             };
-            const cplx<T> v = scale(proj(sx0, sy0), gx * gy) + scale(proj(sx0, sy1), gx * fy) +
-                              scale(proj(sx1, sy0), fx * gy) + scale(proj(sx1, sy1), fx * fy);
+            proj(sx0, sy0, gx * gy);
+            proj(sx0, sy1, gx * fy);
+            proj(sx1, sy0, fx * gy);
+            proj(sx1, sy1, fx * fy);
             const cplx<T> ph = scale(twz[(k * z0) % Nz], gz) + scale(twz[(k * z1) % Nz], fz);
             const T mq = k == 0 ? -q : (T)(-2) * q;
             acc[j] = acc[j] + scale(v * ph, mq);
+            accs[j] = accs[j] + scale(vs * ph, mq);
         }
     }
     flush();
@@ -196,6 +220,23 @@ __global__ void __launch_bounds__(kBlock) k_adj_sources(Plan p, const c64* gamma
         acc += g[k].re * cs + g[k].im * s;      // Re[g e^{-i k_z z}]
     }
     gbar[(size_t)t * p.n_q + i] = acc;
+}
+
+// Step 7, fixed charges: pitch[t] = sum_{w,k} Re[Gamma^s_w(k, t) Qhat_w(k, t)],
+// one block per lag t.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_pitch_lag(Plan p, const c64* gammas, const cplx<T>* qhat,
+                                                          double* pitch) {
+    __shared__ double red[kBlock / 64];
+    const int t = blockIdx.x, n_items = p.n_cols * p.nzh;
+    double acc = 0.0;
+    for (int it = threadIdx.x; it < n_items; it += blockDim.x) {
+        const c64 g = gammas[(size_t)t * n_items + it];
+        const cplx<T> q = qhat[(size_t)t * n_items + it];
+        acc += g.re * (double)q.re - g.im * (double)q.im;
+    }
+    acc = block_sum_all(acc, red);
+    if (threadIdx.x == 0) pitch[t] = acc;
 }
 
 // Step 4.  One thread per unknown (the gauge row gets 0) and frequency.
@@ -264,7 +305,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_outer(Plan p, const c64* qw, con
 // Collocation-matrix terms: dA_ij/d(offset of row column) and dA_ij/d(width of
 // source column), each times K_ij, from the lattice-sum derivative tables as
 // the matrix itself is built from g.
-__global__ void __launch_bounds__(kBlock) k_adj_dA(Plan p, const double* gd, const double* K, double* prod) {
+__global__ void __launch_bounds__(kBlock) k_adj_dA(Plan p, const double* gd, const double* A, const double* K,
+                                                   double* prod) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (j >= p.n_q) return;
@@ -273,25 +315,30 @@ __global__ void __launch_bounds__(kBlock) k_adj_dA(Plan p, const double* gd, con
     const size_t table = (size_t)p.n_cols * p.n_cols * p.nkz_tab;
     const double* gx = gd + (size_t)(v * p.n_cols + w) * p.nkz_tab;
     const double* gs = gx + table;
-    double ax = 0.0, as = 0.0;
+    const double* gp = gs + table;
+    double ax = 0.0, as = 0.0, ap = 0.0;
     for (int iz = p.col[v].mmax[2]; iz >= 1; --iz) {
         double t = iz * u;
         t -= rint(t);
         const double c = cospi(2.0 * t);
         ax += gx[iz] * c;
         as += gs[iz] * c;
+        ap += gp[iz] * c;
     }
     const double inv = 1.0 / (p.eps * p.L[0] * p.L[1] * p.L[2]);
     const double kij = K[(size_t)i * p.n_q + j];
     const size_t nn = (size_t)p.n_q * p.n_q;
     prod[(size_t)i * p.n_q + j] = (gx[0] + 2.0 * ax) * inv * kij;
     prod[nn + (size_t)i * p.n_q + j] = kColWidthFraction * (gs[0] + 2.0 * as) * inv * kij;
+    // pitch: the lattice-sum derivative and -2 A from the cell volume
+    prod[2 * nn + (size_t)i * p.n_q + j] = ((gp[0] + 2.0 * ap) * inv - 2.0 * A[(size_t)i * p.n_q + j]) * kij;
 }
 
 // Final reduction, one block: out[w][0..3] = dL/d resistivity (0 past
-// n_resistivity), out[w][4] = dL/d radius.
+// n_resistivity), out[w][4] = dL/d radius, out[5 n_cols] = dL/d pitch (per
+// metre of L_x: the scale derivative divided by L_x).
 __global__ void __launch_bounds__(kBlock) k_adj_params(Plan p, const double* part, const double* prod,
-                                                       double* out) {
+                                                       const double* pitch, double* out) {
     __shared__ double red[kBlock / 64];
     const int tid = threadIdx.x, nq = p.n_q, W = p.n_cols;
     const size_t nn = (size_t)nq * nq;
@@ -320,30 +367,47 @@ __global__ void __launch_bounds__(kBlock) k_adj_params(Plan p, const double* par
             out[w * 5 + 4] = s1 - sx - ss;
         }
     }
+    double sp = 0.0, sq = 0.0;
+    for (size_t idx = tid; idx < nn; idx += blockDim.x) sp += prod[2 * nn + idx];
+    for (int t = tid; t < p.n_time; t += blockDim.x) sq += pitch[t];
+    sp = block_sum_all(sp, red);
+    sq = block_sum_all(sq, red);
+    if (tid == 0) out[W * 5] = (sq - sp) / p.L[0];
 }
 
 template <typename T>
 hipError_t adjoint_rhs(const Plan& p, const GradLayout& g, const char* ws, int n_carriers, const T* pos,
                        const T* charge, const int* track, const T* grad_i, char* gws, hipStream_t s) {
     cplx<T>* phi = reinterpret_cast<cplx<T>*>(gws + g.off_phi);
+    cplx<T>* phis = reinterpret_cast<cplx<T>*>(gws + g.off_phis);
     const int n_items = p.n_cols * p.nzh;
     const size_t n_phi = (size_t)g.n_tracks * p.n_time * n_items * 2;
     const int zgrid = (int)std::min<size_t>((n_phi + kBlock - 1) / kBlock, 4096);
     hipLaunchKernelGGL(k_adj_fill<T>, dim3(zgrid), dim3(kBlock), 0, s, reinterpret_cast<T*>(phi), n_phi);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_fill<T>, dim3(zgrid), dim3(kBlock), 0, s, reinterpret_cast<T*>(phis), n_phi);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n_carriers > 0) {
         const int chunk = std::max(64, (n_carriers + 65534) / 65535);
         dim3 grid(p.n_time, (n_carriers + chunk - 1) / chunk, (n_items + kItems * kBlock - 1) / (kItems * kBlock));
         hipLaunchKernelGGL(k_adj_events<T>, grid, dim3(kBlock), 0, s, p,
                            reinterpret_cast<const cplx<T>*>(ws + p.off_ehat),
+                           reinterpret_cast<const cplx<T>*>(gws + g.off_eds),
                            reinterpret_cast<const cplx<T>*>(ws + p.off_tw[2]), n_carriers, g.n_tracks, pos, charge,
-                           track, chunk, phi);
+                           track, chunk, phi, phis);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     c64* gamma = reinterpret_cast<c64*>(gws + g.off_gamma);
     hipLaunchKernelGGL(k_adj_gamma<T>, dim3((n_items + kBlock - 1) / kBlock, p.n_time), dim3(kBlock), 0, s, p,
                        g.n_tracks, (const cplx<T>*)phi, grad_i, gamma);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    c64* gammas = reinterpret_cast<c64*>(gws + g.off_gammas);
+    hipLaunchKernelGGL(k_adj_gamma<T>, dim3((n_items + kBlock - 1) / kBlock, p.n_time), dim3(kBlock), 0, s, p,
+                       g.n_tracks, (const cplx<T>*)phis, grad_i, gammas);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_pitch_lag<T>, dim3(p.n_time), dim3(kBlock), 0, s, p, (const c64*)gammas,
+                       reinterpret_cast<const cplx<T>*>(ws + p.off_qhat), reinterpret_cast<double*>(gws + g.off_pitch));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     double* gbar = reinterpret_cast<double*>(gws + g.off_gbar);
     hipLaunchKernelGGL(k_adj_sources, dim3((p.n_q + kBlock - 1) / kBlock, p.n_time), dim3(kBlock), 0, s, p,
@@ -383,9 +447,11 @@ hipError_t launch_adjoint_params(const Plan& p, const GradLayout& g, const void*
     hipLaunchKernelGGL(k_adj_outer, dim3((p.n_q + kBlock - 1) / kBlock, p.n_q), dim3(kBlock), 0, s, p, qw, lam, K);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_dA, dim3((p.n_q + kBlock - 1) / kBlock, p.n_q), dim3(kBlock), 0, s, p,
-                       reinterpret_cast<const double*>(gb + g.off_gd), (const double*)K, prod);
+                       reinterpret_cast<const double*>(gb + g.off_gd), reinterpret_cast<const double*>(b + p.off_A),
+                       (const double*)K, prod);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(kBlock), 0, s, p, (const double*)part, (const double*)prod, out);
+    hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(kBlock), 0, s, p, (const double*)part, (const double*)prod,
+                       reinterpret_cast<const double*>(gb + g.off_pitch), out);
     return hipGetLastError();
 }
 

@@ -24,8 +24,12 @@ namespace {
 constexpr int kBlock = 256;
 constexpr size_t kLineLds = 64 * 1024;
 
+// deriv = 1: the derivative of M(k) under a uniform scaling of the cell's
+// in-plane size (pitch) by s, at s = 1, with the grid counts held: k_x and
+// k_y scale as 1/s, k_x s_x and k_y s_y are unchanged and V scales as s^2, so
+// dM_a/ds = M_a (2 (k_x^2 + k_y^2)/|k|^2 - 2 - [a in {x, y}]).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_multiplier(Plan p, cplx<T>* e) {
+__global__ void __launch_bounds__(kBlock) k_multiplier(Plan p, int deriv, cplx<T>* e) {
     const int Nx = p.N[0], Ny = p.N[1], nzh = p.nzh;
     const size_t total = (size_t)Nx * Ny * nzh;
     const double vol = p.L[0] * p.L[1] * p.L[2];
@@ -47,9 +51,11 @@ __global__ void __launch_bounds__(kBlock) k_multiplier(Plan p, cplx<T>* e) {
         const double k2 = kx * kx + ky * ky + kz * kz;
         const double ax = kx * p.s_bulk[0], ay = ky * p.s_bulk[1], az = kz * p.s_bulk[2];
         const double w = exp(-0.5 * (ax * ax + ay * ay + az * az)) / (k2 * p.eps * vol);
-        out[0] = cplx<T>{(T)0, (T)(-kx * w)};
-        out[1] = cplx<T>{(T)0, (T)(-ky * w)};
-        out[2] = cplx<T>{(T)0, (T)(-kz * w)};
+        const double d = deriv ? 2.0 * (kx * kx + ky * ky) / k2 - 2.0 : 1.0;
+        const double dxy = deriv ? d - 1.0 : 1.0;
+        out[0] = cplx<T>{(T)0, (T)(-kx * w * dxy)};
+        out[1] = cplx<T>{(T)0, (T)(-ky * w * dxy)};
+        out[2] = cplx<T>{(T)0, (T)(-kz * w * d)};
     }
 }
 
@@ -580,12 +586,12 @@ int lines_per_block(int N) {
     return lpb;
 }
 
+// The field table (deriv = 0) or its pitch derivative (deriv = 1) into e.
 template <typename T>
-hipError_t field_table(const Plan& p, char* b, hipStream_t s) {
-    cplx<T>* e = reinterpret_cast<cplx<T>*>(b + p.off_ehat);
+hipError_t field_table(const Plan& p, char* b, cplx<T>* e, int deriv, hipStream_t s) {
     const size_t total = (size_t)p.N[0] * p.N[1] * p.nzh;
     const int grid = (int)((total + kBlock - 1) / kBlock < 65536 ? (total + kBlock - 1) / kBlock : 65536);
-    hipLaunchKernelGGL(k_multiplier<T>, dim3(grid), dim3(kBlock), 0, s, p, e);
+    hipLaunchKernelGGL(k_multiplier<T>, dim3(grid), dim3(kBlock), 0, s, p, deriv, e);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int C = p.nzh * 3;
@@ -674,7 +680,14 @@ hipError_t synthesis(const Plan& p, char* b, void* h, hipStream_t s) {
 
 hipError_t launch_field_table(const Plan& p, void* ws, hipStream_t s) {
     char* b = static_cast<char*>(ws);
-    return p.precision == 0 ? field_table<double>(p, b, s) : field_table<float>(p, b, s);
+    return p.precision == 0 ? field_table<double>(p, b, reinterpret_cast<cplx<double>*>(b + p.off_ehat), 0, s)
+                            : field_table<float>(p, b, reinterpret_cast<cplx<float>*>(b + p.off_ehat), 0, s);
+}
+
+hipError_t launch_field_table_pitch_derivative(const Plan& p, const void* ws, void* out, hipStream_t s) {
+    char* b = const_cast<char*>(static_cast<const char*>(ws));   // twiddles only are read from ws
+    return p.precision == 0 ? field_table<double>(p, b, static_cast<cplx<double>*>(out), 1, s)
+                            : field_table<float>(p, b, static_cast<cplx<float>*>(out), 1, s);
 }
 
 hipError_t launch_h_scale(const Plan& p, void* ws, void* h, hipStream_t s) {

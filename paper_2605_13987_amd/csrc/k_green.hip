@@ -46,7 +46,11 @@ __global__ void k_twiddles(int n0, int n1, int n2, cplx<T>* t0, cplx<T>* t1, cpl
 // g_vw(k_z); kind 1: its derivative in the in-plane offset dx (collocation
 // column's radius), sum exp(-k^2 s^2/2)/k^2 (-k_x sin(k_x dx + k_y dy));
 // kind 2: its derivative in the source width s, sum -s exp(-k^2 s^2/2)
-// cos(k_x dx + k_y dy).
+// cos(k_x dx + k_y dy); kind 3: its derivative under a uniform scaling of the
+// in-plane cell size and column positions by t (pitch), at t = 1: k_x, k_y
+// scale as 1/t and the offset dx as (X_w - X_v) t + r, so with f =
+// exp(-k^2 s^2/2)/k^2 the term is f (s^2 + 2/k^2)(k_x^2 + k_y^2) cos(k_x dx +
+// k_y dy) + f k_x r sin(k_x dx + k_y dy).
 __global__ void __launch_bounds__(kBlock) k_lattice(Plan p, int kind, double* g) {
     __shared__ double red[kBlock / 64];
     const int iz = blockIdx.x;
@@ -80,8 +84,10 @@ __global__ void __launch_bounds__(kBlock) k_lattice(Plan p, int kind, double* g)
             acc += e / k2 * cospi(2.0 * u);
         else if (kind == 1)
             acc -= e / k2 * kx * sinpi(2.0 * u);
-        else
+        else if (kind == 2)
             acc -= sc * e * cospi(2.0 * u);
+        else
+            acc += e / k2 * ((sc * sc + 2.0 / k2) * (kx * kx + ky * ky) * cospi(2.0 * u) + kx * cw.radius * sinpi(2.0 * u));
     }
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) out[iz] = s;
@@ -150,7 +156,7 @@ hipError_t launch_green_tables(const Plan& p, void* ws, hipStream_t s) {
 
 hipError_t launch_lattice_derivatives(const Plan& p, double* gd, hipStream_t s) {
     const size_t table = (size_t)p.n_cols * p.n_cols * p.nkz_tab;
-    for (int kind = 1; kind <= 2; ++kind) {
+    for (int kind = 1; kind <= 3; ++kind) {
         hipLaunchKernelGGL(k_lattice, dim3(p.nkz_tab, p.n_cols * p.n_cols), dim3(kBlock), 0, s, p, kind,
                            gd + (kind - 1) * table);
         const hipError_t e = hipGetLastError();

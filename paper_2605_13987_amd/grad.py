@@ -5,7 +5,9 @@ adjoint (wt_h_gradient).
 The parameters are, per column, its quarter-column resistivities and its
 radius, packed as a CPU float64 tensor theta[n_cols][5]: resistivity[p] (ohm
 m) in slots p < n_resistivity, the radius (m) in slot 4; unused slots are
-ignored and get a zero gradient.  The backward reads only the solve's
+ignored and get a zero gradient; and the pitch (a CPU float64 scalar tensor,
+m): the in-plane cell size L_x, with L_y, the column axes and the carriers'
+in-plane coordinates scaled by the same factor.  The backward reads only the solve's
 workspace (collocation matrix, charges q(w), field table): H is released as
 soon as the currents are computed and is never recomputed, so the forward's
 FFT stages need no storage at all in the backward.
@@ -74,48 +76,74 @@ class ColumnModel:
             out.append(dict(c, resistivity=[float(th[w, p]) for p in range(n)], radius=float(th[w, 4])))
         return out
 
-    def solve(self, theta):
-        """Plan, solve and currents at theta -> (_Plan, currents [n_tracks][n_time])."""
-        handle, lay = wt.wt_h_plan_create(self.cell, self.columns_at(theta), self.spectrum, self.precision,
-                                          self.ir_max_iter, self.ir_tol)
+    def pitch0(self):
+        """The model's own pitch (L_x) as a CPU float64 scalar tensor."""
+        return torch.tensor(float(self.cell["L"][0]), dtype=torch.float64)
+
+    def geometry_at(self, theta, pitch=None):
+        """(cell, columns, positions) at theta and pitch (positions on the device)."""
+        cols = self.columns_at(theta)
+        if pitch is None:
+            return self.cell, cols, self.pos
+        s = float(pitch) / float(self.cell["L"][0])
+        if s == 1.0:
+            return self.cell, cols, self.pos
+        L = self.cell["L"]
+        cell = dict(self.cell, L=(L[0] * s, L[1] * s, L[2]))
+        cols = [dict(c, x=c["x"] * s, y=c["y"] * s) for c in cols]
+        pos = self.pos.clone()
+        pos[..., :2] *= s
+        return cell, cols, pos
+
+    def solve(self, theta, pitch=None):
+        """Plan, solve and currents at theta (and pitch) -> (_Plan, currents [n_tracks][n_time])."""
+        cell, cols, pos = self.geometry_at(theta, pitch)
+        handle, lay = wt.wt_h_plan_create(cell, cols, self.spectrum, self.precision, self.ir_max_iter, self.ir_tol)
         ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device=self.pos.device)
         plan = _Plan(handle, lay, ws)
         hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device=self.pos.device)
         wt.wt_h_solve(self.ctx, handle, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), hbuf.numel())
         out = torch.empty((self.n_tracks, self.spectrum["n_time"]), dtype=self.dtype, device=self.pos.device)
-        wt.wt_current(self.ctx, handle, hbuf.data_ptr(), self.pos.shape[0], self.n_tracks, self.pos.data_ptr(),
+        wt.wt_current(self.ctx, handle, hbuf.data_ptr(), pos.shape[0], self.n_tracks, pos.data_ptr(),
                       self.charge.data_ptr(), self.track.data_ptr(), out.data_ptr())
+        plan.pos = pos
         # H is consumed in stream order; dropping the last reference lets the
         # caching allocator reuse it for work enqueued after this point.
         del hbuf
         return plan, out
 
     def gradient(self, plan, grad_current):
-        """dL/dtheta [n_cols][5] (CPU float64) for dL/di on the device."""
+        """(dL/dtheta [n_cols][5], dL/dpitch []) (CPU float64) for dL/di on the device."""
         g = grad_current.to(self.dtype).contiguous()
         nbytes = wt.wt_h_gradient_workspace(plan.handle, self.n_tracks)
         gws = torch.empty(nbytes, dtype=torch.uint8, device=self.pos.device)
-        out = torch.empty((len(self.columns), 5), dtype=torch.float64, device=self.pos.device)
-        wt.wt_h_gradient(self.ctx, plan.handle, plan.ws.data_ptr(), plan.ws.numel(), self.pos.shape[0],
-                         self.n_tracks, self.pos.data_ptr(), self.charge.data_ptr(), self.track.data_ptr(),
+        n = len(self.columns)
+        out = torch.empty(5 * n + 1, dtype=torch.float64, device=self.pos.device)
+        pos = plan.pos
+        wt.wt_h_gradient(self.ctx, plan.handle, plan.ws.data_ptr(), plan.ws.numel(), pos.shape[0],
+                         self.n_tracks, pos.data_ptr(), self.charge.data_ptr(), self.track.data_ptr(),
                          g.data_ptr(), gws.data_ptr(), nbytes, out.data_ptr())
-        return out.cpu()
+        out = out.cpu()
+        return out[:5 * n].view(n, 5), out[5 * n]
 
-    def currents(self, theta):
+    def currents(self, theta, pitch=None):
         """Differentiable currents [n_tracks][n_time] on the device."""
-        return ColumnCurrents.apply(theta, self)
+        if pitch is None:
+            pitch = self.pitch0()
+        return ColumnCurrents.apply(theta, pitch, self)
 
 
 class ColumnCurrents(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, theta, model):
-        plan, out = model.solve(theta)
+    def forward(ctx, theta, pitch, model):
+        plan, out = model.solve(theta, pitch)
         ctx.plan, ctx.model = plan, model
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
-        return ctx.model.gradient(ctx.plan, grad_out), None
+        g_theta, g_pitch = ctx.model.gradient(ctx.plan, grad_out)
+        return g_theta, g_pitch, None
 
 
 def signal_features(i, dt, t_center, t_sigma, t_max):

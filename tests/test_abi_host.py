@@ -165,8 +165,9 @@ def test_gradient_workspace_and_validation():
         n1 = wt.wt_h_gradient_workspace(plan, 1)
         n100 = wt.wt_h_gradient_workspace(plan, 100)
         nq, nf, nt, nzh = lay["n_q"], spec["n_freq"], spec["n_time"], cell["N"][2] // 2
-        # per extra track: one [n_time][n_cols][N_z/2] complex float block of event projections
-        assert n100 - n1 >= 99 * nt * 2 * nzh * 8 and n100 - n1 <= 99 * nt * 2 * nzh * 8 + 512
+        # per extra track: two [n_time][n_cols][N_z/2] complex float blocks of event projections
+        per = 2 * nt * 2 * nzh * 8
+        assert 99 * per <= n100 - n1 <= 99 * per + 1024
         assert n1 >= nq * nq * 8 * 3 + 2 * nf * (nq + 1) * 16
         n = ctypes.c_size_t()
         assert wt.LIB.wt_h_gradient_workspace(plan, 0, ctypes.byref(n)) == wt.WT_E_INVALID_ARG

@@ -1,8 +1,9 @@
 """GPU parity of the adjoint (wt_h_gradient, behind torch.autograd):
 
 * small multi-tile case, both precisions: the adjoint gradient of a seeded
-  loss against the FP64 oracle's forward-mode derivatives (FP64 path 1e-6,
-  FP32 path 1e-3, relative to the largest log-derivative);
+  loss against the FP64 oracle's forward-mode derivatives, and for the pitch
+  against the oracle's central differences (FP64 path 1e-6, FP32 path 1e-3,
+  relative to the largest log-derivative);
 * the 128x128x256 pixel with its MIP track: the FP64 adjoint against central
   differences of the GPU's own FP64 forward (1e-5), and the FP32 adjoint
   against the FP64 one (1e-3);
@@ -54,13 +55,15 @@ def test_adjoint_matches_oracle_forward_mode(small, precision, tol):
     theta = model.theta0()
     G = _seeded_loss_weights(car["n_tracks"], cfg["spectrum"]["n_time"], 61)
     plan, cur = model.solve(theta)
-    g = model.gradient(plan, torch.as_tensor(G, device="cuda"))
+    g, gp = model.gradient(plan, torch.as_tensor(G, device="cuda"))
     torch.cuda.synchronize()
     jac, i0 = ograd.current_jacobian(cfg["cell"], cfg["columns"], cfg["spectrum"], car)
     ref = np.array([np.sum(G * jac[prm]) for prm in ograd.parameter_names(cfg["columns"])])
+    ref_p = np.sum(G * ograd.pitch_derivative(cfg["cell"], cfg["columns"], cfg["spectrum"], car))
     th = theta.numpy()
-    ref_log = np.array([th[w, s] * r for (w, s), r in zip(_slots(cfg["columns"]), ref)])
-    got_log = _log_grad(th, g.numpy(), cfg["columns"])
+    p0 = cfg["cell"]["L"][0]
+    ref_log = np.array([th[w, s] * r for (w, s), r in zip(_slots(cfg["columns"]), ref)] + [p0 * ref_p])
+    got_log = np.concatenate([_log_grad(th, g.numpy(), cfg["columns"]), [p0 * float(gp)]])
     err = np.max(np.abs(got_log - ref_log)) / np.max(np.abs(ref_log))
     say(f"    log-gradient ref {ref_log}\n    got {got_log}\n    max err / max = {err:.3e}")
     assert err <= tol
@@ -82,7 +85,8 @@ def test_full_size_adjoint_against_central_differences(px128):
     theta = model.theta0()
     G = torch.as_tensor(_seeded_loss_weights(1, cfg["spectrum"]["n_time"], 62), device="cuda")
     plan, _ = model.solve(theta)
-    g64 = model.gradient(plan, G).numpy()
+    g64, gp64 = model.gradient(plan, G)
+    g64 = g64.numpy()
     del plan
     fd = np.zeros_like(g64)
     for w, s in _slots(cfg["columns"]):
@@ -95,9 +99,16 @@ def test_full_size_adjoint_against_central_differences(px128):
             vals.append(float((cur * G).sum().item()))
             del p
         fd[w, s] = (vals[0] - vals[1]) / (2 * h)
+    p0 = float(model.pitch0())
+    vals = []
+    for sign in (1.0, -1.0):
+        p, cur = model.solve(theta, torch.tensor(p0 * (1.0 + sign * 1e-4), dtype=torch.float64))
+        vals.append(float((cur * G).sum().item()))
+        del p
+    fdp = (vals[0] - vals[1]) / (2e-4 * p0)
     th = theta.numpy()
-    a = _log_grad(th, g64, cfg["columns"])
-    b = _log_grad(th, fd, cfg["columns"])
+    a = np.concatenate([_log_grad(th, g64, cfg["columns"]), [p0 * float(gp64)]])
+    b = np.concatenate([_log_grad(th, fd, cfg["columns"]), [p0 * fdp]])
     err = np.max(np.abs(a - b)) / np.max(np.abs(b))
     say(f"    adjoint {a}\n    central differences {b}\n    max err / max = {err:.3e}")
     assert err <= 1e-5
@@ -105,8 +116,8 @@ def test_full_size_adjoint_against_central_differences(px128):
     say("  full-size gradient: FP32 adjoint vs FP64 adjoint")
     m32 = ColumnModel(cfg["cell"], cfg["columns"], cfg["spectrum"], cfg["carriers"], precision=wt.WT_F32)
     p32, _ = m32.solve(theta)
-    g32 = m32.gradient(p32, G).numpy()
-    c = _log_grad(th, g32, cfg["columns"])
+    g32, gp32 = m32.gradient(p32, G)
+    c = np.concatenate([_log_grad(th, g32.numpy(), cfg["columns"]), [p0 * float(gp32)]])
     err32 = np.max(np.abs(c - a)) / np.max(np.abs(a))
     say(f"    FP32 adjoint {c}\n    max err / max = {err32:.3e}")
     assert err32 <= 1e-3
@@ -121,9 +132,10 @@ def test_signal_features_through_autograd(px128):
     t_c, t_s = rng.uniform(0.5e-9, 1.5e-9), rng.uniform(0.1e-9, 0.4e-9)
     m32 = ColumnModel(cfg["cell"], cfg["columns"], cfg["spectrum"], cfg["carriers"], precision=wt.WT_F32)
     theta = m32.theta0().requires_grad_(True)
-    t_peak, q_w = signal_features(m32.currents(theta), dt, t_c, t_s, 2e-9)
-    gp = torch.autograd.grad(t_peak.sum(), theta, retain_graph=True)[0].numpy()
-    gq = torch.autograd.grad(q_w.sum(), theta)[0].numpy()
+    pitch = m32.pitch0().requires_grad_(True)
+    t_peak, q_w = signal_features(m32.currents(theta, pitch), dt, t_c, t_s, 2e-9)
+    gp, gpp = (g.numpy() for g in torch.autograd.grad(t_peak.sum(), (theta, pitch), retain_graph=True))
+    gq, gqp = (g.numpy() for g in torch.autograd.grad(q_w.sum(), (theta, pitch)))
     m64 = ColumnModel(cfg["cell"], cfg["columns"], cfg["spectrum"], cfg["carriers"], precision=wt.WT_F64)
     th0 = m64.theta0()
     fp, fq = np.zeros_like(gp), np.zeros_like(gq)
@@ -139,9 +151,19 @@ def test_signal_features_through_autograd(px128):
             del p
         fp[w, s] = (vals[0][0] - vals[1][0]) / (2 * h)
         fq[w, s] = (vals[0][1] - vals[1][1]) / (2 * h)
+    p0 = float(m64.pitch0())
+    vals = []
+    for sign in (1.0, -1.0):
+        p, cur = m64.solve(th0, torch.tensor(p0 * (1.0 + sign * 1e-4), dtype=torch.float64))
+        tp, qw = signal_features(cur, dt, t_c, t_s, 2e-9)
+        vals.append((tp.sum().item(), qw.sum().item()))
+        del p
+    fpp = (vals[0][0] - vals[1][0]) / (2e-4 * p0)
+    fqp = (vals[0][1] - vals[1][1]) / (2e-4 * p0)
     th = th0.numpy()
-    for name, got, ref in (("t_peak", gp, fp), ("q_w", gq, fq)):
-        a, b = _log_grad(th, got, cfg["columns"]), _log_grad(th, ref, cfg["columns"])
+    for name, got, ref, gpitch, fpitch in (("t_peak", gp, fp, gpp, fpp), ("q_w", gq, fq, gqp, fqp)):
+        a = np.concatenate([_log_grad(th, got, cfg["columns"]), [p0 * float(gpitch)]])
+        b = np.concatenate([_log_grad(th, ref, cfg["columns"]), [p0 * fpitch]])
         err = np.max(np.abs(a - b)) / np.max(np.abs(b))
         say(f"    {name}: adjoint {a}\n    {name}: central differences {b}\n    max err / max = {err:.3e}")
         assert err <= 2e-3

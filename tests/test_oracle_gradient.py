@@ -65,3 +65,17 @@ def test_parallel_quarter_columns_share_one_conductivity_derivative(tiny):
     scaled = [jac[prm] * cols[1]["resistivity"][prm[2]] ** 2 for prm in params]
     for s in scaled[1:]:
         assert np.linalg.norm(s - scaled[0]) <= 1e-12 * np.linalg.norm(scaled[0])
+
+
+def test_pitch_central_difference_is_converged(tiny):
+    """The pitch reference (central differences of the FP64 pipeline) does not
+    move when the step is halved: its truncation and rounding errors are far
+    below the GPU tolerances it is used with."""
+    cell, cols = tiny["cell"], tiny["columns"]
+    d1 = gradient.pitch_derivative(cell, cols, tiny["spectrum"], tiny["carriers"], 2e-4)
+    d2 = gradient.pitch_derivative(cell, cols, tiny["spectrum"], tiny["carriers"], 1e-4)
+    assert np.linalg.norm(d1 - d2) <= 1e-7 * np.linalg.norm(d2)
+    # scaling by 1 reproduces the unscaled pipeline
+    i1 = gradient.currents_at_scale(cell, cols, tiny["spectrum"], tiny["carriers"], 1.0)
+    assert np.allclose(i1, _currents(tiny, cols), rtol=0, atol=1e-14 * np.abs(i1).max())
+
