@@ -11,9 +11,14 @@
 // system is equilibrated: unknowns q' = a q with a = max |A_ii| and the
 // neutrality row multiplied by a, so that every block is of order one.
 //
-// One workgroup per frequency; the LU factors live in the workspace and the
-// matrix entries are regenerated from A for the refinement residual.
+// One workgroup per frequency; n_q <= 128 factors the source block in
+// registers (Schur complement of the gauge border), n <= 144 the bordered
+// system in registers, larger systems in the workspace by blocks of 16
+// columns; the matrix entries are regenerated from A for the refinement
+// residual.
 #include "common.hpp"
+
+#include <algorithm>
 
 namespace wt {
 
@@ -173,28 +178,39 @@ __device__ void refine_and_store(const Plan& p, const double* A, double inv_a, c
     }
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_solve(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveReport* rep) {
-    __shared__ c64 rowk[kMaxN];
-    __shared__ c64 colk[kMaxN];
-    __shared__ c64 xs[kMaxN];
-    __shared__ c64 rs[kMaxN];
+// Blocked right-looking factorisation for any n <= kMaxN, one workgroup per
+// frequency, the matrix in the workspace.  Per panel of NB columns:
+//  1. the panel (rows k0..n-1) is factored in LDS with partial pivoting;
+//  2. its row interchanges are applied to the columns left and right of it;
+//  3. the block row right of it becomes U12 = L11^-1 A12 (unit lower solve);
+//  4. the trailing matrix is updated once, A22 -= L21 U12, with L21 read from
+//     LDS: every element of A22 is read and written once per panel instead of
+//     once per column, which divides the HBM traffic of the factorisation by NB.
+// The factors and the interchanges are those of the unblocked algorithm (same
+// pivot rule: first row of maximal |re| + |im|), so the refinement's
+// triangular solves are unchanged.
+constexpr int kPanel = 16;
+constexpr int kBlockedThreads = 1024;
+
+__global__ void __launch_bounds__(kBlockedThreads)
+k_solve_blocked(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveReport* rep) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    c64* panel = reinterpret_cast<c64*>(smem);            // [n - k0][kPanel], row-major
     __shared__ int pivs[kMaxN];
     __shared__ c64 zc[kMaxCols];
-    __shared__ double red[16];
-    __shared__ int red_i[16];
-    __shared__ double red_v[16];
+    __shared__ double red[kBlockedThreads / 64];
+    __shared__ int red_i[kBlockedThreads / 64];
+    __shared__ double red_v[kBlockedThreads / 64];
     __shared__ double sh_inv_a;
     __shared__ int sh_piv;
     __shared__ int sh_singular;
 
     const int f = blockIdx.x;
-    const int n = p.n, nq = p.n_q, tid = threadIdx.x;
+    const int n = p.n, nq = p.n_q, tid = threadIdx.x, nth = blockDim.x;
     const double omega = 2.0 * kPi * p.df * f;
     c64* lu = lu_all + (size_t)f * n * n;
     int* piv = piv_all + (size_t)f * n;
 
-    // i w R_w(m) = m * D_w/(pi r^2) * i w / (sigma + i w eps)
     if (tid < p.n_cols) {
         const Column& c = p.col[tid];
         const double delta = fabs(c.z_free - c.z_contact) / (c.n - 1);
@@ -203,7 +219,7 @@ k_solve(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveReport
         zc[tid] = c64{g * omega * omega * p.eps / den, g * omega * c.sigma / den};
     }
     double dmax = 0.0;
-    for (int i = tid; i < nq; i += blockDim.x) dmax = fmax(dmax, fabs(A[(size_t)i * nq + i]));
+    for (int i = tid; i < nq; i += nth) dmax = fmax(dmax, fabs(A[(size_t)i * nq + i]));
     dmax = block_max(dmax, red);
     if (tid == 0) {
         sh_inv_a = 1.0 / dmax;
@@ -211,66 +227,131 @@ k_solve(Plan p, const double* A, c64* lu_all, int* piv_all, c64* qw, SolveReport
     }
     __syncthreads();
     const double inv_a = sh_inv_a;
-
-    for (int idx = tid; idx < n * n; idx += blockDim.x) lu[idx] = s_entry(p, A, inv_a, zc, idx / n, idx % n);
+    for (int idx = tid; idx < n * n; idx += nth) lu[idx] = s_entry(p, A, inv_a, zc, idx / n, idx % n);
     __syncthreads();
 
     double umax = 0.0, umin = 1e308;
-    for (int k = 0; k < n; ++k) {
-        // pivot: first row of maximal |re| + |im| in column k
-        double best = -1.0;
-        int bi = k;
-        for (int i = k + tid; i < n; i += blockDim.x) {
-            const double v = cabs1(lu[(size_t)i * n + k]);
-            if (v > best) { best = v; bi = i; }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ov = __shfl_down(best, o, 64);
-            const int oi = __shfl_down(bi, o, 64);
-            if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-        }
-        if ((tid & 63) == 0) { red_v[tid >> 6] = best; red_i[tid >> 6] = bi; }
-        __syncthreads();
-        if (tid == 0) {
-            double bv = red_v[0];
-            int b = red_i[0];
-            for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-                if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < b)) { bv = red_v[w]; b = red_i[w]; }
-            sh_piv = b;
-            pivs[k] = b;
-            piv[k] = b;
-            if (bv == 0.0) sh_singular = 1;
+    for (int k0 = 0; k0 < n; k0 += kPanel) {
+        const int nb = min(kPanel, n - k0);
+        const int mp = n - k0;
+        // 1. panel into LDS and factored there
+        for (int idx = tid; idx < mp * nb; idx += nth) {
+            const int r = idx / nb, c = idx - (idx / nb) * nb;
+            panel[r * kPanel + c] = lu[(size_t)(k0 + r) * n + k0 + c];
         }
         __syncthreads();
-        const int pr = sh_piv;
-        if (pr != k) {
-            for (int j = tid; j < n; j += blockDim.x) {
-                const c64 t = lu[(size_t)k * n + j];
-                lu[(size_t)k * n + j] = lu[(size_t)pr * n + j];
-                lu[(size_t)pr * n + j] = t;
+        for (int c = 0; c < nb; ++c) {
+            double best = -1.0;
+            int bi = mp;
+            for (int r = c + tid; r < mp; r += nth) {
+                const double v = cabs1(panel[r * kPanel + c]);
+                if (v > best) { best = v; bi = r; }
             }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_down(best, o, 64);
+                const int oi = __shfl_down(bi, o, 64);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if ((tid & 63) == 0) { red_v[tid >> 6] = best; red_i[tid >> 6] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                double bv = red_v[0];
+                int b = red_i[0];
+                for (int w = 1; w < nth / 64; ++w)
+                    if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < b)) { bv = red_v[w]; b = red_i[w]; }
+                sh_piv = b;
+                pivs[k0 + c] = k0 + b;
+                piv[k0 + c] = k0 + b;
+                if (!(bv > 0.0)) sh_singular = 1;
+            }
+            __syncthreads();
+            const int pr = sh_piv;
+            if (pr != c && tid < nb) {
+                const c64 t = panel[c * kPanel + tid];
+                panel[c * kPanel + tid] = panel[pr * kPanel + tid];
+                panel[pr * kPanel + tid] = t;
+            }
+            __syncthreads();
+            const c64 pivot = panel[c * kPanel + c];
+            const double pm = cmod(pivot);
+            umax = fmax(umax, pm);
+            umin = fmin(umin, pm);
+            const c64 ip = cinv(pivot);
+            for (int r = c + 1 + tid; r < mp; r += nth) {
+                c64* row = panel + r * kPanel;
+                const c64 l = row[c] * ip;
+                row[c] = l;
+                for (int cc = c + 1; cc < nb; ++cc) row[cc] = row[cc] - l * panel[c * kPanel + cc];
+            }
+            __syncthreads();
+        }
+        for (int idx = tid; idx < mp * nb; idx += nth) {
+            const int r = idx / nb, c = idx - (idx / nb) * nb;
+            lu[(size_t)(k0 + r) * n + k0 + c] = panel[r * kPanel + c];
+        }
+        // 2. the panel's interchanges on the other columns (in order)
+        for (int c = 0; c < nb; ++c) {
+            const int r1 = k0 + c, r2 = pivs[k0 + c];
+            if (r2 == r1) continue;
+            for (int j = tid; j < n - nb; j += nth) {
+                const int col = j < k0 ? j : j + nb;
+                const c64 t = lu[(size_t)r1 * n + col];
+                lu[(size_t)r1 * n + col] = lu[(size_t)r2 * n + col];
+                lu[(size_t)r2 * n + col] = t;
+            }
+            __syncthreads();
         }
         __syncthreads();
-        const c64 pivot = lu[(size_t)k * n + k];
-        const double pm = cmod(pivot);
-        umax = fmax(umax, pm);
-        umin = fmin(umin, pm);
-        const c64 ip = cinv(pivot);
-        for (int j = k + 1 + tid; j < n; j += blockDim.x) rowk[j] = lu[(size_t)k * n + j];
-        for (int i = k + 1 + tid; i < n; i += blockDim.x) {
-            const c64 l = lu[(size_t)i * n + k] * ip;
-            lu[(size_t)i * n + k] = l;
-            colk[i] = l;
-        }
-        __syncthreads();
-        const int m = n - k - 1;
-        for (int idx = tid; idx < m * m; idx += blockDim.x) {
-            const int i = k + 1 + idx / m, j = k + 1 + idx % m;
-            lu[(size_t)i * n + j] = lu[(size_t)i * n + j] - colk[i] * rowk[j];
+        const int nr = n - k0 - nb;                       // columns (and rows) right of / below the panel
+        if (nr > 0) {
+            // 3. U12 = L11^-1 A12, one column per thread
+            for (int j = k0 + nb + tid; j < n; j += nth) {
+                c64* uj = lu + (size_t)k0 * n + j;
+                for (int r = 1; r < nb; ++r) {
+                    c64 acc = uj[(size_t)r * n];
+                    for (int c = 0; c < r; ++c) acc = acc - panel[r * kPanel + c] * uj[(size_t)c * n];
+                    uj[(size_t)r * n] = acc;
+                }
+            }
+            __syncthreads();
+            // 4. A22 -= L21 U12: each thread a 2 x 4 tile of A22 (4 consecutive columns)
+            const int tcols = (nr + 3) / 4, trows = (nr + 1) / 2;
+            for (int t = tid; t < tcols * trows; t += nth) {
+                const int tc = t % tcols, tr = t / tcols;
+                const int i0 = k0 + nb + 2 * tr, j0 = k0 + nb + 4 * tc;
+                c64 acc[2][4];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = c64{0.0, 0.0};
+                for (int c = 0; c < nb; ++c) {
+                    c64 uv[4];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        uv[b] = j0 + b < n ? lu[(size_t)(k0 + c) * n + j0 + b] : c64{0.0, 0.0};
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        const c64 l = i0 + a < n ? panel[(i0 + a - k0) * kPanel + c] : c64{0.0, 0.0};
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[a][b] = acc[a][b] + l * uv[b];
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (i0 + a < n && j0 + b < n) {
+                            c64* e = lu + (size_t)(i0 + a) * n + j0 + b;
+                            *e = *e - acc[a][b];
+                        }
+            }
         }
         __syncthreads();
     }
 
+    // the panel's LDS holds the refinement vectors from here on
+    c64* xs = panel;
+    c64* rs = panel + kMaxN;
     refine_and_store(p, A, inv_a, zc, lu, pivs, xs, rs, red, f, qw, rep, umax, umin, sh_singular);
 }
 
@@ -820,9 +901,13 @@ hipError_t launch_collocation_solve(const Plan& p, void* ws, hipStream_t s) {
         hipLaunchKernelGGL((k_solve_reg<16, 9, 5>), dim3(p.n_freq), dim3(512), 0, s, p, A, lu, piv, qw, rep);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_solve, dim3(p.n_freq), dim3(kBlock), 0, s, p, (const double*)(b + p.off_A),
-                       (c64*)(b + p.off_lu), (int*)(b + p.off_piv), (c64*)(b + p.off_qw),
-                       (SolveReport*)(b + p.off_rep));
+    const size_t lds = std::max((size_t)kMaxN * kPanel, (size_t)2 * kMaxN) * sizeof(c64);
+    hipError_t e = hipFuncSetAttribute((const void*)k_solve_blocked, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_solve_blocked, dim3(p.n_freq), dim3(kBlockedThreads), lds, s, p,
+                       (const double*)(b + p.off_A), (c64*)(b + p.off_lu), (int*)(b + p.off_piv),
+                       (c64*)(b + p.off_qw), (SolveReport*)(b + p.off_rep));
     return hipGetLastError();
 }
 
