@@ -176,13 +176,16 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
         p.synth_kernel = 2;
         tb = std::min(sp->n_time, wt::synthesis_block(N[2]));
     } else {
+        // the LDS Stockham synthesis: the largest block (<= 32 samples) whose
+        // (3 block + 1) / 2 sample-pair transforms all fit in LDS beside the
+        // staged block, so that a block takes one spectrum pass and one FFT
         p.synth_kernel = 0;
-        tb = std::min(sp->n_time, 32);
-        auto lds_need = [&](int t) {
-            return (size_t)n_cols * p.nzh * 3 * cx + (size_t)N[2] * t * 3 * re + (size_t)2 * N[2] * cx;
+        auto lds_need = [&](int t, int pairs) {
+            return (size_t)n_cols * p.nzh * 3 * cx + (size_t)N[2] * t * 3 * re + (size_t)2 * pairs * N[2] * cx;
         };
-        while (tb > 1 && lds_need(tb) > lds_budget) tb = (tb + 1) / 2;
-        if (lds_need(tb) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
+        tb = std::min(sp->n_time, 32);
+        while (tb > 1 && lds_need(tb, (3 * tb + 1) / 2) > lds_budget) tb = (tb + 1) / 2;
+        if (lds_need(tb, 1) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
     }
     p.tb = tb;
     p.h_format = opt->h_format;

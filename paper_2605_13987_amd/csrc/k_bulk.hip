@@ -107,8 +107,10 @@ __device__ inline cplx<T> column_spectrum(const Plan& p, const cplx<T>* etab, co
 
 // One block per (X, Y) column: H for every z node and time sample, written
 // one time block at a time as a contiguous run [z][t in block][component].
+constexpr int kSynthBlock = 512;
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kSynthBlock)
 k_synthesis(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* tw, T* H, int fb) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int Nx = p.N[0], Ny = p.N[1], Nz = p.N[2], nzh = p.nzh, W = p.n_cols;
@@ -661,15 +663,16 @@ hipError_t synthesis(const Plan& p, char* b, void* h, hipStream_t s) {
             if (p.h_format == 1) return synthesis_pipe_n<T, _Float16>(p, b, h, s);
         return synthesis_pipe_n<T, T>(p, b, h, s);
     }
+    // fb sample-pair transforms per pass: all pairs of a block when they fit
     const size_t fixed = (size_t)p.n_cols * p.nzh * 3 * sizeof(cplx<T>) + (size_t)p.N[2] * p.tb * 3 * sizeof(T);
     const size_t budget = 160 * 1024;
-    int fb = 16;
-    while (fb > 1 && fixed + (size_t)2 * fb * p.N[2] * sizeof(cplx<T>) > budget) fb >>= 1;
+    int fb = (3 * p.tb + 1) / 2;
+    while (fb > 1 && fixed + (size_t)2 * fb * p.N[2] * sizeof(cplx<T>) > budget) --fb;
     const size_t lds = fixed + (size_t)2 * fb * p.N[2] * sizeof(cplx<T>);
     hipError_t err = hipFuncSetAttribute((const void*)k_synthesis<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_synthesis<T>, dim3(p.N[0] * p.N[1]), dim3(kBlock), lds, s, p,
+    hipLaunchKernelGGL(k_synthesis<T>, dim3(p.N[0] * p.N[1]), dim3(kSynthBlock), lds, s, p,
                        reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]), static_cast<T*>(h), fb);
