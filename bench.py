@@ -305,8 +305,10 @@ def current_compulsory_bytes(cfg, elem_bytes):
 def batched_variants(wt, workloads, torch, n_variants, replays):
     """The geometry-variant batch: n_variants seeded cells of uneven grids and
     frequency counts, each a full step (H solve + current of its track), run
-    eagerly and as one captured HIP graph on one stream, sharing one workspace
-    and one H buffer sized for the largest variant."""
+    eagerly with the plans' default synthesis launch, then with every plan
+    autotuned (wt_h_plan_tune), eagerly and as one captured HIP graph on one
+    stream, sharing one workspace and one H buffer sized for the largest
+    variant."""
     import numpy as np
 
     variants = [workloads.geometry_variant(k) for k in range(n_variants)]
@@ -347,6 +349,12 @@ def batched_variants(wt, workloads, torch, n_variants, replays):
 
     with torch.cuda.stream(stream):
         batch()                                                   # warm-up, kernel attributes
+        t_default = timed(batch)
+    t0 = time.perf_counter()
+    tuned = [wt.wt_h_plan_tune(ctx, it["plan"], ws.data_ptr(), ws.numel(), h.data_ptr(), h.numel()) for it in items]
+    tune_s = time.perf_counter() - t0
+    with torch.cuda.stream(stream):
+        batch()
         t_eager = timed(batch)
     ref = [it["out"].clone() for it in items]
     graph = torch.cuda.CUDAGraph()
@@ -363,8 +371,11 @@ def batched_variants(wt, workloads, torch, n_variants, replays):
     for it in items:
         wt.wt_h_plan_destroy(it["plan"])
     wt.wt_context_destroy(ctx)
-    n_pipe = sum(1 for v in variants if v["cell"]["N"][2] in (64, 128, 256))
-    return {"n_variants": n_variants, "grid_freq_pts": pts, "ms_eager": t_eager, "ms_graph": float(np.median(t_graph)),
+    n_pipe = sum(1 for v in variants if v["cell"]["N"][2] in (64, 128, 256, 512))
+    n_tuned = sum(1 for r in tuned if r["n_candidates"] > 1)
+    return {"n_variants": n_variants, "grid_freq_pts": pts, "ms_eager_default_launch": t_default,
+            "autotune_s": tune_s, "variants_autotuned": n_tuned,
+            "ms_eager": t_eager, "ms_graph": float(np.median(t_graph)),
             "value_graph": pts / (np.median(t_graph) * 1e-3), "unit": "grid*freq pts/s",
             "replay_vs_eager_current_max_rel_diff": err, "variants_on_register_fft_synthesis": n_pipe,
             "workload": ("seeded geometry variants: pitch 25-100 um, radius 3-10 um, five resistivities "
@@ -630,7 +641,8 @@ def main():
     batch = None
     if args.variants > 0:
         batch = batched_variants(wt, workloads, torch, args.variants, 3)
-        print(f"# batch of {args.variants} variants: eager {batch['ms_eager']:.1f} ms, graph {batch['ms_graph']:.1f} ms",
+        print(f"# batch of {args.variants} variants: default launch {batch['ms_eager_default_launch']:.1f} ms, "
+              f"autotuned ({batch['autotune_s']:.1f} s) eager {batch['ms_eager']:.1f} ms, graph {batch['ms_graph']:.1f} ms",
               file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 

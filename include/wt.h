@@ -31,7 +31,8 @@
  *  - Every function returns wt_status (0 = WT_OK, negative = error).  No
  *    exception or abort crosses this boundary.  On WT_E_HIP the runtime's
  *    message is kept in the context (wt_context_last_error).
- *  - A context is not thread-safe; a plan is immutable and may be shared.
+ *  - A context is not thread-safe; a plan is immutable and may be shared,
+ *    except while wt_h_plan_tune changes it.
  */
 #ifndef WT_H
 #define WT_H
@@ -195,6 +196,29 @@ wt_status wt_h_plan_create(const wt_cell* cell, const wt_column* cols, int n_col
                            wt_h_plan** plan, wt_h_layout* layout);
 wt_status wt_h_plan_destroy(wt_h_plan* plan);
 wt_status wt_h_plan_layout(const wt_h_plan* plan, wt_h_layout* layout);
+
+/* Result of wt_h_plan_tune. */
+typedef struct {
+    int n_candidates;    /* launch configurations timed (1: nothing to tune) */
+    int h_time_block;    /* the chosen time block of the H layout */
+    int threads;         /* workgroup size of the chosen synthesis launch */
+    double ms_chosen;    /* synthesis time of the chosen configuration (-1 if none timed) */
+    double ms_default;   /* the plan's configuration before tuning (-1 if none timed) */
+} wt_tune_report;
+
+/* Autotuning of the synthesis launch for this plan's grid on this device:
+ * runs wt_h_solve once, then times every candidate configuration of the LDS
+ * Stockham synthesis (used for N_z outside {64, 128, 256, 512}): its time
+ * block (powers of two up to 32 whose staging fits in LDS) and workgroup
+ * size (256, 512), two launches each after a warm-up, keeps the fastest
+ * in the plan and rewrites H in that configuration.  The register-FFT
+ * synthesis has a fixed schedule (n_candidates = 1).  This call changes the
+ * plan: the layout's h_time_block may differ afterwards (re-read it with
+ * wt_h_plan_layout; h_bytes and the workspace size do not change), so no
+ * other call may use the plan concurrently.  Synchronises the stream.
+ * report may be NULL. */
+wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, size_t workspace_bytes,
+                         void* d_h, size_t h_bytes, wt_tune_report* report);
 
 /* Solve for H: Green's tables and collocation matrix, one bordered complex
  * FP64 collocation solve (LU with partial pivoting + refinement) per

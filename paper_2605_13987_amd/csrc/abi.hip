@@ -177,17 +177,20 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
         tb = std::min(sp->n_time, wt::synthesis_block(N[2]));
     } else {
         // the LDS Stockham synthesis: the largest block (<= 32 samples) whose
-        // (3 block + 1) / 2 sample-pair transforms all fit in LDS beside the
-        // staged block, so that a block takes one spectrum pass and one FFT
+        // (3 block + 1) / 2 sample-pair transforms all fit beside the staged
+        // block in 40 KB of LDS, so that a block takes one spectrum pass and
+        // one FFT and four workgroups share a CU (wt_h_plan_tune refines this)
         p.synth_kernel = 0;
         auto lds_need = [&](int t, int pairs) {
             return (size_t)n_cols * p.nzh * 3 * cx + (size_t)N[2] * t * 3 * re + (size_t)2 * pairs * N[2] * cx;
         };
+        const size_t occupancy_budget = 40 * 1024;
         tb = std::min(sp->n_time, 32);
-        while (tb > 1 && lds_need(tb, (3 * tb + 1) / 2) > lds_budget) tb = (tb + 1) / 2;
+        while (tb > 1 && lds_need(tb, (3 * tb + 1) / 2) > occupancy_budget) tb = (tb + 1) / 2;
         if (lds_need(tb, 1) > lds_budget) return WT_E_UNSUPPORTED_SIZE;
     }
     p.tb = tb;
+    p.synth_threads = 256;
     p.h_format = opt->h_format;
     // float16 H is written by the pipelined synthesis only, from the float path
     if (p.h_format == WT_H_F16_SCALED && p.precision != WT_F32) return WT_E_INVALID_ARG;
@@ -487,6 +490,79 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, co
                                    d_i_out, ctx->stream),
            "current");
     if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
+    return WT_OK;
+}
+
+wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, size_t workspace_bytes, void* d_h,
+                         size_t h_bytes, wt_tune_report* report) {
+    if (!ctx || !plan || !d_workspace || !d_h) return WT_E_INVALID_ARG;
+    Plan& p = plan->p;
+    if (workspace_bytes < p.ws_bytes || h_bytes < p.h_bytes) return WT_E_WORKSPACE;
+    wt_status st = wt_h_solve(ctx, plan, d_workspace, workspace_bytes, d_h, h_bytes, nullptr);
+    if (st != WT_OK) return st;
+    hipStream_t s = ctx->stream;
+    // candidates: the LDS Stockham synthesis's time block (every power of two
+    // <= 32 and <= n_time whose staging and one transform pair fit in LDS)
+    // and workgroup size; the register-FFT synthesis has a fixed schedule
+    struct Cand {
+        int tb, threads;
+    };
+    std::vector<Cand> cands;
+    if (p.synth_kernel == 0) {
+        const size_t re = p.precision == WT_F64 ? sizeof(double) : sizeof(float);
+        const size_t cx = 2 * re;
+        for (int t = 32; t >= 1; t /= 2) {
+            if (t > p.n_time && t > 1) continue;
+            const size_t need = (size_t)p.n_cols * p.nzh * 3 * cx + (size_t)p.N[2] * t * 3 * re + (size_t)2 * p.N[2] * cx;
+            if (need > 160 * 1024) continue;
+            for (int thr : {256, 512}) cands.push_back({t, thr});
+        }
+    }
+    const Cand start{p.tb, p.synth_threads};
+    double best_ms = -1.0, start_ms = -1.0;
+    Cand best = start;
+    if (cands.size() > 1) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        WT_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
+        hipError_t err = hipEventCreate(&e1);
+        for (size_t c = 0; err == hipSuccess && c < cands.size(); ++c) {
+            p.tb = cands[c].tb;
+            p.synth_threads = cands[c].threads;
+            err = wt::launch_synthesis(p, d_workspace, d_h, s);                 // warm-up
+            if (err == hipSuccess) err = hipEventRecord(e0, s);
+            for (int r = 0; r < 2 && err == hipSuccess; ++r) err = wt::launch_synthesis(p, d_workspace, d_h, s);
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err != hipSuccess) break;
+            const double t = ms / 2.0;
+            if (cands[c].tb == start.tb && cands[c].threads == start.threads) start_ms = t;
+            if (best_ms < 0.0 || t < best_ms) {
+                best_ms = t;
+                best = cands[c];
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        p.tb = best.tb;
+        p.synth_threads = best.threads;
+        if (err != hipSuccess) {
+            p.tb = start.tb;
+            p.synth_threads = start.threads;
+            return hip_fail(ctx, err, "tune");
+        }
+        // H in the chosen layout
+        WT_HIP(ctx, wt::launch_synthesis(p, d_workspace, d_h, s), "synthesis");
+    }
+    WT_HIP(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (report) {
+        report->n_candidates = cands.size() > 1 ? (int)cands.size() : 1;
+        report->h_time_block = p.tb;
+        report->threads = p.synth_kernel == 0 ? p.synth_threads : wt::synthesis_threads(p.N[2]);
+        report->ms_chosen = best_ms;
+        report->ms_default = start_ms;
+    }
     return WT_OK;
 }
 

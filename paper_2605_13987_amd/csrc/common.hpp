@@ -70,7 +70,8 @@ struct Plan {
     double s_bulk[3];
     int nkz_tab;           // k_z >= 0 entries per Green's table row (max over columns)
     int tb;                // time block of the H layout
-    int synth_kernel;      // 2: pipelined register FFTs (N_z = 64, 128, 256), 0: LDS Stockham
+    int synth_kernel;      // 2: pipelined register FFTs (N_z = 64, 128, 256, 512), 0: LDS Stockham
+    int synth_threads;     // workgroup size of the LDS Stockham synthesis (256, 512 or 1024)
     int nzh;               // Nz / 2
     int nrad[3];
     int rad[3][kMaxRadices];

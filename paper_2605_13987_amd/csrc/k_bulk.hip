@@ -107,10 +107,10 @@ __device__ inline cplx<T> column_spectrum(const Plan& p, const cplx<T>* etab, co
 
 // One block per (X, Y) column: H for every z node and time sample, written
 // one time block at a time as a contiguous run [z][t in block][component].
-constexpr int kSynthBlock = 512;
+constexpr int kSynthMaxBlock = 1024;
 
 template <typename T>
-__global__ void __launch_bounds__(kSynthBlock)
+__global__ void __launch_bounds__(kSynthMaxBlock)
 k_synthesis(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* tw, T* H, int fb) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int Nx = p.N[0], Ny = p.N[1], Nz = p.N[2], nzh = p.nzh, W = p.n_cols;
@@ -672,7 +672,8 @@ hipError_t synthesis(const Plan& p, char* b, void* h, hipStream_t s) {
     hipError_t err = hipFuncSetAttribute((const void*)k_synthesis<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_synthesis<T>, dim3(p.N[0] * p.N[1]), dim3(kSynthBlock), lds, s, p,
+    if (p.synth_threads < 64 || p.synth_threads > kSynthMaxBlock || p.synth_threads % 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_synthesis<T>, dim3(p.N[0] * p.N[1]), dim3(p.synth_threads), lds, s, p,
                        reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]), static_cast<T*>(h), fb);

@@ -75,6 +75,11 @@ class wt_h_layout(ctypes.Structure):
                 ("h_decode_offset", c_size_t)]
 
 
+class wt_tune_report(ctypes.Structure):
+    _fields_ = [("n_candidates", c_int), ("h_time_block", c_int), ("threads", c_int),
+                ("ms_chosen", c_double), ("ms_default", c_double)]
+
+
 class wt_carriers(ctypes.Structure):
     _fields_ = [("n_carriers", c_int), ("n_tracks", c_int), ("d_pos", c_void_p),
                 ("d_charge", c_void_p), ("d_track", c_void_p)]
@@ -109,6 +114,7 @@ def _load():
         "wt_current": (c_int, [c_void_p, c_void_p, c_void_p, P(wt_carriers), c_void_p, c_size_t, c_void_p]),
         "wt_electronics": (c_int, [c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                    c_double, c_double, c_void_p, c_void_p]),
+        "wt_h_plan_tune": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_tune_report)]),
         "wt_h_gradient_workspace": (c_int, [c_void_p, c_int, P(c_size_t)]),
         "wt_h_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, P(wt_carriers), c_void_p, c_void_p,
                                   c_size_t, c_void_p, P(wt_h_report)]),
@@ -231,6 +237,14 @@ def wt_h_plan_layout(plan) -> dict:
     lay = wt_h_layout()
     _check(LIB.wt_h_plan_layout(plan, ctypes.byref(lay)), "wt_h_plan_layout")
     return layout_dict(lay)
+
+
+def wt_h_plan_tune(ctx, plan, d_workspace: int, workspace_bytes: int, d_h: int, h_bytes: int) -> dict:
+    """Autotune the plan's synthesis launch (synchronises; the layout may change)."""
+    rep = wt_tune_report()
+    _check(LIB.wt_h_plan_tune(ctx, plan, c_void_p(d_workspace), int(workspace_bytes), c_void_p(d_h), int(h_bytes),
+                              ctypes.byref(rep)), "wt_h_plan_tune", ctx)
+    return {name: getattr(rep, name) for name, _ in wt_tune_report._fields_}
 
 
 # ---------------------------------------------------------------- solve / current

@@ -108,6 +108,7 @@ def test_null_arguments_are_rejected():
         == wt.WT_E_INVALID_ARG
     assert wt.LIB.wt_h_solve(None, None, None, 0, None, 0, None) == wt.WT_E_INVALID_ARG
     assert wt.LIB.wt_current(None, None, None, None, None, 0, None) == wt.WT_E_INVALID_ARG
+    assert wt.LIB.wt_h_plan_tune(None, None, None, 0, None, 0, None) == wt.WT_E_INVALID_ARG
     assert wt.LIB.wt_h_plan_destroy(None) == wt.WT_E_INVALID_ARG
     assert wt.LIB.wt_context_destroy(None) == wt.WT_E_INVALID_ARG
 
