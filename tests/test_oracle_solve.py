@@ -134,3 +134,47 @@ def test_readout_admittance_is_passive(px32_oracle):
     assert np.all(Y.real[1:] > 0)
     # static capacitance is positive and the charge magnitude falls with frequency
     assert Q[0].real > 0 and np.all(np.diff(np.abs(Q)) < 0)
+
+
+def test_full_height_perfect_conductors_reduce_to_a_2d_line_lattice():
+    """Columns spanning the whole periodic height, at zero frequency (perfect
+    conductors): the solution is z-invariant, a line charge lambda_w per
+    column, and the lambdas solve the 2D problem sum_w' lambda_w' G2(x_w -
+    X_w') + c = V_w, sum lambda = 0 with the 2D Ewald lattice sum of Gaussian
+    line charges (an independent closed form).  256 nodes per column put the
+    aliased k_z = 2 pi n / D terms of the node row below 1e-9; the row of 256
+    sources per column is then ill-conditioned (cond ~ 1e8), which bounds the
+    z-invariance of the solved charges at ~1e-8."""
+    from oracle import collocation, green
+    import ewald
+
+    L = (50e-6, 50e-6, 300e-6)
+    cell = dict(L=L, N=(32, 32, 64), eps_r=5.7, sigma_bulk=0.0)
+    M = 256
+    cols = [dict(x=25e-6, y=25e-6, radius=5e-6, z_contact=0.0, z_free=L[2] * (M - 1) / M,
+                 resistivity=[1e-3], n_colloc=M, v_applied=1.0),
+            dict(x=0.0, y=0.0, radius=5e-6, z_contact=0.0, z_free=L[2] * (M - 1) / M,
+                 resistivity=[1e-3], n_colloc=M, v_applied=0.0)]
+    A = collocation.collocation_matrix(cell, cols)
+    q, c = collocation.solve_frequency(A, cols, 0.0, green.permittivity(cell))
+    q = q.real.reshape(2, M)
+    # z-invariance
+    assert np.max(np.abs(q - q.mean(axis=1, keepdims=True))) <= 1e-7 * np.max(np.abs(q))
+    lam = q.mean(axis=1) / (L[2] / M)
+    # the 2D system
+    s = green.collocation_width(cols[0])
+    X = np.array([[c_["x"], c_["y"]] for c_ in cols])
+    S = np.zeros((3, 3))
+    for i in range(2):
+        for j in range(2):
+            S[i, j] = ewald.potential_2d((X[i] + [cols[i]["radius"], 0.0]) - X[j], L[:2], 5.7, s)[0]
+    S[:2, 2] = 1.0
+    S[2, :2] = 1.0
+    ref = np.linalg.solve(S, np.array([1.0, 0.0, 0.0]))
+    assert np.max(np.abs(lam - ref[:2])) <= 1e-9 * np.max(np.abs(ref[:2]))
+    assert abs(c.real - ref[2]) <= 1e-9
+    # the 2D lattice sum does not depend on its splitting width
+    d = np.array([[3e-6, 1e-6], [20e-6, -7e-6], [0.0, 0.0]])
+    g8, g12 = ewald.potential_2d(d, L[:2], 5.7, s, b=8e-6), ewald.potential_2d(d, L[:2], 5.7, s, b=12e-6)
+    assert np.max(np.abs(g8 - g12)) <= 1e-12 * np.max(np.abs(g12))
+
