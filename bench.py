@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # device-to-device copy gives for the same counters), in
 # profiles/k_synthesis_pipe_128x128x256.md.  Reported only while the kernel's
 # sources are the ones they were measured on.
-SYNTH_TRAFFIC_BYTES = {"plain": 10170361879, "mixed": 5136780749}
-SYNTH_TRAFFIC_SOURCES_SHA256 = "aee28db1f498342ca97d57858976c1132c8caedd67e9dca31a8ee1bd553a470c"
+SYNTH_TRAFFIC_BYTES = {"plain": 10170757073, "mixed": 5136779930}
+SYNTH_TRAFFIC_SOURCES_SHA256 = "45c9d5cf4a98300ef01f04d67c1c47af4c959c53f88bd68a19c5266d9ef7357f"
 SYNTH_SOURCES = ("k_bulk.hip", "fft.hpp", "common.hpp")
 
 

@@ -173,3 +173,31 @@ def test_signal_features_through_autograd(px128):
     bias = abs(sum(th[1, p] * gp[1, p] for p in range(4)))
     say(f"    peak time log-sensitivity: readout {ro:.3e} s, bias (all quarters) {bias:.3e} s")
     assert bias < ro
+
+
+def test_gradient_edge_cases(small):
+    """No carriers: zero gradient; carriers with track ids outside [0, n_tracks)
+    are skipped exactly as by wt_current."""
+    cfg = small
+    car = rounded_carriers(cfg["carriers"], wt.WT_F32)
+    G = torch.as_tensor(_seeded_loss_weights(car["n_tracks"], cfg["spectrum"]["n_time"], 64), device="cuda")
+    empty = dict(pos=np.zeros((0, cfg["spectrum"]["n_time"] + 1, 3)), charge=np.zeros(0),
+                 track=np.zeros(0, np.int32), n_tracks=car["n_tracks"])
+    m0 = ColumnModel(cfg["cell"], cfg["columns"], cfg["spectrum"], empty, precision=wt.WT_F32)
+    p0, cur0 = m0.solve(m0.theta0())
+    g0, gp0 = m0.gradient(p0, G)
+    assert float(cur0.abs().max()) == 0.0 and float(g0.abs().max()) == 0.0 and float(gp0) == 0.0
+    # invalid track ids: the same gradient as without those carriers
+    bad = dict(car, track=np.where(np.arange(len(car["track"])) % 4 == 0, -1, car["track"]).astype(np.int32))
+    bad["track"][1] = car["n_tracks"]
+    keep = (bad["track"] >= 0) & (bad["track"] < car["n_tracks"])
+    sub = dict(pos=car["pos"][keep], charge=car["charge"][keep], track=bad["track"][keep], n_tracks=car["n_tracks"])
+    mb = ColumnModel(cfg["cell"], cfg["columns"], cfg["spectrum"], bad, precision=wt.WT_F32)
+    ms = ColumnModel(cfg["cell"], cfg["columns"], cfg["spectrum"], sub, precision=wt.WT_F32)
+    pb, _ = mb.solve(mb.theta0())
+    psub, _ = ms.solve(ms.theta0())
+    gb, gpb = mb.gradient(pb, G)
+    gs, gps = ms.gradient(psub, G)
+    scale = float(gs.abs().max())
+    assert float((gb - gs).abs().max()) <= 1e-5 * scale
+    assert abs(float(gpb) - float(gps)) <= 1e-5 * abs(float(gps))
