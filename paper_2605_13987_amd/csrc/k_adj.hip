@@ -41,7 +41,6 @@ namespace wt {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kItems = 2;          // (column, k_z) items per thread of the event projection
 
 using c64 = cplx<double>;
 
@@ -75,9 +74,13 @@ __device__ inline int wrap_cell(T f, int n) {
 }
 
 // Step 1.  Block (m, carrier chunk, item group): the moving steps m of the
-// chunk's carriers, lanes over (column w, k_z) items.  Sums stay in registers
-// while consecutive carriers share a track and are added to Phi when it
-// changes.  The corners and weights follow the forward convolution exactly.
+// chunk's carriers, one (column w, k_z) item per thread.  Sums stay in
+// registers while consecutive carriers share a track and are added to Phi
+// when it changes.  Consecutive carriers at one step mostly share their (x, y)
+// cell (a track's carriers drift side by side), so each thread keeps the
+// field table and its pitch derivative at the cell's four (x, y) corners in
+// registers and reloads them only when the cell changes.  The corners and
+// weights follow the forward convolution exactly.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_events(Plan p, const cplx<T>* ehat, const cplx<T>* eds, const cplx<T>* twz, int n_carriers, int n_tracks,
@@ -87,84 +90,101 @@ k_adj_events(Plan p, const cplx<T>* ehat, const cplx<T>* eds, const cplx<T>* twz
     const int c1 = min(n_carriers, c0 + chunk);
     const int Nx = p.N[0], Ny = p.N[1], Nz = p.N[2], nzh = p.nzh, W = p.n_cols, nt = p.n_time;
     const int n_items = W * nzh;
-    int wi[kItems], kk[kItems];
-    bool ok[kItems];
-    cplx<T> acc[kItems], accs[kItems];
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const int it = (blockIdx.z * kItems + j) * kBlock + threadIdx.x;
-        ok[j] = it < n_items;
-        wi[j] = ok[j] ? it / nzh : 0;
-        kk[j] = ok[j] ? it - wi[j] * nzh : 0;
-        acc[j] = accs[j] = cplx<T>{(T)0, (T)0};
-    }
+    const int it = blockIdx.z * kBlock + threadIdx.x;
+    const bool ok = it < n_items;
+    const int wi = ok ? it / nzh : 0;
+    const int k = ok ? it - wi * nzh : 0;
+    const Column& col = p.col[wi];
+    cplx<T> acc{(T)0, (T)0}, accs{(T)0, (T)0};
+    cplx<T> ce[4][3], cd[4][3];                              // at (x0,y0), (x0,y1), (x1,y0), (x1,y1)
+    int cx = -1, cy = -1;
     int cur = -1;
+    // the step m of up to kBlock carriers at a time, loaded by all threads
+    // at once (a serial loop of dependent loads would wait on each carrier)
+    __shared__ T sp[kBlock][6];
+    __shared__ T sq[kBlock];
+    __shared__ int st[kBlock];
     auto flush = [&]() {
-#pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const size_t o = (((size_t)cur * nt + m) * W + wi[j]) * nzh + kk[j];
-            if (cur >= 0 && ok[j] && (acc[j].re != (T)0 || acc[j].im != (T)0)) {
-                atomicAdd(&phi[o].re, acc[j].re);
-                atomicAdd(&phi[o].im, acc[j].im);
-            }
-            if (cur >= 0 && ok[j] && (accs[j].re != (T)0 || accs[j].im != (T)0)) {
-                atomicAdd(&phis[o].re, accs[j].re);
-                atomicAdd(&phis[o].im, accs[j].im);
-            }
-            acc[j] = accs[j] = cplx<T>{(T)0, (T)0};
+        const size_t o = (((size_t)cur * nt + m) * W + wi) * nzh + k;
+        if (cur >= 0 && ok && (acc.re != (T)0 || acc.im != (T)0)) {
+            atomicAdd(&phi[o].re, acc.re);
+            atomicAdd(&phi[o].im, acc.im);
         }
+        if (cur >= 0 && ok && (accs.re != (T)0 || accs.im != (T)0)) {
+            atomicAdd(&phis[o].re, accs.re);
+            atomicAdd(&phis[o].im, accs.im);
+        }
+        acc = accs = cplx<T>{(T)0, (T)0};
     };
-    for (int c = c0; c < c1; ++c) {
-        const int tr = track[c];
-        if (tr < 0 || tr >= n_tracks) continue;
-        const T* P = pos + ((size_t)c * (nt + 1) + m) * 3;
-        const T dx = P[3] - P[0], dy = P[4] - P[1], dz = P[5] - P[2];
-        if (dx == (T)0 && dy == (T)0 && dz == (T)0) continue;
-        const T ux = (P[0] + P[3]) * (T)0.5 * (T)(Nx / p.L[0]);
-        const T uy = (P[1] + P[4]) * (T)0.5 * (T)(Ny / p.L[1]);
-        const T uz = (P[2] + P[5]) * (T)0.5 * (T)(Nz / p.L[2]);
-        if (!(isfinite(ux) && isfinite(uy) && isfinite(uz))) continue;
-        if (tr != cur) {
-            flush();
-            cur = tr;
-        }
-        const T flx = floor(ux), fly = floor(uy), flz = floor(uz);
-        const T fx = ux - flx, fy = uy - fly, fz = uz - flz;
-        const T gx = (T)1 - fx, gy = (T)1 - fy, gz = (T)1 - fz;
-        const int x0 = wrap_cell(flx, Nx), y0 = wrap_cell(fly, Ny), z0 = wrap_cell(flz, Nz);
-        const int x1 = x0 + 1 == Nx ? 0 : x0 + 1;
-        const int y1 = y0 + 1 == Ny ? 0 : y0 + 1;
-        const int z1 = z0 + 1 == Nz ? 0 : z0 + 1;
-        const T q = charge[c];
+    for (int cb = c0; cb < c1; cb += kBlock) {
+        const int nb = min(kBlock, c1 - cb);
+        __syncthreads();
+        if ((int)threadIdx.x < nb) {
+            const int c = cb + threadIdx.x;
+            const T* P = pos + ((size_t)c * (nt + 1) + m) * 3;
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            if (!ok[j]) continue;
-            const Column& col = p.col[wi[j]];
-            const int k = kk[j];
-            const int sx0 = (x0 - col.ix + Nx) % Nx, sx1 = (x1 - col.ix + Nx) % Nx;
-            const int sy0 = (y0 - col.iy + Ny) % Ny, sy1 = (y1 - col.iy + Ny) % Ny;
-            // dx . Ehat at one (x, y) corner into pe; dx . dEhat/ds + the
-            // in-plane part of dx . Ehat into ps
+            for (int e = 0; e < 6; ++e) sp[threadIdx.x][e] = P[e];
+            sq[threadIdx.x] = charge[c];
+            st[threadIdx.x] = track[c];
+        }
+        __syncthreads();
+        for (int ci = 0; ci < nb; ++ci) {
+            const int tr = st[ci];
+            if (tr < 0 || tr >= n_tracks) continue;
+            const T* P = sp[ci];
+            const T dx = P[3] - P[0], dy = P[4] - P[1], dz = P[5] - P[2];
+            if (dx == (T)0 && dy == (T)0 && dz == (T)0) continue;
+            const T ux = (P[0] + P[3]) * (T)0.5 * (T)(Nx / p.L[0]);
+            const T uy = (P[1] + P[4]) * (T)0.5 * (T)(Ny / p.L[1]);
+            const T uz = (P[2] + P[5]) * (T)0.5 * (T)(Nz / p.L[2]);
+            if (!(isfinite(ux) && isfinite(uy) && isfinite(uz))) continue;
+            if (tr != cur) {
+                flush();
+                cur = tr;
+            }
+            const T flx = floor(ux), fly = floor(uy), flz = floor(uz);
+            const T fx = ux - flx, fy = uy - fly, fz = uz - flz;
+            const T gx = (T)1 - fx, gy = (T)1 - fy, gz = (T)1 - fz;
+            const int x0 = wrap_cell(flx, Nx), y0 = wrap_cell(fly, Ny), z0 = wrap_cell(flz, Nz);
+            const int z1 = z0 + 1 == Nz ? 0 : z0 + 1;
+            const T q = sq[ci];
+            if (!ok) continue;
+            if (x0 != cx || y0 != cy) {                          // the same decision in every thread
+                const int x1 = x0 + 1 == Nx ? 0 : x0 + 1;
+                const int y1 = y0 + 1 == Ny ? 0 : y0 + 1;
+                const int sx[2] = {(x0 - col.ix + Nx) % Nx, (x1 - col.ix + Nx) % Nx};
+                const int sy[2] = {(y0 - col.iy + Ny) % Ny, (y1 - col.iy + Ny) % Ny};
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) {
+                    const size_t o = (((size_t)sx[cc >> 1] * Ny + sy[cc & 1]) * nzh + k) * 3;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        ce[cc][a] = ehat[o + a];
+                        cd[cc][a] = eds[o + a];
+                    }
+                }
+                cx = x0;
+                cy = y0;
+            }
+            // dx . Ehat at each (x, y) corner, and dx . dEhat/ds + the in-plane
+            // part of dx . Ehat, weighted by the corner's in-plane weight
+            const T wxy[4] = {gx * gy, gx * fy, fx * gy, fx * fy};
             cplx<T> v{(T)0, (T)0}, vs{(T)0, (T)0};
-            auto proj = [&](int sx, int sy, T wxy) {
-                const size_t o = (((size_t)sx * Ny + sy) * nzh + k) * 3;
-                const cplx<T> a = ehat[o], b = ehat[o + 1], cz = ehat[o + 2];
-                const cplx<T> da = eds[o], db = eds[o + 1], dc = eds[o + 2];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const cplx<T> a = ce[cc][0], b = ce[cc][1], cz = ce[cc][2];
+                const cplx<T> da = cd[cc][0], db = cd[cc][1], dc = cd[cc][2];
                 const cplx<T> pxy{a.re * dx + b.re * dy, a.im * dx + b.im * dy};
                 const cplx<T> pe{pxy.re + cz.re * dz, pxy.im + cz.im * dz};
                 const cplx<T> ps{pxy.re + da.re * dx + db.re * dy + dc.re * dz,
                                  pxy.im + da.im * dx + db.im * dy + dc.im * dz};
-                v = v + scale(pe, wxy);
-                vs = vs + scale(ps, wxy);
-            };
-            proj(sx0, sy0, gx * gy);
-            proj(sx0, sy1, gx * fy);
-            proj(sx1, sy0, fx * gy);
-            proj(sx1, sy1, fx * fy);
+                v = v + scale(pe, wxy[cc]);
+                vs = vs + scale(ps, wxy[cc]);
+            }
             const cplx<T> ph = scale(twz[(k * z0) % Nz], gz) + scale(twz[(k * z1) % Nz], fz);
             const T mq = k == 0 ? -q : (T)(-2) * q;
-            acc[j] = acc[j] + scale(v * ph, mq);
-            accs[j] = accs[j] + scale(vs * ph, mq);
+            acc = acc + scale(v * ph, mq);
+            accs = accs + scale(vs * ph, mq);
         }
     }
     flush();
@@ -390,7 +410,7 @@ hipError_t adjoint_rhs(const Plan& p, const GradLayout& g, const char* ws, int n
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n_carriers > 0) {
         const int chunk = std::max(64, (n_carriers + 65534) / 65535);
-        dim3 grid(p.n_time, (n_carriers + chunk - 1) / chunk, (n_items + kItems * kBlock - 1) / (kItems * kBlock));
+        dim3 grid(p.n_time, (n_carriers + chunk - 1) / chunk, (n_items + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_adj_events<T>, grid, dim3(kBlock), 0, s, p,
                            reinterpret_cast<const cplx<T>*>(ws + p.off_ehat),
                            reinterpret_cast<const cplx<T>*>(gws + g.off_eds),
