@@ -485,17 +485,21 @@ def main():
     tr = torch.from_numpy(car["track"]).to("cuda")
     n_c, n_tr = pos.shape[0], car["n_tracks"]
 
-    def run_path(h_format):
-        """Time the whole step with H stored in h_format; returns the figures and buffers."""
-        plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2,
+    def run_path(h_format, precision=wt.WT_F32):
+        """Time the whole step with H stored in h_format (or the whole path in
+        float64); returns the figures and buffers."""
+        plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=precision, ir_max_iter=2,
                                         ir_tol=1e-12, h_format=h_format)
+        f64 = precision == wt.WT_F64
+        dt = torch.float64 if f64 else torch.float32
         ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
         hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
-        out = torch.empty((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
+        out = torch.empty((n_tr, spec["n_time"]), dtype=dt, device="cuda")
+        pos_p, q_p = (pos.double(), q.double()) if f64 else (pos, q)
 
         def step():
             wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
-            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
+            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos_p.data_ptr(), q_p.data_ptr(), tr.data_ptr(),
                           out.data_ptr())
 
         st, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True)
@@ -522,7 +526,7 @@ def main():
             wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
             for name, t in wt.wt_context_stage_times(ctx):
                 stage[name] = stage.get(name, 0.0) + t / reps
-            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
+            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos_p.data_ptr(), q_p.data_ptr(), tr.data_ptr(),
                           out.data_ptr())
             for name, t in wt.wt_context_stage_times(ctx):
                 stage[name] = stage.get(name, 0.0) + t / reps
@@ -534,7 +538,7 @@ def main():
             off = lay["h_decode_offset"]
             decode = float(hbuf[off:off + 4].view(torch.float32).item())
         else:
-            h, decode = hbuf.view(torch.float32), 1.0
+            h, decode = hbuf.view(dt), 1.0
         t_h = sum(v for k, v in stage.items() if k != "current") * 1e-3
         t_cur = stage["current"] * 1e-3
         # synthesis kernel: algorithmic bytes = write of H + read of the field table per column
@@ -552,6 +556,7 @@ def main():
 
     plain = run_path(wt.WT_H_PLAIN)
     mixed = run_path(wt.WT_H_F16_SCALED)
+    full64 = run_path(wt.WT_H_PLAIN, wt.WT_F64)
     cur_bytes, n_steps = current_compulsory_bytes(cfg, 4)
     cur_bytes16, _ = current_compulsory_bytes(cfg, 2)
     # FP64 boundary fit with M = 256 nodes per column (n = 513) at 512
@@ -654,6 +659,9 @@ def main():
     i_plain = plain["out"].double().cpu().numpy()
     i_mixed = mixed["out"].double().cpu().numpy()
     i_err_mixed = float(np.linalg.norm(i_mixed - i_plain) / np.linalg.norm(i_plain))
+    i_f64 = full64["out"].cpu().numpy()
+    i_err_plain_vs_f64 = float(np.linalg.norm(i_plain - i_f64) / np.linalg.norm(i_f64))
+    i_err_mixed_vs_f64 = float(np.linalg.norm(i_mixed - i_f64) / np.linalg.norm(i_f64))
 
     stage, ms = plain["stage"], plain["ms"]
     measured = (list(N) == [128, 128, 256] and spec["n_time"] == 200 and w == 2
@@ -699,6 +707,15 @@ def main():
         "graph": {"ms_per_step": graph_ms, "note": "the same step captured once as a HIP graph and replayed"},
         "batched_variants": batch,
         "px256": c5,
+        "f64": {
+            "path": "the whole path in float64 (H in float64, 20 GB; LDS Stockham synthesis)",
+            "value": n_pts * spec["n_freq"] / (full64["ms"] * 1e-3),
+            "ms_per_step": full64["ms"],
+            "tracks_per_s": n_tr / full64["t_cur"],
+            "stage_ms": {k: round(v, 4) for k, v in full64["stage"].items()},
+            "rel_err": {"i_float32_path_vs_float64_path": i_err_plain_vs_f64,
+                        "i_mixed_path_vs_float64_path": i_err_mixed_vs_f64},
+        },
         "mixed": {
             "h_storage": "float16 holding H * h_scale (h_scale a power of two), decoded in float32",
             "h_scale": mixed["rep"]["h_scale"],
@@ -717,10 +734,12 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        base, err = cpu_baseline(cfg, {"plain": columns_of(plain), "mixed": columns_of(mixed)}, args.cpu_seconds)
+        base, err = cpu_baseline(cfg, {"plain": columns_of(plain), "mixed": columns_of(mixed),
+                                       "f64": columns_of(full64)}, args.cpu_seconds)
         line["cpu_baseline"] = base
         line["rel_err"] = {"H_sampled_columns_vs_fp64_oracle": err["plain"]}
         line["mixed"]["rel_err"]["H_sampled_columns_vs_fp64_oracle"] = err["mixed"]
+        line["f64"]["rel_err"]["H_sampled_columns_vs_fp64_oracle"] = err["f64"]
         if c5 is not None:
             c5["mixed"]["rel_err_H_sampled_columns_vs_fp64_oracle"] = c5_oracle_errors(c5_cfg, c5_cols)["mixed"]
     print(json.dumps(line), flush=True)
