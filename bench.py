@@ -29,12 +29,12 @@ if ROOT not in sys.path:
 METRIC = "H(x,t) grid·freq pts/s + carrier tracks/s, mixed vs plain FP64 at stated rel err"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of k_synthesis_pipe on this workload (float32 H, float16
+# HBM bytes per launch of k_synthesis_pipe on this workload (float32, float16 and float64
 # H): rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB
 # device-to-device copy gives for the same counters), in
 # profiles/k_synthesis_pipe_128x128x256.md.  Reported only while the kernel's
 # sources are the ones they were measured on.
-SYNTH_TRAFFIC_BYTES = {"plain": 10170757073, "mixed": 5136779930}
+SYNTH_TRAFFIC_BYTES = {"plain": 10170757073, "mixed": 5136779930, "f64": None}
 SYNTH_TRAFFIC_SOURCES_SHA256 = "45c9d5cf4a98300ef01f04d67c1c47af4c959c53f88bd68a19c5266d9ef7357f"
 SYNTH_SOURCES = ("k_bulk.hip", "fft.hpp", "common.hpp")
 
@@ -542,7 +542,7 @@ def main():
         t_h = sum(v for k, v in stage.items() if k != "current") * 1e-3
         t_cur = stage["current"] * 1e-3
         # synthesis kernel: algorithmic bytes = write of H + read of the field table per column
-        synth_bytes = h.numel() * h.element_size() + N[0] * N[1] * w * (N[2] // 2) * 3 * 8
+        synth_bytes = h.numel() * h.element_size() + N[0] * N[1] * w * (N[2] // 2) * 3 * (16 if f64 else 8)
         achieved = synth_bytes / (stage["synthesis"] * 1e-3) / 1e9
         return dict(ms=ms, stage=stage, t_h=t_h, t_cur=t_cur, rep=rep, h=h, decode=decode, out=out,
                     synth_bytes=synth_bytes, achieved=achieved, lay=lay)
@@ -708,11 +708,15 @@ def main():
         "batched_variants": batch,
         "px256": c5,
         "f64": {
-            "path": "the whole path in float64 (H in float64, 20 GB; LDS Stockham synthesis)",
+            "path": "the whole path in float64 (H in float64, 20 GB; register-FFT synthesis in blocks of 8 samples)",
             "value": n_pts * spec["n_freq"] / (full64["ms"] * 1e-3),
             "ms_per_step": full64["ms"],
             "tracks_per_s": n_tr / full64["t_cur"],
             "stage_ms": {k: round(v, 4) for k, v in full64["stage"].items()},
+            "roofline": {"kernel": "k_synthesis_pipe (float64 H)", "bound": "hbm", "achieved": full64["achieved"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": full64["achieved"] / HBM_PEAK_GBS,
+                         "traffic": SYNTH_TRAFFIC_BYTES["f64"] if measured else None,
+                         "traffic_unit": "bytes/launch", "bytes_per_launch": full64["synth_bytes"]},
             "rel_err": {"i_float32_path_vs_float64_path": i_err_plain_vs_f64,
                         "i_mixed_path_vs_float64_path": i_err_mixed_vs_f64},
         },

@@ -166,7 +166,8 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     // Time block of the H layout (the synthesis stages a whole block in LDS):
     // the pipelined register-FFT synthesis for N_z in {64, 128, 256, 512} with
     // at most 4 columns when its two staging buffers fit (blocks of 16
-    // samples, 8 for N_z = 512);
+    // samples, 8 where two such buffers would not fit: N_z = 512, and 256 in
+    // double);
     // otherwise the LDS Stockham synthesis, whose block is halved until its
     // tables fit.
     const size_t lds_budget = 160 * 1024;
@@ -174,7 +175,7 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     int tb;
     if (pipe_size && n_cols <= 4 && wt::synthesis_pipe_lds(N[2], re) <= lds_budget) {
         p.synth_kernel = 2;
-        tb = std::min(sp->n_time, wt::synthesis_block(N[2]));
+        tb = std::min(sp->n_time, wt::synthesis_block(N[2], (int)re));
     } else {
         // the LDS Stockham synthesis: the largest block (<= 32 samples) whose
         // (3 block + 1) / 2 sample-pair transforms all fit beside the staged
@@ -559,7 +560,7 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
     if (report) {
         report->n_candidates = cands.size() > 1 ? (int)cands.size() : 1;
         report->h_time_block = p.tb;
-        report->threads = p.synth_kernel == 0 ? p.synth_threads : wt::synthesis_threads(p.N[2]);
+        report->threads = p.synth_kernel == 0 ? p.synth_threads : wt::synthesis_threads(p.N[2], p.precision == WT_F64 ? 8 : 4);
         report->ms_chosen = best_ms;
         report->ms_default = start_ms;
     }

@@ -141,36 +141,41 @@ hipError_t launch_adjoint_params(const Plan& p, const GradLayout& g, const void*
 // Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256, 512}).
 __host__ __device__ constexpr int synthesis_n2(int nz) { return nz == 64 ? 8 : (nz == 512 ? 32 : 16); }
 
-// H is produced in blocks of kPipeBlock samples (8 for N_z = 512, so that two
-// staging buffers fit in LDS), each staged in LDS as rows of 3 x block values:
-// sample pair q, component c, real/imaginary part at column 6 q + c (+3),
-// plus a gap from pair block/4 on, row z at RS z + 3 floor(z / N2).  The gap
-// and the padding keep the transforms' LDS accesses free of bank conflicts
-// (two groups of a half-wavefront take sample pairs block/4 apart).
+// H is produced in blocks of kPipeBlock samples (8 where two 16-sample
+// staging buffers would not fit in LDS: N_z = 512, and N_z = 256 in double),
+// each staged in LDS as rows of 3 x block values: sample pair q, component c,
+// real/imaginary part at column 6 q + c (+3), plus a gap from pair block/4 on,
+// row z at RS z + 3 floor(z / N2).  The gap and the padding keep the
+// transforms' LDS accesses free of bank conflicts (two groups of a
+// half-wavefront take sample pairs block/4 apart).  elem: bytes per real.
 constexpr int kPipeBlock = 16;
 constexpr int kPipeRowPad = 3;
-__host__ __device__ constexpr int synthesis_block(int nz) { return nz == 512 ? 8 : kPipeBlock; }
-__host__ __device__ constexpr int synthesis_gap(int nz) { return nz == 512 ? 4 : 24; }
-__host__ __device__ constexpr int synthesis_row_stride(int nz) {
-    return 3 * synthesis_block(nz) + synthesis_gap(nz) + 1;
+__host__ __device__ constexpr int synthesis_block(int nz, int elem) {
+    return (nz == 512 || (nz == 256 && elem == 8)) ? 8 : kPipeBlock;
+}
+__host__ __device__ constexpr int synthesis_gap(int nz, int elem) { return synthesis_block(nz, elem) == 8 ? 4 : 24; }
+__host__ __device__ constexpr int synthesis_row_stride(int nz, int elem) {
+    return 3 * synthesis_block(nz, elem) + synthesis_gap(nz, elem) + 1;
 }
 // Threads: the transform team (3 block/2 transforms x N1 lanes) and the
-// memory team (a multiple of N_z/2: each of its threads owns one k_z).
-__host__ __device__ constexpr int synthesis_transform_team(int nz) {
-    return 3 * (synthesis_block(nz) / 2) * (nz / synthesis_n2(nz));
+// memory team (a multiple of N_z/2 and of 64: each of its threads owns one k_z).
+__host__ __device__ constexpr int synthesis_transform_team(int nz, int elem) {
+    return 3 * (synthesis_block(nz, elem) / 2) * (nz / synthesis_n2(nz));
 }
-__host__ __device__ constexpr int synthesis_memory_team(int nz) {
-    return nz == 512 ? 256 : synthesis_transform_team(nz);
+__host__ __device__ constexpr int synthesis_memory_team(int nz, int elem) {
+    return synthesis_block(nz, elem) == 8 ? (nz / 2 < 64 ? 64 : nz / 2) : synthesis_transform_team(nz, elem);
 }
-__host__ __device__ constexpr int synthesis_threads(int nz) {
-    return synthesis_transform_team(nz) + synthesis_memory_team(nz);
+__host__ __device__ constexpr int synthesis_threads(int nz, int elem) {
+    return synthesis_transform_team(nz, elem) + synthesis_memory_team(nz, elem);
 }
 
 // Elements of one staging buffer, and LDS bytes of the workgroup (two buffers).
-__host__ __device__ constexpr int synthesis_buffer(int nz) {
-    return nz * synthesis_row_stride(nz) + nz / synthesis_n2(nz) * kPipeRowPad;
+__host__ __device__ constexpr int synthesis_buffer(int nz, int elem) {
+    return nz * synthesis_row_stride(nz, elem) + nz / synthesis_n2(nz) * kPipeRowPad;
 }
-inline size_t synthesis_pipe_lds(int nz, size_t re) { return 2 * (size_t)synthesis_buffer(nz) * re; }
+inline size_t synthesis_pipe_lds(int nz, size_t re) {
+    return 2 * (size_t)synthesis_buffer(nz, (int)re) * re;
+}
 
 // Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.
 inline int factorize(int n, int* rad) {

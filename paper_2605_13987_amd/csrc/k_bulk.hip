@@ -181,9 +181,9 @@ constexpr int const_gcd(int a, int b) { return b == 0 ? a : const_gcd(b, a % b);
 
 // Synthesis of H(X, Y, z, t) for N_z = N1 x N2 in {64, 128, 256, 512}, with
 // the length-N_z transforms done in registers.  One workgroup per (X, Y)
-// column; H is produced in blocks of 16 samples (8 for N_z = 512), each
-// staged whole in LDS as [z][sample][component] (the row layout is described
-// at kPipeBlock):
+// column; H is produced in blocks of 16 samples (8 for N_z = 512, and for
+// N_z = 256 in double), each staged whole in LDS as [z][sample][component]
+// (the row layout is described at kPipeBlock):
 //
 // 1. Spectra.  A memory-team thread owns k_z index kk and keeps the field
 //    table entries Ehat_a(X - X_w, Y - Y_w, kk) of all components and columns
@@ -211,21 +211,22 @@ constexpr int const_gcd(int a, int b) { return b == 0 ? a : const_gcd(b, a % b);
 // spectra into it (phase 2).  A workgroup barrier ends each phase; within a
 // phase the teams touch different buffers.
 template <typename T, int N1, int N2, int WC, typename TO>
-__global__ void __launch_bounds__(synthesis_threads(N1 * N2))
+__global__ void __launch_bounds__(synthesis_threads(N1 * N2, (int)sizeof(T)))
 k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, const float* h_scale,
                  TO* H) {
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
     constexpr int C = N2 / N1;
-    constexpr int TBC = synthesis_block(NZ);                   // samples per block
+    constexpr int EL = (int)sizeof(T);
+    constexpr int TBC = synthesis_block(NZ, EL);               // samples per block
     constexpr int NP = TBC / 2;                                // sample pairs per block
     constexpr int NG = 3 * NP;                                 // transforms per block
     constexpr int NTT = NG * N1;                               // transform team
-    constexpr int NTM = synthesis_memory_team(NZ);             // memory team
-    constexpr int GAP = synthesis_gap(NZ);
-    constexpr int RS = synthesis_row_stride(NZ);
+    constexpr int NTM = synthesis_memory_team(NZ, EL);         // memory team
+    constexpr int GAP = synthesis_gap(NZ, EL);
+    constexpr int RS = synthesis_row_stride(NZ, EL);
     constexpr int PAD = kPipeRowPad;                           // row z at z RS + (z / N2) PAD
-    constexpr int BUF = synthesis_buffer(NZ);                  // elements per staging buffer
+    constexpr int BUF = synthesis_buffer(NZ, EL);              // elements per staging buffer
     constexpr int PPT = NTM / NZH;                             // pairs covered by one pass of the team
     constexpr int PFI = (NP + PPT - 1) / PPT;                  // (kk, pair) items per thread
     constexpr int LW = 3 * TBC / 2;                            // value pairs per row
@@ -236,7 +237,7 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
     constexpr int CROWS = NTM * CR / LW;
     constexpr int CJ = NZ / CROWS;
     static_assert(N2 == synthesis_n2(NZ) && NTT % 64 == 0 && NTM % 64 == 0 && N2 % N1 == 0, "synthesis split");
-    static_assert(NTT + NTM == synthesis_threads(NZ), "synthesis teams");
+    static_assert(NTT + NTM == synthesis_threads(NZ, EL), "synthesis teams");
     static_assert(NTM % NZH == 0 && NZ % CROWS == 0 && (N2 % CROWS == 0 || CROWS % N2 == 0) && GAP % 2 == 0,
                   "synthesis thread mapping");
     extern __shared__ __align__(16) unsigned char smem[];
@@ -628,7 +629,8 @@ hipError_t synthesis_pipe(const Plan& p, char* b, void* h, hipStream_t s) {
     hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_pipe<T, N1, N2, WC, TO>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_synthesis_pipe<T, N1, N2, WC, TO>), dim3(p.N[0] * p.N[1]), dim3(synthesis_threads(NZ)), lds, s, p,
+    hipLaunchKernelGGL((k_synthesis_pipe<T, N1, N2, WC, TO>), dim3(p.N[0] * p.N[1]),
+                       dim3(synthesis_threads(NZ, (int)sizeof(T))), lds, s, p,
                        reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]),
@@ -652,7 +654,11 @@ hipError_t synthesis_pipe_n(const Plan& p, char* b, void* h, hipStream_t s) {
         case 64: return synthesis_pipe_w<T, 8, 8, TO>(p, b, h, s);
         case 128: return synthesis_pipe_w<T, 8, 16, TO>(p, b, h, s);
         case 256: return synthesis_pipe_w<T, 16, 16, TO>(p, b, h, s);
-        default: return synthesis_pipe_w<T, 16, 32, TO>(p, b, h, s);
+        default:
+            // N_z = 512: two 8-sample staging buffers of doubles exceed LDS,
+            // so plans in double take the Stockham synthesis there
+            if constexpr (sizeof(T) == 4) return synthesis_pipe_w<T, 16, 32, TO>(p, b, h, s);
+            return hipErrorInvalidValue;
     }
 }
 

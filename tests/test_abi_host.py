@@ -51,6 +51,11 @@ def test_plan_layout_32_and_128_grids():
     assert lay["h_bytes"] == 128 * 128 * 256 * 200 * 3 * 4
     assert lay["h_time_block"] == 16
     wt.wt_h_plan_destroy(plan)
+    # in double the register-FFT synthesis stages blocks of 8 samples at N_z = 256
+    plan, lay = wt.wt_h_plan_create(px128, cols, spec2, precision=wt.WT_F64)
+    assert lay["h_bytes"] == 128 * 128 * 256 * 200 * 3 * 8
+    assert lay["h_time_block"] == 8
+    wt.wt_h_plan_destroy(plan)
 
 
 def _status(mutate, precision=wt.WT_F32, **kw):

@@ -38,10 +38,15 @@ def px128_run(ctx, px128):
 COLS = [(0, 0), (64, 64), (77, 64), (64, 51), (10, 100), (127, 3), (96, 32), (33, 90)]
 
 
-def test_128x128x256_field_on_sampled_columns(px128, px128_run):
-    assert px128_run["status"] == wt.WT_OK, px128_run["report"]
+@pytest.fixture(scope="module")
+def px128_ref(px128):
     say("oracle: boundary fit + direct sums on 8 columns")
-    ref = oracle.weighting_field(px128["cell"], px128["columns"], px128["spectrum"], route="columns", cols_ij=COLS)
+    return oracle.weighting_field(px128["cell"], px128["columns"], px128["spectrum"], route="columns", cols_ij=COLS)
+
+
+def test_128x128x256_field_on_sampled_columns(px128, px128_run, px128_ref):
+    assert px128_run["status"] == wt.WT_OK, px128_run["report"]
+    ref = px128_ref
     im = intermediates(px128_run, px128)
     assert rel_l2(im["q"], ref["q"]) <= 1e-10
     assert rel_l2(im["q_t"], ref["q_t"]) <= 1e-10
@@ -49,6 +54,18 @@ def test_128x128x256_field_on_sampled_columns(px128, px128_run):
     for k, ij in enumerate(COLS):
         say(f"  column {ij}: rel L2 {rel_l2(got[k], ref['H_cols'][k]):.2e}")
     assert rel_l2(got, ref["H_cols"]) <= 1e-5
+
+
+def test_128x128x256_float64_field_on_sampled_columns(ctx, px128, px128_ref):
+    """The whole path in double (register-FFT synthesis with 8-sample blocks)."""
+    say("px128 solve (float64 field)")
+    run = solve_h(ctx, px128, wt.WT_F64)
+    assert run["status"] == wt.WT_OK, run["report"]
+    assert run["layout"]["h_time_block"] == 8
+    got = h_columns(run, px128, COLS)
+    err = rel_l2(got, px128_ref["H_cols"])
+    say(f"  float64 H on 8 columns: rel L2 {err:.2e}")
+    assert err <= 1e-9
 
 
 def _synthetic_device_field(f, N, nt, tb):

@@ -64,6 +64,7 @@ SMALL = [
     (20, 20, 5, 70, 8),
     (16, 128, 6, 37, 12),     # register-FFT synthesis with N_z = 8 x 16 and a ragged last block
     (8, 512, 5, 21, 8),       # N_z = 16 x 32, blocks of 8 samples, ragged odd last block
+    (8, 256, 5, 19, 8),       # N_z = 16 x 16: blocks of 8 in double, of 16 in float; ragged odd last block
 ]
 
 
