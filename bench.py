@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 # device-to-device copy gives for the same counters), in
 # profiles/k_synthesis_pipe_128x128x256.md.  Reported only while the kernel's
 # sources are the ones they were measured on.
-SYNTH_TRAFFIC_BYTES = {"plain": 10170757073, "mixed": 5136779930, "f64": None}
-SYNTH_TRAFFIC_SOURCES_SHA256 = "45c9d5cf4a98300ef01f04d67c1c47af4c959c53f88bd68a19c5266d9ef7357f"
-SYNTH_SOURCES = ("k_bulk.hip", "fft.hpp", "common.hpp")
+SYNTH_TRAFFIC_BYTES = {"plain": 10170749021, "mixed": 5136761805, "f64": 20341394389}
+SYNTH_TRAFFIC_SOURCES_SHA256 = "bda48876799aab6c47174087cc17d59be5d9d204781fa6ae8134cd62a0def774"
+SYNTH_SOURCES = ("k_bulk.hip", "synth_pipe.hpp", "fft.hpp", "common.hpp")
 
 
 def synthesis_sources_sha256():
@@ -371,7 +371,8 @@ def batched_variants(wt, workloads, torch, n_variants, replays):
     for it in items:
         wt.wt_h_plan_destroy(it["plan"])
     wt.wt_context_destroy(ctx)
-    n_pipe = sum(1 for v in variants if v["cell"]["N"][2] in (64, 128, 256, 512))
+    # a plan whose synthesis has a single candidate runs the register FFT
+    n_pipe = sum(1 for r in tuned if r["n_candidates"] == 1)
     n_tuned = sum(1 for r in tuned if r["n_candidates"] > 1)
     return {"n_variants": n_variants, "grid_freq_pts": pts, "ms_eager_default_launch": t_default,
             "autotune_s": tune_s, "variants_autotuned": n_tuned,

@@ -101,9 +101,13 @@ typedef enum {
     WT_H_F16_SCALED = 1    /* H stored as float16 values of H * h_scale, with
                               h_scale = 2^s chosen from a bound on |H| so that
                               every stored magnitude is <= 16384 (requires
-                              WT_F32 and N_z in {64, 128, 256, 512} with at most 4
-                              columns); the synthesis and the convolution
-                              compute in float */
+                              WT_F32 and a grid the register-FFT synthesis
+                              takes: N_z in {64, 128, 256, 512} with at most 4
+                              columns, or two columns and an even 2,3,5-smooth
+                              N_z in [72, 320]: 72, 80, 90, 96, 100, 108, 120,
+                              144, 150, 160, 162, 180, 192, 200, 216, 240, 250,
+                              270, 288, 300, 320); the synthesis and the
+                              convolution compute in float */
 } wt_h_format;
 
 typedef struct {
@@ -208,7 +212,10 @@ typedef struct {
 
 /* Autotuning of the synthesis launch for this plan's grid on this device:
  * runs wt_h_solve once, then times every candidate configuration of the LDS
- * Stockham synthesis (used for N_z outside {64, 128, 256, 512}): its time
+ * Stockham synthesis (used where the register-FFT synthesis has no form: N_z
+ * neither in {64, 128, 256, 512} nor among the smooth sizes listed at
+ * WT_H_F16_SCALED; a smooth size in double or without exactly two columns;
+ * N_z = 512 in double; more than 4 columns): its time
  * block (powers of two up to 32 whose staging fits in LDS) and workgroup
  * size (256, 512), two launches each after a warm-up, keeps the fastest
  * in the plan and rewrites H in that configuration.  The register-FFT

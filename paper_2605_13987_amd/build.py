@@ -17,8 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwt.so")
-SOURCES = ["abi.hip", "k_green.hip", "k_solve.hip", "k_time.hip", "k_bulk.hip", "k_conv.hip", "k_elec.hip",
-           "k_adj.hip"]
+SOURCES = ["abi.hip", "k_green.hip", "k_solve.hip", "k_time.hip", "k_bulk.hip", "k_synth_smooth.hip", "k_conv.hip",
+           "k_elec.hip", "k_adj.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -164,16 +164,19 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     const size_t re = p.precision == WT_F64 ? sizeof(double) : sizeof(float);
     const size_t cx = 2 * re;
     // Time block of the H layout (the synthesis stages a whole block in LDS):
-    // the pipelined register-FFT synthesis for N_z in {64, 128, 256, 512} with
-    // at most 4 columns when its two staging buffers fit (blocks of 16
-    // samples, 8 where two such buffers would not fit: N_z = 512, and 256 in
-    // double);
+    // the pipelined register-FFT synthesis where it has a form (N_z in
+    // {64, 128, 256, 512} with at most 4 columns; the other 2,3,5-smooth
+    // sizes of synthesis_n1 with two columns in float) and its two staging
+    // buffers fit (blocks of 16 samples, or of 8 where two such buffers
+    // would not fit: N_z = 512, and 256 in double);
     // otherwise the LDS Stockham synthesis, whose block is halved until its
     // tables fit.
     const size_t lds_budget = 160 * 1024;
-    const bool pipe_size = N[2] == 64 || N[2] == 128 || N[2] == 256 || N[2] == 512;
+    const bool pipe_size = wt::synthesis_pow2(N[2])
+                               ? n_cols <= 4
+                               : (wt::synthesis_n1(N[2]) > 0 && n_cols == 2 && p.precision == WT_F32);
     int tb;
-    if (pipe_size && n_cols <= 4 && wt::synthesis_pipe_lds(N[2], re) <= lds_budget) {
+    if (pipe_size && wt::synthesis_pipe_lds(N[2], re) <= lds_budget) {
         p.synth_kernel = 2;
         tb = std::min(sp->n_time, wt::synthesis_block(N[2], (int)re));
     } else {

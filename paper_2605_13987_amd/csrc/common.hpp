@@ -138,44 +138,97 @@ hipError_t launch_adjoint_rhs(const Plan& p, const GradLayout& g, const void* ws
 hipError_t launch_adjoint_params(const Plan& p, const GradLayout& g, const void* ws, void* gws, double* out,
                                  hipStream_t s);
 
-// Register-FFT synthesis (N_z = N1 x N2 in {64, 128, 256, 512}).
-__host__ __device__ constexpr int synthesis_n2(int nz) { return nz == 64 ? 8 : (nz == 512 ? 32 : 16); }
+// Register-FFT synthesis: N_z = N1 x N2 with both factors at most 32 and
+// 2,3,5-smooth.  Pass 1 transforms over N2 (one lane per k1 < N1), pass 2
+// over N1.  Powers of two: 64 = 8 x 8, 128 = 8 x 16, 256 = 16 x 16, 512 =
+// 16 x 32; the other even 2,3,5-smooth sizes up to 320 take N1 >= 8 (so that
+// the transform team has several wavefronts) and the factor pair with the
+// fewest issued lane-operations.  0: no register-FFT form.
+__host__ __device__ constexpr int synthesis_n1(int nz) {
+    switch (nz) {
+        case 64: return 8;
+        case 128: return 8;
+        case 256: return 16;
+        case 512: return 16;
+        case 72: return 9;
+        case 80: return 10;
+        case 90: return 10;
+        case 96: return 8;
+        case 100: return 10;
+        case 108: return 12;
+        case 120: return 8;
+        case 144: return 12;
+        case 150: return 10;
+        case 160: return 8;
+        case 162: return 9;
+        case 180: return 10;
+        case 192: return 8;
+        case 200: return 10;
+        case 216: return 8;
+        case 240: return 8;
+        case 250: return 10;
+        case 270: return 10;
+        case 288: return 12;
+        case 300: return 10;
+        case 320: return 10;
+        default: return 0;
+    }
+}
+__host__ __device__ constexpr bool synthesis_pow2(int nz) { return nz == 64 || nz == 128 || nz == 256 || nz == 512; }
 
-// H is produced in blocks of kPipeBlock samples (8 where two 16-sample
-// staging buffers would not fit in LDS: N_z = 512, and N_z = 256 in double),
-// each staged in LDS as rows of 3 x block values: sample pair q, component c,
-// real/imaginary part at column 6 q + c (+3), plus a gap from pair block/4 on,
-// row z at RS z + 3 floor(z / N2).  The gap and the padding keep the
-// transforms' LDS accesses free of bank conflicts (two groups of a
-// half-wavefront take sample pairs block/4 apart).  elem: bytes per real.
-constexpr int kPipeBlock = 16;
-constexpr int kPipeRowPad = 3;
-__host__ __device__ constexpr int synthesis_block(int nz, int elem) {
-    return (nz == 512 || (nz == 256 && elem == 8)) ? 8 : kPipeBlock;
+// Launch shape of the register-FFT synthesis for N_z and elem bytes per real.
+// H is produced in blocks of tbc samples (16, or 8 where two 16-sample
+// staging buffers would not fit in LDS), each staged in LDS as rows of
+// 3 x tbc values: sample pair q, component c, real/imaginary part at column
+// 6 q + c (+3), plus a gap from pair tbc/4 on; row z at rs z + pad floor(z / N2).
+// For the powers of two the gap and the padding keep the transforms' LDS
+// accesses free of bank conflicts (two groups of a half-wavefront take sample
+// pairs tbc/4 apart); the other sizes use neither.
+// Teams: the transform team holds gpw groups of N1 lanes per wavefront (a
+// group never straddles two), one group per transform (3 tbc/2 of them); the
+// memory team's first ntm_act = (N_z/2) ppt threads own one k_z each and ppt
+// sample pairs per pass, rounded up to whole wavefronts.
+struct PipeShape {
+    int n1, n2, tbc, gap, pad, rs, gpw, ntt, ppt, ntm_act, ntm, threads, buffer;
+};
+__host__ __device__ constexpr PipeShape pipe_shape_block(int nz, int tbc) {
+    PipeShape s{};
+    s.n1 = synthesis_n1(nz);
+    if (s.n1 == 0) return s;
+    s.n2 = nz / s.n1;
+    s.tbc = tbc;
+    const bool p2 = synthesis_pow2(nz);
+    s.gap = p2 ? (tbc == 8 ? 4 : 24) : 0;
+    s.pad = p2 ? 3 : 0;
+    s.rs = 3 * tbc + s.gap + 1;
+    s.gpw = 64 / s.n1;
+    const int ng = 3 * (tbc / 2);
+    s.ntt = (ng + s.gpw - 1) / s.gpw * 64;
+    const int nzh = nz / 2;
+    // powers of two: as many pairs per pass as the transform team has
+    // threads; other sizes: about 256 memory threads (enough stores in
+    // flight for the copy-out)
+    int ppt = p2 ? s.ntt / nzh : (256 + nzh / 2) / nzh;
+    ppt = ppt > tbc / 2 ? tbc / 2 : ppt;
+    s.ppt = ppt < 1 ? 1 : ppt;
+    s.ntm_act = nzh * s.ppt;
+    s.ntm = (s.ntm_act + 63) / 64 * 64;
+    s.threads = s.ntt + s.ntm;
+    s.buffer = nz * s.rs + nz / s.n2 * s.pad;
+    return s;
 }
-__host__ __device__ constexpr int synthesis_gap(int nz, int elem) { return synthesis_block(nz, elem) == 8 ? 4 : 24; }
-__host__ __device__ constexpr int synthesis_row_stride(int nz, int elem) {
-    return 3 * synthesis_block(nz, elem) + synthesis_gap(nz, elem) + 1;
+constexpr size_t kPipeLdsBudget = 160 * 1024;
+__host__ __device__ constexpr PipeShape pipe_shape(int nz, int elem) {
+    const PipeShape s16 = pipe_shape_block(nz, 16);
+    return 2 * (size_t)s16.buffer * elem <= kPipeLdsBudget ? s16 : pipe_shape_block(nz, 8);
 }
-// Threads: the transform team (3 block/2 transforms x N1 lanes) and the
-// memory team (a multiple of N_z/2 and of 64: each of its threads owns one k_z).
-__host__ __device__ constexpr int synthesis_transform_team(int nz, int elem) {
-    return 3 * (synthesis_block(nz, elem) / 2) * (nz / synthesis_n2(nz));
-}
-__host__ __device__ constexpr int synthesis_memory_team(int nz, int elem) {
-    return synthesis_block(nz, elem) == 8 ? (nz / 2 < 64 ? 64 : nz / 2) : synthesis_transform_team(nz, elem);
-}
-__host__ __device__ constexpr int synthesis_threads(int nz, int elem) {
-    return synthesis_transform_team(nz, elem) + synthesis_memory_team(nz, elem);
-}
-
-// Elements of one staging buffer, and LDS bytes of the workgroup (two buffers).
-__host__ __device__ constexpr int synthesis_buffer(int nz, int elem) {
-    return nz * synthesis_row_stride(nz, elem) + nz / synthesis_n2(nz) * kPipeRowPad;
-}
-inline size_t synthesis_pipe_lds(int nz, size_t re) {
-    return 2 * (size_t)synthesis_buffer(nz, (int)re) * re;
-}
+__host__ __device__ constexpr int synthesis_block(int nz, int elem) { return pipe_shape(nz, elem).tbc; }
+__host__ __device__ constexpr int synthesis_threads(int nz, int elem) { return pipe_shape(nz, elem).threads; }
+// LDS bytes of the workgroup (two staging buffers).
+inline size_t synthesis_pipe_lds(int nz, size_t re) { return 2 * (size_t)pipe_shape(nz, (int)re).buffer * re; }
+// Register-FFT synthesis of the other 2,3,5-smooth sizes: float path, two
+// columns (the standard cell), k_synth_smooth.hip.
+hipError_t launch_synthesis_smooth(const Plan& p, char* b, void* h, hipStream_t s);
 
 // Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.
 inline int factorize(int n, int* rad) {

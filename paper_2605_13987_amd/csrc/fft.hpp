@@ -174,4 +174,103 @@ __device__ inline void dft_reg(cplx<T>* x) {
     }
 }
 
+// cos and sin of 2 pi j / R for compile-time constants: the angle is reduced
+// with integer arithmetic to q quarter turns plus x in [0, pi/4], and x goes
+// through the Taylor series (14 terms: the remainder is below 1e-30), so
+// that quarter turns are exact.
+struct UnitRoot {
+    double c, s;
+};
+__host__ __device__ constexpr double taylor_sin(double x) {
+    double t = x, s = x;
+    for (int n = 1; n < 14; ++n) {
+        t *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+        s += t;
+    }
+    return s;
+}
+__host__ __device__ constexpr double taylor_cos(double x) {
+    double t = 1.0, s = 1.0;
+    for (int n = 1; n < 14; ++n) {
+        t *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+        s += t;
+    }
+    return s;
+}
+__host__ __device__ constexpr UnitRoot unit_root(int j, int R) {
+    constexpr double kHalfPi = 1.57079632679489661923;
+    j %= R;
+    if (j < 0) j += R;
+    const int q = 4 * j / R, f = 4 * j - q * R;               // angle = (pi/2) (q + f/R)
+    double c = 0.0, s = 0.0;
+    if (2 * f <= R) {
+        const double x = kHalfPi * f / R;
+        c = taylor_cos(x);
+        s = taylor_sin(x);
+    } else {
+        const double x = kHalfPi * (R - f) / R;                // (pi/2) f/R = pi/2 - x
+        c = taylor_sin(x);
+        s = taylor_cos(x);
+    }
+    if (q == 0) return UnitRoot{c, s};
+    if (q == 1) return UnitRoot{-s, c};
+    if (q == 2) return UnitRoot{-c, -s};
+    return UnitRoot{s, -c};
+}
+
+// x exp(+2 pi i e / R) for compile-time e and R (quarter turns as swaps).
+template <typename T>
+__device__ inline cplx<T> mul_unit_root(const cplx<T>& x, int e, int R) {
+    e %= R;
+    if (e == 0) return x;
+    if (2 * e == R) return cplx<T>{-x.re, -x.im};
+    if (4 * e == R) return mul_i(x);
+    if (4 * e == 3 * R) return cplx<T>{x.im, -x.re};
+    const UnitRoot w = unit_root(e, R);
+    const T c = (T)w.c, s = (T)w.s;
+    return cplx<T>{fma(x.re, c, -x.im * s), fma(x.re, s, x.im * c)};
+}
+
+template <int L>
+__host__ __device__ constexpr int first_radix() {
+    return L % 4 == 0 ? 4 : (L % 2 == 0 ? 2 : (L % 3 == 0 ? 3 : 5));
+}
+
+// In-register inverse DFT of a 2,3,5-smooth R (the Stockham passes of
+// fft_inverse_lds with compile-time indices: radix 4 first, then 2, 3, 5; the
+// copies between passes are register renames).  P: product of the radices
+// already applied.
+template <typename T, int R, int P>
+__device__ inline void dft_mixed_pass(cplx<T>* a) {
+    if constexpr (P < R) {
+        constexpr int r = first_radix<R / P>();
+        constexpr int m = R / r;
+        constexpr int tws = R / (P * r);
+        static_assert(R % (P * r) == 0 && (r == 2 || r == 3 || r == 4 || r == 5), "smooth register DFT");
+        cplx<T> b[R];
+#pragma unroll
+        for (int i = 0; i < m; ++i) {
+            const int k = i % P;
+            cplx<T> x[r];
+#pragma unroll
+            for (int q = 0; q < r; ++q) x[q] = mul_unit_root(a[i + q * m], q * k * tws, R);
+            butterfly<T, r>(x);
+#pragma unroll
+            for (int s = 0; s < r; ++s) b[(i - k) * r + k + s * P] = x[s];
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) a[i] = b[i];
+        dft_mixed_pass<T, R, P * r>(a);
+    }
+}
+
+// x[n] <- sum_k x[k] exp(+2 pi i n k / R) in registers, any R the synthesis uses.
+template <typename T, int R>
+__device__ inline void dft_any(cplx<T>* x) {
+    if constexpr ((R & (R - 1)) == 0)
+        dft_reg<T, R>(x);
+    else
+        dft_mixed_pass<T, R, 1>(x);
+}
+
 }  // namespace wt
