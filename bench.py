@@ -302,13 +302,14 @@ def current_compulsory_bytes(cfg, elem_bytes):
     return h_bytes + 24 * n_steps + car["n_tracks"] * nt * 4, n_steps
 
 
-def batched_variants(wt, workloads, torch, n_variants, replays):
+def batched_variants(wt, workloads, torch, n_variants, replays, n_lanes=4):
     """The geometry-variant batch: n_variants seeded cells of uneven grids and
     frequency counts, each a full step (H solve + current of its track), run
     eagerly with the plans' default synthesis launch, then with every plan
     autotuned (wt_h_plan_tune), eagerly and as one captured HIP graph on one
     stream, sharing one workspace and one H buffer sized for the largest
-    variant."""
+    variant; then the same batch through wt_batch_run over n_lanes lanes of
+    streams (a workspace and an H buffer per lane), eager and captured."""
     import numpy as np
 
     variants = [workloads.geometry_variant(k) for k in range(n_variants)]
@@ -368,6 +369,32 @@ def batched_variants(wt, workloads, torch, n_variants, replays):
         err = max(err, max(float((it["out"] - r).abs().max() / r.abs().max().clamp_min(1e-30))
                            for it, r in zip(items, ref)))
     del graph
+    # the same batch on lanes of streams (wt_batch_run: longest item first, to
+    # the lane with the least work), eager and as one captured graph
+    del ws, h
+    lane_ws = [torch.empty(ws_bytes, dtype=torch.uint8, device="cuda") for _ in range(n_lanes)]
+    lane_h = [torch.empty(h_bytes, dtype=torch.uint8, device="cuda") for _ in range(n_lanes)]
+    args = [dict(plan=it["plan"], n_carriers=it["pos"].shape[0], n_tracks=it["n_tr"], d_pos=it["pos"].data_ptr(),
+                 d_charge=it["q"].data_ptr(), d_track=it["tr"].data_ptr(), d_current=it["out"].data_ptr())
+            for it in items]
+
+    def lanes():
+        wt.wt_batch_run(ctx, args, [w.data_ptr() for w in lane_ws], ws_bytes, [x.data_ptr() for x in lane_h], h_bytes)
+
+    with torch.cuda.stream(stream):
+        lanes()
+        t_lanes = timed(lanes)
+    err_lanes = max(float((it["out"] - r).abs().max() / r.abs().max().clamp_min(1e-30)) for it, r in zip(items, ref))
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        lanes()
+    t_lanes_graph = []
+    for _ in range(replays):
+        with torch.cuda.stream(stream):
+            t_lanes_graph.append(timed(graph.replay))
+        err_lanes = max(err_lanes, max(float((it["out"] - r).abs().max() / r.abs().max().clamp_min(1e-30))
+                                       for it, r in zip(items, ref)))
+    del graph, lane_ws, lane_h
     for it in items:
         wt.wt_h_plan_destroy(it["plan"])
     wt.wt_context_destroy(ctx)
@@ -379,6 +406,11 @@ def batched_variants(wt, workloads, torch, n_variants, replays):
             "ms_eager": t_eager, "ms_graph": float(np.median(t_graph)),
             "value_graph": pts / (np.median(t_graph) * 1e-3), "unit": "grid*freq pts/s",
             "replay_vs_eager_current_max_rel_diff": err, "variants_on_register_fft_synthesis": n_pipe,
+            "lanes": {"n_lanes": n_lanes, "ms_eager": t_lanes, "ms_graph": float(np.median(t_lanes_graph)),
+                      "value_graph": pts / (np.median(t_lanes_graph) * 1e-3),
+                      "current_max_rel_diff_vs_one_stream": err_lanes,
+                      "note": "wt_batch_run: the items spread over lanes of streams, each lane its own workspace "
+                              "and H buffer"},
             "workload": ("seeded geometry variants: pitch 25-100 um, radius 3-10 um, five resistivities "
                          "0.01-1 ohm cm, grids 64..160 x 64..160 x 64..320 (even 2*3*5-smooth), 64-256 frequencies, "
                          "200 x 10 ps, one 1e3-pair MIP track each; float32 H, one shared workspace and H buffer")}

@@ -252,6 +252,43 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h,
                      const wt_carriers* carriers, void* d_workspace, size_t workspace_bytes,
                      void* d_i_out);
 
+/* Batched forward runs over many geometry variants (each variant is one
+ * cell, column set and spectrum: one plan; the workloads of the paper's
+ * Section 4 studies vary pitch, diameter and resistivity).  For every item,
+ * wt_h_solve followed by wt_current, exactly as the two calls would run
+ * them; the items are spread over n_lanes HIP streams that fork from the
+ * context's stream and join it again, so that one item's small launches
+ * (tables, boundary fit, time transform) overlap another's synthesis.
+ *   items        [n_items] host array; plan, carriers as for wt_current,
+ *                d_current [n_tracks][n_time] in the plan's precision
+ *   d_workspace  [n_lanes] device buffers of workspace_bytes each (256-byte
+ *                aligned), d_h [n_lanes] buffers of h_bytes each (16-byte
+ *                aligned): lane l's scratch, reused by its items in turn
+ *   item_status  [n_items] host array or NULL: WT_OK, or why item i was
+ *                skipped without running (WT_E_WORKSPACE: its plan's
+ *                workspace or H does not fit a lane's buffers;
+ *                WT_E_INVALID_ARG: no plan, output or carriers)
+ * Items are taken longest first (H bytes plus a fixed per-item cost) and
+ * each goes to the lane with the least work so far; a lane runs its items
+ * in that order.  n_lanes: 1..8.  Stream-ordered like the other calls:
+ * nothing is waited for, so the whole call can be captured into a HIP graph
+ * (the lanes join the capture through events); the lanes' streams (default
+ * priority, non-blocking) and events are created by the first call on the
+ * context, which therefore must not itself be under capture.  Returns WT_OK
+ * when every item ran, else the status of the first skipped item
+ * (WT_E_INVALID_ARG for bad arguments, with nothing run). */
+typedef struct {
+    const wt_h_plan* plan;
+    wt_carriers carriers;
+    void* d_current;
+} wt_batch_item;
+
+#define WT_MAX_LANES 8
+
+wt_status wt_batch_run(wt_context* ctx, int n_items, const wt_batch_item* items, int n_lanes,
+                       void* const* d_workspace, size_t workspace_bytes,
+                       void* const* d_h, size_t h_bytes, int* item_status);
+
 /* Readout electronics and timing features (the workflow's last step,
  * Section 2: the induced signals convolved with the transfer function of the
  * readout electronics, plus noise; the front-end model is the caller's).

@@ -19,6 +19,11 @@ struct wt_context {
     hipEvent_t ev[8];
     int n_events;       // events recorded by the last call
     int stage_ids[8];   // stage id of the interval ending at ev[i+1]
+    // wt_batch_run: lane streams and their events, made on first use
+    int n_lanes;
+    hipStream_t lane[WT_MAX_LANES];
+    hipEvent_t lane_done[WT_MAX_LANES];
+    hipEvent_t fork;
 };
 
 struct wt_h_plan {
@@ -302,6 +307,31 @@ wt_status mark(wt_context* ctx, int stage) {
     return WT_OK;
 }
 
+// The launches of wt_h_solve on stream s; mark_stage(id) is called after
+// each stage (and with -1 before the first).
+template <typename Mark>
+wt_status enqueue_solve(wt_context* ctx, const Plan& p, void* ws, void* d_h, hipStream_t s, Mark mark_stage) {
+    wt_status st;
+    if ((st = mark_stage(-1)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_twiddles(p, ws, s), "twiddles");
+    WT_HIP(ctx, wt::launch_green_tables(p, ws, s), "green_tables");
+    if ((st = mark_stage(kStageTables)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_collocation_solve(p, ws, s), "collocation_solve");
+    if ((st = mark_stage(kStageSolve)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_time_transform(p, ws, s), "time_transform");
+    if ((st = mark_stage(kStageTime)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_field_table(p, ws, s), "field_table");
+    if (p.h_format == WT_H_F16_SCALED) WT_HIP(ctx, wt::launch_h_scale(p, ws, d_h, s), "h_scale");
+    if ((st = mark_stage(kStageFieldTable)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_synthesis(p, ws, d_h, s), "synthesis");
+    return mark_stage(kStageSynthesis);
+}
+
+bool carriers_ok(const wt_carriers* car) {
+    if (car->n_carriers < 0 || car->n_tracks < 1) return false;
+    return car->n_carriers == 0 || (car->d_pos && car->d_charge && car->d_track);
+}
+
 }  // namespace
 
 extern "C" {
@@ -354,6 +384,8 @@ wt_status wt_context_create(wt_context** out, int hip_device, void* hip_stream) 
     ctx->timing = false;
     ctx->n_events = 0;
     for (auto& e : ctx->ev) e = nullptr;
+    ctx->n_lanes = 0;
+    ctx->fork = nullptr;
     *out = ctx;
     return WT_OK;
 }
@@ -362,6 +394,11 @@ wt_status wt_context_destroy(wt_context* ctx) {
     if (!ctx) return WT_E_INVALID_ARG;
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (int l = 0; l < ctx->n_lanes; ++l) {
+        (void)hipEventDestroy(ctx->lane_done[l]);
+        (void)hipStreamDestroy(ctx->lane[l]);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     delete ctx;
     return WT_OK;
 }
@@ -437,19 +474,8 @@ wt_status wt_h_solve(wt_context* ctx, const wt_h_plan* plan, void* d_workspace, 
     if (st != WT_OK) return st;
     ctx->n_events = 0;
     hipStream_t s = ctx->stream;
-    if ((st = mark(ctx, -1)) != WT_OK) return st;
-    WT_HIP(ctx, wt::launch_twiddles(p, d_workspace, s), "twiddles");
-    WT_HIP(ctx, wt::launch_green_tables(p, d_workspace, s), "green_tables");
-    if ((st = mark(ctx, kStageTables)) != WT_OK) return st;
-    WT_HIP(ctx, wt::launch_collocation_solve(p, d_workspace, s), "collocation_solve");
-    if ((st = mark(ctx, kStageSolve)) != WT_OK) return st;
-    WT_HIP(ctx, wt::launch_time_transform(p, d_workspace, s), "time_transform");
-    if ((st = mark(ctx, kStageTime)) != WT_OK) return st;
-    WT_HIP(ctx, wt::launch_field_table(p, d_workspace, s), "field_table");
-    if (p.h_format == WT_H_F16_SCALED) WT_HIP(ctx, wt::launch_h_scale(p, d_workspace, d_h, s), "h_scale");
-    if ((st = mark(ctx, kStageFieldTable)) != WT_OK) return st;
-    WT_HIP(ctx, wt::launch_synthesis(p, d_workspace, d_h, s), "synthesis");
-    if ((st = mark(ctx, kStageSynthesis)) != WT_OK) return st;
+    st = enqueue_solve(ctx, p, d_workspace, d_h, s, [ctx](int stage) { return mark(ctx, stage); });
+    if (st != WT_OK) return st;
     if (!report) return WT_OK;
 
     std::vector<wt::SolveReport> rep(p.n_freq);
@@ -483,8 +509,7 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, co
     (void)d_workspace;
     (void)workspace_bytes;
     if (!ctx || !plan || !d_h || !car || !d_i_out) return WT_E_INVALID_ARG;
-    if (car->n_carriers < 0 || car->n_tracks < 1) return WT_E_INVALID_ARG;
-    if (car->n_carriers > 0 && (!car->d_pos || !car->d_charge || !car->d_track)) return WT_E_INVALID_ARG;
+    if (!carriers_ok(car)) return WT_E_INVALID_ARG;
     const Plan& p = plan->p;
     wt_status st = bind(ctx);
     if (st != WT_OK) return st;
@@ -495,6 +520,78 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, co
            "current");
     if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
     return WT_OK;
+}
+
+wt_status wt_batch_run(wt_context* ctx, int n_items, const wt_batch_item* items, int n_lanes,
+                       void* const* d_workspace, size_t workspace_bytes, void* const* d_h, size_t h_bytes,
+                       int* item_status) {
+    if (!ctx || n_items < 0 || (n_items > 0 && !items) || n_lanes < 1 || n_lanes > WT_MAX_LANES || !d_workspace ||
+        !d_h)
+        return WT_E_INVALID_ARG;
+    for (int l = 0; l < n_lanes; ++l) {
+        if (!d_workspace[l] || !d_h[l]) return WT_E_INVALID_ARG;
+        if ((reinterpret_cast<uintptr_t>(d_workspace[l]) & 255) || (reinterpret_cast<uintptr_t>(d_h[l]) & 15))
+            return WT_E_INVALID_ARG;
+    }
+    wt_status st = bind(ctx);
+    if (st != WT_OK) return st;
+    if (!ctx->fork) WT_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming), "hipEventCreate");
+    while (ctx->n_lanes < n_lanes) {
+        const int l = ctx->n_lanes;
+        WT_HIP(ctx, hipStreamCreateWithFlags(&ctx->lane[l], hipStreamNonBlocking), "hipStreamCreate");
+        if (hipEventCreateWithFlags(&ctx->lane_done[l], hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(ctx->lane[l]);
+            return hip_fail(ctx, hipErrorOutOfMemory, "hipEventCreate");
+        }
+        ++ctx->n_lanes;
+    }
+    // per-item checks; then longest first, each to the lane with the least work
+    wt_status first_bad = WT_OK;
+    std::vector<int> order;
+    std::vector<double> cost(n_items, 0.0);
+    for (int i = 0; i < n_items; ++i) {
+        const wt_batch_item& it = items[i];
+        wt_status si = WT_OK;
+        if (!it.plan || !it.d_current || !carriers_ok(&it.carriers))
+            si = WT_E_INVALID_ARG;
+        else if (it.plan->p.ws_bytes > workspace_bytes || it.plan->p.h_bytes > h_bytes)
+            si = WT_E_WORKSPACE;
+        if (item_status) item_status[i] = si;
+        if (si != WT_OK) {
+            if (first_bad == WT_OK) first_bad = si;
+            continue;
+        }
+        // seconds at 4 TB/s for H, plus ~1 ms of small launches per item
+        cost[i] = (double)it.plan->p.h_bytes / 4e12 + 1e-3;
+        order.push_back(i);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<double> load(n_lanes, 0.0);
+    std::vector<std::vector<int>> queue(n_lanes);
+    for (int i : order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[l] += cost[i];
+        queue[l].push_back(i);
+    }
+    WT_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream), "hipEventRecord");
+    for (int l = 0; l < n_lanes; ++l) {
+        if (queue[l].empty()) continue;
+        hipStream_t s = ctx->lane[l];
+        WT_HIP(ctx, hipStreamWaitEvent(s, ctx->fork, 0), "hipStreamWaitEvent");
+        for (int i : queue[l]) {
+            const wt_batch_item& it = items[i];
+            const Plan& p = it.plan->p;
+            st = enqueue_solve(ctx, p, d_workspace[l], d_h[l], s, [](int) { return WT_OK; });
+            if (st != WT_OK) return st;
+            const wt_carriers& c = it.carriers;
+            WT_HIP(ctx, wt::launch_current(p, d_h[l], c.n_carriers, c.n_tracks, c.d_pos, c.d_charge, c.d_track,
+                                           it.d_current, s),
+                   "current");
+        }
+        WT_HIP(ctx, hipEventRecord(ctx->lane_done[l], s), "hipEventRecord");
+        WT_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->lane_done[l], 0), "hipStreamWaitEvent");
+    }
+    return first_bad;
 }
 
 wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, size_t workspace_bytes, void* d_h,

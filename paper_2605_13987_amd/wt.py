@@ -85,6 +85,13 @@ class wt_carriers(ctypes.Structure):
                 ("d_charge", c_void_p), ("d_track", c_void_p)]
 
 
+class wt_batch_item(ctypes.Structure):
+    _fields_ = [("plan", c_void_p), ("carriers", wt_carriers), ("d_current", c_void_p)]
+
+
+WT_MAX_LANES = 8
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_13987_amd.build`")
@@ -115,6 +122,8 @@ def _load():
         "wt_electronics": (c_int, [c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                    c_double, c_double, c_void_p, c_void_p]),
         "wt_h_plan_tune": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_tune_report)]),
+        "wt_batch_run": (c_int, [c_void_p, c_int, P(wt_batch_item), c_int, P(c_void_p), c_size_t, P(c_void_p),
+                                 c_size_t, P(c_int)]),
         "wt_h_gradient_workspace": (c_int, [c_void_p, c_int, P(c_size_t)]),
         "wt_h_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, P(wt_carriers), c_void_p, c_void_p,
                                   c_size_t, c_void_p, P(wt_h_report)]),
@@ -269,6 +278,29 @@ def wt_current(ctx, plan, d_h: int, n_carriers: int, n_tracks: int, d_pos: int, 
     car = wt_carriers(int(n_carriers), int(n_tracks), c_void_p(d_pos), c_void_p(d_charge), c_void_p(d_track))
     _check(LIB.wt_current(ctx, plan, c_void_p(d_h), ctypes.byref(car), c_void_p(d_workspace or None),
                           int(workspace_bytes), c_void_p(d_i_out)), "wt_current", ctx)
+
+
+def wt_batch_run(ctx, items, d_workspaces, workspace_bytes: int, d_hs, h_bytes: int, raise_on_error: bool = True):
+    """Batched wt_h_solve + wt_current over lanes of streams.
+
+    items: list of dicts with plan, n_carriers, n_tracks, d_pos, d_charge,
+    d_track, d_current (device pointers as ints); d_workspaces / d_hs: one
+    device pointer per lane.  Returns (status, [status per item])."""
+    n, lanes = len(items), len(d_workspaces)
+    arr = (wt_batch_item * max(n, 1))()
+    for i, it in enumerate(items):
+        arr[i].plan = it["plan"]
+        arr[i].carriers = wt_carriers(int(it["n_carriers"]), int(it["n_tracks"]), c_void_p(it["d_pos"] or None),
+                                      c_void_p(it["d_charge"] or None), c_void_p(it["d_track"] or None))
+        arr[i].d_current = c_void_p(it["d_current"] or None)
+    ws = (c_void_p * max(lanes, 1))(*[c_void_p(x) for x in d_workspaces])
+    hs = (c_void_p * max(len(d_hs), 1))(*[c_void_p(x) for x in d_hs])
+    status = (c_int * max(n, 1))()
+    st = LIB.wt_batch_run(ctx, n, arr, lanes, ws, int(workspace_bytes), hs, int(h_bytes), status)
+    per_item = [int(status[i]) for i in range(n)]
+    if raise_on_error and st != WT_OK:
+        _check(st, "wt_batch_run", ctx)
+    return st, per_item
 
 
 def wt_electronics(ctx, precision: int, n_tracks: int, n_time: int, dt: float, d_current: int, d_response: int,

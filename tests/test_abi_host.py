@@ -192,3 +192,8 @@ def test_gradient_workspace_and_validation():
     finally:
         wt.wt_h_plan_destroy(plan)
 
+
+
+def test_batch_run_rejects_a_null_context():
+    st, per = wt.wt_batch_run(None, [], [0], 0, [0], 0, raise_on_error=False)
+    assert st == wt.WT_E_INVALID_ARG and per == []
