@@ -398,8 +398,7 @@ def batched_variants(wt, workloads, torch, n_variants, replays, n_lanes=4):
     for it in items:
         wt.wt_h_plan_destroy(it["plan"])
     wt.wt_context_destroy(ctx)
-    # a plan whose synthesis has a single candidate runs the register FFT
-    n_pipe = sum(1 for r in tuned if r["n_candidates"] == 1)
+    n_pipe = sum(1 for r in tuned if r["fft_n1"] > 0)
     n_tuned = sum(1 for r in tuned if r["n_candidates"] > 1)
     return {"n_variants": n_variants, "grid_freq_pts": pts, "ms_eager_default_launch": t_default,
             "autotune_s": tune_s, "variants_autotuned": n_tuned,

@@ -115,7 +115,18 @@ typedef struct {
     int ir_max_iter;    /* refinement sweeps after the LU solve, 0..16 */
     double ir_tol;      /* target normwise backward error (>= 0) */
     int h_format;       /* wt_h_format */
+    int fft_schedule;   /* register-FFT synthesis of a non-power-of-two smooth
+                           N_z: which of its compiled schedules to start from,
+                           0 .. wt_fft_schedule_count(N_z) - 1 (0: the
+                           default, the fastest measured); must be 0 for
+                           other grids (WT_E_INVALID_ARG otherwise) */
 } wt_h_options;
+
+/* Number of register-FFT synthesis schedules compiled for a float plan with
+ * two columns and this N_z: 1 for 64, 128, 256, 512; the count of the
+ * smooth size's schedules (a factor pair N_z = N1 x N2 and a staging block)
+ * for the non-power-of-two sizes listed at WT_H_F16_SCALED; 0 otherwise. */
+int wt_fft_schedule_count(int n_z);
 
 /* Filled by wt_h_solve when a report pointer is given (that call then
  * synchronises the stream). */
@@ -208,6 +219,9 @@ typedef struct {
     int threads;         /* workgroup size of the chosen synthesis launch */
     double ms_chosen;    /* synthesis time of the chosen configuration (-1 if none timed) */
     double ms_default;   /* the plan's configuration before tuning (-1 if none timed) */
+    int fft_n1;          /* register-FFT synthesis: N_z = fft_n1 x (N_z / fft_n1)
+                            (pass-1 lanes per transform); 0: the LDS Stockham
+                            synthesis */
 } wt_tune_report;
 
 /* Autotuning of the synthesis launch for this plan's grid on this device:
@@ -217,9 +231,11 @@ typedef struct {
  * WT_H_F16_SCALED; a smooth size in double or without exactly two columns;
  * N_z = 512 in double; more than 4 columns): its time
  * block (powers of two up to 32 whose staging fits in LDS) and workgroup
- * size (256, 512), two launches each after a warm-up, keeps the fastest
- * in the plan and rewrites H in that configuration.  The register-FFT
- * synthesis has a fixed schedule (n_candidates = 1).  This call changes the
+ * size (256, 512), or of the register-FFT synthesis of a non-power-of-two
+ * smooth N_z: its factor pairs N_z = N1 x N2 and staging blocks (8 or 16
+ * samples) compiled into the library; two launches each after a warm-up,
+ * keeps the fastest in the plan and rewrites H in that configuration.  A
+ * power-of-two N_z has one schedule (n_candidates = 1).  This call changes the
  * plan: the layout's h_time_block may differ afterwards (re-read it with
  * wt_h_plan_layout; h_bytes and the workspace size do not change), so no
  * other call may use the plan concurrently.  Synchronises the stream.

@@ -86,6 +86,7 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     if (opt->precision != WT_F64 && opt->precision != WT_F32) return WT_E_INVALID_ARG;
     if (opt->ir_max_iter < 0 || opt->ir_max_iter > 16) return WT_E_INVALID_ARG;
     if (!(std::isfinite(opt->ir_tol) && opt->ir_tol >= 0.0)) return WT_E_INVALID_ARG;
+    if (opt->fft_schedule < 0) return WT_E_INVALID_ARG;
 
     p.eps = cell->eps_r * wt::kEps0;
     p.n_cols = n_cols;
@@ -169,21 +170,34 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     const size_t re = p.precision == WT_F64 ? sizeof(double) : sizeof(float);
     const size_t cx = 2 * re;
     // Time block of the H layout (the synthesis stages a whole block in LDS):
-    // the pipelined register-FFT synthesis where it has a form (N_z in
-    // {64, 128, 256, 512} with at most 4 columns; the other 2,3,5-smooth
-    // sizes of synthesis_n1 with two columns in float) and its two staging
-    // buffers fit (blocks of 16 samples, or of 8 where two such buffers
-    // would not fit: N_z = 512, and 256 in double);
+    // the pipelined register-FFT synthesis where it has a schedule (N_z in
+    // {64, 128, 256, 512} with at most 4 columns, blocks of 16 samples or of
+    // 8 where two such buffers would not fit: N_z = 512, and 256 in double;
+    // the other 2,3,5-smooth sizes of kSmoothSchedules with two columns in
+    // float, their default schedule) and its two staging buffers fit;
     // otherwise the LDS Stockham synthesis, whose block is halved until its
     // tables fit.
     const size_t lds_budget = 160 * 1024;
-    const bool pipe_size = wt::synthesis_pow2(N[2])
-                               ? n_cols <= 4
-                               : (wt::synthesis_n1(N[2]) > 0 && n_cols == 2 && p.precision == WT_F32);
+    wt::PipeShape shape{};
+    if (wt::synthesis_pow2(N[2])) {
+        if (n_cols <= 4) shape = wt::pipe_shape_pow2(N[2], (int)re);
+    } else if (n_cols == 2 && p.precision == WT_F32) {
+        const int d = wt::smooth_default(N[2]);
+        if (d >= 0) {
+            const int k = d + opt->fft_schedule;
+            if (k >= wt::kNumSmoothSchedules || wt::kSmoothSchedules[k].nz != N[2]) return WT_E_INVALID_ARG;
+            shape = wt::pipe_shape_for(N[2], wt::kSmoothSchedules[k].n1, wt::kSmoothSchedules[k].tbc);
+        }
+    }
+    if (opt->fft_schedule > 0 && (shape.n1 == 0 || wt::synthesis_pow2(N[2]))) return WT_E_INVALID_ARG;
     int tb;
-    if (pipe_size && wt::synthesis_pipe_lds(N[2], re) <= lds_budget) {
+    p.synth_n1 = 0;
+    p.synth_tbc = 0;
+    if (wt::pipe_fits(shape, (int)re) && wt::pipe_lds(shape, re) <= lds_budget) {
         p.synth_kernel = 2;
-        tb = std::min(sp->n_time, wt::synthesis_block(N[2], (int)re));
+        p.synth_n1 = shape.n1;
+        p.synth_tbc = shape.tbc;
+        tb = std::min(sp->n_time, shape.tbc);
     } else {
         // the LDS Stockham synthesis: the largest block (<= 32 samples) whose
         // (3 block + 1) / 2 sample-pair transforms all fit beside the staged
@@ -522,6 +536,13 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, co
     return WT_OK;
 }
 
+int wt_fft_schedule_count(int n_z) {
+    if (wt::synthesis_pow2(n_z)) return 1;
+    int n = 0;
+    for (const wt::PipeSchedule& c : wt::kSmoothSchedules) n += c.nz == n_z ? 1 : 0;
+    return n;
+}
+
 wt_status wt_batch_run(wt_context* ctx, int n_items, const wt_batch_item* items, int n_lanes,
                        void* const* d_workspace, size_t workspace_bytes, void* const* d_h, size_t h_bytes,
                        int* item_status) {
@@ -604,9 +625,10 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
     hipStream_t s = ctx->stream;
     // candidates: the LDS Stockham synthesis's time block (every power of two
     // <= 32 and <= n_time whose staging and one transform pair fit in LDS)
-    // and workgroup size; the register-FFT synthesis has a fixed schedule
+    // and workgroup size; the register-FFT synthesis of a smooth size: its
+    // schedules (factor N1 and block); a power of two has one schedule
     struct Cand {
-        int tb, threads;
+        int tb, threads, n1, tbc;
     };
     std::vector<Cand> cands;
     if (p.synth_kernel == 0) {
@@ -616,19 +638,30 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
             if (t > p.n_time && t > 1) continue;
             const size_t need = (size_t)p.n_cols * p.nzh * 3 * cx + (size_t)p.N[2] * t * 3 * re + (size_t)2 * p.N[2] * cx;
             if (need > 160 * 1024) continue;
-            for (int thr : {256, 512}) cands.push_back({t, thr});
+            for (int thr : {256, 512}) cands.push_back({t, thr, 0, 0});
         }
+    } else if (!wt::synthesis_pow2(p.N[2])) {
+        for (const wt::PipeSchedule& c : wt::kSmoothSchedules)
+            if (c.nz == p.N[2]) cands.push_back({std::min(p.n_time, c.tbc), p.synth_threads, c.n1, c.tbc});
     }
-    const Cand start{p.tb, p.synth_threads};
+    const Cand start{p.tb, p.synth_threads, p.synth_n1, p.synth_tbc};
     double best_ms = -1.0, start_ms = -1.0;
     Cand best = start;
+    auto same = [](const Cand& a, const Cand& b) {
+        return a.tb == b.tb && a.threads == b.threads && a.n1 == b.n1 && a.tbc == b.tbc;
+    };
+    auto apply = [&p](const Cand& c) {
+        p.tb = c.tb;
+        p.synth_threads = c.threads;
+        p.synth_n1 = c.n1;
+        p.synth_tbc = c.tbc;
+    };
     if (cands.size() > 1) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         WT_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
         hipError_t err = hipEventCreate(&e1);
         for (size_t c = 0; err == hipSuccess && c < cands.size(); ++c) {
-            p.tb = cands[c].tb;
-            p.synth_threads = cands[c].threads;
+            apply(cands[c]);
             err = wt::launch_synthesis(p, d_workspace, d_h, s);                 // warm-up
             if (err == hipSuccess) err = hipEventRecord(e0, s);
             for (int r = 0; r < 2 && err == hipSuccess; ++r) err = wt::launch_synthesis(p, d_workspace, d_h, s);
@@ -638,7 +671,7 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
             if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
             if (err != hipSuccess) break;
             const double t = ms / 2.0;
-            if (cands[c].tb == start.tb && cands[c].threads == start.threads) start_ms = t;
+            if (same(cands[c], start)) start_ms = t;
             if (best_ms < 0.0 || t < best_ms) {
                 best_ms = t;
                 best = cands[c];
@@ -646,11 +679,9 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
         }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        p.tb = best.tb;
-        p.synth_threads = best.threads;
+        apply(best);
         if (err != hipSuccess) {
-            p.tb = start.tb;
-            p.synth_threads = start.threads;
+            apply(start);
             return hip_fail(ctx, err, "tune");
         }
         // H in the chosen layout
@@ -660,9 +691,11 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
     if (report) {
         report->n_candidates = cands.size() > 1 ? (int)cands.size() : 1;
         report->h_time_block = p.tb;
-        report->threads = p.synth_kernel == 0 ? p.synth_threads : wt::synthesis_threads(p.N[2], p.precision == WT_F64 ? 8 : 4);
+        report->threads = p.synth_kernel == 0 ? p.synth_threads
+                                              : wt::pipe_shape_for(p.N[2], p.synth_n1, p.synth_tbc).threads;
         report->ms_chosen = best_ms;
         report->ms_default = start_ms;
+        report->fft_n1 = p.synth_kernel == 2 ? p.synth_n1 : 0;
     }
     return WT_OK;
 }

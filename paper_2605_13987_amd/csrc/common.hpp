@@ -70,8 +70,10 @@ struct Plan {
     double s_bulk[3];
     int nkz_tab;           // k_z >= 0 entries per Green's table row (max over columns)
     int tb;                // time block of the H layout
-    int synth_kernel;      // 2: pipelined register FFTs (N_z = 64, 128, 256, 512), 0: LDS Stockham
+    int synth_kernel;      // 2: pipelined register FFTs, 0: LDS Stockham
     int synth_threads;     // workgroup size of the LDS Stockham synthesis (256, 512 or 1024)
+    int synth_n1;          // register FFTs: N_z = synth_n1 x (N_z / synth_n1)
+    int synth_tbc;         // register FFTs: samples per staged block (16 or 8)
     int nzh;               // Nz / 2
     int nrad[3];
     int rad[3][kMaxRadices];
@@ -140,45 +142,32 @@ hipError_t launch_adjoint_params(const Plan& p, const GradLayout& g, const void*
 
 // Register-FFT synthesis: N_z = N1 x N2 with both factors at most 32 and
 // 2,3,5-smooth.  Pass 1 transforms over N2 (one lane per k1 < N1), pass 2
-// over N1.  Powers of two: 64 = 8 x 8, 128 = 8 x 16, 256 = 16 x 16, 512 =
-// 16 x 32; the other even 2,3,5-smooth sizes up to 320 take N1 >= 8 (so that
-// the transform team has several wavefronts) and the factor pair with the
-// fewest issued lane-operations.  0: no register-FFT form.
-__host__ __device__ constexpr int synthesis_n1(int nz) {
-    switch (nz) {
-        case 64: return 8;
-        case 128: return 8;
-        case 256: return 16;
-        case 512: return 16;
-        case 72: return 9;
-        case 80: return 10;
-        case 90: return 10;
-        case 96: return 8;
-        case 100: return 10;
-        case 108: return 12;
-        case 120: return 8;
-        case 144: return 12;
-        case 150: return 10;
-        case 160: return 8;
-        case 162: return 9;
-        case 180: return 10;
-        case 192: return 8;
-        case 200: return 10;
-        case 216: return 8;
-        case 240: return 8;
-        case 250: return 10;
-        case 270: return 10;
-        case 288: return 12;
-        case 300: return 10;
-        case 320: return 10;
-        default: return 0;
-    }
-}
+// over N1.  Powers of two have one schedule each: 64 = 8 x 8, 128 = 8 x 16,
+// 256 = 16 x 16, 512 = 16 x 32, blocks of 16 samples (8 where two 16-sample
+// buffers do not fit in LDS).
 __host__ __device__ constexpr bool synthesis_pow2(int nz) { return nz == 64 || nz == 128 || nz == 256 || nz == 512; }
+__host__ __device__ constexpr int synthesis_pow2_n1(int nz) { return nz <= 128 ? 8 : 16; }
 
-// Launch shape of the register-FFT synthesis for N_z and elem bytes per real.
-// H is produced in blocks of tbc samples (16, or 8 where two 16-sample
-// staging buffers would not fit in LDS), each staged in LDS as rows of
+// The other even 2,3,5-smooth N_z from 72 to 320 (float, two columns): the
+// schedules wt_h_plan_tune chooses from, (N_z, N1, block), the default of
+// each size first.
+struct PipeSchedule {
+    int nz, n1, tbc;
+};
+constexpr PipeSchedule kSmoothSchedules[] = {
+#include "smooth_schedules.inc"
+};
+constexpr int kNumSmoothSchedules = (int)(sizeof(kSmoothSchedules) / sizeof(kSmoothSchedules[0]));
+// Index of the default schedule of N_z, -1 if it has none.
+__host__ __device__ constexpr int smooth_default(int nz) {
+    for (int i = 0; i < kNumSmoothSchedules; ++i)
+        if (kSmoothSchedules[i].nz == nz) return i;
+    return -1;
+}
+
+// Launch shape of the register-FFT synthesis for N_z = n1 x (N_z / n1),
+// blocks of tbc samples and elem bytes per real.
+// H is produced in blocks of tbc samples, each staged in LDS as rows of
 // 3 x tbc values: sample pair q, component c, real/imaginary part at column
 // 6 q + c (+3), plus a gap from pair tbc/4 on; row z at rs z + pad floor(z / N2).
 // For the powers of two the gap and the padding keep the transforms' LDS
@@ -191,10 +180,10 @@ __host__ __device__ constexpr bool synthesis_pow2(int nz) { return nz == 64 || n
 struct PipeShape {
     int n1, n2, tbc, gap, pad, rs, gpw, ntt, ppt, ntm_act, ntm, threads, buffer;
 };
-__host__ __device__ constexpr PipeShape pipe_shape_block(int nz, int tbc) {
+__host__ __device__ constexpr PipeShape pipe_shape_for(int nz, int n1, int tbc) {
     PipeShape s{};
-    s.n1 = synthesis_n1(nz);
-    if (s.n1 == 0) return s;
+    if (n1 <= 0 || nz % n1 != 0) return s;
+    s.n1 = n1;
     s.n2 = nz / s.n1;
     s.tbc = tbc;
     const bool p2 = synthesis_pow2(nz);
@@ -218,16 +207,18 @@ __host__ __device__ constexpr PipeShape pipe_shape_block(int nz, int tbc) {
     return s;
 }
 constexpr size_t kPipeLdsBudget = 160 * 1024;
-__host__ __device__ constexpr PipeShape pipe_shape(int nz, int elem) {
-    const PipeShape s16 = pipe_shape_block(nz, 16);
-    return 2 * (size_t)s16.buffer * elem <= kPipeLdsBudget ? s16 : pipe_shape_block(nz, 8);
+__host__ __device__ constexpr bool pipe_fits(const PipeShape& s, int elem) {
+    return s.n1 > 0 && s.threads <= 1024 && 2 * (size_t)s.buffer * elem <= kPipeLdsBudget;
 }
-__host__ __device__ constexpr int synthesis_block(int nz, int elem) { return pipe_shape(nz, elem).tbc; }
-__host__ __device__ constexpr int synthesis_threads(int nz, int elem) { return pipe_shape(nz, elem).threads; }
+// The power-of-two schedule of N_z for elem bytes per real.
+__host__ __device__ constexpr PipeShape pipe_shape_pow2(int nz, int elem) {
+    const PipeShape s16 = pipe_shape_for(nz, synthesis_pow2_n1(nz), 16);
+    return pipe_fits(s16, elem) ? s16 : pipe_shape_for(nz, synthesis_pow2_n1(nz), 8);
+}
 // LDS bytes of the workgroup (two staging buffers).
-inline size_t synthesis_pipe_lds(int nz, size_t re) { return 2 * (size_t)pipe_shape(nz, (int)re).buffer * re; }
-// Register-FFT synthesis of the other 2,3,5-smooth sizes: float path, two
-// columns (the standard cell), k_synth_smooth.hip.
+inline size_t pipe_lds(const PipeShape& s, size_t re) { return 2 * (size_t)s.buffer * re; }
+// Register-FFT synthesis of the smooth sizes (kSmoothSchedules, the plan's
+// synth_n1 and synth_tbc): float path, two columns; k_synth_smooth.hip.
 hipError_t launch_synthesis_smooth(const Plan& p, char* b, void* h, hipStream_t s);
 
 // Mixed-radix factorisation (radix 4 first, then 2, 3, 5) used by the FFTs.

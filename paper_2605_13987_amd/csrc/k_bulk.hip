@@ -290,26 +290,27 @@ hipError_t field_table(const Plan& p, char* b, cplx<T>* e, int deriv, hipStream_
 
 template <typename T, int N1, int N2, typename TO>
 hipError_t synthesis_pipe_w(const Plan& p, char* b, void* h, hipStream_t s) {
+    constexpr int TB = pipe_shape_pow2(N1 * N2, (int)sizeof(T)).tbc;
     switch (p.n_cols) {
-        case 1: return synthesis_pipe<T, N1, N2, 1, TO>(p, b, h, s);
-        case 2: return synthesis_pipe<T, N1, N2, 2, TO>(p, b, h, s);
-        case 3: return synthesis_pipe<T, N1, N2, 3, TO>(p, b, h, s);
-        default: return synthesis_pipe<T, N1, N2, 4, TO>(p, b, h, s);
+        case 1: return synthesis_pipe<T, N1, N2, 1, TO, TB>(p, b, h, s);
+        case 2: return synthesis_pipe<T, N1, N2, 2, TO, TB>(p, b, h, s);
+        case 3: return synthesis_pipe<T, N1, N2, 3, TO, TB>(p, b, h, s);
+        default: return synthesis_pipe<T, N1, N2, 4, TO, TB>(p, b, h, s);
     }
 }
 
 template <typename T, typename TO>
 hipError_t synthesis_pipe_n(const Plan& p, char* b, void* h, hipStream_t s) {
+    if (!synthesis_pow2(p.N[2])) return launch_synthesis_smooth(p, b, h, s);
     switch (p.N[2]) {
         case 64: return synthesis_pipe_w<T, 8, 8, TO>(p, b, h, s);
         case 128: return synthesis_pipe_w<T, 8, 16, TO>(p, b, h, s);
         case 256: return synthesis_pipe_w<T, 16, 16, TO>(p, b, h, s);
-        case 512:
-            // two 8-sample staging buffers of doubles exceed LDS, so plans in
-            // double take the Stockham synthesis there
+        default:
+            // N_z = 512: two 8-sample staging buffers of doubles exceed LDS, so
+            // plans in double take the Stockham synthesis there
             if constexpr (sizeof(T) == 4) return synthesis_pipe_w<T, 16, 32, TO>(p, b, h, s);
             return hipErrorInvalidValue;
-        default: return launch_synthesis_smooth(p, b, h, s);
     }
 }
 

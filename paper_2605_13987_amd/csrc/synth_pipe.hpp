@@ -31,10 +31,9 @@ typedef double vec2d __attribute__((ext_vector_type(2)));
 
 constexpr int const_gcd(int a, int b) { return b == 0 ? a : const_gcd(b, a % b); }
 
-// Synthesis of H(X, Y, z, t) for N_z = N1 x N2 (the sizes synthesis_n1
-// lists), with the length-N_z transforms done in registers.  One workgroup
-// per (X, Y) column; H is produced in blocks of 16 samples (8 where two
-// 16-sample buffers do not fit in LDS), each staged whole in LDS as
+// Synthesis of H(X, Y, z, t) for N_z = N1 x N2, with the length-N_z
+// transforms done in registers.  One workgroup per (X, Y) column; H is
+// produced in blocks of TB samples (16, or 8), each staged whole in LDS as
 // [z][sample][component] (the row layout is described at PipeShape):
 //
 // 1. Spectra.  A memory-team thread owns k_z index kk and keeps the field
@@ -62,13 +61,13 @@ constexpr int const_gcd(int a, int b) { return b == 0 ? a : const_gcd(b, a % b);
 // block s-1 out of the other buffer (phase 1), then builds block s+1's
 // spectra into it (phase 2).  A workgroup barrier ends each phase; within a
 // phase the teams touch different buffers.
-template <typename T, int N1, int N2, int WC, typename TO>
-__global__ void __launch_bounds__(pipe_shape(N1 * N2, (int)sizeof(T)).threads)
+template <typename T, int N1, int N2, int WC, typename TO, int TB>
+__global__ void __launch_bounds__(pipe_shape_for(N1 * N2, N1, TB).threads)
 k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, const float* h_scale,
                  TO* H) {
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
-    constexpr PipeShape SH = pipe_shape(NZ, (int)sizeof(T));
+    constexpr PipeShape SH = pipe_shape_for(NZ, N1, TB);
     constexpr int C = (N2 + N1 - 1) / N1;                      // pass-2 columns per lane
     constexpr int CP = N2 % N1 == 0 ? N2 / N1 : 1;             // rows k1 + N1 k2: (k2 / CP) N2-runs
     constexpr int TBC = SH.tbc;                                // samples per block
@@ -93,7 +92,8 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
     constexpr int CJ = (NZ + CROWS - 1) / CROWS;
     // Z(N_z/2) = Z[K1H + N1 K2H]
     constexpr int K1H = NZH % N1, K2H = NZH / N1;
-    static_assert(SH.n1 == N1 && SH.n2 == N2 && NTT % 64 == 0 && NTM % 64 == 0 && GPW * N1 <= 64,
+    static_assert(SH.n1 == N1 && SH.n2 == N2 && NTT % 64 == 0 && NTM % 64 == 0 && GPW * N1 <= 64 &&
+                      pipe_fits(SH, (int)sizeof(T)),
                   "synthesis split");
     static_assert(NTA % NZH == 0 && NTA <= NTM && NTT >= (NG + GPW - 1) / GPW * 64, "synthesis teams");
     static_assert(PAD == 0 || (N2 % N1 == 0 && NZ % CROWS == 0 && (N2 % CROWS == 0 || CROWS % N2 == 0)),
@@ -367,15 +367,14 @@ k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>
     }
 }
 
-template <typename T, int N1, int N2, int WC, typename TO>
+template <typename T, int N1, int N2, int WC, typename TO, int TB>
 hipError_t synthesis_pipe(const Plan& p, char* b, void* h, hipStream_t s) {
-    constexpr int NZ = N1 * N2;
-    const size_t lds = synthesis_pipe_lds(NZ, sizeof(T));
-    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_pipe<T, N1, N2, WC, TO>,
+    constexpr PipeShape SH = pipe_shape_for(N1 * N2, N1, TB);
+    const size_t lds = pipe_lds(SH, sizeof(T));
+    hipError_t err = hipFuncSetAttribute((const void*)k_synthesis_pipe<T, N1, N2, WC, TO, TB>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_synthesis_pipe<T, N1, N2, WC, TO>), dim3(p.N[0] * p.N[1]),
-                       dim3(synthesis_threads(NZ, (int)sizeof(T))), lds, s, p,
+    hipLaunchKernelGGL((k_synthesis_pipe<T, N1, N2, WC, TO, TB>), dim3(p.N[0] * p.N[1]), dim3(SH.threads), lds, s, p,
                        reinterpret_cast<const cplx<T>*>(b + p.off_ehat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_qhat),
                        reinterpret_cast<const cplx<T>*>(b + p.off_tw[2]),

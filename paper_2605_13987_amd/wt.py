@@ -60,7 +60,8 @@ class wt_spectrum(ctypes.Structure):
 
 
 class wt_h_options(ctypes.Structure):
-    _fields_ = [("precision", c_int), ("ir_max_iter", c_int), ("ir_tol", c_double), ("h_format", c_int)]
+    _fields_ = [("precision", c_int), ("ir_max_iter", c_int), ("ir_tol", c_double), ("h_format", c_int),
+                ("fft_schedule", c_int)]
 
 
 class wt_h_report(ctypes.Structure):
@@ -77,7 +78,7 @@ class wt_h_layout(ctypes.Structure):
 
 class wt_tune_report(ctypes.Structure):
     _fields_ = [("n_candidates", c_int), ("h_time_block", c_int), ("threads", c_int),
-                ("ms_chosen", c_double), ("ms_default", c_double)]
+                ("ms_chosen", c_double), ("ms_default", c_double), ("fft_n1", c_int)]
 
 
 class wt_carriers(ctypes.Structure):
@@ -122,6 +123,7 @@ def _load():
         "wt_electronics": (c_int, [c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                    c_double, c_double, c_void_p, c_void_p]),
         "wt_h_plan_tune": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_tune_report)]),
+        "wt_fft_schedule_count": (c_int, [c_int]),
         "wt_batch_run": (c_int, [c_void_p, c_int, P(wt_batch_item), c_int, P(c_void_p), c_size_t, P(c_void_p),
                                  c_size_t, P(c_int)]),
         "wt_h_gradient_workspace": (c_int, [c_void_p, c_int, P(c_size_t)]),
@@ -211,12 +213,13 @@ def layout_dict(layout: wt_h_layout) -> dict:
 
 
 def wt_h_plan_create(cell: dict, columns, spectrum: dict, precision: int = WT_F32,
-                     ir_max_iter: int = 2, ir_tol: float = 1e-12, h_format: int = WT_H_PLAIN):
+                     ir_max_iter: int = 2, ir_tol: float = 1e-12, h_format: int = WT_H_PLAIN,
+                     fft_schedule: int = 0):
     """Returns (plan handle, layout dict)."""
     plan = c_void_p()
     lay = wt_h_layout()
     sp = wt_spectrum(spectrum["n_freq"], spectrum["df"], spectrum["n_time"], spectrum["dt"])
-    opt = wt_h_options(int(precision), int(ir_max_iter), float(ir_tol), int(h_format))
+    opt = wt_h_options(int(precision), int(ir_max_iter), float(ir_tol), int(h_format), int(fft_schedule))
     cols = make_columns(columns)
     _check(LIB.wt_h_plan_create(ctypes.byref(make_cell(cell)), cols, len(columns), ctypes.byref(sp),
                                 ctypes.byref(opt), ctypes.byref(plan), ctypes.byref(lay)), "wt_h_plan_create")
@@ -224,12 +227,13 @@ def wt_h_plan_create(cell: dict, columns, spectrum: dict, precision: int = WT_F3
 
 
 def wt_h_plan_create_status(cell: dict, columns, spectrum: dict, precision: int = WT_F32,
-                            ir_max_iter: int = 2, ir_tol: float = 1e-12, h_format: int = WT_H_PLAIN) -> int:
+                            ir_max_iter: int = 2, ir_tol: float = 1e-12, h_format: int = WT_H_PLAIN,
+                            fft_schedule: int = 0) -> int:
     """Status code of plan creation (the plan, if any, is destroyed)."""
     plan = c_void_p()
     lay = wt_h_layout()
     sp = wt_spectrum(spectrum["n_freq"], spectrum["df"], spectrum["n_time"], spectrum["dt"])
-    opt = wt_h_options(int(precision), int(ir_max_iter), float(ir_tol), int(h_format))
+    opt = wt_h_options(int(precision), int(ir_max_iter), float(ir_tol), int(h_format), int(fft_schedule))
     cols = make_columns(columns)
     st = LIB.wt_h_plan_create(ctypes.byref(make_cell(cell)), cols, len(columns), ctypes.byref(sp),
                               ctypes.byref(opt), ctypes.byref(plan), ctypes.byref(lay))
@@ -278,6 +282,11 @@ def wt_current(ctx, plan, d_h: int, n_carriers: int, n_tracks: int, d_pos: int, 
     car = wt_carriers(int(n_carriers), int(n_tracks), c_void_p(d_pos), c_void_p(d_charge), c_void_p(d_track))
     _check(LIB.wt_current(ctx, plan, c_void_p(d_h), ctypes.byref(car), c_void_p(d_workspace or None),
                           int(workspace_bytes), c_void_p(d_i_out)), "wt_current", ctx)
+
+
+def wt_fft_schedule_count(n_z: int) -> int:
+    """Register-FFT synthesis schedules compiled for N_z (float, two columns)."""
+    return int(LIB.wt_fft_schedule_count(int(n_z)))
 
 
 def wt_batch_run(ctx, items, d_workspaces, workspace_bytes: int, d_hs, h_bytes: int, raise_on_error: bool = True):

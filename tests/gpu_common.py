@@ -26,11 +26,12 @@ def context():
     return wt.wt_context_create(0, torch.cuda.current_stream().cuda_stream)
 
 
-def solve_h(ctx, cfg, precision, ir_max_iter=2, ir_tol=1e-12, h_format=wt.WT_H_PLAIN):
+def solve_h(ctx, cfg, precision, ir_max_iter=2, ir_tol=1e-12, h_format=wt.WT_H_PLAIN, fft_schedule=0):
     say(f"  wt_h_solve {cfg['name']} grid={cfg['cell']['N']} nf={cfg['spectrum']['n_freq']} "
         f"nt={cfg['spectrum']['n_time']} precision={precision} h_format={h_format}")
     plan, lay = wt.wt_h_plan_create(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=precision,
-                                    ir_max_iter=ir_max_iter, ir_tol=ir_tol, h_format=h_format)
+                                    ir_max_iter=ir_max_iter, ir_tol=ir_tol, h_format=h_format,
+                                    fft_schedule=fft_schedule)
     ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
     hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
     st, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True,

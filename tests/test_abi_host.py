@@ -197,3 +197,25 @@ def test_gradient_workspace_and_validation():
 def test_batch_run_rejects_a_null_context():
     st, per = wt.wt_batch_run(None, [], [0], 0, [0], 0, raise_on_error=False)
     assert st == wt.WT_E_INVALID_ARG and per == []
+
+
+def test_fft_schedules_of_the_smooth_sizes():
+    assert [wt.wt_fft_schedule_count(n) for n in (64, 128, 256, 512)] == [1, 1, 1, 1]
+    assert wt.wt_fft_schedule_count(40) == 0 and wt.wt_fft_schedule_count(330) == 0
+    assert all(wt.wt_fft_schedule_count(n) == 3 for n in (72, 150, 320))
+    cfg = workloads.small_pixel(k=5, n_xy=8, n_z=72, n_freq=4, n_time=19, n_pairs=2, n_colloc=8)
+    cell, cols, spec = cfg["cell"], cfg["columns"], cfg["spectrum"]
+    # the default schedule of 72 is 9 x 8 with blocks of 8 samples; the third, blocks of 16
+    blocks = []
+    for k in range(3):
+        plan, lay = wt.wt_h_plan_create(cell, cols, spec, precision=wt.WT_F32, fft_schedule=k)
+        blocks.append(lay["h_time_block"])
+        wt.wt_h_plan_destroy(plan)
+    assert blocks == [8, 16, 16]
+    assert wt.wt_h_plan_create_status(cell, cols, spec, precision=wt.WT_F32, fft_schedule=3) == wt.WT_E_INVALID_ARG
+    assert wt.wt_h_plan_create_status(cell, cols, spec, precision=wt.WT_F32, fft_schedule=-1) == wt.WT_E_INVALID_ARG
+    # no register-FFT schedule to choose: double plans of a smooth size, powers of two
+    assert wt.wt_h_plan_create_status(cell, cols, spec, precision=wt.WT_F64, fft_schedule=1) == wt.WT_E_INVALID_ARG
+    c64 = workloads.small_pixel(k=5, n_xy=8, n_z=64, n_freq=4, n_time=19, n_pairs=2, n_colloc=8)
+    assert wt.wt_h_plan_create_status(c64["cell"], c64["columns"], c64["spectrum"], precision=wt.WT_F32,
+                                      fft_schedule=1) == wt.WT_E_INVALID_ARG
