@@ -43,6 +43,12 @@ __device__ inline void flush(T* out, int track, int nt, int lane, T* acc) {
     }
 }
 
+// Two dwords with the alignment of one (an 8-byte load from a 4-byte
+// aligned address).
+struct alignas(4) Dword2 {
+    unsigned lo, hi;
+};
+
 // Field of one moving step projected on its displacement, at lag tau, for
 // the 8 trilinear corners (weights already carry -q / V_w).  The corner
 // columns are held as pointers; offsets inside a column (at most N_z n_time 3
@@ -69,13 +75,16 @@ __device__ inline T step_value(const Step<T, TH>& s, int tau, int TB, int Nz, in
         if constexpr (std::is_same<TH, _Float16>::value) {
             // the three float16 components with one 8-byte load from the 4-byte
             // aligned word below them (the buffer has at least 2 bytes after
-            // its last value)
-            const uintptr_t a = reinterpret_cast<uintptr_t>(h);
-            const unsigned long long w = *reinterpret_cast<const unsigned long long*>(a & ~(uintptr_t)3);
-            const unsigned long long v = w >> ((a & 2) * 8);
-            const T hx = (T)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu));
-            const T hy = (T)__builtin_bit_cast(_Float16, (unsigned short)((v >> 16) & 0xffffu));
-            const T hz = (T)__builtin_bit_cast(_Float16, (unsigned short)((v >> 32) & 0xffffu));
+            // its last value); the word is reached by pointer arithmetic on h,
+            // so the load stays a global one (a pointer rebuilt from an integer
+            // would be flat, and flat loads are waited for with the LDS ones)
+            const unsigned odd = (unsigned)(reinterpret_cast<uintptr_t>(h) >> 1) & 1u;
+            const Dword2 wv = *reinterpret_cast<const Dword2*>(h - odd);
+            const unsigned short e0 = (unsigned short)(wv.lo & 0xffffu), e1 = (unsigned short)(wv.lo >> 16);
+            const unsigned short e2 = (unsigned short)(wv.hi & 0xffffu), e3 = (unsigned short)(wv.hi >> 16);
+            const T hx = (T)__builtin_bit_cast(_Float16, odd ? e1 : e0);
+            const T hy = (T)__builtin_bit_cast(_Float16, odd ? e2 : e1);
+            const T hz = (T)__builtin_bit_cast(_Float16, odd ? e3 : e2);
             return hx * s.dx + hy * s.dy + hz * s.dz;
         } else {
             return (T)h[0] * s.dx + (T)h[1] * s.dy + (T)h[2] * s.dz;
