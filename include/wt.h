@@ -222,7 +222,19 @@ typedef struct {
     int fft_n1;          /* register-FFT synthesis: N_z = fft_n1 x (N_z / fft_n1)
                             (pass-1 lanes per transform); 0: the LDS Stockham
                             synthesis */
+    int from_cache;      /* 1: the choice came from the context's tuning cache
+                            (nothing timed; ms_chosen is the cached time) */
 } wt_tune_report;
+
+/* Tuning cache of the context (a text file): wt_h_plan_tune first looks up
+ * the plan's device (architecture, compute units) and grid (N_x, N_y, N_z,
+ * n_time, precision, h_format, n_cols) there and applies a cached choice
+ * that is still among its candidates without timing; otherwise it times the
+ * candidates as usual and rewrites the file with the new entry.  The file is
+ * read here (a missing file is an empty cache; a malformed one gives
+ * WT_E_INVALID_ARG and leaves the cache off); path NULL or "" turns the
+ * cache off.  One context per file: concurrent writers are not coordinated. */
+wt_status wt_context_set_tune_cache(wt_context* ctx, const char* path);
 
 /* Autotuning of the synthesis launch for this plan's grid on this device:
  * runs wt_h_solve once, then times every candidate configuration of the LDS

@@ -4,8 +4,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -24,6 +28,14 @@ struct wt_context {
     hipStream_t lane[WT_MAX_LANES];
     hipEvent_t lane_done[WT_MAX_LANES];
     hipEvent_t fork;
+    // wt_h_plan_tune's cache: key (device and grid) -> chosen synthesis launch
+    struct TuneEntry {
+        int tb, threads, n1, tbc;
+        double ms;
+    };
+    std::string tune_path;
+    std::string device_key;
+    std::map<std::string, TuneEntry> tune_cache;
 };
 
 struct wt_h_plan {
@@ -341,6 +353,61 @@ wt_status enqueue_solve(wt_context* ctx, const Plan& p, void* ws, void* d_h, hip
     return mark_stage(kStageSynthesis);
 }
 
+// Key of a tuning result: the device (architecture and compute units) and
+// everything of the plan the synthesis launch depends on.
+wt_status tune_key(wt_context* ctx, const Plan& p, std::string* key) {
+    if (ctx->device_key.empty()) {
+        hipDeviceProp_t prop;
+        WT_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device), "hipGetDeviceProperties");
+        std::string arch = prop.gcnArchName;
+        for (char& ch : arch)
+            if (ch == ' ') ch = '_';
+        ctx->device_key = arch + " " + std::to_string(prop.multiProcessorCount);
+    }
+    std::ostringstream o;
+    o << ctx->device_key << ' ' << p.N[0] << ' ' << p.N[1] << ' ' << p.N[2] << ' ' << p.n_time << ' ' << p.precision
+      << ' ' << p.h_format << ' ' << p.n_cols;
+    *key = o.str();
+    return WT_OK;
+}
+
+// Tuning cache file: '#' comment lines, then one line per key:
+//   <arch> <CUs> <Nx> <Ny> <Nz> <n_time> <precision> <h_format> <n_cols>  <tb> <threads> <n1> <block> <ms>
+bool tune_cache_read(const std::string& path, std::map<std::string, wt_context::TuneEntry>* out) {
+    std::ifstream in(path);
+    if (!in) return true;                                  // no file yet: an empty cache
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        std::string arch;
+        long cus, nx, ny, nz, nt, prec, fmt, nc;
+        wt_context::TuneEntry e;
+        if (!(is >> arch >> cus >> nx >> ny >> nz >> nt >> prec >> fmt >> nc >> e.tb >> e.threads >> e.n1 >> e.tbc >> e.ms))
+            return false;
+        std::ostringstream k;
+        k << arch << ' ' << cus << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << nt << ' ' << prec << ' ' << fmt << ' '
+          << nc;
+        (*out)[k.str()] = e;
+    }
+    return true;
+}
+
+bool tune_cache_write(const std::string& path, const std::map<std::string, wt_context::TuneEntry>& cache) {
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream o(tmp, std::ios::trunc);
+        if (!o) return false;
+        o << "# wt_h_plan_tune cache: arch CUs Nx Ny Nz n_time precision h_format n_cols  tb threads n1 block ms\n";
+        for (const auto& kv : cache) {
+            const auto& e = kv.second;
+            o << kv.first << "  " << e.tb << ' ' << e.threads << ' ' << e.n1 << ' ' << e.tbc << ' ' << e.ms << '\n';
+        }
+        if (!o) return false;
+    }
+    return std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
 bool carriers_ok(const wt_carriers* car) {
     if (car->n_carriers < 0 || car->n_tracks < 1) return false;
     return car->n_carriers == 0 || (car->d_pos && car->d_charge && car->d_track);
@@ -536,6 +603,21 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, co
     return WT_OK;
 }
 
+wt_status wt_context_set_tune_cache(wt_context* ctx, const char* path) {
+    if (!ctx) return WT_E_INVALID_ARG;
+    ctx->tune_cache.clear();
+    ctx->tune_path.clear();
+    if (!path || !*path) return WT_OK;
+    std::map<std::string, wt_context::TuneEntry> entries;
+    if (!tune_cache_read(path, &entries)) {
+        ctx->last_error = std::string("tune cache: malformed line in ") + path;
+        return WT_E_INVALID_ARG;
+    }
+    ctx->tune_path = path;
+    ctx->tune_cache.swap(entries);
+    return WT_OK;
+}
+
 int wt_fft_schedule_count(int n_z) {
     if (wt::synthesis_pow2(n_z)) return 1;
     int n = 0;
@@ -656,7 +738,26 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
         p.synth_n1 = c.n1;
         p.synth_tbc = c.tbc;
     };
-    if (cands.size() > 1) {
+    // a cached result for this device and grid, if it names a candidate
+    std::string key;
+    bool cached = false;
+    if (!ctx->tune_path.empty() && cands.size() > 1) {
+        if ((st = tune_key(ctx, p, &key)) != WT_OK) return st;
+        const auto it = ctx->tune_cache.find(key);
+        if (it != ctx->tune_cache.end()) {
+            const Cand c{it->second.tb, it->second.threads, it->second.n1, it->second.tbc};
+            for (const Cand& k : cands)
+                if (same(k, c)) cached = true;
+            if (cached) {
+                apply(c);
+                best = c;
+                best_ms = it->second.ms;
+                // H in the cached layout
+                WT_HIP(ctx, wt::launch_synthesis(p, d_workspace, d_h, s), "synthesis");
+            }
+        }
+    }
+    if (cands.size() > 1 && !cached) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         WT_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
         hipError_t err = hipEventCreate(&e1);
@@ -686,6 +787,13 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
         }
         // H in the chosen layout
         WT_HIP(ctx, wt::launch_synthesis(p, d_workspace, d_h, s), "synthesis");
+        if (!key.empty()) {
+            ctx->tune_cache[key] = wt_context::TuneEntry{best.tb, best.threads, best.n1, best.tbc, best_ms};
+            if (!tune_cache_write(ctx->tune_path, ctx->tune_cache)) {
+                ctx->last_error = "tune cache: cannot write " + ctx->tune_path;
+                return WT_E_INVALID_ARG;
+            }
+        }
     }
     WT_HIP(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
     if (report) {
@@ -696,6 +804,7 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
         report->ms_chosen = best_ms;
         report->ms_default = start_ms;
         report->fft_n1 = p.synth_kernel == 2 ? p.synth_n1 : 0;
+        report->from_cache = cached ? 1 : 0;
     }
     return WT_OK;
 }

@@ -78,7 +78,7 @@ class wt_h_layout(ctypes.Structure):
 
 class wt_tune_report(ctypes.Structure):
     _fields_ = [("n_candidates", c_int), ("h_time_block", c_int), ("threads", c_int),
-                ("ms_chosen", c_double), ("ms_default", c_double), ("fft_n1", c_int)]
+                ("ms_chosen", c_double), ("ms_default", c_double), ("fft_n1", c_int), ("from_cache", c_int)]
 
 
 class wt_carriers(ctypes.Structure):
@@ -124,6 +124,7 @@ def _load():
                                    c_double, c_double, c_void_p, c_void_p]),
         "wt_h_plan_tune": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_tune_report)]),
         "wt_fft_schedule_count": (c_int, [c_int]),
+        "wt_context_set_tune_cache": (c_int, [c_void_p, c_char_p]),
         "wt_batch_run": (c_int, [c_void_p, c_int, P(wt_batch_item), c_int, P(c_void_p), c_size_t, P(c_void_p),
                                  c_size_t, P(c_int)]),
         "wt_h_gradient_workspace": (c_int, [c_void_p, c_int, P(c_size_t)]),
@@ -282,6 +283,14 @@ def wt_current(ctx, plan, d_h: int, n_carriers: int, n_tracks: int, d_pos: int, 
     car = wt_carriers(int(n_carriers), int(n_tracks), c_void_p(d_pos), c_void_p(d_charge), c_void_p(d_track))
     _check(LIB.wt_current(ctx, plan, c_void_p(d_h), ctypes.byref(car), c_void_p(d_workspace or None),
                           int(workspace_bytes), c_void_p(d_i_out)), "wt_current", ctx)
+
+
+def wt_context_set_tune_cache(ctx, path, raise_on_error: bool = True) -> int:
+    """Use (path) or stop using (None) a tuning cache file for wt_h_plan_tune."""
+    st = LIB.wt_context_set_tune_cache(ctx, None if path is None else os.fsencode(path))
+    if raise_on_error:
+        _check(st, "wt_context_set_tune_cache", ctx)
+    return st
 
 
 def wt_fft_schedule_count(n_z: int) -> int:

@@ -1,5 +1,6 @@
 """The synthesis autotuner (wt_h_plan_tune): it keeps results exact in the
-layout it chooses, and leaves the register-FFT sizes alone."""
+layout it chooses, has nothing to tune for the power-of-two register-FFT
+sizes, and records and reuses its choices through a tuning cache file."""
 import numpy as np
 import pytest
 import torch
@@ -65,3 +66,60 @@ def test_register_fft_sizes_have_nothing_to_tune(ctx):
         assert wt.wt_h_plan_layout(plan)["h_time_block"] == lay["h_time_block"] == 16
     finally:
         wt.wt_h_plan_destroy(plan)
+
+
+def _h_of(lay_after, hbuf, cfg):
+    run = dict(layout=lay_after, h=hbuf.view(torch.float32), decode=1.0)
+    return h_standard(run, cfg)
+
+
+@pytest.mark.parametrize("n_z", [150, 40], ids=["register-fft", "stockham"])
+def test_tuning_cache_file(ctx, tmp_path, n_z):
+    """The context's tuning cache: the first tune of a grid times and records
+    its choice; a later plan of the same grid (and a context that reads the
+    file again) takes it without timing, with H still exact; a malformed file
+    is refused and leaves the cache off."""
+    cfg = workloads.small_pixel(k=84, n_xy=16, n_z=n_z, n_freq=4, n_time=21, n_pairs=4, n_colloc=8)
+    ref = oracle.weighting_field(cfg["cell"], cfg["columns"], cfg["spectrum"])
+    path = tmp_path / "tune.txt"
+    wt.wt_context_set_tune_cache(ctx, str(path))
+    reps = []
+    try:
+        for k in range(2):
+            plan, lay = wt.wt_h_plan_create(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=wt.WT_F32)
+            ws, hbuf = _buffers(lay)
+            rep = wt.wt_h_plan_tune(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), hbuf.numel())
+            torch.cuda.synchronize()
+            say(f"  n_z={n_z} tune {k}: {rep}")
+            reps.append(rep)
+            lay2 = wt.wt_h_plan_layout(plan)
+            assert lay2["h_time_block"] == rep["h_time_block"]
+            assert rel_l2(_h_of(lay2, hbuf, cfg), ref["H"]) <= 1e-5
+            wt.wt_h_plan_destroy(plan)
+        assert reps[0]["from_cache"] == 0 and reps[0]["n_candidates"] > 1
+        assert reps[1]["from_cache"] == 1
+        for f in ("h_time_block", "threads", "fft_n1"):
+            assert reps[1][f] == reps[0][f]
+        lines = [l for l in path.read_text().splitlines() if l and not l.startswith("#")]
+        assert len(lines) == 1 and len(lines[0].split()) == 14
+        # another context reading the same file
+        c2 = context()
+        try:
+            wt.wt_context_set_tune_cache(c2, str(path))
+            plan, lay = wt.wt_h_plan_create(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=wt.WT_F32)
+            ws, hbuf = _buffers(lay)
+            rep = wt.wt_h_plan_tune(c2, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), hbuf.numel())
+            assert rep["from_cache"] == 1 and rep["h_time_block"] == reps[0]["h_time_block"]
+            wt.wt_h_plan_destroy(plan)
+        finally:
+            wt.wt_context_destroy(c2)
+        # a malformed file is refused; the cache is then off
+        path.write_text("not a tuning line\n")
+        assert wt.wt_context_set_tune_cache(ctx, str(path), raise_on_error=False) == wt.WT_E_INVALID_ARG
+        plan, lay = wt.wt_h_plan_create(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=wt.WT_F32)
+        ws, hbuf = _buffers(lay)
+        rep = wt.wt_h_plan_tune(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), hbuf.numel())
+        assert rep["from_cache"] == 0
+        wt.wt_h_plan_destroy(plan)
+    finally:
+        wt.wt_context_set_tune_cache(ctx, None)
