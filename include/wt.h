@@ -115,17 +115,20 @@ typedef struct {
     int ir_max_iter;    /* refinement sweeps after the LU solve, 0..16 */
     double ir_tol;      /* target normwise backward error (>= 0) */
     int h_format;       /* wt_h_format */
-    int fft_schedule;   /* register-FFT synthesis of a non-power-of-two smooth
-                           N_z: which of its compiled schedules to start from,
-                           0 .. wt_fft_schedule_count(N_z) - 1 (0: the
-                           default, the fastest measured); must be 0 for
-                           other grids (WT_E_INVALID_ARG otherwise) */
+    int fft_schedule;   /* register-FFT synthesis: which of the size's
+                           compiled schedules (factor pair and staging block)
+                           to start from, 0 .. wt_fft_schedule_count(N_z) - 1
+                           (0: the default, the fastest measured; in double
+                           only those that fit in LDS count); must be 0 for
+                           grids without a register form (WT_E_INVALID_ARG
+                           otherwise) */
 } wt_h_options;
 
-/* Number of register-FFT synthesis schedules compiled for a float plan with
- * two columns and this N_z: 1 for 64, 128, 256, 512; the count of the
- * smooth size's schedules (a factor pair N_z = N1 x N2 and a staging block)
- * for the non-power-of-two sizes listed at WT_H_F16_SCALED; 0 otherwise. */
+/* Number of register-FFT synthesis schedules (a factor pair N_z = N1 x N2
+ * and a staging block of 8 or 16 samples) compiled for a float plan with
+ * two columns and this N_z: 2 for 64, 128 and 256 (blocks of 8 and 16), 1
+ * for 512; 3 for each non-power-of-two size listed at WT_H_F16_SCALED; 0
+ * otherwise. */
 int wt_fft_schedule_count(int n_z);
 
 /* Filled by wt_h_solve when a report pointer is given (that call then
@@ -243,11 +246,12 @@ wt_status wt_context_set_tune_cache(wt_context* ctx, const char* path);
  * WT_H_F16_SCALED; a smooth size in double or without exactly two columns;
  * N_z = 512 in double; more than 4 columns): its time
  * block (powers of two up to 32 whose staging fits in LDS) and workgroup
- * size (256, 512), or of the register-FFT synthesis of a non-power-of-two
- * smooth N_z: its factor pairs N_z = N1 x N2 and staging blocks (8 or 16
- * samples) compiled into the library; two launches each after a warm-up,
- * keeps the fastest in the plan and rewrites H in that configuration.  A
- * power-of-two N_z has one schedule (n_candidates = 1).  This call changes the
+ * size (256, 512), or of the register-FFT synthesis: the size's schedules
+ * (factor pairs N_z = N1 x N2 and staging blocks of 8 or 16 samples)
+ * compiled into the library; two launches each after a warm-up,
+ * keeps the fastest in the plan and rewrites H in that configuration.  The
+ * register-FFT synthesis of a power of two has two schedules (blocks of 8
+ * and 16 samples), one at N_z = 512 (n_candidates = 1).  This call changes the
  * plan: the layout's h_time_block may differ afterwards (re-read it with
  * wt_h_plan_layout; h_bytes and the workspace size do not change), so no
  * other call may use the plan concurrently.  Synchronises the stream.

@@ -182,26 +182,20 @@ wt_status validate_and_build(const wt_cell* cell, const wt_column* cols, int n_c
     const size_t re = p.precision == WT_F64 ? sizeof(double) : sizeof(float);
     const size_t cx = 2 * re;
     // Time block of the H layout (the synthesis stages a whole block in LDS):
-    // the pipelined register-FFT synthesis where it has a schedule (N_z in
-    // {64, 128, 256, 512} with at most 4 columns, blocks of 16 samples or of
-    // 8 where two such buffers would not fit: N_z = 512, and 256 in double;
-    // the other 2,3,5-smooth sizes of kSmoothSchedules with two columns in
-    // float, their default schedule) and its two staging buffers fit;
+    // the pipelined register-FFT synthesis where it has a schedule that fits
+    // (N_z in {64, 128, 256, 512} with at most 4 columns; the other
+    // 2,3,5-smooth sizes of kSmoothSchedules with two columns in float): the
+    // size's default schedule, or the one wt_h_options.fft_schedule names;
     // otherwise the LDS Stockham synthesis, whose block is halved until its
     // tables fit.
     const size_t lds_budget = 160 * 1024;
     wt::PipeShape shape{};
-    if (wt::synthesis_pow2(N[2])) {
-        if (n_cols <= 4) shape = wt::pipe_shape_pow2(N[2], (int)re);
-    } else if (n_cols == 2 && p.precision == WT_F32) {
-        const int d = wt::smooth_default(N[2]);
-        if (d >= 0) {
-            const int k = d + opt->fft_schedule;
-            if (k >= wt::kNumSmoothSchedules || wt::kSmoothSchedules[k].nz != N[2]) return WT_E_INVALID_ARG;
-            shape = wt::pipe_shape_for(N[2], wt::kSmoothSchedules[k].n1, wt::kSmoothSchedules[k].tbc);
-        }
+    const bool register_form = wt::synthesis_pow2(N[2]) ? n_cols <= 4 : (n_cols == 2 && p.precision == WT_F32);
+    if (register_form && wt::pipe_schedule_count(N[2], (int)re) > 0) {
+        if (opt->fft_schedule >= wt::pipe_schedule_count(N[2], (int)re)) return WT_E_INVALID_ARG;
+        shape = wt::pipe_schedule(N[2], (int)re, opt->fft_schedule);
     }
-    if (opt->fft_schedule > 0 && (shape.n1 == 0 || wt::synthesis_pow2(N[2]))) return WT_E_INVALID_ARG;
+    if (opt->fft_schedule > 0 && shape.n1 == 0) return WT_E_INVALID_ARG;
     int tb;
     p.synth_n1 = 0;
     p.synth_tbc = 0;
@@ -618,12 +612,7 @@ wt_status wt_context_set_tune_cache(wt_context* ctx, const char* path) {
     return WT_OK;
 }
 
-int wt_fft_schedule_count(int n_z) {
-    if (wt::synthesis_pow2(n_z)) return 1;
-    int n = 0;
-    for (const wt::PipeSchedule& c : wt::kSmoothSchedules) n += c.nz == n_z ? 1 : 0;
-    return n;
-}
+int wt_fft_schedule_count(int n_z) { return wt::pipe_schedule_count(n_z, 4); }
 
 wt_status wt_batch_run(wt_context* ctx, int n_items, const wt_batch_item* items, int n_lanes,
                        void* const* d_workspace, size_t workspace_bytes, void* const* d_h, size_t h_bytes,
@@ -707,8 +696,8 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
     hipStream_t s = ctx->stream;
     // candidates: the LDS Stockham synthesis's time block (every power of two
     // <= 32 and <= n_time whose staging and one transform pair fit in LDS)
-    // and workgroup size; the register-FFT synthesis of a smooth size: its
-    // schedules (factor N1 and block); a power of two has one schedule
+    // and workgroup size; the register-FFT synthesis: the size's schedules
+    // (factor N1 and block) that fit
     struct Cand {
         int tb, threads, n1, tbc;
     };
@@ -722,9 +711,12 @@ wt_status wt_h_plan_tune(wt_context* ctx, wt_h_plan* plan, void* d_workspace, si
             if (need > 160 * 1024) continue;
             for (int thr : {256, 512}) cands.push_back({t, thr, 0, 0});
         }
-    } else if (!wt::synthesis_pow2(p.N[2])) {
-        for (const wt::PipeSchedule& c : wt::kSmoothSchedules)
-            if (c.nz == p.N[2]) cands.push_back({std::min(p.n_time, c.tbc), p.synth_threads, c.n1, c.tbc});
+    } else {
+        const int elem = p.precision == WT_F64 ? 8 : 4;
+        for (int k = 0; k < wt::pipe_schedule_count(p.N[2], elem); ++k) {
+            const wt::PipeShape c = wt::pipe_schedule(p.N[2], elem, k);
+            cands.push_back({std::min(p.n_time, c.tbc), p.synth_threads, c.n1, c.tbc});
+        }
     }
     const Cand start{p.tb, p.synth_threads, p.synth_n1, p.synth_tbc};
     double best_ms = -1.0, start_ms = -1.0;

@@ -142,28 +142,29 @@ hipError_t launch_adjoint_params(const Plan& p, const GradLayout& g, const void*
 
 // Register-FFT synthesis: N_z = N1 x N2 with both factors at most 32 and
 // 2,3,5-smooth.  Pass 1 transforms over N2 (one lane per k1 < N1), pass 2
-// over N1.  Powers of two have one schedule each: 64 = 8 x 8, 128 = 8 x 16,
-// 256 = 16 x 16, 512 = 16 x 32, blocks of 16 samples (8 where two 16-sample
-// buffers do not fit in LDS).
+// over N1.  A schedule is (N_z, N1, samples per staged block); the ones
+// wt_h_plan_tune chooses from are listed per size, the default first.
 __host__ __device__ constexpr bool synthesis_pow2(int nz) { return nz == 64 || nz == 128 || nz == 256 || nz == 512; }
 __host__ __device__ constexpr int synthesis_pow2_n1(int nz) { return nz <= 128 ? 8 : 16; }
 
-// The other even 2,3,5-smooth N_z from 72 to 320 (float, two columns): the
-// schedules wt_h_plan_tune chooses from, (N_z, N1, block), the default of
-// each size first.
 struct PipeSchedule {
     int nz, n1, tbc;
 };
+// Powers of two: 64 = 8 x 8, 128 = 8 x 16, 256 = 16 x 16, 512 = 16 x 32,
+// any number of columns up to 4, float or double (a schedule whose buffers
+// do not fit in LDS for double is skipped).  Blocks of 8 samples come first
+// where they were measured faster on one MI355X (128 x 128 x N_z, 200
+// samples, float H: 1.00 against 1.20 ms at N_z = 128, 2.12 against 2.52 ms
+// at 256): two workgroups then share a CU.
+constexpr PipeSchedule kPow2Schedules[] = {
+    {64, 8, 16}, {64, 8, 8}, {128, 8, 8}, {128, 8, 16}, {256, 16, 8}, {256, 16, 16}, {512, 16, 8},
+};
+constexpr int kNumPow2Schedules = (int)(sizeof(kPow2Schedules) / sizeof(kPow2Schedules[0]));
+// The other even 2,3,5-smooth N_z from 72 to 320: float, two columns.
 constexpr PipeSchedule kSmoothSchedules[] = {
 #include "smooth_schedules.inc"
 };
 constexpr int kNumSmoothSchedules = (int)(sizeof(kSmoothSchedules) / sizeof(kSmoothSchedules[0]));
-// Index of the default schedule of N_z, -1 if it has none.
-__host__ __device__ constexpr int smooth_default(int nz) {
-    for (int i = 0; i < kNumSmoothSchedules; ++i)
-        if (kSmoothSchedules[i].nz == nz) return i;
-    return -1;
-}
 
 // Launch shape of the register-FFT synthesis for N_z = n1 x (N_z / n1),
 // blocks of tbc samples and elem bytes per real.
@@ -210,10 +211,25 @@ constexpr size_t kPipeLdsBudget = 160 * 1024;
 __host__ __device__ constexpr bool pipe_fits(const PipeShape& s, int elem) {
     return s.n1 > 0 && s.threads <= 1024 && 2 * (size_t)s.buffer * elem <= kPipeLdsBudget;
 }
-// The power-of-two schedule of N_z for elem bytes per real.
-__host__ __device__ constexpr PipeShape pipe_shape_pow2(int nz, int elem) {
-    const PipeShape s16 = pipe_shape_for(nz, synthesis_pow2_n1(nz), 16);
-    return pipe_fits(s16, elem) ? s16 : pipe_shape_for(nz, synthesis_pow2_n1(nz), 8);
+// The k-th schedule of N_z (0: the default) that fits elem bytes per real,
+// a shape with n1 = 0 if there is none.
+__host__ __device__ constexpr PipeShape pipe_schedule(int nz, int elem, int k) {
+    const bool p2 = synthesis_pow2(nz);
+    const PipeSchedule* t = p2 ? kPow2Schedules : kSmoothSchedules;
+    const int n = p2 ? kNumPow2Schedules : kNumSmoothSchedules;
+    for (int i = 0; i < n; ++i) {
+        if (t[i].nz != nz) continue;
+        const PipeShape s = pipe_shape_for(nz, t[i].n1, t[i].tbc);
+        if (!pipe_fits(s, elem)) continue;
+        if (k-- == 0) return s;
+    }
+    return PipeShape{};
+}
+// Number of schedules of N_z that fit elem bytes per real.
+__host__ __device__ constexpr int pipe_schedule_count(int nz, int elem) {
+    int n = 0;
+    while (pipe_schedule(nz, elem, n).n1 > 0) ++n;
+    return n;
 }
 // LDS bytes of the workgroup (two staging buffers).
 inline size_t pipe_lds(const PipeShape& s, size_t re) { return 2 * (size_t)s.buffer * re; }

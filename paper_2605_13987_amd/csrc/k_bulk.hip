@@ -288,9 +288,8 @@ hipError_t field_table(const Plan& p, char* b, cplx<T>* e, int deriv, hipStream_
 }
 
 
-template <typename T, int N1, int N2, typename TO>
+template <typename T, int N1, int N2, typename TO, int TB>
 hipError_t synthesis_pipe_w(const Plan& p, char* b, void* h, hipStream_t s) {
-    constexpr int TB = pipe_shape_pow2(N1 * N2, (int)sizeof(T)).tbc;
     switch (p.n_cols) {
         case 1: return synthesis_pipe<T, N1, N2, 1, TO, TB>(p, b, h, s);
         case 2: return synthesis_pipe<T, N1, N2, 2, TO, TB>(p, b, h, s);
@@ -299,19 +298,26 @@ hipError_t synthesis_pipe_w(const Plan& p, char* b, void* h, hipStream_t s) {
     }
 }
 
+// The power-of-two schedule I of kPow2Schedules that the plan names, if it
+// fits in LDS for T.
+template <int I, typename T, typename TO>
+hipError_t synthesis_pipe_pow2(const Plan& p, char* b, void* h, hipStream_t s) {
+    if constexpr (I == kNumPow2Schedules) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr PipeSchedule c = kPow2Schedules[I];
+        if constexpr (pipe_fits(pipe_shape_for(c.nz, c.n1, c.tbc), (int)sizeof(T))) {
+            if (p.N[2] == c.nz && p.synth_n1 == c.n1 && p.synth_tbc == c.tbc)
+                return synthesis_pipe_w<T, c.n1, c.nz / c.n1, TO, c.tbc>(p, b, h, s);
+        }
+        return synthesis_pipe_pow2<I + 1, T, TO>(p, b, h, s);
+    }
+}
+
 template <typename T, typename TO>
 hipError_t synthesis_pipe_n(const Plan& p, char* b, void* h, hipStream_t s) {
     if (!synthesis_pow2(p.N[2])) return launch_synthesis_smooth(p, b, h, s);
-    switch (p.N[2]) {
-        case 64: return synthesis_pipe_w<T, 8, 8, TO>(p, b, h, s);
-        case 128: return synthesis_pipe_w<T, 8, 16, TO>(p, b, h, s);
-        case 256: return synthesis_pipe_w<T, 16, 16, TO>(p, b, h, s);
-        default:
-            // N_z = 512: two 8-sample staging buffers of doubles exceed LDS, so
-            // plans in double take the Stockham synthesis there
-            if constexpr (sizeof(T) == 4) return synthesis_pipe_w<T, 16, 32, TO>(p, b, h, s);
-            return hipErrorInvalidValue;
-    }
+    return synthesis_pipe_pow2<0, T, TO>(p, b, h, s);
 }
 
 template <typename T>

@@ -49,6 +49,9 @@ def test_plan_layout_32_and_128_grids():
     spec2 = dict(n_freq=256, df=workloads.frequency_grid_to_nyquist(256, 10e-12), n_time=200, dt=10e-12)
     plan, lay = wt.wt_h_plan_create(px128, cols, spec2, precision=wt.WT_F32)
     assert lay["h_bytes"] == 128 * 128 * 256 * 200 * 3 * 4
+    assert lay["h_time_block"] == 8                   # the default schedule of 256: blocks of 8
+    wt.wt_h_plan_destroy(plan)
+    plan, lay = wt.wt_h_plan_create(px128, cols, spec2, precision=wt.WT_F32, fft_schedule=1)
     assert lay["h_time_block"] == 16
     wt.wt_h_plan_destroy(plan)
     # in double the register-FFT synthesis stages blocks of 8 samples at N_z = 256
@@ -200,7 +203,7 @@ def test_batch_run_rejects_a_null_context():
 
 
 def test_fft_schedules_of_the_smooth_sizes():
-    assert [wt.wt_fft_schedule_count(n) for n in (64, 128, 256, 512)] == [1, 1, 1, 1]
+    assert [wt.wt_fft_schedule_count(n) for n in (64, 128, 256, 512)] == [2, 2, 2, 1]
     assert wt.wt_fft_schedule_count(40) == 0 and wt.wt_fft_schedule_count(330) == 0
     assert all(wt.wt_fft_schedule_count(n) == 3 for n in (72, 150, 320))
     cfg = workloads.small_pixel(k=5, n_xy=8, n_z=72, n_freq=4, n_time=19, n_pairs=2, n_colloc=8)
@@ -214,8 +217,10 @@ def test_fft_schedules_of_the_smooth_sizes():
     assert blocks == [8, 16, 16]
     assert wt.wt_h_plan_create_status(cell, cols, spec, precision=wt.WT_F32, fft_schedule=3) == wt.WT_E_INVALID_ARG
     assert wt.wt_h_plan_create_status(cell, cols, spec, precision=wt.WT_F32, fft_schedule=-1) == wt.WT_E_INVALID_ARG
-    # no register-FFT schedule to choose: double plans of a smooth size, powers of two
+    # no register-FFT schedule to choose in double plans of a smooth size; powers of two have two
     assert wt.wt_h_plan_create_status(cell, cols, spec, precision=wt.WT_F64, fft_schedule=1) == wt.WT_E_INVALID_ARG
     c64 = workloads.small_pixel(k=5, n_xy=8, n_z=64, n_freq=4, n_time=19, n_pairs=2, n_colloc=8)
     assert wt.wt_h_plan_create_status(c64["cell"], c64["columns"], c64["spectrum"], precision=wt.WT_F32,
-                                      fft_schedule=1) == wt.WT_E_INVALID_ARG
+                                      fft_schedule=1) == wt.WT_OK
+    assert wt.wt_h_plan_create_status(c64["cell"], c64["columns"], c64["spectrum"], precision=wt.WT_F32,
+                                      fft_schedule=2) == wt.WT_E_INVALID_ARG

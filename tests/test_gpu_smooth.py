@@ -9,7 +9,9 @@ The sizes cover the shapes the kernel distinguishes: N1 > N2 (72 = 9 x 8,
 10 x 25), N1 dividing N2 (162 = 9 x 18, 200 = 10 x 20), and ragged last
 blocks (21 samples: one full block of 16 and an odd tail).  The tuner's
 report names the register-FFT factor N1 of the plan, which the test uses to
-check that this path, not the Stockham one, ran.
+check that this path, not the Stockham one, ran.  Every compiled schedule of every
+register-FFT size, powers of two included (blocks of 8 and 16), is checked
+against the oracle through wt_h_options.fft_schedule.
 """
 import pytest
 
@@ -58,14 +60,15 @@ def test_smooth_register_synthesis(ctx, n_z, h_format):
 ALL_SIZES = [72, 80, 90, 96, 100, 108, 120, 144, 150, 160, 162, 180, 192, 200, 216, 240, 250, 270, 288, 300, 320]
 
 
-@pytest.mark.parametrize("n_z", ALL_SIZES)
+@pytest.mark.parametrize("n_z", [64, 128, 256, 512] + ALL_SIZES)
 def test_every_compiled_schedule(ctx, n_z):
-    """Each schedule of each smooth size (wt_h_options.fft_schedule), float32
-    H against the oracle; then the tuner's choice rewrites H, checked too."""
+    """Each register-FFT schedule of each size (wt_h_options.fft_schedule),
+    float32 H against the oracle; then the tuner's choice rewrites H, checked
+    too."""
     cfg = workloads.small_pixel(k=60 + n_z % 23, n_xy=8, n_z=n_z, n_freq=4, n_time=19, n_pairs=4, n_colloc=8)
     ref = oracle.weighting_field(cfg["cell"], cfg["columns"], cfg["spectrum"])
     n = wt.wt_fft_schedule_count(n_z)
-    assert n == 3
+    assert n == {64: 2, 128: 2, 256: 2, 512: 1}.get(n_z, 3)
     for k in range(n):
         say(f"test_every_compiled_schedule n_z={n_z} schedule={k}")
         run = solve_h(ctx, cfg, wt.WT_F32, fft_schedule=k)
@@ -75,7 +78,7 @@ def test_every_compiled_schedule(ctx, n_z):
         assert err <= 1e-5
     ws, hb = run["ws"], run["hbuf"]
     rep = wt.wt_h_plan_tune(ctx, run["plan"], ws.data_ptr(), ws.numel(), hb.data_ptr(), hb.numel())
-    assert rep["n_candidates"] == n and rep["fft_n1"] > 0
+    assert rep["n_candidates"] == n and rep["fft_n1"] > 0 and rep["from_cache"] == 0
     run["layout"] = wt.wt_h_plan_layout(run["plan"])
     assert run["layout"]["h_time_block"] == rep["h_time_block"]
     assert rel_l2(h_standard(run, cfg), ref["H"]) <= 1e-5

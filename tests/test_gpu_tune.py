@@ -1,6 +1,6 @@
 """The synthesis autotuner (wt_h_plan_tune): it keeps results exact in the
-layout it chooses, has nothing to tune for the power-of-two register-FFT
-sizes, and records and reuses its choices through a tuning cache file."""
+layout it chooses, has nothing to tune where a size has one register-FFT
+schedule, and records and reuses its choices through a tuning cache file."""
 import numpy as np
 import pytest
 import torch
@@ -56,14 +56,15 @@ def test_tuned_stockham_synthesis_is_exact(ctx, precision):
         wt.wt_h_plan_destroy(plan)
 
 
-def test_register_fft_sizes_have_nothing_to_tune(ctx):
-    cfg = workloads.small_pixel(k=82, n_xy=16, n_z=64, n_freq=4, n_time=20, n_pairs=4, n_colloc=8)
+def test_register_fft_size_with_one_schedule_has_nothing_to_tune(ctx):
+    """N_z = 512 has one register-FFT schedule (blocks of 8)."""
+    cfg = workloads.small_pixel(k=82, n_xy=8, n_z=512, n_freq=4, n_time=20, n_pairs=4, n_colloc=8)
     plan, lay = wt.wt_h_plan_create(cfg["cell"], cfg["columns"], cfg["spectrum"], precision=wt.WT_F32)
     try:
         ws, hbuf = _buffers(lay)
         rep = wt.wt_h_plan_tune(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), hbuf.numel())
-        assert rep["n_candidates"] == 1 and rep["ms_chosen"] < 0
-        assert wt.wt_h_plan_layout(plan)["h_time_block"] == lay["h_time_block"] == 16
+        assert rep["n_candidates"] == 1 and rep["ms_chosen"] < 0 and rep["fft_n1"] == 16
+        assert wt.wt_h_plan_layout(plan)["h_time_block"] == lay["h_time_block"] == 8
     finally:
         wt.wt_h_plan_destroy(plan)
 
