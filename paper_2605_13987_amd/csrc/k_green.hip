@@ -51,8 +51,17 @@ __global__ void k_twiddles(int n0, int n1, int n2, cplx<T>* t0, cplx<T>* t1, cpl
 // scale as 1/t and the offset dx as (X_w - X_v) t + r, so with f =
 // exp(-k^2 s^2/2)/k^2 the term is f (s^2 + 2/k^2)(k_x^2 + k_y^2) cos(k_x dx +
 // k_y dy) + f k_x r sin(k_x dx + k_y dy).
+// The in-plane sums factor along the axes except for 1/k^2: with
+// exp(-k^2 s^2/2) = e_x(m_x) e_y(m_y) e_z and cos(2 pi (m_x a_x + m_y a_y))
+// from the per-axis cosines and sines, one term costs a few products and a
+// division instead of an exponential and a cosine.  The per-axis tables live
+// in LDS (up to kMaxAxisModes modes per axis; wider mode boxes take the
+// direct form).
+constexpr int kMaxAxisModes = 1024;
+
 __global__ void __launch_bounds__(kBlock) k_lattice(Plan p, int kind, double* g) {
     __shared__ double red[kBlock / 64];
+    __shared__ double tx[3][kMaxAxisModes], ty[3][kMaxAxisModes];   // e, cos, sin per axis mode
     const int iz = blockIdx.x;
     const int v = blockIdx.y / p.n_cols, w = blockIdx.y % p.n_cols;
     const Column& cv = p.col[v];
@@ -67,9 +76,50 @@ __global__ void __launch_bounds__(kBlock) k_lattice(Plan p, int kind, double* g)
     const double ay = (cw.y - cv.y) / p.L[1];
     const double kz = 2.0 * kPi * iz / p.L[2];
     const int mx0 = cv.mmax[0], my0 = cv.mmax[1];
-    const int ny = 2 * my0 + 1;
-    const int total = (2 * mx0 + 1) * ny;
+    const int nx = 2 * mx0 + 1, ny = 2 * my0 + 1;
+    const int total = nx * ny;
     double acc = 0.0;
+    if (nx <= kMaxAxisModes && ny <= kMaxAxisModes) {
+        for (int i = threadIdx.x; i < nx + ny; i += blockDim.x) {
+            const bool isx = i < nx;
+            const int m = isx ? i - mx0 : i - nx - my0;
+            const double k = 2.0 * kPi * m / (isx ? p.L[0] : p.L[1]);
+            double u = m * (isx ? ax : ay);
+            u -= rint(u);
+            double sn, cs;
+            sincospi(2.0 * u, &sn, &cs);
+            double* t = isx ? &tx[0][i] : &ty[0][i - nx];
+            t[0] = exp(-0.5 * k * k * sc * sc);
+            t[kMaxAxisModes] = cs;
+            t[2 * kMaxAxisModes] = sn;
+        }
+        __syncthreads();
+        const double ez = exp(-0.5 * kz * kz * sc * sc);
+        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+            const int ix = idx / ny, iy = idx - (idx / ny) * ny;
+            const int mx = ix - mx0, my = iy - my0;
+            if (iz == 0 && mx == 0 && my == 0) continue;
+            const double kx = 2.0 * kPi * mx / p.L[0];
+            const double ky = 2.0 * kPi * my / p.L[1];
+            const double k2 = kx * kx + ky * ky + kz * kz;
+            const double e = ez * tx[0][ix] * ty[0][iy];
+            const double c = tx[1][ix] * ty[1][iy] - tx[2][ix] * ty[2][iy];    // cos(2 pi (m_x a_x + m_y a_y))
+            if (kind == 0) {
+                acc += e / k2 * c;
+            } else {
+                const double sn = tx[2][ix] * ty[1][iy] + tx[1][ix] * ty[2][iy]; // sin(...)
+                if (kind == 1)
+                    acc -= e / k2 * kx * sn;
+                else if (kind == 2)
+                    acc -= sc * e * c;
+                else
+                    acc += e / k2 * ((sc * sc + 2.0 / k2) * (kx * kx + ky * ky) * c + kx * cw.radius * sn);
+            }
+        }
+        const double sum = block_sum(acc, red);
+        if (threadIdx.x == 0) out[iz] = sum;
+        return;
+    }
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int mx = idx / ny - mx0;
         const int my = idx % ny - my0;
