@@ -152,12 +152,13 @@ struct PipeSchedule {
 };
 // Powers of two: 64 = 8 x 8, 128 = 8 x 16, 256 = 16 x 16, 512 = 16 x 32,
 // any number of columns up to 4, float or double (a schedule whose buffers
-// do not fit in LDS for double is skipped).  Blocks of 8 samples come first
-// where they were measured faster on one MI355X (128 x 128 x N_z, 200
-// samples, float H: 1.00 against 1.20 ms at N_z = 128, 2.12 against 2.52 ms
-// at 256): two workgroups then share a CU.
+// do not fit in LDS for double is skipped).  Blocks of 8 samples come first:
+// they were measured faster on one MI355X (128 x 128 x N_z, 200 samples,
+// float H: 0.50 against 0.52 ms at N_z = 64, 0.96 against 1.10 ms at 128,
+// 2.12 against 2.52 ms at 256; double: 0.93 against 1.05 ms at 64, 1.99
+// against 2.42 ms at 128), more workgroups then sharing a CU.
 constexpr PipeSchedule kPow2Schedules[] = {
-    {64, 8, 16}, {64, 8, 8}, {128, 8, 8}, {128, 8, 16}, {256, 16, 8}, {256, 16, 16}, {512, 16, 8},
+    {64, 8, 8}, {64, 8, 16}, {128, 8, 8}, {128, 8, 16}, {256, 16, 8}, {256, 16, 16}, {512, 16, 8},
 };
 constexpr int kNumPow2Schedules = (int)(sizeof(kPow2Schedules) / sizeof(kPow2Schedules[0]));
 // The other even 2,3,5-smooth N_z from 72 to 320: float, two columns.

@@ -41,7 +41,7 @@ def test_plan_layout_32_and_128_grids():
     plan, lay = wt.wt_h_plan_create(cell, cols, spec, precision=wt.WT_F64)
     assert lay["n_q"] == 128
     assert lay["h_bytes"] == 32 * 32 * 64 * 64 * 3 * 8
-    assert lay["h_time_block"] == 16
+    assert lay["h_time_block"] == 8
     assert lay["workspace_bytes"] > lay["off_ehat"] + 32 * 32 * 32 * 3 * 16 - 1
     assert wt.wt_h_plan_layout(plan) == lay
     wt.wt_h_plan_destroy(plan)
