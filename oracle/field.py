@@ -16,6 +16,10 @@ evaluate the same discrete quantity:
 * ``field_columns``: the same mode sum evaluated directly (no FFT) on selected
   (x, y) grid columns, for every z node; used on grids too large for the FFT
   route in memory.
+* ``field_columns_planar_fft``: the same sum on selected columns, with the
+  in-plane (k_x, k_y) part of every column at once from 2D inverse FFTs and
+  the k_z part by 1D inverse FFTs along z; used where many columns of a large
+  grid are needed.
 """
 from __future__ import annotations
 
@@ -109,4 +113,47 @@ def field_columns(cell, s, src, q_t, cols_ij) -> np.ndarray:
                 acc[a] += B[:, None] * Dw
         for a in range(3):
             out[c, :, :, a] = (ez @ acc[a]).real
+    return out
+
+
+def field_columns_planar_fft(cell, s, src, q_t, cols_ij, chunk=16) -> np.ndarray:
+    """H on grid columns (ix, iy) for all z nodes -> (n_cols, nz, n_time, 3).
+
+    The discrete sum of ``field_columns``, regrouped by source axis w:
+
+        H_a(X, Y, z, t) = Re sum_{k_z} e^{i k_z z} sum_w B_a(X - X_w, Y - Y_w, k_z) D_w(k_z, t),
+        B_a(X, Y, k_z)  = sum_{k_x, k_y} M_a(k) e^{i (k_x X + k_y Y)},
+        D_w(k_z, t)     = sum_{sources i on axis w} q_i(t) e^{-i k_z z_i}.
+
+    On the grid, B_a is the 2D inverse DFT of M_a over (k_x, k_y), taken for
+    every k_z at once (numpy.fft.ifft2 scaled by N_x N_y); the axes lie on grid
+    nodes, so the shift by (X_w, Y_w) is an index shift; the k_z sum is a 1D
+    inverse DFT along z (numpy.fft.ifft scaled by N_z).  M_a is the multiplier
+    of ``field_fft`` (zero at k = 0 and on the Nyquist planes).
+    """
+    L, N = cell["L"], cell["N"]
+    h = np.asarray(green.spacing(cell), dtype=np.float64)
+    Mk, (_, _, KZ) = _multiplier(cell, s)
+    kz = KZ[0, 0, :]                                                     # numpy order, Nyquist included
+    B = [np.fft.ifft2(Mk[a], axes=(0, 1)) * (N[0] * N[1]) for a in range(3)]
+    del Mk
+    axes = np.unique(src[:, :2], axis=0)
+    shift = np.rint(axes / h[None, :2]).astype(np.int64)
+    if np.max(np.abs(axes / h[None, :2] - shift)) > 1e-6:
+        raise ValueError("source axes must lie on grid nodes")
+    D = []
+    for ax in axes:
+        sel = np.all(src[:, :2] == ax, axis=1)
+        D.append(np.exp(-1j * np.outer(kz, src[sel, 2])) @ q_t[:, sel].T)   # (nz, nt)
+    nt = q_t.shape[0]
+    out = np.empty((len(cols_ij), N[2], nt, 3))
+    for c0 in range(0, len(cols_ij), chunk):
+        part = cols_ij[c0:c0 + chunk]
+        for a in range(3):
+            A = np.zeros((len(part), N[2], nt), dtype=np.complex128)
+            for (sx, sy), Dw in zip(shift, D):
+                bx = np.array([(ix - sx) % N[0] for ix, _ in part])
+                by = np.array([(iy - sy) % N[1] for _, iy in part])
+                A += B[a][bx, by, :][:, :, None] * Dw[None, :, :]
+            out[c0:c0 + len(part), :, :, a] = (np.fft.ifft(A, axis=1) * N[2]).real
     return out

@@ -56,3 +56,31 @@ def test_c4_and_mirror_symmetry_about_the_readout(px32, px32_oracle):
     Hm = H[(N - i) % N]
     assert np.max(np.abs(Hm[..., 0] + H[..., 0])) <= 1e-12 * sc
     assert np.max(np.abs(Hm[..., 1:] - H[..., 1:])) <= 1e-12 * sc
+
+
+def test_planar_fft_column_route_matches_the_other_routes(px32, px32_oracle):
+    """The in-plane-FFT column route equals the direct column sums and the 3D
+    FFT route, on a grid with both column axes (readout and corner bias)."""
+    cell, cols = px32["cell"], px32["columns"]
+    s = green.smoothing_widths(cell, cols)
+    ij = [(0, 0), (16, 16), (5, 27), (31, 2), (17, 15), (0, 31)]
+    H4 = field.field_columns_planar_fft(cell, s, px32_oracle["src"], px32_oracle["q_t"], ij, chunk=4)
+    H3 = field.field_columns(cell, s, px32_oracle["src"], px32_oracle["q_t"], ij)
+    H = px32_oracle["H"]
+    sc = np.max(np.abs(H))
+    assert np.max(np.abs(H4 - H3)) <= 1e-12 * sc
+    for c, (i, j) in enumerate(ij):
+        assert np.max(np.abs(H4[c] - H[i, j])) <= 1e-11 * sc
+
+
+def test_planar_fft_column_route_on_an_anisotropic_grid():
+    cfg = workloads.small_pixel(k=23, n_xy=12, n_z=20, n_freq=4, n_time=6, n_pairs=2, n_colloc=6)
+    cell, cols, spec = cfg["cell"], cfg["columns"], cfg["spectrum"]
+    s = green.smoothing_widths(cell, cols)
+    sol = collocation.solve_spectrum(cell, cols, spec)
+    qt = timegrid.to_time(sol["q"], spec)
+    src = collocation.sources(cols)
+    ij = [(i, j) for i in range(12) for j in range(0, 12, 5)]
+    H4 = field.field_columns_planar_fft(cell, s, src, qt, ij, chunk=5)
+    H3 = field.field_columns(cell, s, src, qt, ij)
+    assert np.max(np.abs(H4 - H3)) <= 1e-12 * np.max(np.abs(H3))
