@@ -286,7 +286,7 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h,
 
 /* Batched forward runs over many geometry variants (each variant is one
  * cell, column set and spectrum: one plan; the workloads of the paper's
- * Section 4 studies vary pitch, diameter and resistivity).  For every item,
+ * Section 5 results vary pitch, diameter and resistivity).  For every item,
  * wt_h_solve followed by wt_current, exactly as the two calls would run
  * them; the items are spread over n_lanes HIP streams that fork from the
  * context's stream and join it again, so that one item's small launches
@@ -350,7 +350,7 @@ wt_status wt_h_gradient_workspace(const wt_h_plan* plan, int n_tracks, size_t* b
 
 /* Gradient of a loss L of the currents with respect to every column's
  * quarter-column resistivities and radius and to the pixel pitch (the
- * electrode parameters of the paper's Section 4 studies: resistance
+ * electrode parameters of the paper's Section 5 results: resistance
  * R = 4 rho L / (pi d^2) through the resistivity and the diameter, and the
  * pixel geometry), by the adjoint of the whole path.
  *   d_grad_current [n_tracks][n_time]: dL/di, element type of the plan's

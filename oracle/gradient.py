@@ -2,7 +2,7 @@
 
 Forward mode, written out step by step on the oracle's own pipeline.  The
 parameters are, per column, the resistivity of each of its quarter-columns and
-its radius (the quantities the paper varies in its Section 4 studies: the
+its radius (the quantities the paper varies in its Section 5 results: the
 electrode resistance R = 4 rho L / (pi d^2) through resistivity and diameter).
 
 The carrier polylines are inputs and stay fixed: a change of radius moves the

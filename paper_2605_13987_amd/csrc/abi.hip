@@ -704,22 +704,40 @@ wt_status wt_batch_run(wt_context* ctx, int n_items, const wt_batch_item* items,
         queue[l].push_back(i);
     }
     WT_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream), "hipEventRecord");
+    // A lane that has waited on the fork is joined back into the context's
+    // stream before the call returns, also when a later enqueue fails, so
+    // that no work is left outside the caller's stream order.
+    std::vector<char> forked(n_lanes, 0);
+    auto join = [&](int l) -> wt_status {
+        WT_HIP(ctx, hipEventRecord(ctx->lane_done[l], ctx->lane[l]), "hipEventRecord");
+        WT_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->lane_done[l], 0), "hipStreamWaitEvent");
+        forked[l] = 0;
+        return WT_OK;
+    };
+    auto fail = [&](wt_status err) -> wt_status {
+        const std::string msg = ctx->last_error;
+        for (int l = 0; l < n_lanes; ++l)
+            if (forked[l]) (void)join(l);
+        ctx->last_error = msg;
+        return err;
+    };
     for (int l = 0; l < n_lanes; ++l) {
         if (queue[l].empty()) continue;
         hipStream_t s = ctx->lane[l];
-        WT_HIP(ctx, hipStreamWaitEvent(s, ctx->fork, 0), "hipStreamWaitEvent");
+        hipError_t e = hipStreamWaitEvent(s, ctx->fork, 0);
+        if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamWaitEvent"));
+        forked[l] = 1;
         for (int i : queue[l]) {
             const wt_batch_item& it = items[i];
             const Plan& p = it.plan->p;
             st = enqueue_solve(ctx, p, d_workspace[l], d_h[l], s, [](int) { return WT_OK; }, false);
-            if (st != WT_OK) return st;
+            if (st != WT_OK) return fail(st);
             const wt_carriers& c = it.carriers;
-            WT_HIP(ctx, wt::launch_current(p, d_h[l], c.n_carriers, c.n_tracks, c.d_pos, c.d_charge, c.d_track,
-                                           it.d_current, s),
-                   "current");
+            e = wt::launch_current(p, d_h[l], c.n_carriers, c.n_tracks, c.d_pos, c.d_charge, c.d_track,
+                                   it.d_current, s);
+            if (e != hipSuccess) return fail(hip_fail(ctx, e, "current"));
         }
-        WT_HIP(ctx, hipEventRecord(ctx->lane_done[l], s), "hipEventRecord");
-        WT_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->lane_done[l], 0), "hipStreamWaitEvent");
+        if ((st = join(l)) != WT_OK) return fail(st);
     }
     return first_bad;
 }

@@ -1,6 +1,6 @@
 // Adjoint of the path: the gradient of a loss L(i) of the Eq. 1 currents with
 // respect to each column's quarter-column resistivities and radius (the
-// electrode parameters of the paper's Section 4 studies), given dL/di.
+// electrode parameters of the paper's Section 5 results), given dL/di.
 //
 // Everything after the boundary fit is linear in the charges, so the chain
 // is run backwards without forming H or its derivative:

@@ -26,7 +26,10 @@ k_electronics(int nt, T dt, const T* cur, const T* g, const T* noise, T sigma, T
         sg[n] = g[n];
     }
     __syncthreads();
-    // v[n] = dt sum_{m<=n} g[n-m] i[m] + sigma noise[n]; first index of max |v| per thread
+    // v[n] = dt sum_{m<=n} g[n-m] i[m] + sigma noise[n]; first index of max |v|
+    // per thread, a NaN counting as the largest value (the first NaN wins, as
+    // in an argmax that propagates NaN), so that a record of NaN currents
+    // still names a sample
     T ba = (T)-1;
     int bn = nt;
     for (int n = threadIdx.x; n < nt; n += kElecBlock) {
@@ -37,7 +40,7 @@ k_electronics(int nt, T dt, const T* cur, const T* g, const T* noise, T sigma, T
         sv[n] = v;
         v_out[(size_t)k * nt + n] = v;
         const T a = fabs(v);
-        if (a > ba) {
+        if (!isnan(ba) && (isnan(a) || a > ba)) {
             ba = a;
             bn = n;
         }
@@ -47,9 +50,13 @@ k_electronics(int nt, T dt, const T* cur, const T* g, const T* noise, T sigma, T
     __syncthreads();
     for (int h = kElecBlock / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
+            const T a1 = best_a[threadIdx.x];
+            const int n1 = best_n[threadIdx.x];
             const T a2 = best_a[threadIdx.x + h];
             const int n2 = best_n[threadIdx.x + h];
-            if (a2 > best_a[threadIdx.x] || (a2 == best_a[threadIdx.x] && n2 < best_n[threadIdx.x])) {
+            const bool nan1 = isnan(a1), nan2 = isnan(a2);
+            const bool take = nan1 ? (nan2 && n2 < n1) : (nan2 || a2 > a1 || (a2 == a1 && n2 < n1));
+            if (take) {
                 best_a[threadIdx.x] = a2;
                 best_n[threadIdx.x] = n2;
             }
@@ -57,7 +64,8 @@ k_electronics(int nt, T dt, const T* cur, const T* g, const T* noise, T sigma, T
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const int np = best_n[0];
+        // every sample n < nt was examined by some thread, so np < nt
+        const int np = best_n[0] < nt ? best_n[0] : 0;
         const T amp = sv[np];
         T* f = feat + (size_t)k * 3;
         f[0] = amp;

@@ -112,3 +112,24 @@ def test_electronics_edge_cases(ctx):
         assert st == wt.WT_E_INVALID_ARG
     st, _, _ = _run(ctx, wt.WT_F64, np.ones((1, 600)), np.ones(600), None, 0.0, 0.5, raise_on_error=False)
     assert st == wt.WT_E_UNSUPPORTED_SIZE
+
+
+@pytest.mark.parametrize("precision", [wt.WT_F64, wt.WT_F32])
+def test_electronics_nan_currents(ctx, precision):
+    """Rows of NaN currents (all NaN, and NaN from some sample on, at the
+    longest record): the features are those the oracle extracts from the
+    same signal, the peak at the first NaN sample."""
+    say(f"test_electronics_nan_currents precision={precision}")
+    n_t = 512
+    g = workloads.cr_rc_response(n_t, DT)
+    cur = np.full((3, n_t), 1e-6)
+    cur[0, :] = np.nan
+    cur[1, 300:] = np.nan
+    cur[2, :] = np.sin(np.arange(n_t) * 0.05) * 1e-6
+    st, v, f = _run(ctx, precision, cur, g, None, 0.0, 0.5)
+    assert st == wt.WT_OK
+    f_ref = oel.features(v, DT, 0.5)
+    assert np.array_equal(np.isnan(f), np.isnan(f_ref))
+    assert f[0, 1] == 0.0 and f[1, 1] == pytest.approx(300 * DT, rel=1e-6)
+    tol = 1e-9 if precision == wt.WT_F64 else 1e-3
+    assert np.allclose(f[:, 1:2], f_ref[:, 1:2], rtol=0, atol=tol * DT, equal_nan=True)

@@ -167,7 +167,7 @@ def test_signal_features_through_autograd(px128):
         err = np.max(np.abs(a - b)) / np.max(np.abs(b))
         say(f"    {name}: adjoint {a}\n    {name}: central differences {b}\n    max err / max = {err:.3e}")
         assert err <= 2e-3
-    # The paper's Section 4 finding: the bias columns' resistance barely moves
+    # The paper's Section 5 finding: the bias columns' resistance barely moves
     # the timing, the readout column's dominates.
     ro = abs(th[0, 0] * gp[0, 0])
     bias = abs(sum(th[1, p] * gp[1, p] for p in range(4)))

@@ -58,3 +58,14 @@ def test_no_crossing_and_zero_signal():
     assert np.isnan(electronics.features(v, dt, 0.5)[0][2])
     z = electronics.features(np.zeros(16), dt, 0.5)[0]
     assert z[0] == 0.0 and np.isnan(z[2])
+
+
+def test_nan_samples_name_the_first_nan():
+    # a NaN in |v| counts as the largest value: the peak is the first NaN
+    # sample, the amplitude NaN, the peak time that sample's time (no parabola
+    # through NaN), and there is no constant-fraction crossing
+    dt = 10e-12
+    v = np.array([[1.0, 3.0, np.nan, 9.0, np.nan, 2.0], [np.nan] * 6])
+    f = electronics.features(v, dt, 0.5)
+    assert np.isnan(f[0, 0]) and f[0, 1] == 2 * dt and np.isnan(f[0, 2])
+    assert np.isnan(f[1, 0]) and f[1, 1] == 0.0 and np.isnan(f[1, 2])
