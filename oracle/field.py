@@ -20,6 +20,10 @@ evaluate the same discrete quantity:
   in-plane (k_x, k_y) part of every column at once from 2D inverse FFTs and
   the k_z part by 1D inverse FFTs along z; used where many columns of a large
   grid are needed.
+* ``field_nodes_planar_fft``: the same sum at selected grid nodes only, with
+  the in-plane part from the same 2D inverse FFTs and the k_z sum taken
+  directly at each node; used for the nodes that carrier paths touch on
+  large grids.
 """
 from __future__ import annotations
 
@@ -156,4 +160,50 @@ def field_columns_planar_fft(cell, s, src, q_t, cols_ij, chunk=16) -> np.ndarray
                 by = np.array([(iy - sy) % N[1] for _, iy in part])
                 A += B[a][bx, by, :][:, :, None] * Dw[None, :, :]
             out[c0:c0 + len(part), :, :, a] = (np.fft.ifft(A, axis=1) * N[2]).real
+    return out
+
+
+def planar_table(cell, s):
+    """B_a(X, Y, k_z) = sum_{k_x, k_y} M_a(k) e^{i (k_x X + k_y Y)} on the grid,
+    for every k_z in numpy order: [3] arrays (N_x, N_y, N_z) complex, and k_z."""
+    N = cell["N"]
+    Mk, (_, _, KZ) = _multiplier(cell, s)
+    B = [np.fft.ifft2(Mk[a], axes=(0, 1)) * (N[0] * N[1]) for a in range(3)]
+    return B, KZ[0, 0, :].copy()
+
+
+def field_nodes_planar_fft(cell, s, src, q_t, ix, iy, iz, table=None, chunk=4096) -> np.ndarray:
+    """H at grid nodes (ix[i], iy[i], iz[i]) -> (n, n_time, 3).
+
+    The discrete sum of ``field_columns_planar_fft`` taken node by node:
+
+        H_a(X, Y, z, t) = Re sum_{k_z} e^{i k_z z} sum_w B_a(X - X_w, Y - Y_w, k_z) D_w(k_z, t)
+
+    with B_a from ``planar_table`` (2D inverse DFTs of the multiplier) and D_w
+    the z-transform of the charges on axis w; the k_z sum is a direct sum at
+    each requested node (a product of the per-node row e^{i k_z z} B_a(., k_z)
+    with D_w).  ``table`` may hold a precomputed ``planar_table``.
+    """
+    L, N = cell["L"], cell["N"]
+    h = np.asarray(green.spacing(cell), dtype=np.float64)
+    B, kz = planar_table(cell, s) if table is None else table
+    axes = np.unique(src[:, :2], axis=0)
+    shift = np.rint(axes / h[None, :2]).astype(np.int64)
+    if np.max(np.abs(axes / h[None, :2] - shift)) > 1e-6:
+        raise ValueError("source axes must lie on grid nodes")
+    D = []
+    for ax in axes:
+        sel = np.all(src[:, :2] == ax, axis=1)
+        D.append(np.exp(-1j * np.outer(kz, src[sel, 2])) @ q_t[:, sel].T)   # (nz, nt)
+    ix, iy, iz = (np.asarray(v, dtype=np.int64) for v in (ix, iy, iz))
+    nt = q_t.shape[0]
+    out = np.empty((ix.size, nt, 3))
+    for i0 in range(0, ix.size, chunk):
+        sl = slice(i0, i0 + chunk)
+        ez = np.exp(1j * np.outer(iz[sl] * h[2], kz))                        # (n, nz)
+        for a in range(3):
+            acc = np.zeros((ez.shape[0], nt), dtype=np.complex128)
+            for (sx, sy), Dw in zip(shift, D):
+                acc += (ez * B[a][(ix[sl] - sx) % N[0], (iy[sl] - sy) % N[1], :]) @ Dw
+            out[sl, :, a] = acc.real
     return out
