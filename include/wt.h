@@ -271,6 +271,26 @@ wt_status wt_h_solve(wt_context* ctx, const wt_h_plan* plan,
                      void* d_workspace, size_t workspace_bytes,
                      void* d_h, size_t h_bytes, wt_h_report* report);
 
+/* Size of the static workspace of wt_h_solve_static, per GPU. */
+#define WT_STATIC_WORKSPACE_BYTES ((size_t)32 << 20)
+
+/* wt_h_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  The
+ * workspace is a library-owned static device array of
+ * WT_STATIC_WORKSPACE_BYTES (32 MiB) on every GPU the library runs on, held
+ * until the process ends; nothing is allocated or freed by this call.  The
+ * caller still passes H (d_h, >= layout.h_bytes, 16-byte aligned).  Plans
+ * whose layout.workspace_bytes exceeds WT_STATIC_WORKSPACE_BYTES are
+ * rejected with WT_E_WORKSPACE before any work is enqueued (the message in
+ * the context gives both sizes).  Same kernels, results and report as
+ * wt_h_solve; the intermediates (collocation matrix, charges, field table)
+ * are left in the static workspace, which keeps the last call's contents.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams, threads or contexts) race and must be
+ * serialised by the caller. */
+wt_status wt_h_solve_static(wt_context* ctx, const wt_h_plan* plan, void* d_h, size_t h_bytes,
+                            wt_h_report* report);
+
 /* Induced current (Eq. 1): for every carrier and every polyline step m with a
  * non-zero displacement dx = P(t_{m+1}) - P(t_m), the field at the step
  * midpoint (trilinear interpolation of the nodal H, periodic wrap) at lag

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -45,6 +46,43 @@ struct wt_context {
 struct wt_h_plan {
     wt::Plan p;
 };
+
+// Workspace of wt_h_solve_static: a static device array, one copy on every
+// GPU the library runs on, held until the process ends.  In host code the
+// name `scratch` only stands for the symbol; its device address on each GPU
+// comes from hipGetSymbolAddress (resolved once per device, with that device
+// current, when the first context on it is created) and only that address is
+// ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[WT_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_resolved[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device); nullptr and
+// the runtime's error when it cannot be resolved.
+void* static_scratch(int device, hipError_t* err) {
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_resolved[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_err[device] = e;
+        g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+        g_scratch_resolved[device] = true;
+    }
+    *err = g_scratch_err[device];
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -426,6 +464,48 @@ bool carriers_ok(const wt_carriers* car) {
     return car->n_carriers == 0 || (car->d_pos && car->d_charge && car->d_track);
 }
 
+// Body of wt_h_solve and wt_h_solve_static, once the workspace is known.
+wt_status solve_on(wt_context* ctx, const Plan& p, void* d_workspace, void* d_h, wt_h_report* report) {
+    wt_status st = bind(ctx);
+    if (st != WT_OK) return st;
+    ctx->n_events = 0;
+    hipStream_t s = ctx->stream;
+    // the field table on the second stream, except under stream capture: a
+    // replayed graph ran the forked form slower (3.95 ms against 3.57 ms
+    // eager at 128 x 128 x 256) than the sequential one (3.74 ms)
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    WT_HIP(ctx, hipStreamIsCapturing(s, &capture), "hipStreamIsCapturing");
+    st = enqueue_solve(ctx, p, d_workspace, d_h, s, [ctx](int stage) { return mark(ctx, stage); },
+                       capture == hipStreamCaptureStatusNone);
+    if (st != WT_OK) return st;
+    if (!report) return WT_OK;
+
+    std::vector<wt::SolveReport> rep(p.n_freq);
+    WT_HIP(ctx, hipMemcpyAsync(rep.data(), static_cast<char*>(d_workspace) + p.off_rep,
+                               rep.size() * sizeof(wt::SolveReport), hipMemcpyDeviceToHost, s),
+           "report copy");
+    float h_scale = 1.0f;
+    if (p.h_format == WT_H_F16_SCALED)
+        WT_HIP(ctx, hipMemcpyAsync(&h_scale, static_cast<char*>(d_workspace) + p.off_hscale, sizeof(float),
+                                   hipMemcpyDeviceToHost, s),
+               "scale copy");
+    WT_HIP(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+    report->h_scale = h_scale;
+    report->backward_error_max = 0.0;
+    report->pivot_ratio_max = 0.0;
+    report->ir_iters_max = 0;
+    report->singular_count = 0;
+    for (const auto& r : rep) {
+        report->backward_error_max = std::fmax(report->backward_error_max, r.backward_error);
+        report->pivot_ratio_max = std::fmax(report->pivot_ratio_max, r.pivot_ratio);
+        report->ir_iters_max = report->ir_iters_max > r.iters ? report->ir_iters_max : r.iters;
+        report->singular_count += r.singular ? 1 : 0;
+    }
+    if (report->singular_count > 0) return WT_E_SINGULAR;
+    if (!(report->backward_error_max <= p.ir_tol)) return WT_E_NOT_CONVERGED;
+    return WT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -482,6 +562,10 @@ wt_status wt_context_create(wt_context** out, int hip_device, void* hip_stream) 
     ctx->fork = nullptr;
     ctx->aux = nullptr;
     ctx->aux_fork = ctx->aux_join = nullptr;
+    // the static workspace of wt_h_solve_static on this device (its address
+    // is resolved here, once per device; a failure is reported by that call)
+    hipError_t scratch_err = hipSuccess;
+    (void)static_scratch(hip_device, &scratch_err);
     // the second stream of wt_h_solve (default priority, non-blocking)
     if ((err = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking)) != hipSuccess ||
         (err = hipEventCreateWithFlags(&ctx->aux_fork, hipEventDisableTiming)) != hipSuccess ||
@@ -577,44 +661,27 @@ wt_status wt_h_solve(wt_context* ctx, const wt_h_plan* plan, void* d_workspace, 
     if (workspace_bytes < p.ws_bytes || h_bytes < p.h_bytes) return WT_E_WORKSPACE;
     if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) || (reinterpret_cast<uintptr_t>(d_h) & 15))
         return WT_E_INVALID_ARG;
+    return solve_on(ctx, p, d_workspace, d_h, report);
+}
+
+wt_status wt_h_solve_static(wt_context* ctx, const wt_h_plan* plan, void* d_h, size_t h_bytes,
+                            wt_h_report* report) {
+    if (!ctx || !plan || !d_h) return WT_E_INVALID_ARG;
+    const Plan& p = plan->p;
+    if (p.ws_bytes > WT_STATIC_WORKSPACE_BYTES) {
+        ctx->last_error = "wt_h_solve_static: the plan needs " + std::to_string(p.ws_bytes) +
+                          " bytes of workspace; the static workspace holds " +
+                          std::to_string((size_t)WT_STATIC_WORKSPACE_BYTES);
+        return WT_E_WORKSPACE;
+    }
+    if (h_bytes < p.h_bytes) return WT_E_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(d_h) & 15) return WT_E_INVALID_ARG;
     wt_status st = bind(ctx);
     if (st != WT_OK) return st;
-    ctx->n_events = 0;
-    hipStream_t s = ctx->stream;
-    // the field table on the second stream, except under stream capture: a
-    // replayed graph ran the forked form slower (3.95 ms against 3.57 ms
-    // eager at 128 x 128 x 256) than the sequential one (3.74 ms)
-    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
-    WT_HIP(ctx, hipStreamIsCapturing(s, &capture), "hipStreamIsCapturing");
-    st = enqueue_solve(ctx, p, d_workspace, d_h, s, [ctx](int stage) { return mark(ctx, stage); },
-                       capture == hipStreamCaptureStatusNone);
-    if (st != WT_OK) return st;
-    if (!report) return WT_OK;
-
-    std::vector<wt::SolveReport> rep(p.n_freq);
-    WT_HIP(ctx, hipMemcpyAsync(rep.data(), static_cast<char*>(d_workspace) + p.off_rep,
-                               rep.size() * sizeof(wt::SolveReport), hipMemcpyDeviceToHost, s),
-           "report copy");
-    float h_scale = 1.0f;
-    if (p.h_format == WT_H_F16_SCALED)
-        WT_HIP(ctx, hipMemcpyAsync(&h_scale, static_cast<char*>(d_workspace) + p.off_hscale, sizeof(float),
-                                   hipMemcpyDeviceToHost, s),
-               "scale copy");
-    WT_HIP(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
-    report->h_scale = h_scale;
-    report->backward_error_max = 0.0;
-    report->pivot_ratio_max = 0.0;
-    report->ir_iters_max = 0;
-    report->singular_count = 0;
-    for (const auto& r : rep) {
-        report->backward_error_max = std::fmax(report->backward_error_max, r.backward_error);
-        report->pivot_ratio_max = std::fmax(report->pivot_ratio_max, r.pivot_ratio);
-        report->ir_iters_max = report->ir_iters_max > r.iters ? report->ir_iters_max : r.iters;
-        report->singular_count += r.singular ? 1 : 0;
-    }
-    if (report->singular_count > 0) return WT_E_SINGULAR;
-    if (!(report->backward_error_max <= p.ir_tol)) return WT_E_NOT_CONVERGED;
-    return WT_OK;
+    hipError_t err = hipSuccess;
+    void* ws = static_scratch(ctx->device, &err);
+    if (!ws) return hip_fail(ctx, err == hipSuccess ? hipErrorInvalidSymbol : err, "hipGetSymbolAddress(scratch)");
+    return solve_on(ctx, p, ws, d_h, report);
 }
 
 wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, const wt_carriers* car,

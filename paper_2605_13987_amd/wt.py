@@ -91,6 +91,7 @@ class wt_batch_item(ctypes.Structure):
 
 
 WT_MAX_LANES = 8
+WT_STATIC_WORKSPACE_BYTES = 32 << 20
 
 
 def _load():
@@ -119,6 +120,7 @@ def _load():
         "wt_h_plan_destroy": (c_int, [c_void_p]),
         "wt_h_plan_layout": (c_int, [c_void_p, P(wt_h_layout)]),
         "wt_h_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_h_report)]),
+        "wt_h_solve_static": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, P(wt_h_report)]),
         "wt_current": (c_int, [c_void_p, c_void_p, c_void_p, P(wt_carriers), c_void_p, c_size_t, c_void_p]),
         "wt_electronics": (c_int, [c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                    c_double, c_double, c_void_p, c_void_p]),
@@ -272,6 +274,19 @@ def wt_h_solve(ctx, plan, d_workspace: int, workspace_bytes: int, d_h: int, h_by
                         ctypes.byref(rep) if report else None)
     if raise_on_error and st != WT_OK:
         _check(st, "wt_h_solve", ctx)
+    out = None
+    if report:
+        out = {name: getattr(rep, name) for name, _ in wt_h_report._fields_}
+    return st, out
+
+
+def wt_h_solve_static(ctx, plan, d_h: int, h_bytes: int, report: bool = False, raise_on_error: bool = True):
+    """wt_h_solve with the library's static workspace (no device allocation).
+    Returns (status, report dict or None) like wt_h_solve."""
+    rep = wt_h_report() if report else None
+    st = LIB.wt_h_solve_static(ctx, plan, c_void_p(d_h), int(h_bytes), ctypes.byref(rep) if report else None)
+    if raise_on_error and st != WT_OK:
+        _check(st, "wt_h_solve_static", ctx)
     out = None
     if report:
         out = {name: getattr(rep, name) for name, _ in wt_h_report._fields_}
