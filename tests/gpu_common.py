@@ -112,3 +112,25 @@ def rounded_carriers(carriers, precision):
     out["pos"] = np.asarray(carriers["pos"]).astype(np.float32).astype(np.float64)
     out["charge"] = np.asarray(carriers["charge"]).astype(np.float32).astype(np.float64)
     return out
+
+
+def oracle_current_on_nodes(cfg, carriers):
+    """The FP64 oracle's Eq. 1 currents for ``carriers`` (numpy arrays, as the
+    GPU received them), with H evaluated by the oracle's node route only at
+    the grid nodes the carrier paths touch: its own boundary fit, time
+    transform and in-plane table (nothing from the GPU)."""
+    import oracle
+    from oracle import collocation, field, green, timegrid
+
+    cell, cols, spec = cfg["cell"], cfg["columns"], cfg["spectrum"]
+    s = green.smoothing_widths(cell, cols)
+    sol = collocation.solve_spectrum(cell, cols, spec)
+    q_t = timegrid.to_time(sol["q"], spec)
+    src = collocation.sources(cols)
+    table = field.planar_table(cell, s)
+
+    def h_at(ix, iy, iz):
+        say(f"  oracle field at {ix.size} nodes")
+        return field.field_nodes_planar_fft(cell, s, src, q_t, ix, iy, iz, table=table)
+
+    return oracle.induced_current(h_at, cell, carriers)

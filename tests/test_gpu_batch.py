@@ -159,3 +159,79 @@ def test_batch_graph_replays_match_eager():
     for it in items:
         wt.wt_h_plan_destroy(it["plan"])
     wt.wt_context_destroy(ctx)
+
+
+def _oracle_refs(keys):
+    """The FP64 oracle's H (whole grid) and currents for the items SHAPES[k]."""
+    import oracle
+
+    refs = {}
+    for k in keys:
+        n_xy, n_z, nf, nt = SHAPES[k]
+        cfg = workloads.small_pixel(k=120 + k, n_xy=n_xy, n_z=n_z, n_freq=nf, n_time=nt, n_pairs=40, n_colloc=10)
+        ref = oracle.weighting_field(cfg["cell"], cfg["columns"], cfg["spectrum"])
+        car = dict(cfg["carriers"])
+        car["pos"] = np.asarray(car["pos"]).astype(np.float32).astype(np.float64)
+        car["charge"] = np.asarray(car["charge"]).astype(np.float32).astype(np.float64)
+        refs[k] = dict(cfg=cfg, H=ref["H"], i=oracle.induced_current(ref["H"], cfg["cell"], car))
+    return refs
+
+
+def _check_items_against_oracle(items, keys, hs, refs, label):
+    from gpu_common import h_standard, rel_l2
+
+    # two items on two lanes: the larger H goes first, to lane 0 (longest
+    # first, each to the lane with the least work)
+    order = sorted(range(len(keys)), key=lambda j: -items[j]["lay"]["h_bytes"])
+    for lane, j in enumerate(order):
+        k, it = keys[j], items[j]
+        r = refs[k]
+        N, nt = r["cfg"]["cell"]["N"], r["cfg"]["spectrum"]["n_time"]
+        n_vals = N[0] * N[1] * N[2] * nt * 3
+        run = dict(layout=it["lay"], h=hs[lane].view(torch.float32)[:n_vals], decode=1.0)
+        e_h = rel_l2(h_standard(run, r["cfg"]), r["H"])
+        e_i = rel_l2(it["out"].double().cpu().numpy(), r["i"])
+        say(f"  {label} item {k} {SHAPES[k]} (lane {lane}): H rel L2 {e_h:.2e}, i rel L2 {e_i:.2e}")
+        assert e_h <= 1e-5 and e_i <= 1e-4
+
+
+def test_batch_items_against_the_oracle():
+    """Two variants of uneven grids through wt_batch_run on two lanes, eager
+    and as replays of a captured graph: each lane's H (whole grid) and each
+    item's currents against the FP64 oracle (float32 H 1e-5, i 1e-4)."""
+    keys = [1, 4]
+    say("oracle: two variants, whole-grid H and currents")
+    refs = _oracle_refs(keys)
+    stream = torch.cuda.Stream()
+    ctx = wt.wt_context_create(0, stream.cuda_stream)
+    all_items = _items()
+    items = [all_items[k] for k in keys]
+    ws, ws_b, hs, h_b = _lane_buffers(items, 2)
+    args = [_arg(it) for it in items]
+
+    def run():
+        wt.wt_batch_run(ctx, args, [w.data_ptr() for w in ws], ws_b, [h.data_ptr() for h in hs], h_b)
+
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        run()
+    stream.synchronize()
+    _check_items_against_oracle(items, keys, hs, refs, "eager")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        run()
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for it in items:
+            it["out"].fill_(float("nan"))
+        for h in hs:
+            h.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            graph.replay()
+        torch.cuda.synchronize()
+        _check_items_against_oracle(items, keys, hs, refs, f"replay {rep}")
+    del graph
+    for it in all_items:
+        wt.wt_h_plan_destroy(it["plan"])
+    wt.wt_context_destroy(ctx)

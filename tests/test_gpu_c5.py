@@ -1,8 +1,13 @@
 """Parity at the 256x256x512 workload: 512 frequencies to 50 GHz, 400 samples
 of 10 ps, 100 MIP tracks of 5e3 e/h pairs with drift and diffusion (1e6
-carriers), H stored as scaled float16 (80.5 GB).
+carriers), H stored as scaled float16 (80.5 GB) or float32 (161 GB).
 
-* H on sampled (x, y) columns against the oracle's direct mode sums (1e-3);
+* H on sampled (x, y) columns against the oracle's direct mode sums
+  (float16 1e-3, float32 1e-5);
+* the currents on the solved H, end to end: every 10th carrier of tracks 0
+  and 1 (2000 carriers, ~3e4 moving steps, ~2.4e5 touched nodes) through
+  wt_current, against the oracle's own fit, field at the touched nodes and
+  Eq. 1 (float16 1e-3, float32 1e-4);
 * the convolution at full size on a synthetic float16 field: against the
   oracle on every 100th carrier (1e-3, the float16 rounding of the field) and
   through linearity over all carriers (1e-5).
@@ -12,7 +17,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_common import context, h_columns, rel_l2, say, solve_h
+from gpu_common import context, h_columns, oracle_current_on_nodes, rel_l2, say, solve_h
 from paper_2605_13987_amd import layout, workloads, wt
 
 pytestmark = pytest.mark.gpu
@@ -35,18 +40,47 @@ def c5():
     return cfg
 
 
-def test_256x256x512_f16_field_on_sampled_columns(ctx, c5):
-    run = solve_h(ctx, c5, wt.WT_F32, h_format=wt.WT_H_F16_SCALED)
+@pytest.fixture(scope="module")
+def c5_ref_cols(c5):
+    say("oracle: boundary fit + direct sums on 6 columns")
+    return oracle.weighting_field(c5["cell"], c5["columns"], c5["spectrum"], route="columns", cols_ij=COLS)
+
+
+def _subset(c5):
+    car = c5["carriers"]
+    return torch.nonzero(car["track"] < 2).flatten()[::10].contiguous()
+
+
+@pytest.fixture(scope="module")
+def c5_ref_current(c5):
+    car = c5["carriers"]
+    idx = _subset(c5)
+    sub = dict(pos=car["pos"].index_select(0, idx).double().cpu().numpy(),
+               charge=car["charge"].index_select(0, idx).double().cpu().numpy(),
+               track=car["track"].index_select(0, idx).cpu().numpy(), n_tracks=car["n_tracks"])
+    say(f"oracle: currents of {idx.numel()} carriers of tracks 0 and 1 on the solved field")
+    return oracle_current_on_nodes(c5, sub)
+
+
+@pytest.mark.parametrize("h_format,tol_h,tol_i", [(wt.WT_H_F16_SCALED, 1e-3, 1e-3), (wt.WT_H_PLAIN, 1e-5, 1e-4)])
+def test_256x256x512_field_and_current_against_the_oracle(ctx, c5, c5_ref_cols, c5_ref_current, h_format, tol_h,
+                                                          tol_i):
+    run = solve_h(ctx, c5, wt.WT_F32, h_format=h_format)
     assert run["status"] == wt.WT_OK, run["report"]
     assert run["layout"]["h_time_block"] == 8
-    say("oracle: boundary fit + direct sums on 6 columns")
-    ref = oracle.weighting_field(c5["cell"], c5["columns"], c5["spectrum"], route="columns", cols_ij=COLS)
     got = h_columns(run, c5, COLS)
     for k, ij in enumerate(COLS):
-        say(f"  column {ij}: rel L2 {rel_l2(got[k], ref['H_cols'][k]):.2e}")
-    err = rel_l2(got, ref["H_cols"])
-    say(f"  all sampled columns: rel L2 {err:.2e}")
-    assert err <= 1e-3
+        say(f"  column {ij}: rel L2 {rel_l2(got[k], c5_ref_cols['H_cols'][k]):.2e}")
+    err = rel_l2(got, c5_ref_cols["H_cols"])
+    say(f"  all sampled columns: rel L2 {err:.2e} (<= {tol_h})")
+    assert err <= tol_h
+    car, nt = c5["carriers"], c5["spectrum"]["n_time"]
+    i_gpu = _currents(ctx, run["plan"], run["hbuf"], car, _subset(c5), nt)
+    for tr in (0, 1):
+        e = rel_l2(i_gpu[tr], c5_ref_current[tr])
+        say(f"  track {tr}: i rel L2 {e:.2e} (<= {tol_i})")
+        assert e <= tol_i
+    assert np.all(i_gpu[2:] == 0.0)
     wt.wt_h_plan_destroy(run["plan"])
     del run
     torch.cuda.empty_cache()
