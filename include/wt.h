@@ -291,15 +291,30 @@ wt_status wt_h_solve(wt_context* ctx, const wt_h_plan* plan,
 wt_status wt_h_solve_static(wt_context* ctx, const wt_h_plan* plan, void* d_h, size_t h_bytes,
                             wt_h_report* report);
 
+/* Bytes of the workspace of wt_current for n_carriers carriers and room for
+ * max_events moving steps (max_events <= 0: n_carriers * n_time, every step
+ * of every carrier; at most 2^32 - 16 are used).  The fixed part (control
+ * words, bin counts and offsets over the grid's cell columns and z-tiles,
+ * one 8-byte step mask per carrier and 64 steps) is needed in full; each
+ * event then takes 32 bytes (64 for a WT_F64 plan). */
+wt_status wt_current_workspace(const wt_h_plan* plan, int n_carriers, long long max_events, size_t* bytes);
+
 /* Induced current (Eq. 1): for every carrier and every polyline step m with a
  * non-zero displacement dx = P(t_{m+1}) - P(t_m), the field at the step
  * midpoint (trilinear interpolation of the nodal H, periodic wrap) at lag
  * n - m is projected on dx and accumulated:
  *   i[track][n] = -(1/V_w) sum_{c in track} q_c sum_{m<=n} H(xbar_{c,m}, t_{n-m}) . dx_{c,m}
  * d_h is H as written by wt_h_solve for the same plan; d_i_out [n_tracks]
- * [n_time] is overwritten.  No workspace is needed (d_workspace may be NULL
- * and workspace_bytes 0).  Summation order across carriers is not fixed
- * (atomic accumulation), so results can differ in the last bits. */
+ * [n_time] is overwritten.
+ * With a workspace (d_workspace 256-byte aligned, at least
+ * wt_current_workspace(plan, n_carriers, 1) bytes, overwritten), the moving
+ * steps are binned by grid cell and H is read node column by node column,
+ * each node's lag series once (the fast form).  If the moving steps exceed
+ * the events that fit the workspace, the device falls back to the form
+ * without a workspace in the same call (same results, nothing synchronises).
+ * d_workspace NULL: one wavefront per carrier gathering its steps' corners.
+ * Summation order across carriers is not fixed (atomic accumulation), so
+ * results can differ in the last bits. */
 wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h,
                      const wt_carriers* carriers, void* d_workspace, size_t workspace_bytes,
                      void* d_i_out);

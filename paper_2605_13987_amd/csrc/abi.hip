@@ -684,19 +684,34 @@ wt_status wt_h_solve_static(wt_context* ctx, const wt_h_plan* plan, void* d_h, s
     return solve_on(ctx, p, ws, d_h, report);
 }
 
+wt_status wt_current_workspace(const wt_h_plan* plan, int n_carriers, long long max_events, size_t* bytes) {
+    if (!plan || !bytes || n_carriers < 0) return WT_E_INVALID_ARG;
+    const Plan& p = plan->p;
+    const wt::ConvTiling tl = wt::conv_tiling(p, p.precision == WT_F64 ? 8 : (p.h_format == WT_H_F16_SCALED ? 2 : 4));
+    const wt::CurrentLayout cl = wt::current_layout(p, tl, n_carriers);
+    long long cap = max_events > 0 ? max_events : (long long)n_carriers * p.n_time;
+    if (cap < 1) cap = 1;
+    *bytes = cl.fixed_bytes + (size_t)cap * wt::current_event_bytes(p);
+    return WT_OK;
+}
+
 wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, const wt_carriers* car,
                      void* d_workspace, size_t workspace_bytes, void* d_i_out) {
-    (void)d_workspace;
-    (void)workspace_bytes;
     if (!ctx || !plan || !d_h || !car || !d_i_out) return WT_E_INVALID_ARG;
     if (!carriers_ok(car)) return WT_E_INVALID_ARG;
     const Plan& p = plan->p;
+    if (d_workspace) {
+        if (reinterpret_cast<uintptr_t>(d_workspace) & 255) return WT_E_INVALID_ARG;
+        size_t need = 0;
+        (void)wt_current_workspace(plan, car->n_carriers, 1, &need);
+        if (workspace_bytes < need) return WT_E_WORKSPACE;
+    }
     wt_status st = bind(ctx);
     if (st != WT_OK) return st;
     ctx->n_events = 0;
     if ((st = mark(ctx, -1)) != WT_OK) return st;
     WT_HIP(ctx, wt::launch_current(p, d_h, car->n_carriers, car->n_tracks, car->d_pos, car->d_charge, car->d_track,
-                                   d_i_out, ctx->stream),
+                                   d_workspace, d_workspace ? workspace_bytes : 0, d_i_out, ctx->stream),
            "current");
     if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
     return WT_OK;
@@ -800,8 +815,13 @@ wt_status wt_batch_run(wt_context* ctx, int n_items, const wt_batch_item* items,
             st = enqueue_solve(ctx, p, d_workspace[l], d_h[l], s, [](int) { return WT_OK; }, false);
             if (st != WT_OK) return fail(st);
             const wt_carriers& c = it.carriers;
+            // the lane's workspace is free again once H is written: the
+            // current bins its events there (or runs unbinned if it is too small)
+            size_t need = 0;
+            (void)wt_current_workspace(it.plan, c.n_carriers, 1, &need);
+            const bool fits = workspace_bytes >= need;
             e = wt::launch_current(p, d_h[l], c.n_carriers, c.n_tracks, c.d_pos, c.d_charge, c.d_track,
-                                   it.d_current, s);
+                                   fits ? d_workspace[l] : nullptr, fits ? workspace_bytes : 0, it.d_current, s);
             if (e != hipSuccess) return fail(hip_fail(ctx, e, "current"));
         }
         if ((st = join(l)) != WT_OK) return fail(st);

@@ -104,12 +104,13 @@ class ColumnModel:
         hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device=self.pos.device)
         wt.wt_h_solve(self.ctx, handle, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), hbuf.numel())
         out = torch.empty((self.n_tracks, self.spectrum["n_time"]), dtype=self.dtype, device=self.pos.device)
+        cws = torch.empty(wt.wt_current_workspace(handle, pos.shape[0]), dtype=torch.uint8, device=self.pos.device)
         wt.wt_current(self.ctx, handle, hbuf.data_ptr(), pos.shape[0], self.n_tracks, pos.data_ptr(),
-                      self.charge.data_ptr(), self.track.data_ptr(), out.data_ptr())
+                      self.charge.data_ptr(), self.track.data_ptr(), out.data_ptr(), cws.data_ptr(), cws.numel())
         plan.pos = pos
         # H is consumed in stream order; dropping the last reference lets the
         # caching allocator reuse it for work enqueued after this point.
-        del hbuf
+        del hbuf, cws
         return plan, out
 
     def gradient(self, plan, grad_current):

@@ -121,6 +121,7 @@ def _load():
         "wt_h_plan_layout": (c_int, [c_void_p, P(wt_h_layout)]),
         "wt_h_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_h_report)]),
         "wt_h_solve_static": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, P(wt_h_report)]),
+        "wt_current_workspace": (c_int, [c_void_p, c_int, ctypes.c_longlong, P(c_size_t)]),
         "wt_current": (c_int, [c_void_p, c_void_p, c_void_p, P(wt_carriers), c_void_p, c_size_t, c_void_p]),
         "wt_electronics": (c_int, [c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                    c_double, c_double, c_void_p, c_void_p]),
@@ -291,6 +292,13 @@ def wt_h_solve_static(ctx, plan, d_h: int, h_bytes: int, report: bool = False, r
     if report:
         out = {name: getattr(rep, name) for name, _ in wt_h_report._fields_}
     return st, out
+
+
+def wt_current_workspace(plan, n_carriers: int, max_events: int = 0) -> int:
+    """Bytes of wt_current's workspace (max_events <= 0: room for every step)."""
+    n = c_size_t()
+    _check(LIB.wt_current_workspace(plan, int(n_carriers), int(max_events), ctypes.byref(n)), "wt_current_workspace")
+    return n.value
 
 
 def wt_current(ctx, plan, d_h: int, n_carriers: int, n_tracks: int, d_pos: int, d_charge: int,

@@ -84,7 +84,9 @@ def h_columns(run, cfg, cols_ij):
     return layout.to_standard(cols, N, nt, run["layout"]["h_time_block"])
 
 
-def current(ctx, run, carriers, precision=None, subset=None):
+def current(ctx, run, carriers, precision=None, subset=None, binned=True, max_events=0):
+    """wt_current through the C ABI; binned=True gives it a workspace (room
+    for max_events moving steps, default every step), binned=False none."""
     precision = run["precision"] if precision is None else precision
     dt = dtype_of(precision)
     pos = np.asarray(carriers["pos"])
@@ -97,9 +99,15 @@ def current(ctx, run, carriers, precision=None, subset=None):
     d_q = torch.from_numpy(np.ascontiguousarray(q)).to(device="cuda", dtype=dt)
     d_tr = torch.from_numpy(np.ascontiguousarray(tr)).to(device="cuda")
     out = torch.empty((n_tracks, pos.shape[1] - 1), dtype=dt, device="cuda")
-    say(f"  wt_current n_carriers={pos.shape[0]} n_tracks={n_tracks} nt={pos.shape[1] - 1}")
+    ws = None
+    if binned:
+        nb = wt.wt_current_workspace(run["plan"], pos.shape[0], max_events)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    say(f"  wt_current n_carriers={pos.shape[0]} n_tracks={n_tracks} nt={pos.shape[1] - 1} "
+        f"workspace={0 if ws is None else ws.numel()}")
     wt.wt_current(ctx, run["plan"], run["h"].data_ptr(), pos.shape[0], n_tracks, d_pos.data_ptr(),
-                  d_q.data_ptr(), d_tr.data_ptr(), out.data_ptr())
+                  d_q.data_ptr(), d_tr.data_ptr(), out.data_ptr(), 0 if ws is None else ws.data_ptr(),
+                  0 if ws is None else ws.numel())
     torch.cuda.synchronize()
     return out.cpu().numpy().astype(np.float64)
 

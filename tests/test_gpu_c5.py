@@ -86,14 +86,19 @@ def test_256x256x512_field_and_current_against_the_oracle(ctx, c5, c5_ref_cols, 
     torch.cuda.empty_cache()
 
 
-def _currents(ctx, plan, hbuf, car, idx, nt):
+def _currents(ctx, plan, hbuf, car, idx, nt, binned=True):
     pos = car["pos"].index_select(0, idx).contiguous()
     q = car["charge"].index_select(0, idx).contiguous()
     tr = car["track"].index_select(0, idx).contiguous()
     out = torch.empty((car["n_tracks"], nt), dtype=torch.float32, device="cuda")
+    ws = None
+    if binned:
+        ws = torch.empty(wt.wt_current_workspace(plan, pos.shape[0]), dtype=torch.uint8, device="cuda")
+    say(f"  wt_current on {pos.shape[0]} carriers, workspace {0 if ws is None else ws.numel()} B")
     wt.wt_current(ctx, plan, hbuf.data_ptr(), pos.shape[0], car["n_tracks"], pos.data_ptr(), q.data_ptr(),
-                  tr.data_ptr(), out.data_ptr())
+                  tr.data_ptr(), out.data_ptr(), 0 if ws is None else ws.data_ptr(), 0 if ws is None else ws.numel())
     torch.cuda.synchronize()
+    del ws
     return out.double().cpu().numpy()
 
 
@@ -120,6 +125,10 @@ def test_256x256x512_current_on_synthetic_f16_field(ctx, c5):
     n = car["pos"].shape[0]
     say(f"  currents of all {n} carriers, and of the even and odd halves")
     i_all = _currents(ctx, plan, hbuf, car, torch.arange(n, device="cuda"), nt)
+    i_direct = _currents(ctx, plan, hbuf, car, torch.arange(n, device="cuda"), nt, binned=False)
+    err_forms = rel_l2(i_all, i_direct)
+    say(f"  binned vs one wavefront per carrier, all carriers: rel L2 {err_forms:.2e}")
+    assert err_forms <= 1e-5
     i_even = _currents(ctx, plan, hbuf, car, torch.arange(0, n, 2, device="cuda"), nt)
     i_odd = _currents(ctx, plan, hbuf, car, torch.arange(1, n, 2, device="cuda"), nt)
     err_lin = rel_l2(i_even + i_odd, i_all)

@@ -11,8 +11,9 @@ from paper_2605_13987_amd import workloads, wt
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("binned", [False, True], ids=["direct", "binned"])
 @pytest.mark.parametrize("h_format", [wt.WT_H_PLAIN, wt.WT_H_F16_SCALED], ids=["f32", "f16"])
-def test_captured_step_replays_match_eager(h_format):
+def test_captured_step_replays_match_eager(h_format, binned):
     cfg = workloads.small_pixel(k=51, n_xy=32, n_z=128, n_freq=24, n_time=53, n_pairs=200, n_colloc=24)
     say(f"test_captured_step_replays_match_eager h_format={h_format}")
     cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
@@ -26,11 +27,12 @@ def test_captured_step_replays_match_eager(h_format):
     tr = torch.from_numpy(car["track"]).to("cuda")
     n_c, n_tr = pos.shape[0], car["n_tracks"]
     out = torch.zeros((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
+    cws = torch.zeros(wt.wt_current_workspace(plan, n_c) if binned else 0, dtype=torch.uint8, device="cuda")
 
     def step():
         wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"])
         wt.wt_current(ctx, plan, h.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
-                      out.data_ptr())
+                      out.data_ptr(), cws.data_ptr() if binned else 0, cws.numel())
 
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
@@ -44,6 +46,7 @@ def test_captured_step_replays_match_eager(h_format):
     for rep in range(4):
         h.zero_()                                  # eager work between replays
         out.fill_(float("nan"))
+        cws.fill_(0x5a)
         torch.cuda.synchronize()
         with torch.cuda.stream(stream):
             graph.replay()
