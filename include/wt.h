@@ -291,6 +291,12 @@ wt_status wt_h_solve(wt_context* ctx, const wt_h_plan* plan,
 wt_status wt_h_solve_static(wt_context* ctx, const wt_h_plan* plan, void* d_h, size_t h_bytes,
                             wt_h_report* report);
 
+/* Which form wt_current takes on this context when it is given a workspace:
+ * 0 (the default) bins the moving steps from 2^24 polyline steps
+ * (n_carriers * n_time) on and gathers per carrier below that, where it is
+ * faster; 1 bins at any size; 2 never bins.  Results agree to rounding. */
+wt_status wt_context_set_current_form(wt_context* ctx, int form);
+
 /* Bytes of the workspace of wt_current for n_carriers carriers and room for
  * max_events moving steps (max_events <= 0: n_carriers * n_time, every step
  * of every carrier; at most 2^32 - 16 are used).  The fixed part (control

@@ -28,6 +28,8 @@ struct wt_context {
     // the field table is built while the boundary fit runs
     hipStream_t aux;
     hipEvent_t aux_fork, aux_join;
+    // wt_current's form (wt_context_set_current_form)
+    int current_form;
     // wt_batch_run: lane streams and their events, made on first use
     int n_lanes;
     hipStream_t lane[WT_MAX_LANES];
@@ -90,10 +92,11 @@ using wt::Plan;
 
 constexpr int kMaxUnknowns = 528;
 constexpr int kStageTables = 0, kStageSolve = 1, kStageTime = 2, kStageFieldTable = 3, kStageSynthesis = 4,
-              kStageCurrent = 5, kStageAdjointProjection = 6, kStageAdjointSolve = 7, kStageAdjointParams = 8;
+              kStageCurrent = 5, kStageAdjointProjection = 6, kStageAdjointSolve = 7, kStageAdjointParams = 8,
+              kStageCurrentBinning = 9;
 const char* const kStageNames[] = {"green_tables", "collocation_solve", "time_transform",
                                    "field_table",  "synthesis",         "current",
-                                   "adjoint_projection", "adjoint_solve", "adjoint_params"};
+                                   "adjoint_projection", "adjoint_solve", "adjoint_params", "current_binning"};
 // The adjoint's transposed solves use the Schur-complement form of the boundary fit.
 constexpr int kMaxGradientCharges = 128;
 
@@ -562,6 +565,7 @@ wt_status wt_context_create(wt_context** out, int hip_device, void* hip_stream) 
     ctx->fork = nullptr;
     ctx->aux = nullptr;
     ctx->aux_fork = ctx->aux_join = nullptr;
+    ctx->current_form = 0;
     // the static workspace of wt_h_solve_static on this device (its address
     // is resolved here, once per device; a failure is reported by that call)
     hipError_t scratch_err = hipSuccess;
@@ -684,6 +688,12 @@ wt_status wt_h_solve_static(wt_context* ctx, const wt_h_plan* plan, void* d_h, s
     return solve_on(ctx, p, ws, d_h, report);
 }
 
+wt_status wt_context_set_current_form(wt_context* ctx, int form) {
+    if (!ctx || form < 0 || form > 2) return WT_E_INVALID_ARG;
+    ctx->current_form = form;
+    return WT_OK;
+}
+
 wt_status wt_current_workspace(const wt_h_plan* plan, int n_carriers, long long max_events, size_t* bytes) {
     if (!plan || !bytes || n_carriers < 0) return WT_E_INVALID_ARG;
     const Plan& p = plan->p;
@@ -711,7 +721,13 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, co
     ctx->n_events = 0;
     if ((st = mark(ctx, -1)) != WT_OK) return st;
     WT_HIP(ctx, wt::launch_current(p, d_h, car->n_carriers, car->n_tracks, car->d_pos, car->d_charge, car->d_track,
-                                   d_workspace, d_workspace ? workspace_bytes : 0, d_i_out, ctx->stream),
+                                   d_workspace, d_workspace ? workspace_bytes : 0, d_i_out, ctx->stream, 1,
+                                   ctx->current_form),
+           "current_binning");
+    if ((st = mark(ctx, kStageCurrentBinning)) != WT_OK) return st;
+    WT_HIP(ctx, wt::launch_current(p, d_h, car->n_carriers, car->n_tracks, car->d_pos, car->d_charge, car->d_track,
+                                   d_workspace, d_workspace ? workspace_bytes : 0, d_i_out, ctx->stream, 2,
+                                   ctx->current_form),
            "current");
     if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
     return WT_OK;
@@ -820,8 +836,10 @@ wt_status wt_batch_run(wt_context* ctx, int n_items, const wt_batch_item* items,
             size_t need = 0;
             (void)wt_current_workspace(it.plan, c.n_carriers, 1, &need);
             const bool fits = workspace_bytes >= need;
-            e = wt::launch_current(p, d_h[l], c.n_carriers, c.n_tracks, c.d_pos, c.d_charge, c.d_track,
-                                   fits ? d_workspace[l] : nullptr, fits ? workspace_bytes : 0, it.d_current, s);
+            for (int phase = 1; phase <= 2 && e == hipSuccess; ++phase)
+                e = wt::launch_current(p, d_h[l], c.n_carriers, c.n_tracks, c.d_pos, c.d_charge, c.d_track,
+                                       fits ? d_workspace[l] : nullptr, fits ? workspace_bytes : 0, it.d_current, s,
+                                       phase, ctx->current_form);
             if (e != hipSuccess) return fail(hip_fail(ctx, e, "current"));
         }
         if ((st = join(l)) != WT_OK) return fail(st);

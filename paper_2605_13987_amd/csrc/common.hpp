@@ -123,19 +123,20 @@ hipError_t launch_h_scale(const Plan& p, void* ws, void* h, hipStream_t s);
 hipError_t launch_synthesis(const Plan& p, void* ws, void* h, hipStream_t s);
 hipError_t launch_electronics(int precision, int n_tracks, int nt, double dt, const void* cur, const void* g,
                               const void* noise, double sigma, double frac, void* v, void* feat, hipStream_t s);
-// Tiling of the binned convolution (k_conv_tiles): node columns are taken
-// in blocks of bx x by per workgroup; each node column in z-tiles of zt
+// Tiling of the binned convolution (k_conv_tiles): one workgroup per node
+// column and range of tpr z-tiles (n_zr ranges per column); a z-tile is zt
 // cells, whose zt + 1 nodes are staged in LDS as rows of sl lags (a row
 // holds lag t at position 64 + t; the 64 positions before and those past
 // n_time read as zero).  One workgroup lane per output sample: threads =
 // 64 ceil(n_time / 64).  Events are binned by (cell column, z-tile).
 struct ConvTiling {
     int zt, n_zt, sl, threads, n_chunks;
-    int bx, by, nbx, nby;
+    int tpr, n_zr;
     int vec;              // full time blocks of H are 16-byte aligned: staged with 16-byte loads
     size_t n_bins;
-    size_t lds_h, lds_ev, lds_bytes;
+    size_t lds_h, lds_ev, lds_acc, lds_bytes;
 };
+constexpr int kConvSlots = 16;   // per-track accumulators of a workgroup of k_conv_tiles
 // h_elem: bytes per stored H value (2 float16, 4 float, 8 double).
 inline ConvTiling conv_tiling(const Plan& p, int h_elem) {
     ConvTiling t{};
@@ -144,22 +145,36 @@ inline ConvTiling conv_tiling(const Plan& p, int h_elem) {
     t.n_chunks = nw;
     t.sl = 64 + 64 * nw;
     const size_t row = (size_t)t.sl * 4 * h_elem;
-    // LDS for the staged rows: float16 H leaves room for three workgroups
-    // per CU, float and double for two
-    const size_t budget = h_elem == 2 ? 36 * 1024 : 56 * 1024;
+    // LDS for the staged rows, beside the per-track accumulators: two
+    // workgroups per CU
+    const size_t acc_elem = h_elem == 8 ? 8 : 4;
+    const size_t lds_acc = (size_t)kConvSlots * t.threads * acc_elem;
+    const size_t total = 76 * 1024;
+    const size_t rest = lds_acc + 64 * 64 + 4 * 1024;
+    const size_t budget = total > rest + 2 * row ? total - rest : 2 * row;
     int zt = (int)(budget / row) - 1;
+    // time blocks of 8 or 16 samples are prefetched one (node, block) unit
+    // per thread: (zt + 1) blocks-per-node units must not exceed the threads
+    if (p.tb == 8 || p.tb == 16) {
+        const int nb = (p.n_time + p.tb - 1) / p.tb;
+        const int zp = t.threads / nb - 1;
+        zt = zt < zp ? zt : zp;
+    }
     zt = zt < 1 ? 1 : (zt > 16 ? 16 : zt);
     t.zt = zt;
     t.n_zt = (p.N[2] + zt - 1) / zt;
-    t.bx = p.N[0] < 4 ? p.N[0] : 4;
-    t.by = p.N[1] < 4 ? p.N[1] : 4;
-    t.nbx = (p.N[0] + t.bx - 1) / t.bx;
-    t.nby = (p.N[1] + t.by - 1) / t.by;
+    // ranges of about max(64, N_z / 4) nodes: enough workgroups where the
+    // events crowd into few columns, few flushes per column otherwise
+    const int span = p.N[2] / 4 > 64 ? p.N[2] / 4 : 64;
+    t.tpr = (span + zt - 1) / zt;
+    if (t.tpr > t.n_zt) t.tpr = t.n_zt;
+    t.n_zr = (t.n_zt + t.tpr - 1) / t.tpr;
     t.n_bins = (size_t)p.N[0] * p.N[1] * t.n_zt;
     t.lds_h = (size_t)(zt + 1) * row;
-    const size_t staged = h_elem == 8 ? 64 : 32;   // bytes of a staged event (16-byte aligned)
-    t.lds_ev = (size_t)t.threads * staged;
-    t.lds_bytes = t.lds_h + t.lds_ev + (size_t)4 * (t.n_zt + 1) * sizeof(unsigned);
+    const size_t staged = h_elem == 8 ? 64 : 48;   // bytes of a staged event (16-byte aligned)
+    t.lds_ev = (size_t)64 * staged;                // one wavefront's events at a time
+    t.lds_acc = lds_acc;
+    t.lds_bytes = t.lds_h + t.lds_ev + t.lds_acc + (size_t)4 * (t.tpr + 1) * sizeof(unsigned);
     t.vec = 0;
     return t;
 }
@@ -176,7 +191,7 @@ inline CurrentLayout current_layout(const Plan& p, const ConvTiling& t, long lon
     c.off_count = 256;                                    // right after the control words: zeroed together
     c.off_offs = a256(c.off_count + t.n_bins * sizeof(unsigned));
     c.off_bsum = a256(c.off_offs + (t.n_bins + 1) * sizeof(unsigned));
-    c.off_mask = a256(c.off_bsum + ((t.n_bins + 4095) / 4096) * sizeof(unsigned));
+    c.off_mask = a256(c.off_bsum + ((t.n_bins + 4095) / 4096) * sizeof(unsigned long long));
     c.off_events = a256(c.off_mask + (size_t)n_carriers * t.n_chunks * sizeof(unsigned long long));
     c.fixed_bytes = c.off_events;
     (void)p;
@@ -184,10 +199,13 @@ inline CurrentLayout current_layout(const Plan& p, const ConvTiling& t, long lon
 }
 // Bytes of one binned event (precision 0: double).
 inline size_t current_event_bytes(const Plan& p) { return p.precision == 0 ? 64 : 32; }
-// d_ws may be null (then one wavefront per carrier, no binning).
+// d_ws may be null (then one wavefront per carrier, no binning).  phase 1:
+// zero the output and bin the events; phase 2 (after phase 1 on the same
+// stream): accumulate.  form: 0 binned from kBinnedMinSteps polyline steps
+// on, 1 binned whenever there is a workspace, 2 never binned.
 hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks,
                           const void* pos, const void* charge, const int* track,
-                          void* ws, size_t ws_bytes, void* out, hipStream_t s);
+                          void* ws, size_t ws_bytes, void* out, hipStream_t s, int phase, int form);
 // Adjoint: lattice-sum derivatives (d/d collocation offset, d/d source width)
 // into gd; transposed boundary-fit solves with right-hand sides rhs into lam;
 // the event projection to dL/dq(w) (right-hand sides) and the final

@@ -43,8 +43,10 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kMaxJ = kMaxTime / kWave;
-constexpr int kSlots = 48;             // track accumulators per wavefront of k_conv_tiles
+constexpr int kSlots = kConvSlots;     // track accumulators of a workgroup of k_conv_tiles
 constexpr int kScanItems = 4096;       // bin counts per workgroup of the scan
+constexpr unsigned long long kBinnedMinSteps = 1ull << 24;   // polyline steps from which wt_current bins
+
 constexpr int kScanThreads = 1024;
 
 template <typename T>
@@ -297,16 +299,22 @@ struct alignas(16) EvRec {
     T g[3];
 };
 
-// An event as one node column of k_conv_tiles uses it: slot of its lower
-// z-corner in the staged tile and step (zm = zl | m << 16), track, and
-// -q dx times the trilinear weights of its two corners in this column.
+// An event as one node column of k_conv_tiles uses it: off = byte offset in
+// the staged rows of lag 0 - m of its lower z-corner (lane n reads
+// off + n * sizeof(Lag4), the upper corner one row further), row = the byte
+// offset of that row (lanes before the step read its zero positions);
+// info = the accumulator slot of its track (kSlots: none) | 64 if it is the
+// last event of its track's run | track << 8; and -q dx times the trilinear
+// weights of its two corners in this column.
 template <typename T>
 struct alignas(16) Staged {
-    int zm;
-    int track;
+    int off;
+    int row;
+    int info;
     T g0[3];
     T g1[3];
 };
+constexpr int kLastOfRun = 64;
 
 // One lag of one staged node: the three components and a zero.
 template <typename TH>
@@ -335,10 +343,12 @@ __device__ inline void load_lag(const Lag4<TH>* a, T& x, T& y, T& z) {
 // (the direct form then runs), [2] the event capacity.
 __global__ void k_set_capacity(unsigned long long* ctl, unsigned long long cap) { ctl[2] = cap; }
 
+// One wavefront per (carrier, 64 steps): the bit mask of the steps that are
+// events, and one count per event in its bin.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_ev_count(Plan p, ConvTiling tl, int n_carriers, int n_tracks, const T* pos, const int* track,
-           unsigned long long* mask, unsigned* count, unsigned long long* ctl) {
+           unsigned long long* mask, unsigned* count) {
     const int lane = threadIdx.x & (kWave - 1);
     const size_t wave = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     const size_t c = wave / tl.n_chunks;
@@ -356,42 +366,42 @@ k_ev_count(Plan p, ConvTiling tl, int n_carriers, int n_tracks, const T* pos, co
         bin = ((unsigned)x0 * p.N[1] + y0) * tl.n_zt + z0 / tl.zt;
     }
     const unsigned long long bal = __ballot(ev);
-    if (lane == 0) {
-        mask[wave] = bal;
-        if (bal) atomicAdd(ctl, (unsigned long long)__popcll(bal));
-    }
+    if (lane == 0) mask[wave] = bal;
     if (ev) atomicAdd(count + bin, 1u);
 }
 
 // Inclusive scan of one value per thread over the workgroup (LDS scratch of
-// one int per wavefront, plus one).
-__device__ inline unsigned block_scan(unsigned v, unsigned* wsum, unsigned* total) {
+// one value per wavefront); *total receives the workgroup's sum.
+template <typename U>
+__device__ inline U block_scan(U v, U* wsum, U* total) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
-        const unsigned u = __shfl_up(v, d, kWave);
+        const U u = __shfl_up(v, d, kWave);
         if (lane >= d) v += u;
     }
     if (lane == kWave - 1) wsum[w] = v;
     __syncthreads();
     if (w == 0) {
-        unsigned s = lane < nw ? wsum[lane] : 0u;
+        U s = lane < nw ? wsum[lane] : (U)0;
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) {
-            const unsigned u = __shfl_up(s, d, kWave);
+            const U u = __shfl_up(s, d, kWave);
             if (lane >= d) s += u;
         }
         if (lane < nw) wsum[lane] = s;
         if (lane == nw - 1) *total = s;
     }
     __syncthreads();
-    return v + (w > 0 ? wsum[w - 1] : 0u);
+    return v + (w > 0 ? wsum[w - 1] : (U)0);
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const unsigned* count, size_t n, unsigned* bsum) {
-    __shared__ unsigned s[kScanThreads];
+// Sum of each workgroup's 4096 bin counts (64-bit).
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_reduce(const unsigned* count, size_t n, unsigned long long* bsum) {
+    __shared__ unsigned long long s[kScanThreads];
     const size_t base = (size_t)blockIdx.x * kScanItems;
-    unsigned v = 0;
+    unsigned long long v = 0;
     for (int k = 0; k < kScanItems / kScanThreads; ++k) {
         const size_t i = base + (size_t)k * kScanThreads + threadIdx.x;
         if (i < n) v += count[i];
@@ -405,26 +415,31 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const unsigned* co
     if (threadIdx.x == 0) bsum[blockIdx.x] = s[0];
 }
 
-// One workgroup: exclusive scan of the block sums in place; the overflow
-// flag when the events exceed the capacity.
-__global__ void __launch_bounds__(kScanThreads) k_scan_top(unsigned* bsum, int nb, unsigned long long* ctl) {
-    __shared__ unsigned wsum[kScanThreads / kWave];
-    __shared__ unsigned total;
-    unsigned carry = 0;
+// One workgroup: exclusive scan of the block sums in place, the number of
+// events, and the overflow flag when they exceed the capacity.
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_top(unsigned long long* bsum, int nb, unsigned long long* ctl) {
+    __shared__ unsigned long long wsum[kScanThreads / kWave];
+    __shared__ unsigned long long total;
+    unsigned long long carry = 0;
     for (int b0 = 0; b0 < nb; b0 += kScanThreads) {
         const int i = b0 + threadIdx.x;
-        const unsigned v = i < nb ? bsum[i] : 0u;
-        const unsigned inc = block_scan(v, wsum, &total);
+        const unsigned long long v = i < nb ? bsum[i] : 0ull;
+        const unsigned long long inc = block_scan(v, wsum, &total);
         if (i < nb) bsum[i] = carry + inc - v;
         carry += total;
         __syncthreads();
     }
-    if (threadIdx.x == 0) ctl[1] = ctl[0] > ctl[2] ? 1ull : 0ull;
+    if (threadIdx.x == 0) {
+        ctl[0] = carry;
+        ctl[1] = carry > ctl[2] ? 1ull : 0ull;
+    }
 }
 
-// offs[i] = exclusive prefix of count, for i < n; offs[n] = the total.
+// offs[i] = exclusive prefix of count, for i < n; offs[n] = the total
+// (32-bit: only used when the events fit the capacity, below 2^32).
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_apply(const unsigned* count, size_t n, const unsigned* bsum, unsigned* offs) {
+k_scan_apply(const unsigned* count, size_t n, const unsigned long long* bsum, unsigned* offs) {
     __shared__ unsigned wsum[kScanThreads / kWave];
     __shared__ unsigned total;
     constexpr int per = kScanItems / kScanThreads;
@@ -436,7 +451,7 @@ k_scan_apply(const unsigned* count, size_t n, const unsigned* bsum, unsigned* of
         v[k] = base + k < n ? count[base + k] : 0u;
         sum += v[k];
     }
-    unsigned run = block_scan(sum, wsum, &total) - sum + bsum[blockIdx.x];
+    unsigned run = block_scan(sum, wsum, &total) - sum + (unsigned)bsum[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < per; ++k) {
         if (base + k < n) offs[base + k] = run;
@@ -446,6 +461,8 @@ k_scan_apply(const unsigned* count, size_t n, const unsigned* bsum, unsigned* of
     if (base < n && base + per >= n) offs[n] = run;
 }
 
+// One wavefront per (carrier, 64 steps) again: every event written into its
+// bin (the order inside a bin is not fixed).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charge, const int* track,
@@ -479,109 +496,161 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
     ev[slot] = r;
 }
 
-// The per-track accumulators of a lane are registers: every access below
-// uses a compile-time index (recursion instead of loops), so that the array
-// is split into registers before any pass could merge the accesses into a
-// run-time index (which would put it in scratch memory).
-// acc[s] += v for a slot s that is the same on every lane: a switch written
-// out in the kernel body (a helper function's cases would be merged into one
-// access at a run-time index before it is inlined).
-#define WT_SLOT_CASE(k) \
-    case k: \
-        acc[k] += cur; \
-        break;
-#define WT_SLOT_CASES8(b)                                                                                           \
-    WT_SLOT_CASE(b) WT_SLOT_CASE(b + 1) WT_SLOT_CASE(b + 2) WT_SLOT_CASE(b + 3) WT_SLOT_CASE(b + 4)                 \
-    WT_SLOT_CASE(b + 5) WT_SLOT_CASE(b + 6) WT_SLOT_CASE(b + 7)
+// Geometry of the staged z-tile of a node column: nodes zb .. zb + ns - 1
+// (node N_z read as node 0), time blocks of TB samples (nb of them, the last
+// last_len long) of the H layout H[x][y][tb][z][tin][a].
+struct TileGeom {
+    int zb, ns, nb, TB, last_len;
+};
 
-template <int S, typename T>
-__device__ __attribute__((always_inline)) inline void zero_slots(T (&acc)[kSlots]) {
-    if constexpr (S < kSlots) {
-        acc[S] = (T)0;
-        zero_slots<S + 1>(acc);
-    }
-}
-
-// out[track of slot S][n] += acc[S] * dec for every used slot.
-template <int S, typename T>
-__device__ __attribute__((always_inline)) inline void flush_slots(const T (&acc)[kSlots], const int* table, int n,
-                                                                  int nt, int n_tracks, T dec, T* out) {
-    if constexpr (S < kSlots) {
-        const int trk = table[S];
-        if (trk >= 0 && trk < n_tracks && n < nt && acc[S] != (T)0) atomicAdd(out + (size_t)trk * nt + n, acc[S] * dec);
-        flush_slots<S + 1>(acc, table, n, nt, n_tracks, dec, out);
-    }
-}
-
-// Stage the lag series of nodes z0 .. z0 + ns - 1 (node N_z read as node 0)
-// of node column col into LDS rows of SL lags (lag t at row position 64 + t).
-// The H layout is time-blocked: block tb of a column holds, for every z, the
-// block's len samples x 3 components contiguously.  Full blocks of TBC
-// samples whose values are 16-byte aligned (vec) move as 16-byte words.
+// One (node, time block) unit per thread: its TBC x 3 values, prefetched in
+// registers as 16-byte words when the block is full and aligned.
 template <int TBC, typename TH>
-__device__ inline void stage_tile(const Plan& p, const ConvTiling& tl, const TH* H, size_t col, int z0, int ns,
-                                  Lag4<TH>* hs) {
-    const int nt = p.n_time, Nz = p.N[2], TB = p.tb;
-    const int nb = (nt + TB - 1) / TB, last_len = nt - (nb - 1) * TB;
-    const TH* cb = H + col * (size_t)Nz * nt * 3;
-    const int units = ns * nb;
+struct HPrefetch {
+    static constexpr int kWords = TBC > 0 ? TBC * 3 * (int)sizeof(TH) / 16 : 1;
+    uint4 w[kWords];
+    bool full;
+};
+
+template <int TBC, typename TH>
+__device__ inline const TH* unit_src(const Plan& p, const TH* colH, const TileGeom& g, int s, int tb, int& len) {
+    int z = g.zb + s;
+    if (z >= p.N[2]) z -= p.N[2];
+    len = tb == g.nb - 1 ? g.last_len : g.TB;
+    return colH + (size_t)tb * g.TB * p.N[2] * 3 + (size_t)z * len * 3;
+}
+
+// The loads are unconditional (a unit that is not a full block loads the
+// column's first block instead and is marked not full), so that their
+// registers are written by the loads alone and nothing waits for them before
+// the next tile commits them.
+template <int TBC, typename TH>
+__device__ inline void prefetch_h(const Plan& p, const TH* colH, const TileGeom& g, HPrefetch<TBC, TH>& pf) {
+    if constexpr (TBC > 0) {
+        int s = (int)threadIdx.x % g.ns, tb = (int)threadIdx.x / g.ns;
+        pf.full = tb < g.nb && (tb < g.nb - 1 || g.last_len == TBC);
+        if (!pf.full) s = tb = 0;                      // block 0 is a full block of TBC samples
+        int len;
+        const uint4* s4 = reinterpret_cast<const uint4*>(unit_src<TBC>(p, colH, g, s, tb, len));
+#pragma unroll
+        for (int k = 0; k < HPrefetch<TBC, TH>::kWords; ++k) pf.w[k] = s4[k];
+    } else {
+        pf.full = false;
+    }
+}
+
+// Write the tile's lag series into the LDS rows (lag t at row position 64 + t):
+// the prefetched unit of this thread from registers, every other unit
+// (partial last blocks, unaligned layouts, blocks not a compile-time size)
+// value by value from global memory.
+template <int TBC, typename TH>
+__device__ inline void commit_h(const Plan& p, const ConvTiling& tl, const TH* colH, const TileGeom& g,
+                                const HPrefetch<TBC, TH>& pf, Lag4<TH>* hs) {
+    const int units = g.ns * g.nb;
     for (int u = threadIdx.x; u < units; u += blockDim.x) {
-        const int s = u % ns, tb = u / ns;
-        int z = z0 + s;
-        if (z >= Nz) z -= Nz;
-        const int len = tb == nb - 1 ? last_len : TB;
-        const TH* src = cb + (size_t)tb * TB * Nz * 3 + (size_t)z * len * 3;
-        Lag4<TH>* dst = hs + s * tl.sl + 64 + tb * TB;
-        constexpr int kVecVals = 16 / sizeof(TH);
-        if (TBC > 0 && tl.vec && len == TBC && (TBC * 3) % kVecVals == 0) {
-            constexpr int nv = TBC * 3 / kVecVals;
-            union {
-                uint4 w[nv];
-                TH h[TBC * 3];
-            } buf;
-            const uint4* s4 = reinterpret_cast<const uint4*>(src);
+        const int s = u % g.ns, tb = u / g.ns;
+        Lag4<TH>* dst = hs + s * tl.sl + 64 + tb * g.TB;
+        if constexpr (TBC > 0) {
+            if (u == (int)threadIdx.x && pf.full) {
+                union {
+                    uint4 w[HPrefetch<TBC, TH>::kWords];
+                    TH h[TBC * 3];
+                } buf;
 #pragma unroll
-            for (int k = 0; k < nv; ++k) buf.w[k] = s4[k];
+                for (int k = 0; k < HPrefetch<TBC, TH>::kWords; ++k) buf.w[k] = pf.w[k];
 #pragma unroll
-            for (int i = 0; i < TBC; ++i) {
-                Lag4<TH> l;
-                l.v[0] = buf.h[3 * i];
-                l.v[1] = buf.h[3 * i + 1];
-                l.v[2] = buf.h[3 * i + 2];
-                l.v[3] = (TH)0;
-                dst[i] = l;
+                for (int i = 0; i < TBC; ++i) {
+                    Lag4<TH> l;
+                    l.v[0] = buf.h[3 * i];
+                    l.v[1] = buf.h[3 * i + 1];
+                    l.v[2] = buf.h[3 * i + 2];
+                    l.v[3] = (TH)0;
+                    dst[i] = l;
+                }
+                continue;
             }
-        } else {
-            for (int i = 0; i < len; ++i) {
-                Lag4<TH> l;
-                l.v[0] = src[3 * i];
-                l.v[1] = src[3 * i + 1];
-                l.v[2] = src[3 * i + 2];
-                l.v[3] = (TH)0;
-                dst[i] = l;
-            }
+        }
+        int len;
+        const TH* src = unit_src<TBC>(p, colH, g, s, tb, len);
+        for (int i = 0; i < len; ++i) {
+            Lag4<TH> l;
+            l.v[0] = src[3 * i];
+            l.v[1] = src[3 * i + 1];
+            l.v[2] = src[3 * i + 2];
+            l.v[3] = (TH)0;
+            dst[i] = l;
         }
     }
 }
 
+// Contribution of a staged event for this lane's sample (nb = the lane's
+// byte offset n * sizeof(Lag4), slb = the bytes of one row).
+template <typename T, typename TH>
+__device__ __attribute__((always_inline)) inline T event_value(const Staged<T>& se, const unsigned char* hs, int nb,
+                                                               int slb) {
+    const int a0 = max(nb + se.off, se.row);
+    T x0, y0, z0, x1, y1, z1;
+    load_lag(reinterpret_cast<const Lag4<TH>*>(hs + a0), x0, y0, z0);
+    load_lag(reinterpret_cast<const Lag4<TH>*>(hs + a0 + slb), x1, y1, z1);
+    T v = se.g0[0] * x0;
+    v += se.g0[1] * y0;
+    v += se.g0[2] * z0;
+    v += se.g1[0] * x1;
+    v += se.g1[1] * y1;
+    v += se.g1[2] * z1;
+    return v;
+}
+
+// One workgroup per (node column, range of z-tiles); lanes own output
+// samples n = 64 w + lane.  Per z-tile with events: the tile's lag series in
+// LDS (prefetched during the previous tile); its events (the four
+// neighbouring cell columns' bins), 64 at a time, staged by the first
+// wavefront with their two z-corner weights in this column and grouped by
+// track with ballots (runs of one track, each with an accumulator slot);
+// then every wavefront walks every event, four at a time, and adds a run's
+// sum to its track's accumulator in LDS when the run ends (the lanes own
+// their samples, so no two lanes touch one accumulator).  The accumulators go
+// to the output once, when the workgroup ends.
 template <int TBC, typename T, typename TH>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_conv_tiles(Plan p, ConvTiling tl, const TH* H, const float* decode, const unsigned* offs, const EvRec<T>* ev,
              const unsigned long long* ctl, int n_tracks, T* out) {
     if (ctl[1] != 0ull) return;                        // the direct form takes these events
     extern __shared__ __align__(16) unsigned char smem[];
     Lag4<TH>* hs = reinterpret_cast<Lag4<TH>*>(smem);                             // [zt + 1][sl]
-    Staged<T>* st = reinterpret_cast<Staged<T>*>(smem + tl.lds_h);               // [threads]
-    unsigned* boffs = reinterpret_cast<unsigned*>(smem + tl.lds_h + tl.lds_ev);  // [4][n_zt + 1]
+    Staged<T>* st = reinterpret_cast<Staged<T>*>(smem + tl.lds_h);               // [64]
+    T* acc = reinterpret_cast<T*>(smem + tl.lds_h + tl.lds_ev);                  // [kSlots][threads]
+    unsigned* boffs = reinterpret_cast<unsigned*>(smem + tl.lds_h + tl.lds_ev + tl.lds_acc);   // [4][tpr + 1]
     __shared__ int s_table[kSlots];
-    __shared__ int s_cnt[kSlots + 1], s_base[kSlots + 1];
-    __shared__ int s_nruns, s_run_key[kSlots + 1], s_run_beg[kSlots + 1], s_run_end[kSlots + 1];
+    __shared__ int s_nstaged;
 
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int n = tid;                                  // this thread's output sample
     const int nt = p.n_time, Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
     const int ZT = tl.zt, SL = tl.sl, nzt = tl.n_zt;
+    const int col = blockIdx.x / tl.n_zr, zr = blockIdx.x - col * tl.n_zr;
+    const int x = col / Ny, y = col - x * Ny;
+    const int tA = zr * tl.tpr, tB = min(nzt, tA + tl.tpr), nr = tB - tA;
+    if (nr <= 0) return;
+    const int R = nr + 1;
+    // bin offsets of the four cell columns with a corner on node column
+    // (x, y) (q = 2 qx + qy: cell x = x - 1 + qx, cell y = y - 1 + qy), tiles tA .. tB
+    for (int i = tid; i < 4 * R; i += nthr) {
+        const int q = i / R, k = i - q * R;
+        const int cx = (q >> 1) ? x : (x == 0 ? Nx - 1 : x - 1);
+        const int cy = (q & 1) ? y : (y == 0 ? Ny - 1 : y - 1);
+        boffs[i] = offs[((size_t)cx * Ny + cy) * nzt + tA + k];
+    }
     for (int s = tid; s < kSlots; s += nthr) s_table[s] = -1;
+    __syncthreads();
+    auto count_of = [&](int k) -> unsigned {
+        return (boffs[k + 1] - boffs[k]) + (boffs[R + k + 1] - boffs[R + k]) + (boffs[2 * R + k + 1] - boffs[2 * R + k]) +
+               (boffs[3 * R + k + 1] - boffs[3 * R + k]);
+    };
+    if (boffs[nr] - boffs[0] + boffs[R + nr] - boffs[R] + boffs[2 * R + nr] - boffs[2 * R] + boffs[3 * R + nr] -
+            boffs[3 * R] ==
+        0u)
+        return;                                          // no event touches this range
     // the lags outside [0, nt) of every staged row read as zero: lanes before
     // an event's step and lanes past the last sample touch them
     for (int i = tid; i < (ZT + 1) * SL; i += nthr) {
@@ -592,171 +661,174 @@ k_conv_tiles(Plan p, ConvTiling tl, const TH* H, const float* decode, const unsi
             hs[i] = z;
         }
     }
-    T acc[kSlots];
-    zero_slots<0>(acc);
-    const int bx = blockIdx.x / tl.nby, by = blockIdx.x - bx * tl.nby;
-    const int xe = min(Nx, (bx + 1) * tl.bx), ye = min(Ny, (by + 1) * tl.by);
-    for (int x = bx * tl.bx; x < xe; ++x) {
-        for (int y = by * tl.by; y < ye; ++y) {
-            // the four cell columns with a corner on node column (x, y):
-            // q = 2 qx + qy, cell x = x - 1 + qx, cell y = y - 1 + qy
-            __syncthreads();
-            for (int i = tid; i < 4 * (nzt + 1); i += nthr) {
-                const int q = i / (nzt + 1), k = i - q * (nzt + 1);
-                const int cx = (q >> 1) ? x : (x == 0 ? Nx - 1 : x - 1);
-                const int cy = (q & 1) ? y : (y == 0 ? Ny - 1 : y - 1);
-                boffs[i] = offs[((size_t)cx * Ny + cy) * nzt + k];
-            }
-            __syncthreads();
-            for (int zt = nzt - 1; zt >= 0; --zt) {
-                // events of the four bins: [pre_q, pre_{q+1}) of the staging order
-                const unsigned b0 = boffs[zt], b1 = boffs[(nzt + 1) + zt], b2 = boffs[2 * (nzt + 1) + zt],
-                               b3 = boffs[3 * (nzt + 1) + zt];
-                const unsigned pre1 = boffs[zt + 1] - b0;
-                const unsigned pre2 = pre1 + (boffs[(nzt + 1) + zt + 1] - b1);
-                const unsigned pre3 = pre2 + (boffs[2 * (nzt + 1) + zt + 1] - b2);
-                const int E = (int)(pre3 + (boffs[3 * (nzt + 1) + zt + 1] - b3));
-                if (E == 0) continue;
-                const int zb = zt * ZT;
-                const int ns = min(ZT, Nz - zb) + 1;
-                stage_tile<TBC>(p, tl, H, (size_t)x * Ny + y, zb, ns, hs);
-                for (int e0 = 0; e0 < E; e0 += nthr) {
-                    if (tid <= kSlots) s_cnt[tid] = 0;
-                    __syncthreads();
-                    // stage event e0 + tid: its two corners in this column
-                    const int i = e0 + tid;
-                    int key = 0, rank = 0;
-                    Staged<T> sr;
-                    if (i < E) {
-                        const unsigned ui = (unsigned)i;
-                        const int q = (ui >= pre1) + (ui >= pre2) + (ui >= pre3);
-                        const unsigned src = q == 0 ? b0 + ui : q == 1 ? b1 + (ui - pre1)
-                                                              : q == 2 ? b2 + (ui - pre2) : b3 + (ui - pre3);
-                        const EvRec<T> r = ev[src];
-                        const T wx = (q >> 1) ? (T)1 - r.f[0] : r.f[0];
-                        const T wy = (q & 1) ? (T)1 - r.f[1] : r.f[1];
-                        const T w1 = wx * wy * r.f[2], w0 = wx * wy * ((T)1 - r.f[2]);
-                        const int zl = (int)(r.zm & 0xffffu) - zb;
-                        sr.zm = zl | (int)(r.zm & 0xffff0000u);
-                        sr.track = r.track;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            sr.g0[a] = r.g[a] * w0;
-                            sr.g1[a] = r.g[a] * w1;
-                        }
-                        // the track's accumulator slot; slots fill from 0 up
-                        int slot = -1;
-                        for (int s = 0; s < kSlots; ++s) {
-                            const int t = s_table[s];
-                            if (t == r.track) {
-                                slot = s;
-                                break;
-                            }
-                            if (t == -1) break;
-                        }
-                        if (slot < 0) {
-                            for (int s = 0; s < kSlots; ++s) {
-                                const int old = atomicCAS(&s_table[s], -1, r.track);
-                                if (old == -1 || old == r.track) {
-                                    slot = s;
-                                    break;
-                                }
-                            }
-                        }
-                        key = slot < 0 ? kSlots : slot;
-                        rank = atomicAdd(&s_cnt[key], 1);
-                    }
-                    __syncthreads();
-                    // counting sort by slot: bases and the list of runs
-                    if (w == 0) {
-                        const int c = lane <= kSlots ? s_cnt[lane] : 0;
-                        int incl = c;
+    for (int s = 0; s < kSlots; ++s) acc[s * nthr + n] = (T)0;
+    const TH* colH = H + (size_t)col * Nz * nt * 3;
+    const int nb = (nt + p.tb - 1) / p.tb;
+    constexpr int LB = (int)sizeof(Lag4<TH>);
+    const int slb = SL * LB;
+    const int nbyte = n * LB;
+    auto geom = [&](int k) {
+        TileGeom g;
+        g.zb = (tA + k) * ZT;
+        g.ns = min(ZT, Nz - g.zb) + 1;
+        g.nb = nb;
+        g.TB = p.tb;
+        g.last_len = nt - (nb - 1) * p.tb;
+        return g;
+    };
+    // event i of tile k: which of the four bins (q), and its record
+    auto locate = [&](int k, unsigned i, int& q) -> unsigned {
+        const unsigned b0 = boffs[k], b1 = boffs[R + k], b2 = boffs[2 * R + k], b3 = boffs[3 * R + k];
+        const unsigned pre1 = boffs[k + 1] - b0;
+        const unsigned pre2 = pre1 + (boffs[R + k + 1] - b1);
+        const unsigned pre3 = pre2 + (boffs[2 * R + k + 1] - b2);
+        q = (i >= pre1) + (i >= pre2) + (i >= pre3);
+        return q == 0 ? b0 + i : q == 1 ? b1 + (i - pre1) : q == 2 ? b2 + (i - pre2) : b3 + (i - pre3);
+    };
+    T dec = (T)1;
+    if constexpr (!std::is_same<T, TH>::value) dec = (T)decode[0];
+
+    int k = nr - 1;
+    while (k >= 0 && count_of(k) == 0u) --k;
+    HPrefetch<TBC, TH> pf;
+    prefetch_h<TBC>(p, colH, geom(k), pf);
+    // the first wavefront holds the next 64 events of the tile in its lanes
+    EvRec<T> rnext;
+    int qnext = 0;
+    if (w == 0 && (unsigned)lane < count_of(k)) rnext = ev[locate(k, (unsigned)lane, qnext)];
+    while (k >= 0) {
+        int kn = k - 1;
+        while (kn >= 0 && count_of(kn) == 0u) --kn;
+        const TileGeom g = geom(k);
+        const unsigned E = count_of(k);
+        __syncthreads();                                 // the previous tile's rows and events are read
+        commit_h<TBC>(p, tl, colH, g, pf, hs);
+        if (kn >= 0) prefetch_h<TBC>(p, colH, geom(kn), pf);   // lands while this tile is processed
+        for (unsigned e0 = 0; e0 < E; e0 += kWave) {
+            if (e0 > 0) __syncthreads();                 // the previous chunk's events are read
+            if (w == 0) {
+                // stage events e0 .. e0 + 63 of this tile, grouped by track
+                const unsigned i = e0 + (unsigned)lane;
+                const bool have = i < E;
+                EvRec<T> r = rnext;
+                int q = qnext;
+                if (e0 > 0 && have) r = ev[locate(k, i, q)];
+                Staged<T> sr;
+                if (have) {
+                    const T wx = (q >> 1) ? (T)1 - r.f[0] : r.f[0];
+                    const T wy = (q & 1) ? (T)1 - r.f[1] : r.f[1];
+                    const T w1 = wx * wy * r.f[2], w0 = wx * wy * ((T)1 - r.f[2]);
+                    const int zl = (int)(r.zm & 0xffffu) - g.zb;
+                    const int m = (int)(r.zm >> 16);
+                    sr.row = zl * slb;
+                    sr.off = sr.row + (64 - m) * LB;
 #pragma unroll
-                        for (int d = 1; d < kWave; d <<= 1) {
-                            const int u = __shfl_up(incl, d, kWave);
-                            if (lane >= d) incl += u;
-                        }
-                        if (lane <= kSlots) s_base[lane] = incl - c;
-                        const unsigned long long live = __ballot(c > 0);
-                        if (c > 0) {
-                            const int r = __popcll(live & ((1ull << lane) - 1ull));
-                            s_run_key[r] = lane;
-                            s_run_beg[r] = incl - c;
-                            s_run_end[r] = incl;
-                        }
-                        if (lane == 0) s_nruns = __popcll(live);
+                    for (int a = 0; a < 3; ++a) {
+                        sr.g0[a] = r.g[a] * w0;
+                        sr.g1[a] = r.g[a] * w1;
                     }
-                    __syncthreads();
-                    if (i < E) st[s_base[key] + rank] = sr;
-                    __syncthreads();
-                    // every wavefront walks every run; lanes own samples
-                    const int nruns = s_nruns;
-                    const int wlast = __builtin_amdgcn_readfirstlane(kWave * w + kWave - 1);
-                    for (int r = 0; r < nruns; ++r) {
-                        const int key_r = __builtin_amdgcn_readfirstlane(s_run_key[r]);
-                        const int beg = __builtin_amdgcn_readfirstlane(s_run_beg[r]);
-                        const int end = __builtin_amdgcn_readfirstlane(s_run_end[r]);
-                        const bool spill = key_r == kSlots;     // tracks without a slot
-                        T cur = (T)0;
-                        for (int k = beg; k < end; ++k) {
-                            const Staged<T> e = st[k];
-                            const int zm = __builtin_amdgcn_readfirstlane(e.zm);
-                            const int m = zm >> 16;
-                            if (wlast < m) continue;
-                            const int zl = zm & 0xffff;
-                            const Lag4<TH>* a = hs + zl * SL + 64 + n - m;
-                            T x0, y0, z0, x1, y1, z1;
-                            load_lag(a, x0, y0, z0);
-                            load_lag(a + SL, x1, y1, z1);
-                            T v = e.g0[0] * x0;
-                            v += e.g0[1] * y0;
-                            v += e.g0[2] * z0;
-                            v += e.g1[0] * x1;
-                            v += e.g1[1] * y1;
-                            v += e.g1[2] * z1;
-                            if (spill) {
-                                const int trk = __builtin_amdgcn_readfirstlane(e.track);
-                                T vv = v;
-                                if constexpr (!std::is_same<T, TH>::value) vv *= (T)decode[0];
-                                if (n < nt && vv != (T)0) atomicAdd(out + (size_t)trk * nt + n, vv);
-                            } else {
-                                cur += v;
-                            }
-                        }
-                        static_assert(kSlots == 48, "the switch below lists 48 slots");
-                        if (!spill) {
-                            switch (key_r) {
-                                WT_SLOT_CASES8(0)
-                                WT_SLOT_CASES8(8)
-                                WT_SLOT_CASES8(16)
-                                WT_SLOT_CASES8(24)
-                                WT_SLOT_CASES8(32)
-                                WT_SLOT_CASES8(40)
-                                default: break;
-                            }
+                }
+                const int trk = have ? r.track : -1;
+                int tab = lane < kSlots ? s_table[lane] : -2;     // the slot table, one entry per lane
+                unsigned long long pending = __ballot(have);
+                const unsigned long long lt = (1ull << lane) - 1ull;
+                int base = 0, pos = 0;
+                while (pending) {
+                    const int tk = __builtin_amdgcn_readlane(trk, (int)__builtin_ctzll(pending));
+                    const unsigned long long same = __ballot(trk == tk) & pending;
+                    const unsigned long long hit = __ballot(tab == tk);
+                    int slot;
+                    if (hit) {
+                        slot = (int)__builtin_ctzll(hit);
+                    } else {
+                        const unsigned long long fr = __ballot(tab == -1);
+                        slot = fr ? (int)__builtin_ctzll(fr) : kSlots;
+                        if (slot < kSlots && lane == slot) {
+                            tab = tk;
+                            s_table[slot] = tk;
                         }
                     }
-                    __syncthreads();
+                    const int cnt = __popcll(same);
+                    if ((same >> lane) & 1ull) {
+                        pos = base + __popcll(same & lt);
+                        sr.info = slot | (pos == base + cnt - 1 ? kLastOfRun : 0) | (tk << 8);
+                    }
+                    base += cnt;
+                    pending &= ~same;
+                }
+                if (have) st[pos] = sr;
+                if (lane == 0) s_nstaged = base;
+                // the next 64 events (of this tile, else of the next one)
+                const unsigned inext = e0 + kWave + (unsigned)lane;
+                if (e0 + kWave < E) {
+                    if (inext < E) rnext = ev[locate(k, inext, qnext)];
+                } else if (kn >= 0 && (unsigned)lane < count_of(kn)) {
+                    rnext = ev[locate(kn, (unsigned)lane, qnext)];
                 }
             }
+            __syncthreads();
+            // every wavefront walks every event, four at a time; a track's
+            // sum goes to its accumulator after the last event of its run
+            const int ne = s_nstaged;
+            const unsigned char* hb = reinterpret_cast<const unsigned char*>(hs);
+            T cur = (T)0;
+            auto close = [&](int info) {
+                if (!(info & kLastOfRun)) return;
+                const int slot = info & 63;
+                if (slot == kSlots) {                    // a track without a slot
+                    if (n < nt && cur != (T)0) atomicAdd(out + (size_t)(info >> 8) * nt + n, cur * dec);
+                } else {
+                    acc[slot * nthr + n] += cur;
+                }
+                cur = (T)0;
+            };
+            int e = 0;
+            for (; e + 4 <= ne; e += 4) {
+                const Staged<T> s0 = st[e], s1 = st[e + 1], s2 = st[e + 2], s3 = st[e + 3];
+                const T v0 = event_value<T, TH>(s0, hb, nbyte, slb), v1 = event_value<T, TH>(s1, hb, nbyte, slb);
+                const T v2 = event_value<T, TH>(s2, hb, nbyte, slb), v3 = event_value<T, TH>(s3, hb, nbyte, slb);
+                cur += v0;
+                close(__builtin_amdgcn_readfirstlane(s0.info));
+                cur += v1;
+                close(__builtin_amdgcn_readfirstlane(s1.info));
+                cur += v2;
+                close(__builtin_amdgcn_readfirstlane(s2.info));
+                cur += v3;
+                close(__builtin_amdgcn_readfirstlane(s3.info));
+            }
+            for (; e < ne; ++e) {
+                const Staged<T> s0 = st[e];
+                cur += event_value<T, TH>(s0, hb, nbyte, slb);
+                close(__builtin_amdgcn_readfirstlane(s0.info));
+            }
         }
+        k = kn;
     }
     // the per-track sums of this workgroup
     __syncthreads();
-    T dec = (T)1;
-    if constexpr (!std::is_same<T, TH>::value) dec = (T)decode[0];
-    flush_slots<0>(acc, s_table, n, nt, n_tracks, dec, out);
+    for (int s = 0; s < kSlots; ++s) {
+        const int trk = s_table[s];
+        const T v = acc[s * nthr + n];
+        if (trk >= 0 && trk < n_tracks && n < nt && v != (T)0) atomicAdd(out + (size_t)trk * nt + n, v * dec);
+    }
 }
 
+// phase 1: the output zeroed and the events binned; phase 2: the
+// accumulation (binned, or the unbinned kernel when the events did not fit
+// or there is no workspace).  Phase 2 follows phase 1 on the same stream.
 template <typename T, typename TH>
 hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, const void* pos, const void* charge,
-                   const int* track, void* ws, size_t ws_bytes, void* out, hipStream_t s) {
+                   const int* track, void* ws, size_t ws_bytes, void* out, hipStream_t s, int phase, int form) {
     const size_t n_out = (size_t)n_tracks * p.n_time;
-    hipError_t e;
-    const int zgrid = (int)((n_out + kBlock - 1) / kBlock < 4096 ? (n_out + kBlock - 1) / kBlock : 4096);
-    hipLaunchKernelGGL(k_fill_zero<T>, dim3(zgrid > 0 ? zgrid : 1), dim3(kBlock), 0, s, static_cast<T*>(out), n_out);
-    e = hipGetLastError();
-    if (e != hipSuccess || n_carriers == 0) return e;
+    hipError_t e = hipSuccess;
+    if (phase == 1) {
+        const int zgrid = (int)((n_out + kBlock - 1) / kBlock < 4096 ? (n_out + kBlock - 1) / kBlock : 4096);
+        hipLaunchKernelGGL(k_fill_zero<T>, dim3(zgrid > 0 ? zgrid : 1), dim3(kBlock), 0, s, static_cast<T*>(out),
+                           n_out);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (n_carriers == 0) return e;
     const float* decode = reinterpret_cast<const float*>(static_cast<const char*>(h) + p.h_values_bytes);
     ConvTiling tl = conv_tiling(p, sizeof(TH));
     // 16-byte loads of whole time blocks: H and every block of every column aligned
@@ -765,20 +837,27 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
                  ? 1
                  : 0;
     const CurrentLayout cl = current_layout(p, tl, n_carriers);
-    const bool binned = ws != nullptr && ws_bytes >= cl.fixed_bytes + sizeof(EvRec<T>);
     static_assert(sizeof(EvRec<float>) == 32 && sizeof(EvRec<double>) == 64, "event record size");
-    static_assert(sizeof(Staged<float>) == 32 && sizeof(Staged<double>) == 64, "staged event size");
+    static_assert(sizeof(Staged<float>) == 48 && sizeof(Staged<double>) == 64, "staged event size");
+    // per-bin counts are 32-bit: bin only while every step fits them; below
+    // kBinnedMinSteps polyline steps the unbinned kernel is faster (its cost
+    // is the steps that move, the binned form's also the grid's columns and
+    // tiles: at 2e4 carriers x 200 samples, 0.39 against 1.4 ms on one MI355X)
+    const unsigned long long steps = (unsigned long long)n_carriers * p.n_time;
+    const bool binned = ws != nullptr && ws_bytes >= cl.fixed_bytes + sizeof(EvRec<T>) && steps < 0xfffffff0ull &&
+                        form != 2 && (steps >= kBinnedMinSteps || form == 1);
     unsigned long long* ctl = nullptr;
     if (binned) {
         char* b = static_cast<char*>(ws);
         ctl = reinterpret_cast<unsigned long long*>(b + cl.off_ctl);
         unsigned* count = reinterpret_cast<unsigned*>(b + cl.off_count);
         unsigned* offs = reinterpret_cast<unsigned*>(b + cl.off_offs);
-        unsigned* bsum = reinterpret_cast<unsigned*>(b + cl.off_bsum);
+        unsigned long long* bsum = reinterpret_cast<unsigned long long*>(b + cl.off_bsum);
         unsigned long long* mask = reinterpret_cast<unsigned long long*>(b + cl.off_mask);
         EvRec<T>* evs = reinterpret_cast<EvRec<T>*>(b + cl.off_events);
         size_t cap = (ws_bytes - cl.off_events) / sizeof(EvRec<T>);
         if (cap > 0xfffffff0ull) cap = 0xfffffff0ull;
+      if (phase == 1) {
         // control words and bin counts are one zero-filled run (no memset
         // nodes, so the sequence can be captured); then the capacity
         const size_t n_zero = (cl.off_count + tl.n_bins * sizeof(unsigned)) / sizeof(unsigned);
@@ -788,7 +867,7 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
         const size_t waves = (size_t)n_carriers * tl.n_chunks;
         const unsigned grid = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
         hipLaunchKernelGGL(k_ev_count<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers, n_tracks,
-                           static_cast<const T*>(pos), track, mask, count, ctl);
+                           static_cast<const T*>(pos), track, mask, count);
         const unsigned nb = (unsigned)((tl.n_bins + kScanItems - 1) / kScanItems);
         hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, count, tl.n_bins, bsum);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, bsum, (int)nb, ctl);
@@ -796,22 +875,29 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
         hipLaunchKernelGGL(k_ev_scatter<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers,
                            static_cast<const T*>(pos), static_cast<const T*>(charge), track, mask, offs, count, ctl,
                            evs);
+        return hipGetLastError();
+      }
         auto tiles = [&](auto kernel) {
             e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)tl.lds_bytes);
             if (e != hipSuccess) return;
-            hipLaunchKernelGGL(kernel, dim3(tl.nbx * tl.nby), dim3(tl.threads), tl.lds_bytes, s, p, tl,
-                               static_cast<const TH*>(h), decode, offs, evs, ctl, n_tracks, static_cast<T*>(out));
+            hipLaunchKernelGGL(kernel, dim3((unsigned)((size_t)p.N[0] * p.N[1] * tl.n_zr)), dim3(tl.threads),
+                               tl.lds_bytes, s, p, tl, static_cast<const TH*>(h), decode, offs, evs, ctl, n_tracks,
+                               static_cast<T*>(out));
         };
-        if (p.tb == 16)
+        // time blocks of 8 or 16 samples, 16-byte aligned: prefetched in
+        // registers, unless a unit is more than 6 words; otherwise staged
+        // value by value
+        if (tl.vec && p.tb == 16 && 16 * 3 * sizeof(TH) <= 96)
             tiles(k_conv_tiles<16, T, TH>);
-        else if (p.tb == 8)
+        else if (tl.vec && p.tb == 8 && 8 * 3 * sizeof(TH) <= 96)
             tiles(k_conv_tiles<8, T, TH>);
         else
             tiles(k_conv_tiles<0, T, TH>);
         if (e != hipSuccess) return e;
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (phase == 1) return hipSuccess;
     // the carriers of workgroup b come from a permutation of [0, 8 * per_xcd)
     // workgroups (some past the last carrier, which then do nothing)
     const int blocks = (n_carriers + kBlock / kWave - 1) / (kBlock / kWave);
@@ -834,12 +920,14 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
 
 hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks, const void* pos,
                           const void* charge, const int* track, void* ws, size_t ws_bytes, void* out,
-                          hipStream_t s) {
+                          hipStream_t s, int phase, int form) {
     if (p.precision == 0)
-        return current<double, double>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s);
+        return current<double, double>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s, phase,
+                                       form);
     if (p.h_format == 1)
-        return current<float, _Float16>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s);
-    return current<float, float>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s);
+        return current<float, _Float16>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s, phase,
+                                        form);
+    return current<float, float>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s, phase, form);
 }
 
 }  // namespace wt

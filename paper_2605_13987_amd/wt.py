@@ -122,6 +122,7 @@ def _load():
         "wt_h_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_h_report)]),
         "wt_h_solve_static": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, P(wt_h_report)]),
         "wt_current_workspace": (c_int, [c_void_p, c_int, ctypes.c_longlong, P(c_size_t)]),
+        "wt_context_set_current_form": (c_int, [c_void_p, c_int]),
         "wt_current": (c_int, [c_void_p, c_void_p, c_void_p, P(wt_carriers), c_void_p, c_size_t, c_void_p]),
         "wt_electronics": (c_int, [c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                    c_double, c_double, c_void_p, c_void_p]),
@@ -292,6 +293,14 @@ def wt_h_solve_static(ctx, plan, d_h: int, h_bytes: int, report: bool = False, r
     if report:
         out = {name: getattr(rep, name) for name, _ in wt_h_report._fields_}
     return st, out
+
+
+WT_CURRENT_AUTO, WT_CURRENT_BINNED, WT_CURRENT_UNBINNED = 0, 1, 2
+
+
+def wt_context_set_current_form(ctx, form: int):
+    """0: bin from 2^24 polyline steps on; 1: bin whenever given a workspace; 2: never bin."""
+    _check(LIB.wt_context_set_current_form(ctx, int(form)), "wt_context_set_current_form", ctx)
 
 
 def wt_current_workspace(plan, n_carriers: int, max_events: int = 0) -> int:

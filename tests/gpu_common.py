@@ -22,8 +22,12 @@ def dtype_of(precision):
     return torch.float64 if precision == wt.WT_F64 else torch.float32
 
 
-def context():
-    return wt.wt_context_create(0, torch.cuda.current_stream().cuda_stream)
+def context(current_form=wt.WT_CURRENT_BINNED):
+    """A context on the current stream; by default wt_current bins whenever it
+    is given a workspace (so that small test cases run the binned kernels)."""
+    ctx = wt.wt_context_create(0, torch.cuda.current_stream().cuda_stream)
+    wt.wt_context_set_current_form(ctx, current_form)
+    return ctx
 
 
 def solve_h(ctx, cfg, precision, ir_max_iter=2, ir_tol=1e-12, h_format=wt.WT_H_PLAIN, fft_schedule=0):

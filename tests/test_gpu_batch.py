@@ -204,6 +204,7 @@ def test_batch_items_against_the_oracle():
     refs = _oracle_refs(keys)
     stream = torch.cuda.Stream()
     ctx = wt.wt_context_create(0, stream.cuda_stream)
+    wt.wt_context_set_current_form(ctx, wt.WT_CURRENT_BINNED)    # the lanes' currents binned
     all_items = _items()
     items = [all_items[k] for k in keys]
     ws, ws_b, hs, h_b = _lane_buffers(items, 2)

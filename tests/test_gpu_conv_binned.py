@@ -186,6 +186,34 @@ def test_many_tracks_and_crowded_tiles(ctx, precision):
     wt.wt_h_plan_destroy(run["plan"])
 
 
+def test_automatic_form(ctx):
+    """The default form: small inputs are not binned (the workspace's control
+    words stay as the caller left them), the same inputs with the binned form
+    give the same currents."""
+    cfg = workloads.small_pixel(k=79, n_xy=12, n_z=20, n_freq=4, n_time=30, n_pairs=2, n_colloc=6)
+    run, Hs = _synthetic_run(ctx, cfg, wt.WT_F32)
+    car = _random_carriers(cfg, 100, 3, 80, wt.WT_F32)
+    d = {k: torch.from_numpy(np.ascontiguousarray(car[k])).to("cuda") for k in ("pos", "charge", "track")}
+    d["pos"], d["charge"] = d["pos"].float(), d["charge"].float()
+    ws = torch.full((wt.wt_current_workspace(run["plan"], 100),), 0x11, dtype=torch.uint8, device="cuda")
+    outs = {}
+    for form in (wt.WT_CURRENT_AUTO, wt.WT_CURRENT_BINNED):
+        wt.wt_context_set_current_form(ctx, form)
+        o = torch.empty((3, 30), dtype=torch.float32, device="cuda")
+        wt.wt_current(ctx, run["plan"], run["h"].data_ptr(), 100, 3, d["pos"].data_ptr(), d["charge"].data_ptr(),
+                      d["track"].data_ptr(), o.data_ptr(), ws.data_ptr(), ws.numel())
+        torch.cuda.synchronize()
+        outs[form] = o.double().cpu().numpy()
+        if form == wt.WT_CURRENT_AUTO:
+            assert bool(torch.all(ws[:24] == 0x11))             # not binned: workspace untouched
+    wt.wt_context_set_current_form(ctx, wt.WT_CURRENT_BINNED)
+    assert rel_l2(outs[wt.WT_CURRENT_AUTO], outs[wt.WT_CURRENT_BINNED]) <= 1e-5
+    assert rel_l2(outs[wt.WT_CURRENT_BINNED], _oracle(Hs, cfg, car)) <= 1e-4
+    with pytest.raises(wt.WtError):
+        wt.wt_context_set_current_form(ctx, 3)
+    wt.wt_h_plan_destroy(run["plan"])
+
+
 def test_no_carriers_and_no_moving_steps(ctx):
     cfg = workloads.small_pixel(k=77, n_xy=12, n_z=20, n_freq=4, n_time=30, n_pairs=2, n_colloc=6)
     run, _ = _synthetic_run(ctx, cfg, wt.WT_F32)

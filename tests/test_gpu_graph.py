@@ -19,6 +19,7 @@ def test_captured_step_replays_match_eager(h_format, binned):
     cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
     stream = torch.cuda.Stream()
     ctx = wt.wt_context_create(0, stream.cuda_stream)
+    wt.wt_context_set_current_form(ctx, wt.WT_CURRENT_BINNED if binned else wt.WT_CURRENT_AUTO)
     plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, h_format=h_format)
     ws = torch.zeros(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
     h = torch.zeros(lay["h_bytes"], dtype=torch.uint8, device="cuda")

@@ -193,7 +193,7 @@ def test_stage_timing(ctx, px32):
         assert names == ["green_tables", "collocation_solve", "time_transform", "field_table", "synthesis"]
         current(ctx, run, rounded_carriers(px32["carriers"], wt.WT_F32))
         st = wt.wt_context_stage_times(ctx)
-        assert [n for n, _ in st] == ["current"] and st[0][1] > 0
+        assert [n for n, _ in st] == ["current_binning", "current"] and st[0][1] > 0 and st[1][1] > 0
     finally:
         wt.wt_context_enable_timing(ctx, False)
 
