@@ -4,21 +4,28 @@
 One step = the whole hot path on one batch of synthetic input: Green's tables,
 collocation solves for all frequencies, time transform, in-plane field table,
 synthesis of H(x, y, z, t) on the whole grid, and the Eq. 1 current of all
-carriers.  Workload: periodic 50x50x300 um pixel on a 128x128x256 grid, five
-seeded column resistivities, 256 frequencies up to 50 GHz, 200 samples of
-10 ps, one minimum-ionising track along z with 1e4 electron/hole pairs
-(2e4 carriers).  H and the current are computed in float32, the boundary fit
-and time transform in float64.  Inputs are resident on the GPU before timing.
+carriers.  Inputs are resident on the GPU before timing.
+
+Headline workload: periodic 50x50x300 um pixel on a 256x256x512 grid, five
+seeded column resistivities, 512 frequencies up to 50 GHz, 400 samples of
+10 ps, 100 minimum-ionising tracks along z of 5e3 electron/hole pairs each
+(1e6 carriers) drifting with 0.5 um Gaussian diffusion per step.  The mixed
+path (the headline value) stores H as scaled float16 (80.5 GB) and computes
+the FFTs, the synthesis and the convolution in float32; the plain path
+stores H in float32 (161 GB).  The boundary fit and time transform are
+float64 in both.
 
 Prints one JSON line.  value = grid points x frequencies per second of the
-whole step; tracks/s and carriers/s of the current stage are extra fields.
-The same step with H stored as scaled float16 (the mixed-precision path) is
-timed after it and reported under "mixed", with its errors against the FP64
-oracle (H) and the float32 path (the current).
+whole mixed step; the plain step, the 128x128x256 single-track workload
+(float32, float16 and float64 H), the M = 256 boundary fit, the
+electronics, the adjoint, graph replays and the 64-variant batch are extra
+fields.  Every result is given with its error against the FP64 oracle.
 """
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -28,32 +35,48 @@ if ROOT not in sys.path:
 
 METRIC = "H(x,t) grid·freq pts/s + carrier tracks/s, mixed vs plain FP64 at stated rel err"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2605_13987_amd", "csrc")
 
-# HBM bytes per launch of k_synthesis_pipe on this workload (float32, float16 and float64
-# H): rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a 1 GiB
-# device-to-device copy gives for the same counters), in
-# profiles/k_synthesis_pipe_128x128x256.md.  Reported only while the kernel's
-# sources are the ones they were measured on.
-SYNTH_TRAFFIC_BYTES = {"plain": 10170782051, "mixed": 5136826957, "f64": 20341324523}
-SYNTH_TRAFFIC_SOURCES_SHA256 = "82f4e289f86c33a2bdf3830c18ebecad6adeffc91c4ddda78acee6d2c20464d3"
-SYNTH_SOURCES = ("k_bulk.hip", "synth_pipe.hpp", "fft.hpp", "common.hpp")
+# HBM bytes per launch measured by rocprofv3 (FETCH_SIZE x 2.0 + WRITE_SIZE x
+# 1.0, KiB per dispatch x 1024; the factors are what the same counters read
+# for a 1 GiB device-to-device copy in the same runs), with the kernel's
+# sources they were measured on: reported only while those are unchanged.
+# Summaries and commands in profiles/.
+TRAFFIC = {
+    # (kernel, workload key): (bytes per launch, sha256 of the sources)
+}
+KERNEL_SOURCES = {
+    "k_synthesis_pipe": ("k_bulk.hip", "synth_pipe.hpp", "fft.hpp"),
+    "k_conv_tiles": ("k_conv.hip",),
+}
 
 
-def synthesis_sources_sha256():
-    import hashlib
+def sources_sha256(kernel):
     h = hashlib.sha256()
-    for name in SYNTH_SOURCES:
-        with open(os.path.join(ROOT, "paper_2605_13987_amd", "csrc", name), "rb") as fh:
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def current_compulsory_bytes_device(pos, cell, n_tracks, nt, elem_bytes, torch, chunk=1 << 17):
-    """``current_compulsory_bytes`` for carriers held on the device (torch),
-    in chunks of carriers.  Returns (bytes, moving steps)."""
+def measured_traffic(kernel, key):
+    v = TRAFFIC.get((kernel, key))
+    if v is None or v[1] != sources_sha256(kernel):
+        return None
+    return v[0]
+
+
+def current_compulsory_bytes(pos, cell, n_tracks, nt, elem_bytes, torch, chunk=1 << 16):
+    """Compulsory HBM bytes of the Eq. 1 convolution (carriers on the device):
+    every node that is a trilinear corner of some moving step, times the lags
+    it is read for (a step at m reads lags 0..n_time-1-m, so a node needs
+    n_time - min m), times 3 components, plus 24 B per moving step (midpoint
+    and displacement) and the output.  One int16 per grid node holds the
+    smallest step reaching it; carriers in chunks.  Returns (bytes, steps)."""
     N, L = cell["N"], cell["L"]
+    n_nodes = N[0] * N[1] * N[2]
+    first = torch.full((n_nodes,), 32767, dtype=torch.int16, device=pos.device)
     scale = torch.tensor([N[a] / L[a] for a in range(3)], dtype=torch.float64, device=pos.device)
-    nodes, needs = [], []
     n_steps = 0
     for c0 in range(0, pos.shape[0], chunk):
         P = pos[c0:c0 + chunk].double()
@@ -61,132 +84,36 @@ def current_compulsory_bytes_device(pos, cell, n_tracks, nt, elem_bytes, torch, 
         ci, mi = moving.nonzero(as_tuple=True)
         n_steps += int(ci.numel())
         lo = torch.floor(0.5 * (P[ci, mi] + P[ci, mi + 1]) * scale).long()
-        lags = nt - mi
+        m16 = mi.to(torch.int16)
         for ox in (0, 1):
             for oy in (0, 1):
                 for oz in (0, 1):
                     x = (lo[:, 0] + ox) % N[0]
                     y = (lo[:, 1] + oy) % N[1]
                     z = (lo[:, 2] + oz) % N[2]
-                    nodes.append((x * N[1] + y) * N[2] + z)
-                    needs.append(lags)
-    node = torch.cat(nodes)
-    need = torch.cat(needs)
-    uniq, inv = torch.unique(node, return_inverse=True)
-    best = torch.zeros(uniq.numel(), dtype=need.dtype, device=need.device).scatter_reduce(0, inv, need, "amax")
-    h_bytes = int(best.sum().item()) * 3 * elem_bytes
-    return h_bytes + 24 * n_steps + n_tracks * nt * 4, n_steps
+                    first.scatter_reduce_(0, (x * N[1] + y) * N[2] + z, m16, "amin")
+        del P, moving, ci, mi, lo
+    touched = first < 32767
+    lags = int((nt - first[touched].long()).sum().item())
+    del first, touched
+    return lags * 3 * elem_bytes + 24 * n_steps + n_tracks * nt * 4, n_steps
 
 
-def c5_section(torch, wt, np, steps):
-    """The 256x256x512 workload (1e6 carriers in 100 tracks, 512 frequencies,
-    400 samples): float16-scaled H (80.5 GB) and float32 H (161 GB), one at a
-    time, each a whole step (solve + current) timed over ``steps`` steps."""
-    from paper_2605_13987_amd import layout, workloads
-
-    cfg = workloads.pixel_256x256x512_tracks(device="cuda", out_dtype=torch.float32)
-    cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
-    N, nt, n_tr = cell["N"], spec["n_time"], car["n_tracks"]
-    n_pts = N[0] * N[1] * N[2]
-    n_c = car["pos"].shape[0]
-    stream = torch.cuda.current_stream()
-    ctx = wt.wt_context_create(0, stream.cuda_stream)
-    res = {"workload": (f"{N[0]}x{N[1]}x{N[2]} grid of the 50x50x300 um pixel, {spec['n_freq']} frequencies to "
-                        f"50 GHz, {nt} x 10 ps, {n_tr} MIP tracks of 5e3 e/h pairs ({n_c} carriers), drift + "
-                        f"0.5 um Gaussian diffusion per step"), "n_carriers": n_c, "n_tracks": n_tr}
-    currents, cols_h = {}, {}
-    for name, fmt, eb in (("mixed", wt.WT_H_F16_SCALED, 2), ("plain", wt.WT_H_PLAIN, 4)):
-        plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2, ir_tol=1e-12,
-                                        h_format=fmt)
-        ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
-        hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
-        out = torch.empty((n_tr, nt), dtype=torch.float32, device="cuda")
-
-        def step():
-            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
-            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, car["pos"].data_ptr(), car["charge"].data_ptr(),
-                          car["track"].data_ptr(), out.data_ptr())
-
-        _, rep_s = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True)
-        step()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        wt.wt_context_enable_timing(ctx, True)
-        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
-        stage = dict(wt.wt_context_stage_times(ctx))
-        wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, car["pos"].data_ptr(), car["charge"].data_ptr(),
-                      car["track"].data_ptr(), out.data_ptr())
-        stage.update(dict(wt.wt_context_stage_times(ctx)))
-        wt.wt_context_enable_timing(ctx, False)
-        synth_bytes = n_pts * nt * 3 * eb + N[0] * N[1] * len(cfg["columns"]) * (N[2] // 2) * 3 * 8
-        achieved = synth_bytes / (stage["synthesis"] * 1e-3) / 1e9
-        cur_bytes, n_steps = current_compulsory_bytes_device(car["pos"], cell, n_tr, nt, eb, torch)
-        t_cur = stage["current"] * 1e-3
-        res[name] = {"ms_per_step": ms, "value": n_pts * spec["n_freq"] / (ms * 1e-3), "unit": "grid*freq pts/s",
-                     "h_bytes": lay["h_bytes"], "h_scale": rep_s["h_scale"],
-                     "backward_error_max": rep_s["backward_error_max"],
-                     "stage_ms": {k: round(v, 4) for k, v in stage.items()},
-                     "tracks_per_s": n_tr / t_cur, "carriers_per_s": n_c / t_cur, "events_per_s": n_steps / t_cur,
-                     "synthesis_roofline": {"kernel": "k_synthesis_pipe", "bound": "hbm", "achieved": achieved,
-                                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                                            "bytes_per_launch": synth_bytes},
-                     "current_roofline": {"kernel": "k_current", "bound": "hbm", "compulsory_bytes": cur_bytes,
-                                          "achieved": cur_bytes / t_cur / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                          "frac": cur_bytes / t_cur / 1e9 / HBM_PEAK_GBS, "moving_steps": n_steps}}
-        currents[name] = out.double().cpu().numpy()
-        if name == "mixed":
-            per = N[2] * nt * 3
-            idx = torch.tensor([i * N[1] + j for i, j in C5_COLS], device="cuda")
-            h16 = hbuf[:n_pts * nt * 3 * 2].view(torch.float16).view(-1, per)
-            vals = h16.index_select(0, idx).double().cpu().numpy() / rep_s["h_scale"]
-            cols_h[name] = layout.to_standard(vals, N, nt, lay["h_time_block"])
-        print(f"# 256x256x512 {name}: {ms:.2f} ms/step, stages {res[name]['stage_ms']}", file=sys.stderr, flush=True)
-        wt.wt_h_plan_destroy(plan)
-        del ws, hbuf, out
-        torch.cuda.empty_cache()
-    wt.wt_context_destroy(ctx)
-    a, b = currents["mixed"], currents["plain"]
-    res["rel_err"] = {"i_mixed_vs_plain": float(np.linalg.norm(a - b) / np.linalg.norm(b))}
-    return res, cfg, cols_h
-
-
-C5_COLS = [(0, 0), (128, 128), (150, 128), (20, 200)]
-
-
-def c5_oracle_errors(cfg, cols_h):
-    """Errors of the 256x256x512 float16 H on sampled columns against the oracle's direct sums."""
-    import numpy as np
-
-    import oracle
-
-    ref = oracle.weighting_field(cfg["cell"], cfg["columns"], cfg["spectrum"], route="columns", cols_ij=C5_COLS)
-    out = {}
-    for name, h in cols_h.items():
-        out[name] = float(np.linalg.norm(h - ref["H_cols"]) / np.linalg.norm(ref["H_cols"]))
-    return out
-
-
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", type=int, default=64,
-                    help="geometry variants in the batched (graph-captured) measurement; 0 skips it")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0,
-                    help="approximate CPU time of the oracle baseline sample")
-    ap.add_argument("--c5-steps", type=int, default=3,
-                    help="timed steps of the 256x256x512 workload (1e6 carriers); 0 skips it")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
-                    help="first copy MIB mebibytes device-to-device 3 times (counter calibration)")
-    return ap.parse_args()
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
 
 
 def blas_threads():
@@ -198,17 +125,138 @@ def blas_threads():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(cfg, gpu_columns, budget_s):
-    """The FP64 oracle on a bounded sample of the same workload.
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle: its timing on the host cores and every error against it")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the 256x256x512 workload (for profiling)")
+    ap.add_argument("--variants", type=int, default=64,
+                    help="geometry variants in the batched (graph-captured) measurement; 0 skips it")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy MIB mebibytes device-to-device 3 times (counter calibration)")
+    return ap.parse_args()
 
-    Timed parts: the boundary fit for every frequency and the time transform
-    (whole-step work), the field on lattices of 256 grid columns added until
-    about half the time budget is spent, and Eq. 1 on strided subsets of the
-    carriers until about a third of it is.  The whole-step rate is
-    extrapolated from them: fit + per-column time x all columns + per-carrier
-    time x all carriers.  gpu_columns maps a path name to a function that
-    returns the GPU's H on given columns, for the error figures.
-    """
+
+C5_COLS = [(0, 0), (128, 128), (150, 128), (128, 100), (20, 200), (255, 7)]
+
+
+def c5_step(torch, wt, np, cfg, h_format, steps, warmup, cur_bytes, subset, n_cols_sample):
+    """Time the whole step at 256x256x512 with H stored in h_format; returns
+    the figures, H on sampled columns and the currents of a carrier subset."""
+    from paper_2605_13987_amd import layout
+
+    cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
+    N, nt, n_tr = cell["N"], spec["n_time"], car["n_tracks"]
+    n_pts = N[0] * N[1] * N[2]
+    n_c = car["pos"].shape[0]
+    stream = torch.cuda.current_stream()
+    ctx = wt.wt_context_create(0, stream.cuda_stream)
+    plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2, ir_tol=1e-12,
+                                    h_format=h_format)
+    ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
+    cws = torch.empty(wt.wt_current_workspace(plan, n_c), dtype=torch.uint8, device="cuda")
+    out = torch.empty((n_tr, nt), dtype=torch.float32, device="cuda")
+
+    def current(n, pos, q, tr, o):
+        wt.wt_current(ctx, plan, hbuf.data_ptr(), n, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
+                      o.data_ptr(), cws.data_ptr(), cws.numel())
+
+    def step():
+        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
+        current(n_c, car["pos"], car["charge"], car["track"], out)
+
+    _, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1) / steps
+    # per-stage durations from HIP events the library records on its stream
+    # around each stage (the synthesis stage is the one synthesis launch, the
+    # current stage the accumulation kernel)
+    wt.wt_context_enable_timing(ctx, True)
+    stage = {}
+    reps = max(3, min(steps, 5))
+    for _ in range(reps):
+        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
+        for name, t in wt.wt_context_stage_times(ctx):
+            stage[name] = stage.get(name, 0.0) + t / reps
+        current(n_c, car["pos"], car["charge"], car["track"], out)
+        for name, t in wt.wt_context_stage_times(ctx):
+            stage[name] = stage.get(name, 0.0) + t / reps
+    wt.wt_context_enable_timing(ctx, False)
+    ctl = [int(v) for v in cws[:24].view(torch.int64).cpu()]
+    # H on sampled columns, the currents of the carrier subset
+    eb = 2 if h_format == wt.WT_H_F16_SCALED else 4
+    per = N[2] * nt * 3
+    idx = torch.tensor([i * N[1] + j for i, j in C5_COLS[:n_cols_sample]] if n_cols_sample else [], device="cuda",
+                       dtype=torch.long)
+    cols = None
+    if idx.numel():
+        if eb == 2:
+            vals = hbuf[:n_pts * nt * 3 * 2].view(torch.float16).view(-1, per).index_select(0, idx)
+            vals = vals.double().cpu().numpy() / rep["h_scale"]
+        else:
+            vals = hbuf[:n_pts * nt * 3 * 4].view(torch.float32).view(-1, per).index_select(0, idx)
+            vals = vals.double().cpu().numpy()
+        cols = layout.to_standard(vals, N, nt, lay["h_time_block"])
+    i_sub = None
+    if subset is not None:
+        o = torch.empty((n_tr, nt), dtype=torch.float32, device="cuda")
+        current(subset["pos"].shape[0], subset["pos"], subset["charge"], subset["track"], o)
+        i_sub = o.double().cpu().numpy()
+    i_all = out.double().cpu().numpy()
+    wt.wt_h_plan_destroy(plan)
+    wt.wt_context_destroy(ctx)
+    del ws, hbuf, cws, out
+    torch.cuda.empty_cache()
+    synth_bytes = n_pts * nt * 3 * eb + N[0] * N[1] * len(cfg["columns"]) * (N[2] // 2) * 3 * 8
+    t_syn, t_cur = stage["synthesis"] * 1e-3, stage["current"] * 1e-3
+    t_cur_all = (stage["current"] + stage["current_binning"]) * 1e-3
+    key = f"256x256x512 {'f16' if eb == 2 else 'f32'}"
+    rl = {
+        "k_synthesis_pipe": {"kernel": "k_synthesis_pipe", "bound": "hbm", "achieved": synth_bytes / t_syn / 1e9,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": synth_bytes / t_syn / 1e9 / HBM_PEAK_GBS,
+                             "traffic": measured_traffic("k_synthesis_pipe", key), "bytes_per_launch": synth_bytes,
+                             "kernel_ms": stage["synthesis"]},
+        "k_conv_tiles": {"kernel": "k_conv_tiles", "bound": "hbm", "achieved": cur_bytes / t_cur / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": cur_bytes / t_cur / 1e9 / HBM_PEAK_GBS,
+                         "traffic": measured_traffic("k_conv_tiles", key), "bytes_per_launch": cur_bytes,
+                         "kernel_ms": stage["current"]},
+    }
+    dom = max(rl, key=lambda k: rl[k]["kernel_ms"])
+    res = {"ms_per_step": ms, "wall_ms_per_step": 1e3 * t_wall / steps,
+           "value": n_pts * spec["n_freq"] / (ms * 1e-3), "unit": "grid*freq pts/s",
+           "h_grid_freq_pts_per_s": n_pts * spec["n_freq"] / (sum(v for k, v in stage.items()
+                                                                   if not k.startswith("current")) * 1e-3),
+           "tracks_per_s": n_tr / t_cur_all, "carriers_per_s": n_c / t_cur_all,
+           "events_per_s": ctl[0] / t_cur_all, "moving_steps": ctl[0],
+           "h_bytes": lay["h_bytes"], "h_scale": rep["h_scale"], "backward_error_max": rep["backward_error_max"],
+           "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+           "roofline_dominant": rl[dom], "roofline_other": rl["k_conv_tiles" if dom == "k_synthesis_pipe"
+                                                            else "k_synthesis_pipe"]}
+    print(f"# 256x256x512 {key}: {ms:.2f} ms/step, stages {res['stage_ms']}", file=sys.stderr, flush=True)
+    return res, cols, i_sub, i_all
+
+
+def c5_oracle(cfg, n_extra_cols, subset_np, budget_s):
+    """The FP64 oracle on the 256x256x512 workload: the boundary fit for all
+    frequencies and the time transform, H on the sampled columns (direct mode
+    sums) and on n_extra_cols more, the currents of the carrier subset on its
+    own field at the touched nodes, and Eq. 1 on a sample of all carriers
+    for the timing.  Returns references and timings."""
     import numpy as np
 
     from oracle import collocation, convolution, field, green, timegrid
@@ -221,87 +269,56 @@ def cpu_baseline(cfg, gpu_columns, budget_s):
     q_t = timegrid.to_time(sol["q"], spec)
     t_fit = time.perf_counter() - t0
     s, src = green.smoothing_widths(cell, cols), collocation.sources(cols)
-    sample, t_cols = [], 0.0
-    err_num = {name: 0.0 for name in gpu_columns}
-    err_den = 0.0
-    for shift in range(64):                       # 16 x 16 lattices off the column axes
-        lattice = [((i + 3 + shift) % N[0], (j + 5 + 3 * shift) % N[1])
-                   for i in range(0, N[0], N[0] // 16) for j in range(0, N[1], N[1] // 16)]
-        seen = set(sample)
-        lattice = [c for c in lattice if c not in seen]
-        t0 = time.perf_counter()
-        ref = field.field_columns(cell, s, src, q_t, lattice)
-        t_cols += time.perf_counter() - t0
-        for name, fn in gpu_columns.items():
-            err_num[name] += float(np.sum((fn(lattice) - ref) ** 2))
-        err_den += float(np.sum(ref ** 2))
-        sample += lattice
-        if t_cols > 0.5 * budget_s:
-            break
-    err = {name: (v / err_den) ** 0.5 for name, v in err_num.items()}
-    # convolution: strided carrier subsets on a synthetic field of the same grid
-    car = cfg["carriers"]
-    n_car = car["pos"].shape[0]
-    f = workloads.synthetic_h_factors(workloads.rng_for(99), N, spec["n_time"])
-    h_at = lambda ix, iy, iz: workloads.synthetic_h_values(f, ix, iy, iz)
-    stride, n_done, t_conv = 50, 0, 0.0
-    for off in range(stride):
-        sub = np.arange(off, n_car, stride)
-        t0 = time.perf_counter()
-        convolution.induced_current(h_at, cell, car["pos"][sub], car["charge"][sub], car["track"][sub],
-                                    car["n_tracks"])
-        t_conv += time.perf_counter() - t0
-        n_done += sub.size
-        if t_conv > budget_s / 3:
-            break
-    n_cols_all = N[0] * N[1]
-    t_step = t_fit + t_cols * n_cols_all / len(sample) + t_conv * n_car / n_done
-    return dict(value=N[0] * N[1] * N[2] * spec["n_freq"] / t_step, unit="grid*freq pts/s",
-                cores=blas_threads(), kind="oracle",
-                sample=(f"boundary fit for all {spec['n_freq']} frequencies + time transform ({t_fit:.1f} s), "
-                        f"field on {len(sample)} of {n_cols_all} grid columns, all z and t ({t_cols:.1f} s), "
-                        f"Eq. 1 on {n_done} of {n_car} carriers ({t_conv:.1f} s); whole step extrapolated "
-                        f"from these parts: {t_step:.0f} s"),
-                step_s_extrapolated=t_step,
-                tracks_per_s=car["n_tracks"] / (t_conv * n_car / n_done),
-                carriers_per_s=n_done / t_conv), err
+    # the column route has a fixed cost (the mode tables) and a cost per
+    # column: time it on 2 columns and on the sampled plus extra ones
+    t0 = time.perf_counter()
+    field.field_columns(cell, s, src, q_t, C5_COLS[:2])
+    t_two = time.perf_counter() - t0
+    extra = [((37 * k + 11) % N[0], (91 * k + 5) % N[1]) for k in range(n_extra_cols)]
+    t0 = time.perf_counter()
+    H_cols = field.field_columns(cell, s, src, q_t, C5_COLS + extra)
+    t_many = time.perf_counter() - t0
+    per_col = max(t_many - t_two, 0.0) / (len(C5_COLS) + len(extra) - 2)
+    t_setup = max(t_two - 2 * per_col, 0.0)
+    # the currents of the subset on the oracle's own field at the nodes its
+    # paths touch (in-plane table from 2D inverse FFTs, k_z sums per node)
+    table = field.planar_table(cell, s)
+
+    def h_at(ix, iy, iz):
+        return field.field_nodes_planar_fft(cell, s, src, q_t, ix, iy, iz, table=table)
+
+    i_sub = convolution.induced_current(h_at, cell, subset_np["pos"], subset_np["charge"], subset_np["track"],
+                                        subset_np["n_tracks"])
+    del table
+    return dict(t_fit=t_fit, t_setup=t_setup, per_col=per_col, n_cols_timed=len(C5_COLS) + len(extra),
+                H_cols=H_cols, extra=extra, i_sub=i_sub)
 
 
-def current_compulsory_bytes(cfg, elem_bytes):
-    """Compulsory HBM bytes of the Eq. 1 convolution: every node that is a
-    trilinear corner of some moving step, times the lags it is read for (a
-    step at m reads lags 0..N_t-1-m), times 3 components, plus 24 B per step
-    (midpoint and displacement) and the output.  Returns (bytes, steps)."""
+def conv_timing(cfg, pos_dev, charge_dev, track_dev, budget_s):
+    """Seconds per carrier of the oracle's Eq. 1 (strided carrier samples, a
+    synthetic field: the field's own cost is in the column timing)."""
     import numpy as np
 
-    cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
-    N, L, nt = cell["N"], cell["L"], spec["n_time"]
-    P = np.asarray(car["pos"], dtype=np.float32).astype(np.float64)
-    d = P[:, 1:, :] - P[:, :-1, :]
-    moving = np.any(d != 0, axis=2)
-    c_idx, m_idx = np.nonzero(moving)
-    mid = 0.5 * (P[c_idx, m_idx, :] + P[c_idx, m_idx + 1, :]) * (np.asarray(N) / np.asarray(L))
-    lo = np.floor(mid).astype(np.int64)
-    lags = nt - m_idx
-    node = np.empty(0, dtype=np.int64)
-    need = np.empty(0, dtype=np.int64)
-    for ox in (0, 1):
-        for oy in (0, 1):
-            for oz in (0, 1):
-                x = (lo[:, 0] + ox) % N[0]
-                y = (lo[:, 1] + oy) % N[1]
-                z = (lo[:, 2] + oz) % N[2]
-                node = np.concatenate([node, (x * N[1] + y) * N[2] + z])
-                need = np.concatenate([need, lags])
-    order = np.lexsort((-need, node))
-    node, need = node[order], need[order]
-    first = np.ones(node.size, dtype=bool)
-    first[1:] = node[1:] != node[:-1]
-    h_bytes = int(need[first].sum()) * 3 * elem_bytes
-    n_steps = int(c_idx.size)
-    return h_bytes + 24 * n_steps + car["n_tracks"] * nt * 4, n_steps
+    from oracle import convolution
+    from paper_2605_13987_amd import workloads
 
-
+    cell, spec = cfg["cell"], cfg["spectrum"]
+    f = workloads.synthetic_h_factors(workloads.rng_for(99), cell["N"], spec["n_time"])
+    n = pos_dev.shape[0]
+    stride, done, t = 500, 0, 0.0
+    for off in range(stride):
+        sub = np.arange(off, n, stride)
+        pos = pos_dev[off::stride].double().cpu().numpy()
+        q = charge_dev[off::stride].double().cpu().numpy()
+        tr = track_dev[off::stride].cpu().numpy()
+        t0 = time.perf_counter()
+        convolution.induced_current(lambda ix, iy, iz: workloads.synthetic_h_values(f, ix, iy, iz), cell, pos, q, tr,
+                                    cfg["carriers"]["n_tracks"])
+        t += time.perf_counter() - t0
+        done += sub.size
+        if t > budget_s:
+            break
+    return t / done, done
 def batched_variants(wt, workloads, torch, n_variants, replays, n_lanes=4):
     """The geometry-variant batch: n_variants seeded cells of uneven grids and
     frequency counts, each a full step (H solve + current of its track), run
@@ -483,6 +500,205 @@ def adjoint_section(cfg, torch, wt, np, reps):
     return out
 
 
+def px128_section(torch, wt, np, steps, warmup, oracle_on):
+    """The 128x128x256 single-track workload (2e4 carriers, 256 frequencies,
+    200 samples): the step with float32, float16 and float64 H, per-stage
+    times, H on sampled columns against the oracle's direct sums."""
+    from paper_2605_13987_amd import layout, workloads
+
+    cfg = workloads.mip_pixel_128x128x256()
+    cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
+    N, nt = cell["N"], spec["n_time"]
+    n_pts = N[0] * N[1] * N[2]
+    per_col = N[2] * nt * 3
+    stream = torch.cuda.current_stream()
+    ctx = wt.wt_context_create(0, stream.cuda_stream)
+    pos = torch.from_numpy(car["pos"]).to("cuda", torch.float32)
+    q = torch.from_numpy(car["charge"]).to("cuda", torch.float32)
+    tr = torch.from_numpy(car["track"]).to("cuda")
+    n_c, n_tr = pos.shape[0], car["n_tracks"]
+    cols_ij = [(0, 0), (64, 64), (70, 64), (64, 50), (10, 100), (127, 3), (33, 91), (100, 20)]
+    out = {}
+    for name, fmt, prec in (("plain", wt.WT_H_PLAIN, wt.WT_F32), ("mixed", wt.WT_H_F16_SCALED, wt.WT_F32),
+                            ("f64", wt.WT_H_PLAIN, wt.WT_F64)):
+        plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=prec, ir_max_iter=2, ir_tol=1e-12,
+                                        h_format=fmt)
+        f64 = prec == wt.WT_F64
+        dt = torch.float64 if f64 else torch.float32
+        ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
+        hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
+        cws = torch.empty(wt.wt_current_workspace(plan, n_c), dtype=torch.uint8, device="cuda")
+        o = torch.empty((n_tr, nt), dtype=dt, device="cuda")
+        pos_p, q_p = (pos.double(), q.double()) if f64 else (pos, q)
+
+        def step():
+            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
+            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos_p.data_ptr(), q_p.data_ptr(), tr.data_ptr(),
+                          o.data_ptr(), cws.data_ptr(), cws.numel())
+
+        _, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        wt.wt_context_enable_timing(ctx, True)
+        stage = {}
+        reps = max(3, min(steps, 10))
+        for _ in range(reps):
+            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
+            for k, t in wt.wt_context_stage_times(ctx):
+                stage[k] = stage.get(k, 0.0) + t / reps
+            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos_p.data_ptr(), q_p.data_ptr(), tr.data_ptr(),
+                          o.data_ptr(), cws.data_ptr(), cws.numel())
+            for k, t in wt.wt_context_stage_times(ctx):
+                stage[k] = stage.get(k, 0.0) + t / reps
+        wt.wt_context_enable_timing(ctx, False)
+        eb = 8 if f64 else (2 if fmt == wt.WT_H_F16_SCALED else 4)
+        idx = torch.tensor([i * N[1] + j for i, j in cols_ij], device="cuda")
+        if eb == 2:
+            vals = hbuf[:n_pts * nt * 3 * 2].view(torch.float16).view(-1, per_col).index_select(0, idx)
+            vals = vals.double().cpu().numpy() / rep["h_scale"]
+        else:
+            vals = hbuf[:n_pts * nt * 3 * eb].view(dt).view(-1, per_col).index_select(0, idx).double().cpu().numpy()
+        synth_bytes = n_pts * nt * 3 * eb + N[0] * N[1] * len(cfg["columns"]) * (N[2] // 2) * 3 * (16 if f64 else 8)
+        t_cur = (stage["current"] + stage["current_binning"]) * 1e-3
+        out[name] = {"ms_per_step": ms, "value": n_pts * spec["n_freq"] / (ms * 1e-3),
+                     "tracks_per_s": n_tr / t_cur, "carriers_per_s": n_c / t_cur,
+                     "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+                     "synthesis_hbm_frac": synth_bytes / (stage["synthesis"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "cols": layout.to_standard(vals, N, nt, lay["h_time_block"]), "i": o.double().cpu().numpy()}
+        print(f"# 128x128x256 {name}: {ms:.3f} ms/step, stages {out[name]['stage_ms']}", file=sys.stderr,
+              flush=True)
+        wt.wt_h_plan_destroy(plan)
+        del ws, hbuf, cws
+        torch.cuda.empty_cache()
+    wt.wt_context_destroy(ctx)
+    i64 = out["f64"]["i"]
+    for name in ("plain", "mixed"):
+        out[name]["rel_err_i_vs_float64_path"] = float(np.linalg.norm(out[name]["i"] - i64) / np.linalg.norm(i64))
+    if oracle_on:
+        import oracle
+        ref = oracle.weighting_field(cell, cfg["columns"], spec, route="columns", cols_ij=cols_ij)["H_cols"]
+        for name in out:
+            out[name]["rel_err_H_sampled_columns_vs_fp64_oracle"] = float(
+                np.linalg.norm(out[name]["cols"] - ref) / np.linalg.norm(ref))
+    for name in out:
+        del out[name]["cols"], out[name]["i"]
+    out["workload"] = (f"128x128x256 grid of the 50x50x300 um pixel, 256 frequencies to 50 GHz, 200 x 10 ps, one MIP "
+                       f"track with {n_c // 2} e/h pairs ({n_c} carriers); H in float32 (plain), scaled float16 "
+                       f"(mixed) or float64 (f64)")
+    return out, cfg
+
+
+def m256_section(torch, wt, np):
+    """FP64 boundary fit with M = 256 nodes per column (n = 513 unknowns) at
+    512 frequencies to 50 GHz: the fit of the 50x50x300 um cell does not
+    depend on the grid (converged Green's function), so a small grid carries it."""
+    from paper_2605_13987_amd import workloads
+
+    ctx = wt.wt_context_create(0, torch.cuda.current_stream().cuda_stream)
+    m256 = workloads.small_pixel(k=48, n_xy=32, n_z=64, n_freq=512, n_time=16, n_pairs=1, n_colloc=256)
+    plan, lay = wt.wt_h_plan_create(m256["cell"], m256["columns"], m256["spectrum"], precision=wt.WT_F32,
+                                    ir_max_iter=2, ir_tol=1e-12)
+    ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    h = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
+    _, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"], report=True,
+                           raise_on_error=False)
+    wt.wt_context_enable_timing(ctx, True)
+    t = []
+    for _ in range(3):
+        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"])
+        t.append(dict(wt.wt_context_stage_times(ctx))["collocation_solve"])
+    wt.wt_context_enable_timing(ctx, False)
+    wt.wt_h_plan_destroy(plan)
+    wt.wt_context_destroy(ctx)
+    n = lay["n_q"] + 1
+    ms = float(np.median(t))
+    flops = 512 * (8.0 / 3.0 * n ** 3)       # complex LU, 4 real flops per complex multiply-add
+    return {"n_unknowns": n, "n_freq": 512, "ms": ms, "fp64_tflops": flops / (ms * 1e-3) / 1e12,
+            "fp64_frac_of_78.6": flops / (ms * 1e-3) / 78.6e12,
+            "backward_error_max": rep["backward_error_max"], "ir_iters_max": rep["ir_iters_max"]}
+
+
+def electronics_section(torch, wt, workloads, i_cur, spec):
+    """Readout electronics on a current: CR-RC front end (tau = 250 ps,
+    1 kohm), seeded noise, constant fraction 0.5."""
+    n_tr, nt = i_cur.shape
+    ctx = wt.wt_context_create(0, torch.cuda.current_stream().cuda_stream)
+    stream = torch.cuda.current_stream()
+    g = torch.from_numpy(workloads.cr_rc_response(nt, spec["dt"])).to("cuda", torch.float32)
+    noise = torch.from_numpy(workloads.noise_samples(31, n_tr, nt)).to("cuda", torch.float32)
+    v = torch.empty((n_tr, nt), dtype=torch.float32, device="cuda")
+    f = torch.empty((n_tr, 3), dtype=torch.float32, device="cuda")
+    sigma = 1e-2 * float(i_cur.abs().max().item()) * 1e3
+
+    def run():
+        wt.wt_electronics(ctx, wt.WT_F32, n_tr, nt, spec["dt"], i_cur.data_ptr(), g.data_ptr(), noise.data_ptr(), sigma,
+                          0.5, v.data_ptr(), f.data_ptr())
+
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wt.wt_context_destroy(ctx)
+    return {"ms": e0.elapsed_time(e1) / 10, "n_tracks": n_tr, "n_time": nt,
+            "features_first_track": {"amplitude_V": float(f[0, 0]), "t_peak_s": float(f[0, 1]),
+                                     "t_cfd_s": float(f[0, 2])}}
+
+
+def graph_section(torch, wt, cfg, steps, warmup):
+    """The 128x128x256 step captured once as a HIP graph and replayed."""
+    cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
+    pos = torch.from_numpy(car["pos"]).to("cuda", torch.float32)
+    q = torch.from_numpy(car["charge"]).to("cuda", torch.float32)
+    tr = torch.from_numpy(car["track"]).to("cuda")
+    n_c, n_tr = pos.shape[0], car["n_tracks"]
+    g_stream = torch.cuda.Stream()
+    ctx = wt.wt_context_create(0, g_stream.cuda_stream)
+    plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2, ir_tol=1e-12)
+    ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    h = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
+    cws = torch.empty(wt.wt_current_workspace(plan, n_c), dtype=torch.uint8, device="cuda")
+    o = torch.empty((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
+
+    def step():
+        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), h.data_ptr(), lay["h_bytes"])
+        wt.wt_current(ctx, plan, h.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(), o.data_ptr(),
+                      cws.data_ptr(), cws.numel())
+
+    with torch.cuda.stream(g_stream):
+        step()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=g_stream):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(g_stream):                             # a replay runs on the current stream
+        for _ in range(warmup):
+            graph.replay()
+        e0.record(g_stream)
+        for _ in range(steps):
+            graph.replay()
+        e1.record(g_stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del graph, ws, h, cws
+    wt.wt_h_plan_destroy(plan)
+    wt.wt_context_destroy(ctx)
+    torch.cuda.empty_cache()
+    return {"ms_per_step": ms, "note": "the 128x128x256 step captured once as a HIP graph and replayed"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -492,7 +708,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2605_13987_amd import layout, workloads, wt
+    from paper_2605_13987_amd import workloads, wt
 
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
@@ -504,282 +720,120 @@ def main():
         print(f"# copy probe: 3 x {args.copy_probe} MiB read + written", file=sys.stderr, flush=True)
         del src, dst
 
-    cfg = workloads.mip_pixel_128x128x256()
+    # ---- the headline workload: 256 x 256 x 512, 1e6 carriers
+    cfg = workloads.pixel_256x256x512_tracks(device="cuda", out_dtype=torch.float32)
     cell, spec, car = cfg["cell"], cfg["spectrum"], cfg["carriers"]
-    N = cell["N"]
-    n_pts = N[0] * N[1] * N[2]
-    per_col = N[2] * spec["n_time"] * 3
-    w = len(cfg["columns"])
-    stream = torch.cuda.current_stream()
-    ctx = wt.wt_context_create(0, stream.cuda_stream)
-    pos = torch.from_numpy(car["pos"]).to("cuda", torch.float32)
-    q = torch.from_numpy(car["charge"]).to("cuda", torch.float32)
-    tr = torch.from_numpy(car["track"]).to("cuda")
-    n_c, n_tr = pos.shape[0], car["n_tracks"]
-
-    def run_path(h_format, precision=wt.WT_F32):
-        """Time the whole step with H stored in h_format (or the whole path in
-        float64); returns the figures and buffers."""
-        plan, lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=precision, ir_max_iter=2,
-                                        ir_tol=1e-12, h_format=h_format)
-        f64 = precision == wt.WT_F64
-        dt = torch.float64 if f64 else torch.float32
-        ws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
-        hbuf = torch.empty(lay["h_bytes"], dtype=torch.uint8, device="cuda")
-        out = torch.empty((n_tr, spec["n_time"]), dtype=dt, device="cuda")
-        pos_p, q_p = (pos.double(), q.double()) if f64 else (pos, q)
-
-        def step():
-            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
-            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos_p.data_ptr(), q_p.data_ptr(), tr.data_ptr(),
-                          out.data_ptr())
-
-        st, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True)
-        print(f"# h_format {h_format}: solve report {rep}", file=sys.stderr, flush=True)
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t_wall = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t_wall = time.perf_counter() - t_wall
-        ms = e0.elapsed_time(e1) / args.steps
-        print(f"# h_format {h_format}: timed {args.steps} steps: {ms:.3f} ms/step "
-              f"(wall {1e3 * t_wall / args.steps:.3f} ms)", file=sys.stderr, flush=True)
-        # per-stage durations from HIP events recorded by the library on the same stream
-        wt.wt_context_enable_timing(ctx, True)
-        stage = {}
-        reps = max(3, min(args.steps, 10))
-        for _ in range(reps):
-            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
-            for name, t in wt.wt_context_stage_times(ctx):
-                stage[name] = stage.get(name, 0.0) + t / reps
-            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos_p.data_ptr(), q_p.data_ptr(), tr.data_ptr(),
-                          out.data_ptr())
-            for name, t in wt.wt_context_stage_times(ctx):
-                stage[name] = stage.get(name, 0.0) + t / reps
-        wt.wt_context_enable_timing(ctx, False)
-        torch.cuda.synchronize()
-        wt.wt_h_plan_destroy(plan)
-        if h_format == wt.WT_H_F16_SCALED:
-            h = hbuf[:n_pts * spec["n_time"] * 3 * 2].view(torch.float16)
-            off = lay["h_decode_offset"]
-            decode = float(hbuf[off:off + 4].view(torch.float32).item())
-        else:
-            h, decode = hbuf.view(dt), 1.0
-        t_h = sum(v for k, v in stage.items() if k != "current") * 1e-3
-        t_cur = stage["current"] * 1e-3
-        # synthesis kernel: algorithmic bytes = write of H + read of the field table per column
-        synth_bytes = h.numel() * h.element_size() + N[0] * N[1] * w * (N[2] // 2) * 3 * (16 if f64 else 8)
-        achieved = synth_bytes / (stage["synthesis"] * 1e-3) / 1e9
-        return dict(ms=ms, stage=stage, t_h=t_h, t_cur=t_cur, rep=rep, h=h, decode=decode, out=out,
-                    synth_bytes=synth_bytes, achieved=achieved, lay=lay)
-
-    def columns_of(r):
-        def fn(cols):
-            idx = torch.tensor([i * N[1] + j for i, j in cols], device="cuda")
-            vals = r["h"].view(-1, per_col).index_select(0, idx).cpu().numpy().astype(np.float64) * r["decode"]
-            return layout.to_standard(vals, N, spec["n_time"], r["lay"]["h_time_block"])
-        return fn
-
-    plain = run_path(wt.WT_H_PLAIN)
-    mixed = run_path(wt.WT_H_F16_SCALED)
-    full64 = run_path(wt.WT_H_PLAIN, wt.WT_F64)
-    cur_bytes, n_steps = current_compulsory_bytes(cfg, 4)
-    cur_bytes16, _ = current_compulsory_bytes(cfg, 2)
-    # FP64 boundary fit with M = 256 nodes per column (n = 513) at 512
-    # frequencies to 50 GHz: the solve of the 50x50x300 um cell does not depend
-    # on the grid (converged Green's function), so a small grid carries it
-    m256 = workloads.small_pixel(k=48, n_xy=32, n_z=64, n_freq=512, n_time=16, n_pairs=1, n_colloc=256)
-    plan_m, lay_m = wt.wt_h_plan_create(m256["cell"], m256["columns"], m256["spectrum"], precision=wt.WT_F32,
-                                        ir_max_iter=2, ir_tol=1e-12)
-    ws_m = torch.empty(lay_m["workspace_bytes"], dtype=torch.uint8, device="cuda")
-    h_m = torch.empty(lay_m["h_bytes"], dtype=torch.uint8, device="cuda")
-    _, rep_m = wt.wt_h_solve(ctx, plan_m, ws_m.data_ptr(), ws_m.numel(), h_m.data_ptr(), lay_m["h_bytes"],
-                             report=True, raise_on_error=False)
-    wt.wt_context_enable_timing(ctx, True)
-    t_m = []
-    for _ in range(3):
-        wt.wt_h_solve(ctx, plan_m, ws_m.data_ptr(), ws_m.numel(), h_m.data_ptr(), lay_m["h_bytes"])
-        t_m.append(dict(wt.wt_context_stage_times(ctx))["collocation_solve"])
-    wt.wt_context_enable_timing(ctx, False)
-    wt.wt_h_plan_destroy(plan_m)
-    del ws_m, h_m
-    solve_m256 = {"n_unknowns": lay_m["n_q"] + 1, "n_freq": 512, "ms": float(np.median(t_m)),
-                  "backward_error_max": rep_m["backward_error_max"], "ir_iters_max": rep_m["ir_iters_max"]}
-    print(f"# M = 256 solve: {solve_m256}", file=sys.stderr, flush=True)
-
-    # readout electronics on the plain path's current: CR-RC front end
-    # (tau = 250 ps, 1 kohm), seeded noise, constant fraction 0.5
-    g_e = torch.from_numpy(workloads.cr_rc_response(spec["n_time"], spec["dt"])).to("cuda", torch.float32)
-    n_e = torch.from_numpy(workloads.noise_samples(31, n_tr, spec["n_time"])).to("cuda", torch.float32)
-    v_e = torch.empty((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
-    f_e = torch.empty((n_tr, 3), dtype=torch.float32, device="cuda")
-    sigma_e = 1e-2 * float(plain["out"].abs().max().item()) * 1e3   # 1% of the peak current through 1 kohm
-
-    def elec():
-        wt.wt_electronics(ctx, wt.WT_F32, n_tr, spec["n_time"], spec["dt"], plain["out"].data_ptr(), g_e.data_ptr(),
-                          n_e.data_ptr(), sigma_e, 0.5, v_e.data_ptr(), f_e.data_ptr())
-
-    elec()
+    N, nt, n_tr = cell["N"], spec["n_time"], car["n_tracks"]
+    n_pts, n_c = N[0] * N[1] * N[2], car["pos"].shape[0]
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        elec()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    electronics = {"ms": e0.elapsed_time(e1) / 10, "n_tracks": n_tr,
-                   "features_first_track": {"amplitude_V": float(f_e[0, 0]), "t_peak_s": float(f_e[0, 1]),
-                                            "t_cfd_s": float(f_e[0, 2])}}
-
-    adjoint = adjoint_section(cfg, torch, wt, np, max(3, min(args.steps, 10)))
+    cur16, n_steps = current_compulsory_bytes(car["pos"], cell, n_tr, nt, 2, torch)
+    cur32 = cur16 + (cur16 - 24 * n_steps - n_tr * nt * 4)       # the H part doubles with float32 values
+    # every 20th carrier of tracks 0 and 1: their currents end to end against the oracle
+    sub_idx = torch.nonzero(car["track"] < 2).flatten()[::20].contiguous()
+    subset = {k: car[k].index_select(0, sub_idx).contiguous() for k in ("pos", "charge", "track")}
     torch.cuda.empty_cache()
-    print(f"# adjoint: {adjoint}", file=sys.stderr, flush=True)
-
-    # the whole step captured once as a HIP graph and replayed
-    g_stream = torch.cuda.Stream()
-    g_ctx = wt.wt_context_create(0, g_stream.cuda_stream)
-    g_plan, g_lay = wt.wt_h_plan_create(cell, cfg["columns"], spec, precision=wt.WT_F32, ir_max_iter=2, ir_tol=1e-12)
-    g_ws = torch.empty(g_lay["workspace_bytes"], dtype=torch.uint8, device="cuda")
-    g_h = torch.empty(g_lay["h_bytes"], dtype=torch.uint8, device="cuda")
-    g_out = torch.empty((n_tr, spec["n_time"]), dtype=torch.float32, device="cuda")
-
-    def g_step():
-        wt.wt_h_solve(g_ctx, g_plan, g_ws.data_ptr(), g_ws.numel(), g_h.data_ptr(), g_lay["h_bytes"])
-        wt.wt_current(g_ctx, g_plan, g_h.data_ptr(), n_c, n_tr, pos.data_ptr(), q.data_ptr(), tr.data_ptr(),
-                      g_out.data_ptr())
-
-    with torch.cuda.stream(g_stream):
-        g_step()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph, stream=g_stream):
-        g_step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(g_stream):                             # a replay runs on the current stream
-        for _ in range(args.warmup):
-            graph.replay()
-        e0.record(g_stream)
-        for _ in range(args.steps):
-            graph.replay()
-        e1.record(g_stream)
-    torch.cuda.synchronize()
-    graph_ms = e0.elapsed_time(e1) / args.steps
-    del graph, g_ws, g_h
-    wt.wt_h_plan_destroy(g_plan)
-    wt.wt_context_destroy(g_ctx)
+    mixed, cols16, isub16, iall16 = c5_step(torch, wt, np, cfg, wt.WT_H_F16_SCALED, args.steps, args.warmup, cur16,
+                                            subset, len(C5_COLS))
+    plain, cols32, isub32, iall32 = c5_step(torch, wt, np, cfg, wt.WT_H_PLAIN, args.steps, args.warmup, cur32,
+                                            subset, len(C5_COLS))
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    err = {"i_all_carriers_mixed_vs_plain": rel(iall16, iall32)}
+    cpu_base = None
+    if not args.no_cpu_baseline:
+        subset_np = dict(pos=subset["pos"].double().cpu().numpy(), charge=subset["charge"].double().cpu().numpy(),
+                         track=subset["track"].cpu().numpy(), n_tracks=n_tr)
+        t0 = time.perf_counter()
+        ref = c5_oracle(cfg, 58, subset_np, 20.0)
+        per_carrier, n_conv = conv_timing(cfg, car["pos"], car["charge"], car["track"], 6.0)
+        t_oracle = time.perf_counter() - t0
+        H6 = ref["H_cols"][:len(C5_COLS)]
+        err["H_sampled_columns_vs_fp64_oracle"] = {"mixed": rel(cols16, H6), "plain": rel(cols32, H6)}
+        err["i_tracks_0_1_every_20th_carrier_vs_fp64_oracle"] = {"mixed": rel(isub16[:2], ref["i_sub"][:2]),
+                                                                  "plain": rel(isub32[:2], ref["i_sub"][:2])}
+        t_step = ref["t_fit"] + ref["t_setup"] + ref["per_col"] * N[0] * N[1] + per_carrier * n_c
+        model, n_avail = cpu_info()
+        cpu_base = {"value": n_pts * spec["n_freq"] / t_step, "unit": "grid*freq pts/s", "cores": blas_threads(),
+                    "kind": "oracle",
+                    "sample": (f"256x256x512 workload: boundary fit for all {spec['n_freq']} frequencies + time "
+                               f"transform ({ref['t_fit']:.1f} s), H by direct mode sums on {ref['n_cols_timed']} of "
+                               f"{N[0] * N[1]} grid columns, all z and t (mode tables {ref['t_setup']:.1f} s, then "
+                               f"{ref['per_col']:.3f} s per column), Eq. 1 on {n_conv} of {n_c} carriers "
+                               f"({per_carrier * 1e3:.2f} ms per carrier); whole step extrapolated from these parts: "
+                               f"{t_step:.0f} s"),
+                    "step_s_extrapolated": t_step, "tracks_per_s": n_tr / (per_carrier * n_c),
+                    "cpu_model": model, "host_cpus_available": n_avail,
+                    "threads": f"numpy/BLAS threads {blas_threads()} (matrix products); the rest of the oracle runs "
+                               f"on one thread",
+                    "oracle_wall_s": t_oracle}
+    del cfg, car, subset
     torch.cuda.empty_cache()
-    print(f"# captured step replayed: {graph_ms:.3f} ms/step", file=sys.stderr, flush=True)
-    batch = None
-    if args.variants > 0:
-        batch = batched_variants(wt, workloads, torch, args.variants, 3)
-        print(f"# batch of {args.variants} variants: default launch {batch['ms_eager_default_launch']:.1f} ms, "
-              f"autotuned ({batch['autotune_s']:.1f} s) eager {batch['ms_eager']:.1f} ms, graph {batch['ms_graph']:.1f} ms",
-              file=sys.stderr, flush=True)
+
+    extras = {}
+    if not args.no_extras:
+        px128, c2cfg = px128_section(torch, wt, np, args.steps, args.warmup, not args.no_cpu_baseline)
+        extras["px128"] = px128
+        extras["solve_m256"] = m256_section(torch, wt, np)
+        print(f"# M = 256 solve: {extras['solve_m256']}", file=sys.stderr, flush=True)
+        extras["electronics"] = electronics_section(torch, wt, workloads,
+                                                    torch.from_numpy(iall16).to("cuda", torch.float32), spec)
+        extras["adjoint"] = adjoint_section(c2cfg, torch, wt, np, max(3, min(args.steps, 10)))
         torch.cuda.empty_cache()
+        print(f"# adjoint: {extras['adjoint']}", file=sys.stderr, flush=True)
+        extras["graph"] = graph_section(torch, wt, c2cfg, args.steps, args.warmup)
+        print(f"# captured step replayed: {extras['graph']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        if args.variants > 0:
+            extras["batched_variants"] = batched_variants(wt, workloads, torch, args.variants, 3)
+            b = extras["batched_variants"]
+            print(f"# batch of {args.variants} variants: eager {b['ms_eager']:.1f} ms, graph {b['ms_graph']:.1f} ms, "
+                  f"lanes {b['lanes']['ms_eager']:.1f} ms", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
 
-    c5, c5_cfg, c5_cols = None, None, None
-    if args.c5_steps > 0:
-        c5, c5_cfg, c5_cols = c5_section(torch, wt, np, args.c5_steps)
-        torch.cuda.empty_cache()
-
-    i_plain = plain["out"].double().cpu().numpy()
-    i_mixed = mixed["out"].double().cpu().numpy()
-    i_err_mixed = float(np.linalg.norm(i_mixed - i_plain) / np.linalg.norm(i_plain))
-    i_f64 = full64["out"].cpu().numpy()
-    i_err_plain_vs_f64 = float(np.linalg.norm(i_plain - i_f64) / np.linalg.norm(i_f64))
-    i_err_mixed_vs_f64 = float(np.linalg.norm(i_mixed - i_f64) / np.linalg.norm(i_f64))
-
-    stage, ms = plain["stage"], plain["ms"]
-    measured = (list(N) == [128, 128, 256] and spec["n_time"] == 200 and w == 2
-                and synthesis_sources_sha256() == SYNTH_TRAFFIC_SOURCES_SHA256)
-    traffic = SYNTH_TRAFFIC_BYTES["plain"] if measured else None
     line = {
         "metric": METRIC,
-        "value": n_pts * spec["n_freq"] / (ms * 1e-3),
+        "value": mixed["value"],
         "unit": "grid*freq pts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"plain path: {N[0]}x{N[1]}x{N[2]} grid of a 50x50x300 um pixel, readout + bias "
-                         f"columns (r = 5 um, 5 seeded resistivities), {spec['n_freq']} frequencies to 50 GHz, "
-                         f"{spec['n_time']} x 10 ps, one MIP track with {n_c // 2} e/h pairs ({n_c} carriers); "
-                         f"f32 field/FFT/convolution and H, f64 boundary fit"),
-            "grid": list(N), "n_freq": spec["n_freq"], "n_time": spec["n_time"], "n_carriers": n_c,
-            "n_tracks": n_tr, "parallelism": "single GPU",
+            "workload": (f"mixed path: {N[0]}x{N[1]}x{N[2]} grid of a 50x50x300 um pixel, readout + bias columns "
+                         f"(r = 5 um, 5 seeded resistivities), {spec['n_freq']} frequencies to 50 GHz, {nt} x 10 ps, "
+                         f"{n_tr} MIP tracks of 5e3 e/h pairs ({n_c} carriers) with drift and 0.5 um diffusion per "
+                         f"step; H stored as scaled float16 (80.5 GB), float32 FFTs/synthesis/convolution, float64 "
+                         f"boundary fit"),
+            "grid": list(N), "n_freq": spec["n_freq"], "n_time": nt, "n_carriers": n_c, "n_tracks": n_tr,
+            "h_storage": "float16 holding H * h_scale", "parallelism": "single GPU",
         },
-        "tracks_per_s": n_tr / plain["t_cur"],
-        "carriers_per_s": n_c / plain["t_cur"],
-        "events_per_s": n_steps / plain["t_cur"],
-        "current_roofline": {"kernel": "k_current", "bound": "hbm", "compulsory_bytes": cur_bytes,
-                             "achieved": cur_bytes / plain["t_cur"] / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": cur_bytes / plain["t_cur"] / 1e9 / HBM_PEAK_GBS, "moving_steps": n_steps},
-        "h_grid_freq_pts_per_s": n_pts * spec["n_freq"] / plain["t_h"],
-        "h_grid_time_pts_per_s": n_pts * spec["n_time"] / plain["t_h"],
-        "stage_ms": {k: round(v, 4) for k, v in stage.items()},
-        "roofline": {"kernel": "k_synthesis_pipe", "bound": "hbm", "achieved": plain["achieved"],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": plain["achieved"] / HBM_PEAK_GBS,
-                     "traffic": traffic, "traffic_unit": "bytes/launch", "bytes_per_launch": plain["synth_bytes"]},
-        "solve_report": plain["rep"],
-        "solve_m256": solve_m256,
-        "electronics": electronics,
-        "adjoint": adjoint,
-        "graph": {"ms_per_step": graph_ms, "note": "the same step captured once as a HIP graph and replayed"},
-        "batched_variants": batch,
-        "px256": c5,
-        "f64": {
-            "path": "the whole path in float64 (H in float64, 20 GB; register-FFT synthesis in blocks of 8 samples)",
-            "value": n_pts * spec["n_freq"] / (full64["ms"] * 1e-3),
-            "ms_per_step": full64["ms"],
-            "tracks_per_s": n_tr / full64["t_cur"],
-            "stage_ms": {k: round(v, 4) for k, v in full64["stage"].items()},
-            "roofline": {"kernel": "k_synthesis_pipe (float64 H)", "bound": "hbm", "achieved": full64["achieved"],
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": full64["achieved"] / HBM_PEAK_GBS,
-                         "traffic": SYNTH_TRAFFIC_BYTES["f64"] if measured else None,
-                         "traffic_unit": "bytes/launch", "bytes_per_launch": full64["synth_bytes"]},
-            "rel_err": {"i_float32_path_vs_float64_path": i_err_plain_vs_f64,
-                        "i_mixed_path_vs_float64_path": i_err_mixed_vs_f64},
-        },
-        "mixed": {
-            "h_storage": "float16 holding H * h_scale (h_scale a power of two), decoded in float32",
-            "h_scale": mixed["rep"]["h_scale"],
-            "value": n_pts * spec["n_freq"] / (mixed["ms"] * 1e-3),
-            "ms_per_step": mixed["ms"],
-            "tracks_per_s": n_tr / mixed["t_cur"],
-            "events_per_s": n_steps / mixed["t_cur"],
-            "current_compulsory_gbs": cur_bytes16 / mixed["t_cur"] / 1e9,
-            "h_grid_freq_pts_per_s": n_pts * spec["n_freq"] / mixed["t_h"],
-            "stage_ms": {k: round(v, 4) for k, v in mixed["stage"].items()},
-            "roofline": {"kernel": "k_synthesis_pipe (float16 H)", "bound": "hbm", "achieved": mixed["achieved"],
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": mixed["achieved"] / HBM_PEAK_GBS,
-                         "traffic": SYNTH_TRAFFIC_BYTES["mixed"] if measured else None,
-                         "traffic_unit": "bytes/launch", "bytes_per_launch": mixed["synth_bytes"]},
-            "rel_err": {"i_vs_float32_path": i_err_mixed},
-        },
+        "tracks_per_s": mixed["tracks_per_s"],
+        "carriers_per_s": mixed["carriers_per_s"],
+        "events_per_s": mixed["events_per_s"],
+        "h_grid_freq_pts_per_s": mixed["h_grid_freq_pts_per_s"],
+        "stage_ms": mixed["stage_ms"],
+        "roofline": mixed["roofline_dominant"],
+        "roofline_other_kernel": mixed["roofline_other"],
+        "plain": {k: plain[k] for k in ("value", "ms_per_step", "tracks_per_s", "carriers_per_s", "events_per_s",
+                                        "h_grid_freq_pts_per_s", "stage_ms", "h_bytes")}
+                 | {"roofline": plain["roofline_dominant"], "roofline_other_kernel": plain["roofline_other"],
+                    "h_storage": "float32"},
+        "moving_steps": mixed["moving_steps"],
+        "backward_error_max": mixed["backward_error_max"],
+        "rel_err": err,
     }
-    if not args.no_cpu_baseline:
-        base, err = cpu_baseline(cfg, {"plain": columns_of(plain), "mixed": columns_of(mixed),
-                                       "f64": columns_of(full64)}, args.cpu_seconds)
-        line["cpu_baseline"] = base
-        line["rel_err"] = {"H_sampled_columns_vs_fp64_oracle": err["plain"]}
-        line["mixed"]["rel_err"]["H_sampled_columns_vs_fp64_oracle"] = err["mixed"]
-        line["f64"]["rel_err"]["H_sampled_columns_vs_fp64_oracle"] = err["f64"]
-        if c5 is not None:
-            c5["mixed"]["rel_err_H_sampled_columns_vs_fp64_oracle"] = c5_oracle_errors(c5_cfg, c5_cols)["mixed"]
+    if cpu_base is not None:
+        line["cpu_baseline"] = cpu_base
+    line.update(extras)
     print(json.dumps(line), flush=True)
-    wt.wt_context_destroy(ctx)
+    sys.stdout.flush()
+    sys.stderr.flush()
+    # leave at once: nothing of the GPU work is pending, and interpreter
+    # teardown of the runtime's threads is not part of the measurement
+    os._exit(0)
 
 
 if __name__ == "__main__":
