@@ -697,7 +697,7 @@ wt_status wt_context_set_current_form(wt_context* ctx, int form) {
 wt_status wt_current_workspace(const wt_h_plan* plan, int n_carriers, long long max_events, size_t* bytes) {
     if (!plan || !bytes || n_carriers < 0) return WT_E_INVALID_ARG;
     const Plan& p = plan->p;
-    const wt::ConvTiling tl = wt::conv_tiling(p, p.precision == WT_F64 ? 8 : (p.h_format == WT_H_F16_SCALED ? 2 : 4));
+    const wt::ConvTiling tl = wt::conv_tiling(p);
     const wt::CurrentLayout cl = wt::current_layout(p, tl, n_carriers);
     long long cap = max_events > 0 ? max_events : (long long)n_carriers * p.n_time;
     if (cap < 1) cap = 1;

@@ -123,82 +123,75 @@ hipError_t launch_h_scale(const Plan& p, void* ws, void* h, hipStream_t s);
 hipError_t launch_synthesis(const Plan& p, void* ws, void* h, hipStream_t s);
 hipError_t launch_electronics(int precision, int n_tracks, int nt, double dt, const void* cur, const void* g,
                               const void* noise, double sigma, double frac, void* v, void* feat, hipStream_t s);
-// Tiling of the binned convolution (k_conv_tiles): one workgroup per node
-// column and range of tpr z-tiles (n_zr ranges per column); a z-tile is zt
-// cells, whose zt + 1 nodes are staged in LDS as rows of sl lags (a row
-// holds lag t at position 64 + t; the 64 positions before and those past
-// n_time read as zero).  One workgroup lane per output sample: threads =
-// 64 ceil(n_time / 64).  Events are binned by (cell column, z-tile).
+// Shape of the binned convolution (k_conv.hip).  Events are counted per grid
+// cell and written as four node-column records each (one per (x, y) corner
+// column of the cell), ordered by (node column, lower z-node).  One workgroup
+// per node column, one lane per output sample: threads = 64 ceil(n_time /
+// 64); the column's z-nodes are taken zt at a time.  LDS: the tile's zt + 1
+// nodes as rows of 64 + threads lags (4 values each, of the stored H type),
+// the column's record offsets per z-node (N_z + 1), and rb records.  Per-track
+// sums live in registers: slots of them (the column's track table).
 struct ConvTiling {
-    int zt, n_zt, sl, threads, n_chunks;
-    int tpr, n_zr;
-    int vec;              // full time blocks of H are 16-byte aligned: staged with 16-byte loads
-    size_t n_bins;
-    size_t lds_h, lds_ev, lds_acc, lds_bytes;
+    int threads, n_chunks;
+    int zt;
+    int slots, rb;
+    size_t n_cells, n_cols;
+    size_t off_zoff, off_rbuf, lds_bytes;
 };
-constexpr int kConvSlots = 16;   // per-track accumulators of a workgroup of k_conv_tiles
-// h_elem: bytes per stored H value (2 float16, 4 float, 8 double).
-inline ConvTiling conv_tiling(const Plan& p, int h_elem) {
+// per-track sums per lane (registers), float and double path; the last
+// one takes the tracks past the column's table
+constexpr int kConvSlotsF32 = 32;
+constexpr int kConvSlotsF64 = 16;
+// z-nodes per tile for h_elem bytes per stored value: about 50 KB of rows
+// at 448 lanes (three workgroups per CU) and (zt + 1) nodes' lags in flight
+// per lane in registers
+__host__ __device__ constexpr int conv_tile_nodes(int h_elem) { return h_elem == 2 ? 8 : (h_elem == 4 ? 5 : 2); }
+inline ConvTiling conv_tiling(const Plan& p) {
     ConvTiling t{};
+    auto a16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
     const int nw = (p.n_time + 63) / 64;
     t.threads = 64 * nw;
     t.n_chunks = nw;
-    t.sl = 64 + 64 * nw;
-    const size_t row = (size_t)t.sl * 4 * h_elem;
-    // LDS for the staged rows, beside the per-track accumulators: two
-    // workgroups per CU
-    const size_t acc_elem = h_elem == 8 ? 8 : 4;
-    const size_t lds_acc = (size_t)kConvSlots * t.threads * acc_elem;
-    const size_t total = 76 * 1024;
-    const size_t rest = lds_acc + 64 * 64 + 4 * 1024;
-    const size_t budget = total > rest + 2 * row ? total - rest : 2 * row;
-    int zt = (int)(budget / row) - 1;
-    // time blocks of 8 or 16 samples are prefetched one (node, block) unit
-    // per thread: (zt + 1) blocks-per-node units must not exceed the threads
-    if (p.tb == 8 || p.tb == 16) {
-        const int nb = (p.n_time + p.tb - 1) / p.tb;
-        const int zp = t.threads / nb - 1;
-        zt = zt < zp ? zt : zp;
-    }
-    zt = zt < 1 ? 1 : (zt > 16 ? 16 : zt);
-    t.zt = zt;
-    t.n_zt = (p.N[2] + zt - 1) / zt;
-    // ranges of about max(64, N_z / 4) nodes: enough workgroups where the
-    // events crowd into few columns, few flushes per column otherwise
-    const int span = p.N[2] / 4 > 64 ? p.N[2] / 4 : 64;
-    t.tpr = (span + zt - 1) / zt;
-    if (t.tpr > t.n_zt) t.tpr = t.n_zt;
-    t.n_zr = (t.n_zt + t.tpr - 1) / t.tpr;
-    t.n_bins = (size_t)p.N[0] * p.N[1] * t.n_zt;
-    t.lds_h = (size_t)(zt + 1) * row;
-    const size_t staged = h_elem == 8 ? 64 : 48;   // bytes of a staged event (16-byte aligned)
-    t.lds_ev = (size_t)64 * staged;                // one wavefront's events at a time
-    t.lds_acc = lds_acc;
-    t.lds_bytes = t.lds_h + t.lds_ev + t.lds_acc + (size_t)4 * (t.tpr + 1) * sizeof(unsigned);
-    t.vec = 0;
+    const int h_elem = p.precision == 0 ? 8 : (p.h_format == 1 ? 2 : 4);
+    const size_t recb = p.precision == 0 ? 64 : 32;
+    t.zt = conv_tile_nodes(h_elem);
+    t.slots = (p.precision == 0 ? kConvSlotsF64 : kConvSlotsF32) - 1;
+    // a chunk of records is at most two 16-byte words per thread
+    const int rb = (int)(2 * (size_t)t.threads * 16 / recb);
+    t.rb = rb < 64 ? rb : 64;
+    const size_t rows = (size_t)(t.zt + 1) * (64 + t.threads) * 4 * h_elem;
+    t.off_zoff = a16(rows);
+    t.off_rbuf = t.off_zoff + a16((size_t)(p.N[2] + 1) * sizeof(unsigned));
+    t.lds_bytes = t.off_rbuf + (size_t)t.rb * recb;
+    t.n_cols = (size_t)p.N[0] * p.N[1];
+    t.n_cells = t.n_cols * p.N[2];
     return t;
 }
-// Workspace of the binned convolution (byte offsets): control words, bin
-// counts, bin offsets (n_bins + 1), scan block sums, the per-(carrier, 64
-// steps) moving masks, then the events (as many as fit).
+// Workspace of the binned convolution (byte offsets): control words, cell
+// counts and fill counters (zeroed together), record offsets per (node
+// column, z-node) (n_cells + 1), scan block sums, the per-(carrier, 64 steps)
+// moving masks, the per-column track tables, then the records (as many as
+// fit; four per event).
 struct CurrentLayout {
-    size_t off_ctl, off_count, off_offs, off_bsum, off_mask, off_events, fixed_bytes;
+    size_t off_ctl, off_count, off_fill, off_offs, off_bsum, off_mask, off_tables, off_records, fixed_bytes;
 };
 inline CurrentLayout current_layout(const Plan& p, const ConvTiling& t, long long n_carriers) {
     auto a256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
     CurrentLayout c{};
     c.off_ctl = 0;
-    c.off_count = 256;                                    // right after the control words: zeroed together
-    c.off_offs = a256(c.off_count + t.n_bins * sizeof(unsigned));
-    c.off_bsum = a256(c.off_offs + (t.n_bins + 1) * sizeof(unsigned));
-    c.off_mask = a256(c.off_bsum + ((t.n_bins + 4095) / 4096) * sizeof(unsigned long long));
-    c.off_events = a256(c.off_mask + (size_t)n_carriers * t.n_chunks * sizeof(unsigned long long));
-    c.fixed_bytes = c.off_events;
+    c.off_count = 256;
+    c.off_fill = c.off_count + t.n_cells * sizeof(unsigned);
+    c.off_offs = a256(c.off_fill + t.n_cells * sizeof(unsigned));
+    c.off_bsum = a256(c.off_offs + (t.n_cells + 1) * sizeof(unsigned));
+    c.off_mask = a256(c.off_bsum + ((t.n_cells + 4095) / 4096) * sizeof(unsigned long long));
+    c.off_tables = a256(c.off_mask + (size_t)n_carriers * t.n_chunks * sizeof(unsigned long long));
+    c.off_records = a256(c.off_tables + t.n_cols * t.slots * sizeof(int));
+    c.fixed_bytes = c.off_records;
     (void)p;
     return c;
 }
-// Bytes of one binned event (precision 0: double).
-inline size_t current_event_bytes(const Plan& p) { return p.precision == 0 ? 64 : 32; }
+// Bytes of the four records of one binned event (precision 0: double).
+inline size_t current_event_bytes(const Plan& p) { return 4 * (p.precision == 0 ? 64 : 32); }
 // d_ws may be null (then one wavefront per carrier, no binning).  phase 1:
 // zero the output and bin the events; phase 2 (after phase 1 on the same
 // stream): accumulate.  form: 0 binned from kBinnedMinSteps polyline steps

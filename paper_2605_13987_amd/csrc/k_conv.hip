@@ -8,26 +8,27 @@
 //
 // Section 3 of the paper computes the whole correlation of one carrier per
 // GPU thread and reads H through the texture cache.  Here the events are
-// binned by the grid cell they fall in, and H is read node-column by
-// node-column, each node's lag series once:
+// binned by the grid cell they fall in and H is read node column by node
+// column, each needed lag series once:
 //
-//   k_ev_count    one wavefront per (carrier, 64 steps): which steps move
-//                 (a bit mask), and the number of events per bin, a bin being
-//                 a grid column of cells times a tile of ZT cells along z;
-//   k_scan_*      exclusive scan of the bin counts into bin offsets;
-//   k_ev_scatter  the events, written into their bins (lower cell corner,
-//                 fractions, -q dx, step, track);
-//   k_conv_tiles  one workgroup per block of node columns.  For every node
-//                 column and z-tile that some event touches, the lag series
-//                 of the tile's ZT + 1 nodes are staged in LDS once; the
-//                 events of the four neighbouring cell columns are staged
-//                 beside them, sorted by track; lanes own output samples
-//                 n = 64 w + lane and accumulate, per track, the two z-corners
-//                 of every event that lie in this node column.  Per-track sums
-//                 stay in registers until the workgroup ends, then go to the
-//                 output with one atomic per sample and track.
+//   k_ev_count     one wavefront per (carrier, 64 steps): which steps move
+//                  (a bit mask), and the number of events per cell;
+//   k_node_count,  records per (node column, z-node): the events of the four
+//   k_scan_*       cells around it at that z, scanned into offsets;
+//   k_ev_scatter   every event written as four records, one per corner
+//                  column of its cell: step, track and -q dx times the
+//                  trilinear weights of its two z-nodes in that column;
+//   k_slots        one wavefront per node column: its distinct tracks (the
+//                  slots of its per-track sums), and each record's slot;
+//   k_conv_rows    one workgroup per node column, one lane per output
+//                  sample n.  The column's nodes go through LDS a tile of
+//                  z-nodes at a time, as rows of lags (the next tile and the
+//                  next records loading meanwhile); for each record every
+//                  lane adds the projection at lag n - m of its two z-nodes
+//                  to its track's sum, one register per track; the registers
+//                  go to the output once, when the workgroup ends.
 //
-// Without a workspace, or when the events do not fit the caller's
+// Without a workspace, or when the records do not fit the caller's
 // workspace, k_current runs instead: one wavefront per carrier, lanes over
 // output samples, the 8 corner lag series of each moving step read from
 // global memory (decided on the device, so nothing synchronises).
@@ -43,7 +44,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kMaxJ = kMaxTime / kWave;
-constexpr int kSlots = kConvSlots;     // track accumulators of a workgroup of k_conv_tiles
 constexpr int kScanItems = 4096;       // bin counts per workgroup of the scan
 constexpr unsigned long long kBinnedMinSteps = 1ull << 24;   // polyline steps from which wt_current bins
 
@@ -288,63 +288,25 @@ k_current(Plan p, const TH* H, const float* decode, int n_carriers, int n_tracks
 
 // ---------------------------------------------------------------- binned form
 
-// An event in global memory: its lower corner z index and step
-// (zm = z0 | m << 16), track, fractions inside the cell and -q dx.  The
-// cell column is the bin's.
+// A node-column record: one event as seen from one of the four (x, y) corner
+// columns of its cell.  info holds its step m, its lower z-node inside its
+// z-tile and the slot of its track (see kNoSlot); g0 and g1 are -q dx times
+// the trilinear weights of the event's lower and upper z-node in this column.
+// Records are ordered by (node column, lower z-node); inside one such bin by
+// the cell they come from, then by arrival.
 template <typename T>
-struct alignas(16) EvRec {
-    unsigned zm;
-    int track;
-    T f[3];
-    T g[3];
-};
-
-// An event as one node column of k_conv_tiles uses it: off = byte offset in
-// the staged rows of lag 0 - m of its lower z-corner (lane n reads
-// off + n * sizeof(Lag4), the upper corner one row further), row = the byte
-// offset of that row (lanes before the step read its zero positions);
-// info = the accumulator slot of its track (kSlots: none) | 64 if it is the
-// last event of its track's run | track << 8; and -q dx times the trilinear
-// weights of its two corners in this column.
-template <typename T>
-struct alignas(16) Staged {
-    int off;
-    int row;
+struct alignas(sizeof(T) == 8 ? 64 : 32) NodeRec {
     int info;
-    T g0[3];
-    T g1[3];
-};
-constexpr int kLastOfRun = 64;
-
-// One lag of one staged node: the three components and a zero.
-template <typename TH>
-struct alignas(4 * sizeof(TH)) Lag4 {
-    TH v[4];
+    int track;
+    T g[6];
 };
 
-// The three components of a staged lag, read as one word (8 bytes for
-// float16, 16 for float).
-template <typename T, typename TH>
-__device__ inline void load_lag(const Lag4<TH>* a, T& x, T& y, T& z) {
-    if constexpr (std::is_same<TH, _Float16>::value) {
-        const uint2 u = *reinterpret_cast<const uint2*>(a);
-        x = (T)__builtin_bit_cast(_Float16, (unsigned short)(u.x & 0xffffu));
-        y = (T)__builtin_bit_cast(_Float16, (unsigned short)(u.x >> 16));
-        z = (T)__builtin_bit_cast(_Float16, (unsigned short)(u.y & 0xffffu));
-    } else {
-        const Lag4<TH> l = *a;
-        x = (T)l.v[0];
-        y = (T)l.v[1];
-        z = (T)l.v[2];
-    }
-}
-
-// Workspace control words: [0] number of events, [1] 1 when they do not fit
-// (the direct form then runs), [2] the event capacity.
+// Workspace control words: [0] number of records (4 per event), [1] 1 when
+// they do not fit (the direct form then runs), [2] the record capacity.
 __global__ void k_set_capacity(unsigned long long* ctl, unsigned long long cap) { ctl[2] = cap; }
 
 // One wavefront per (carrier, 64 steps): the bit mask of the steps that are
-// events, and one count per event in its bin.
+// events, and one count per event in its cell.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_ev_count(Plan p, ConvTiling tl, int n_carriers, int n_tracks, const T* pos, const int* track,
@@ -357,17 +319,33 @@ k_ev_count(Plan p, ConvTiling tl, int n_carriers, int n_tracks, const T* pos, co
     const int m = (int)(wave - c * tl.n_chunks) * kWave + lane;
     const int tr = track[c];
     bool ev = false;
-    unsigned bin = 0;
+    size_t cell = 0;
     if (tr >= 0 && tr < n_tracks && m < nt) {
         const T* P = pos + c * (size_t)(nt + 1) * 3;
         int x0, y0, z0;
         T fx, fy, fz, dx, dy, dz;
         ev = event_cell(p, P, m, x0, y0, z0, fx, fy, fz, dx, dy, dz);
-        bin = ((unsigned)x0 * p.N[1] + y0) * tl.n_zt + z0 / tl.zt;
+        cell = ((size_t)x0 * p.N[1] + y0) * p.N[2] + z0;
     }
     const unsigned long long bal = __ballot(ev);
     if (lane == 0) mask[wave] = bal;
-    if (ev) atomicAdd(count + bin, 1u);
+    if (ev) atomicAdd(count + cell, 1u);
+}
+
+// Records per (node column, z-node): the events of the four cells that have
+// this node column as a corner column, at this z.
+__global__ void __launch_bounds__(kBlock)
+k_node_count(Plan p, const unsigned* count, unsigned* nodes) {
+    const int Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
+    const size_t n = (size_t)Nx * Ny * Nz;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t col = i / Nz;
+        const int z = (int)(i - col * Nz);
+        const int X = (int)(col / Ny), Y = (int)(col - (size_t)X * Ny);
+        const int Xm = X == 0 ? Nx - 1 : X - 1, Ym = Y == 0 ? Ny - 1 : Y - 1;
+        nodes[i] = count[((size_t)X * Ny + Y) * Nz + z] + count[((size_t)X * Ny + Ym) * Nz + z] +
+                   count[((size_t)Xm * Ny + Y) * Nz + z] + count[((size_t)Xm * Ny + Ym) * Nz + z];
+    }
 }
 
 // Inclusive scan of one value per thread over the workgroup (LDS scratch of
@@ -396,7 +374,7 @@ __device__ inline U block_scan(U v, U* wsum, U* total) {
     return v + (w > 0 ? wsum[w - 1] : (U)0);
 }
 
-// Sum of each workgroup's 4096 bin counts (64-bit).
+// Sum of each workgroup's 4096 counts (64-bit).
 __global__ void __launch_bounds__(kScanThreads)
 k_scan_reduce(const unsigned* count, size_t n, unsigned long long* bsum) {
     __shared__ unsigned long long s[kScanThreads];
@@ -416,7 +394,7 @@ k_scan_reduce(const unsigned* count, size_t n, unsigned long long* bsum) {
 }
 
 // One workgroup: exclusive scan of the block sums in place, the number of
-// events, and the overflow flag when they exceed the capacity.
+// records, and the overflow flag when they exceed the capacity.
 __global__ void __launch_bounds__(kScanThreads)
 k_scan_top(unsigned long long* bsum, int nb, unsigned long long* ctl) {
     __shared__ unsigned long long wsum[kScanThreads / kWave];
@@ -436,10 +414,11 @@ k_scan_top(unsigned long long* bsum, int nb, unsigned long long* ctl) {
     }
 }
 
-// offs[i] = exclusive prefix of count, for i < n; offs[n] = the total
-// (32-bit: only used when the events fit the capacity, below 2^32).
+// In place: the counts become their exclusive prefix (offs[n] = the total;
+// 32-bit: only used when the records fit the capacity, below 2^32).  Each
+// thread reads its own counts before it writes their offsets.
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_apply(const unsigned* count, size_t n, const unsigned long long* bsum, unsigned* offs) {
+k_scan_apply(unsigned* offs, size_t n, const unsigned long long* bsum) {
     __shared__ unsigned wsum[kScanThreads / kWave];
     __shared__ unsigned total;
     constexpr int per = kScanItems / kScanThreads;
@@ -448,7 +427,7 @@ k_scan_apply(const unsigned* count, size_t n, const unsigned long long* bsum, un
     unsigned sum = 0;
 #pragma unroll
     for (int k = 0; k < per; ++k) {
-        v[k] = base + k < n ? count[base + k] : 0u;
+        v[k] = base + k < n ? offs[base + k] : 0u;
         sum += v[k];
     }
     unsigned run = block_scan(sum, wsum, &total) - sum + (unsigned)bsum[blockIdx.x];
@@ -457,17 +436,20 @@ k_scan_apply(const unsigned* count, size_t n, const unsigned long long* bsum, un
         if (base + k < n) offs[base + k] = run;
         run += v[k];
     }
-    // the thread holding the last bin writes the total after it
+    // the thread holding the last count writes the total after it
     if (base < n && base + per >= n) offs[n] = run;
 }
 
-// One wavefront per (carrier, 64 steps) again: every event written into its
-// bin (the order inside a bin is not fixed).
+// One wavefront per (carrier, 64 steps) again: every event written as four
+// node-column records.  In the bin of node column (X, Y) and z-node z0 the
+// records of cell (X, Y) come first, then those of cells (X, Y - 1),
+// (X - 1, Y) and (X - 1, Y - 1); inside one cell in the order the events
+// arrive (fill counter).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charge, const int* track,
-             const unsigned long long* mask, const unsigned* offs, unsigned* count, const unsigned long long* ctl,
-             EvRec<T>* ev) {
+             const unsigned long long* mask, const unsigned* count, unsigned* fill, const unsigned* offs,
+             const unsigned long long* ctl, NodeRec<T>* rec) {
     const int lane = threadIdx.x & (kWave - 1);
     const size_t wave = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     const size_t c = wave / tl.n_chunks;
@@ -475,342 +457,390 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
     const unsigned long long bits = mask[wave];
     if (bits == 0ull || ctl[1] != 0ull) return;
     if (!((bits >> lane) & 1ull)) return;
-    const int nt = p.n_time;
+    const int nt = p.n_time, Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
     const int m = (int)(wave - c * tl.n_chunks) * kWave + lane;
     const T* P = pos + c * (size_t)(nt + 1) * 3;
     int x0, y0, z0;
     T fx, fy, fz, dx, dy, dz;
     if (!event_cell(p, P, m, x0, y0, z0, fx, fy, fz, dx, dy, dz)) return;   // cannot happen: the mask says it moves
-    const unsigned bin = ((unsigned)x0 * p.N[1] + y0) * tl.n_zt + z0 / tl.zt;
-    const unsigned slot = offs[bin] + atomicSub(count + bin, 1u) - 1u;
+    auto cell = [&](int x, int y) { return ((size_t)x * Ny + y) * Nz + z0; };
+    const int x1 = x0 + 1 == Nx ? 0 : x0 + 1, y1 = y0 + 1 == Ny ? 0 : y0 + 1, ym = y0 == 0 ? Ny - 1 : y0 - 1;
+    const unsigned j = atomicAdd(fill + cell(x0, y0), 1u);
+    // records of the cells before this one in each of the four bins
+    const unsigned cA = count[cell(x0, y1)], cB = count[cell(x1, y0)], cC = count[cell(x1, ym)],
+                   cD = count[cell(x1, y1)];
     const T q = charge[c];
-    EvRec<T> r;
-    r.zm = (unsigned)z0 | ((unsigned)m << 16);
-    r.track = track[c];
-    r.f[0] = fx;
-    r.f[1] = fy;
-    r.f[2] = fz;
-    r.g[0] = -q * dx;
-    r.g[1] = -q * dy;
-    r.g[2] = -q * dz;
-    ev[slot] = r;
-}
-
-// Geometry of the staged z-tile of a node column: nodes zb .. zb + ns - 1
-// (node N_z read as node 0), time blocks of TB samples (nb of them, the last
-// last_len long) of the H layout H[x][y][tb][z][tin][a].
-struct TileGeom {
-    int zb, ns, nb, TB, last_len;
-};
-
-// One (node, time block) unit per thread: its TBC x 3 values, prefetched in
-// registers as 16-byte words when the block is full and aligned.
-template <int TBC, typename TH>
-struct HPrefetch {
-    static constexpr int kWords = TBC > 0 ? TBC * 3 * (int)sizeof(TH) / 16 : 1;
-    uint4 w[kWords];
-    bool full;
-};
-
-template <int TBC, typename TH>
-__device__ inline const TH* unit_src(const Plan& p, const TH* colH, const TileGeom& g, int s, int tb, int& len) {
-    int z = g.zb + s;
-    if (z >= p.N[2]) z -= p.N[2];
-    len = tb == g.nb - 1 ? g.last_len : g.TB;
-    return colH + (size_t)tb * g.TB * p.N[2] * 3 + (size_t)z * len * 3;
-}
-
-// The loads are unconditional (a unit that is not a full block loads the
-// column's first block instead and is marked not full), so that their
-// registers are written by the loads alone and nothing waits for them before
-// the next tile commits them.
-template <int TBC, typename TH>
-__device__ inline void prefetch_h(const Plan& p, const TH* colH, const TileGeom& g, HPrefetch<TBC, TH>& pf) {
-    if constexpr (TBC > 0) {
-        int s = (int)threadIdx.x % g.ns, tb = (int)threadIdx.x / g.ns;
-        pf.full = tb < g.nb && (tb < g.nb - 1 || g.last_len == TBC);
-        if (!pf.full) s = tb = 0;                      // block 0 is a full block of TBC samples
-        int len;
-        const uint4* s4 = reinterpret_cast<const uint4*>(unit_src<TBC>(p, colH, g, s, tb, len));
+    const int tr = track[c];
+    const T gx = -q * dx, gy = -q * dy, gz = -q * dz;
 #pragma unroll
-        for (int k = 0; k < HPrefetch<TBC, TH>::kWords; ++k) pf.w[k] = s4[k];
-    } else {
-        pf.full = false;
+    for (int k = 0; k < 4; ++k) {
+        const int ox = k >> 1, oy = k & 1;
+        const unsigned before = k == 0 ? 0u : k == 1 ? cA : k == 2 ? cB + cC : cD + cB + cA;
+        const size_t slot = offs[cell(ox ? x1 : x0, oy ? y1 : y0)] + before + j;
+        const T wxy = (ox ? fx : (T)1 - fx) * (oy ? fy : (T)1 - fy);
+        const T w0 = wxy * ((T)1 - fz), w1 = wxy * fz;
+        NodeRec<T> r;
+        r.info = m | ((z0 % tl.zt) << 16);
+        r.track = tr;
+        r.g[0] = gx * w0;
+        r.g[1] = gy * w0;
+        r.g[2] = gz * w0;
+        r.g[3] = gx * w1;
+        r.g[4] = gy * w1;
+        r.g[5] = gz * w1;
+        rec[slot] = r;
     }
 }
 
-// Write the tile's lag series into the LDS rows (lag t at row position 64 + t):
-// the prefetched unit of this thread from registers, every other unit
-// (partial last blocks, unaligned layouts, blocks not a compile-time size)
-// value by value from global memory.
-template <int TBC, typename TH>
-__device__ inline void commit_h(const Plan& p, const ConvTiling& tl, const TH* colH, const TileGeom& g,
-                                const HPrefetch<TBC, TH>& pf, Lag4<TH>* hs) {
-    const int units = g.ns * g.nb;
-    for (int u = threadIdx.x; u < units; u += blockDim.x) {
-        const int s = u % g.ns, tb = u / g.ns;
-        Lag4<TH>* dst = hs + s * tl.sl + 64 + tb * g.TB;
-        if constexpr (TBC > 0) {
-            if (u == (int)threadIdx.x && pf.full) {
-                union {
-                    uint4 w[HPrefetch<TBC, TH>::kWords];
-                    TH h[TBC * 3];
-                } buf;
-#pragma unroll
-                for (int k = 0; k < HPrefetch<TBC, TH>::kWords; ++k) buf.w[k] = pf.w[k];
-#pragma unroll
-                for (int i = 0; i < TBC; ++i) {
-                    Lag4<TH> l;
-                    l.v[0] = buf.h[3 * i];
-                    l.v[1] = buf.h[3 * i + 1];
-                    l.v[2] = buf.h[3 * i + 2];
-                    l.v[3] = (TH)0;
-                    dst[i] = l;
-                }
-                continue;
+// Info word of a record: step m (bits 0-15), its lower z-node inside its
+// z-tile (bits 16-23), the slot of its track in the column's track table
+// (bits 24-29, kNoSlot when the track is not in it).
+constexpr int kNoSlot = 63;
+
+// One wavefront per node column: the column's distinct tracks in order of
+// first appearance, up to tl.slots of them (-1 pads the table), and every
+// record's slot in its info word.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, const unsigned long long* ctl, int* tables) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const size_t col = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (col >= tl.n_cols || ctl[1] != 0ull) return;
+    const int S = tl.slots, Nz = p.N[2];
+    const unsigned r0 = offs[col * Nz], r1 = offs[col * Nz + Nz];
+    int tab = -1, used = 0;
+    for (unsigned b = r0; b < r1 && used < S; b += kWave) {
+        const unsigned r = b + (unsigned)lane;
+        const int trk = r < r1 ? rec[r].track : -1;
+        unsigned long long pending = __ballot(trk >= 0);
+        while (pending && used < S) {
+            const int tk = __builtin_amdgcn_readlane(trk, (int)__builtin_ctzll(pending));
+            pending &= ~__ballot(trk == tk);
+            if (__ballot(tab == tk) == 0ull) {
+                if (lane == used) tab = tk;
+                ++used;
             }
         }
-        int len;
-        const TH* src = unit_src<TBC>(p, colH, g, s, tb, len);
-        for (int i = 0; i < len; ++i) {
-            Lag4<TH> l;
-            l.v[0] = src[3 * i];
-            l.v[1] = src[3 * i + 1];
-            l.v[2] = src[3 * i + 2];
-            l.v[3] = (TH)0;
-            dst[i] = l;
+    }
+    if (lane < S) tables[col * S + lane] = tab;
+    for (unsigned b = r0; b < r1; b += kWave) {
+        const unsigned r = b + (unsigned)lane;
+        const bool have = r < r1;
+        const int trk = have ? rec[r].track : -1;
+        int slot = kNoSlot;
+        unsigned long long pending = __ballot(have);
+        while (pending) {
+            const int tk = __builtin_amdgcn_readlane(trk, (int)__builtin_ctzll(pending));
+            const unsigned long long same = __ballot(trk == tk) & pending;
+            const unsigned long long hs = __ballot(tab == tk);
+            if ((same >> lane) & 1ull) slot = hs ? (int)__builtin_ctzll(hs) : kNoSlot;
+            pending &= ~same;
         }
+        if (have) rec[r].info |= slot << 24;
     }
 }
 
-// Contribution of a staged event for this lane's sample (nb = the lane's
-// byte offset n * sizeof(Lag4), slb = the bytes of one row).
+// One node at one lane's lag as loaded: float16 as the 8 bytes from the
+// 4-byte aligned word at or below its three values, else the three values.
+template <typename TH>
+struct LagRaw {
+    TH v[3];
+};
+template <>
+struct LagRaw<_Float16> {
+    unsigned lo, hi;
+};
+template <int ZT, typename TH>
+struct RawTile {
+    LagRaw<TH> n[ZT + 1];
+};
+
+// An object in LDS (address space 3), so that accesses stay LDS
+// instructions; LDS is read and written through plain and native vector
+// types only.
+template <typename X>
+using Lds = __attribute__((address_space(3))) X;
+typedef unsigned NU2 __attribute__((ext_vector_type(2)));
+typedef unsigned NU4 __attribute__((ext_vector_type(4)));
+template <typename X>
+using Vec4 = X __attribute__((ext_vector_type(4)));
+
+// One lag of a node in an LDS row: the three components (and one unused).
+template <typename TH>
+struct alignas(4 * sizeof(TH)) Lag4 {
+    TH v[4];
+};
+
+// Load this lane's lag of a node (e = element offset of the lag in the
+// column; a float16 buffer has at least 2 bytes after its last value).
+template <typename TH>
+__device__ inline void load_lag(const TH* colH, unsigned e, LagRaw<TH>& o) {
+    if constexpr (std::is_same<TH, _Float16>::value) {
+        const Dword2 w = *reinterpret_cast<const Dword2*>(colH + (e & ~1u));
+        o.lo = w.lo;
+        o.hi = w.hi;
+    } else {
+        o.v[0] = colH[e];
+        o.v[1] = colH[e + 1];
+        o.v[2] = colH[e + 2];
+    }
+}
+
+// A loaded lag as a row entry (odd: float16 values starting at an odd
+// element, in the high half of the first word).
+template <typename TH>
+__device__ __attribute__((always_inline)) inline void store_lag(const LagRaw<TH>& a, unsigned odd, Lds<Lag4<TH>>* dst) {
+    if constexpr (std::is_same<TH, _Float16>::value) {
+        const unsigned sh = odd * 16u;
+        NU2 w;
+        w.x = __builtin_amdgcn_alignbit(a.hi, a.lo, sh);
+        w.y = a.hi >> sh;
+        *reinterpret_cast<Lds<NU2>*>(dst) = w;
+    } else {
+        Vec4<TH> l;
+        l.x = a.v[0];
+        l.y = a.v[1];
+        l.z = a.v[2];
+        l.w = (TH)0;
+        *reinterpret_cast<Lds<Vec4<TH>>*>(dst) = l;
+    }
+}
+
+// g . H for one row entry, added to v.
 template <typename T, typename TH>
-__device__ __attribute__((always_inline)) inline T event_value(const Staged<T>& se, const unsigned char* hs, int nb,
-                                                               int slb) {
-    const int a0 = max(nb + se.off, se.row);
-    T x0, y0, z0, x1, y1, z1;
-    load_lag(reinterpret_cast<const Lag4<TH>*>(hs + a0), x0, y0, z0);
-    load_lag(reinterpret_cast<const Lag4<TH>*>(hs + a0 + slb), x1, y1, z1);
-    T v = se.g0[0] * x0;
-    v += se.g0[1] * y0;
-    v += se.g0[2] * z0;
-    v += se.g1[0] * x1;
-    v += se.g1[1] * y1;
-    v += se.g1[2] * z1;
+__device__ __attribute__((always_inline)) inline T project(const Lds<Lag4<TH>>* src, const T* g, T v) {
+    if constexpr (std::is_same<TH, _Float16>::value) {
+        const NU2 w = *reinterpret_cast<const Lds<NU2>*>(src);
+        v = fma(g[0], (T)__builtin_bit_cast(_Float16, (unsigned short)(w.x & 0xffffu)), v);
+        v = fma(g[1], (T)__builtin_bit_cast(_Float16, (unsigned short)(w.x >> 16)), v);
+        v = fma(g[2], (T)__builtin_bit_cast(_Float16, (unsigned short)(w.y & 0xffffu)), v);
+    } else {
+        const Vec4<TH> l = *reinterpret_cast<const Lds<Vec4<TH>>*>(src);
+        v = fma(g[0], (T)l.x, v);
+        v = fma(g[1], (T)l.y, v);
+        v = fma(g[2], (T)l.z, v);
+    }
     return v;
 }
 
-// One workgroup per (node column, range of z-tiles); lanes own output
-// samples n = 64 w + lane.  Per z-tile with events: the tile's lag series in
-// LDS (prefetched during the previous tile); its events (the four
-// neighbouring cell columns' bins), 64 at a time, staged by the first
-// wavefront with their two z-corner weights in this column and grouped by
-// track with ballots (runs of one track, each with an accumulator slot);
-// then every wavefront walks every event, four at a time, and adds a run's
-// sum to its track's accumulator in LDS when the run ends (the lanes own
-// their samples, so no two lanes touch one accumulator).  The accumulators go
-// to the output once, when the workgroup ends.
-template <int TBC, typename T, typename TH>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
-k_conv_tiles(Plan p, ConvTiling tl, const TH* H, const float* decode, const unsigned* offs, const EvRec<T>* ev,
-             const unsigned long long* ctl, int n_tracks, T* out) {
-    if (ctl[1] != 0ull) return;                        // the direct form takes these events
-    extern __shared__ __align__(16) unsigned char smem[];
-    Lag4<TH>* hs = reinterpret_cast<Lag4<TH>*>(smem);                             // [zt + 1][sl]
-    Staged<T>* st = reinterpret_cast<Staged<T>*>(smem + tl.lds_h);               // [64]
-    T* acc = reinterpret_cast<T*>(smem + tl.lds_h + tl.lds_ev);                  // [kSlots][threads]
-    unsigned* boffs = reinterpret_cast<unsigned*>(smem + tl.lds_h + tl.lds_ev + tl.lds_acc);   // [4][tpr + 1]
-    __shared__ int s_table[kSlots];
-    __shared__ int s_nstaged;
-
-    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const int n = tid;                                  // this thread's output sample
-    const int nt = p.n_time, Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
-    const int ZT = tl.zt, SL = tl.sl, nzt = tl.n_zt;
-    const int col = blockIdx.x / tl.n_zr, zr = blockIdx.x - col * tl.n_zr;
-    const int x = col / Ny, y = col - x * Ny;
-    const int tA = zr * tl.tpr, tB = min(nzt, tA + tl.tpr), nr = tB - tA;
-    if (nr <= 0) return;
-    const int R = nr + 1;
-    // bin offsets of the four cell columns with a corner on node column
-    // (x, y) (q = 2 qx + qy: cell x = x - 1 + qx, cell y = y - 1 + qy), tiles tA .. tB
-    for (int i = tid; i < 4 * R; i += nthr) {
-        const int q = i / R, k = i - q * R;
-        const int cx = (q >> 1) ? x : (x == 0 ? Nx - 1 : x - 1);
-        const int cy = (q & 1) ? y : (y == 0 ? Ny - 1 : y - 1);
-        boffs[i] = offs[((size_t)cx * Ny + cy) * nzt + tA + k];
-    }
-    for (int s = tid; s < kSlots; s += nthr) s_table[s] = -1;
-    __syncthreads();
-    auto count_of = [&](int k) -> unsigned {
-        return (boffs[k + 1] - boffs[k]) + (boffs[R + k + 1] - boffs[R + k]) + (boffs[2 * R + k + 1] - boffs[2 * R + k]) +
-               (boffs[3 * R + k + 1] - boffs[3 * R + k]);
-    };
-    if (boffs[nr] - boffs[0] + boffs[R + nr] - boffs[R] + boffs[2 * R + nr] - boffs[2 * R] + boffs[3 * R + nr] -
-            boffs[3 * R] ==
-        0u)
-        return;                                          // no event touches this range
-    // the lags outside [0, nt) of every staged row read as zero: lanes before
-    // an event's step and lanes past the last sample touch them
-    for (int i = tid; i < (ZT + 1) * SL; i += nthr) {
-        const int lag = i % SL;
-        if (lag < 64 || lag >= 64 + nt) {
-            Lag4<TH> z;
-            z.v[0] = z.v[1] = z.v[2] = z.v[3] = (TH)0;
-            hs[i] = z;
-        }
-    }
+// A record from LDS, as whole 16-byte words.
+template <typename T>
+__device__ __attribute__((always_inline)) inline NodeRec<T> lds_record(const Lds<NodeRec<T>>* p) {
+    union {
+        NU4 w[sizeof(NodeRec<T>) / 16];
+        NodeRec<T> r;
+    } u;
+    const Lds<NU4>* s = reinterpret_cast<const Lds<NU4>*>(p);
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) acc[s * nthr + n] = (T)0;
-    const TH* colH = H + (size_t)col * Nz * nt * 3;
+    for (int k = 0; k < (int)(sizeof(NodeRec<T>) / 16); ++k) u.w[k] = s[k];
+    return u.r;
+}
+
+// Up to two 16-byte words per thread of a run of records, in flight between
+// their load and their store into LDS.
+struct RecWords {
+    NU4 w[2];
+};
+
+// The per-track sums of one lane: a block of registers indexed with the
+// slot (uniform across the wavefront).
+template <typename T>
+struct SlotSums {
+    static constexpr int N = sizeof(T) == 8 ? kConvSlotsF64 : kConvSlotsF32;
+    using V = T __attribute__((ext_vector_type(N)));
+};
+
+// One workgroup per node column, one lane per output sample n (64
+// ceil(n_time / 64) lanes; those past the last sample compute and drop).
+// The column's z-nodes go in tiles of ZT: the tile's ZT + 1 nodes are rows of
+// lags in LDS (64 zero lags, then lags 0 .. n_time - 1), written by the lanes
+// from the lag each loaded (lane tau: lag tau of every node of the tile).
+// Records go through LDS in chunks of at most tl.rb.  For each record every
+// lane reads lag n - m of its two z-nodes and adds g0 . H(z0) + g1 . H(z0 + 1)
+// to the sum of the record's track (one register per slot of the column's
+// track table; tracks past the table go to the output directly).  While a
+// chunk is processed the next chunk's records, and the next tile's nodes when
+// the chunk starts one, are in flight.  The registers go to the output at
+// the end, one atomic per sample and track.
+template <int ZT, typename T, typename TH>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 6)))
+k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __restrict__ decode,
+            const unsigned* __restrict__ offs, const NodeRec<T>* __restrict__ rec, const int* __restrict__ tables,
+            const unsigned long long* __restrict__ ctl, int n_tracks, T* __restrict__ out) {
+    if (ctl[1] != 0ull) return;                          // the direct form takes these events
+    const int Nz = p.N[2], nt = p.n_time;
+    const size_t col = blockIdx.x;
+    const unsigned* no = offs + col * Nz;
+    const unsigned cbeg = no[0];
+    if (no[Nz] == cbeg) return;                          // no record in this column
+    extern __shared__ __align__(16) unsigned char smem[];
+    Lds<unsigned char>* lds = (Lds<unsigned char>*)smem;
+    Lds<Lag4<TH>>* rows = reinterpret_cast<Lds<Lag4<TH>>*>(lds);                 // [ZT + 1][RL]
+    Lds<unsigned>* zoff = reinterpret_cast<Lds<unsigned>*>(lds + tl.off_zoff);   // [Nz + 1]
+    Lds<NodeRec<T>>* rbuf = reinterpret_cast<Lds<NodeRec<T>>*>(lds + tl.off_rbuf);   // [rb]
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), nthr = blockDim.x;
+    const int S = tl.slots, RB = tl.rb, RL = 64 + nthr;
+    constexpr unsigned LB = sizeof(Lag4<TH>);
+    const unsigned row_b = (unsigned)RL * LB;
+    for (int i = tid; i < (ZT + 1) * 64; i += nthr) {
+        Lds<NU2>* z = reinterpret_cast<Lds<NU2>*>(rows + (i >> 6) * RL + (i & 63));
+#pragma unroll
+        for (int w = 0; w < (int)(sizeof(Lag4<TH>) / 8); ++w) z[w] = NU2{0u, 0u};
+    }
+    for (int i = tid; i <= Nz; i += nthr) zoff[i] = no[i] - cbeg;       // record offsets inside the column
+    const int tabv = lane < S ? tables[col * S + lane] : -1;
+    constexpr int U4 = (int)(sizeof(NodeRec<T>) / 16);
+    const NU4* rsrc = reinterpret_cast<const NU4*>(rec + cbeg);
+    // records [a, b) of the column into registers (every thread loads: past
+    // the run its last word, an empty run the column's first), then into LDS
+    // (every thread stores: past the run the last word again)
+    auto stage_load = [=](RecWords& t, unsigned a, unsigned b) {
+        const int n = (int)(b - a) * U4;
+        const size_t base = n > 0 ? (size_t)a * U4 : 0;
+        const int last = n > 0 ? n - 1 : 0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            // volatile: issued here, ahead of the chunk's work, not moved down
+            // to the store that uses them
+            t.w[j] = *reinterpret_cast<const volatile NU4*>(rsrc + base + min(tid + j * nthr, last));
+        }
+    };
+    auto stage_store = [=](const RecWords& t, unsigned a, unsigned b) {
+        const int n = (int)(b - a) * U4;
+        const int last = n > 0 ? n - 1 : 0;
+        Lds<NU4>* dst = reinterpret_cast<Lds<NU4>*>(rbuf);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) dst[min(tid + j * nthr, last)] = t.w[j];
+    };
+
+    // the lag this lane loads (lanes past the last lag load the last one and
+    // do not store it)
+    const int tl0 = tid < nt ? tid : nt - 1;
     const int nb = (nt + p.tb - 1) / p.tb;
-    constexpr int LB = (int)sizeof(Lag4<TH>);
-    const int slb = SL * LB;
-    const int nbyte = n * LB;
-    auto geom = [&](int k) {
-        TileGeom g;
-        g.zb = (tA + k) * ZT;
-        g.ns = min(ZT, Nz - g.zb) + 1;
-        g.nb = nb;
-        g.TB = p.tb;
-        g.last_len = nt - (nb - 1) * p.tb;
-        return g;
-    };
-    // event i of tile k: which of the four bins (q), and its record
-    auto locate = [&](int k, unsigned i, int& q) -> unsigned {
-        const unsigned b0 = boffs[k], b1 = boffs[R + k], b2 = boffs[2 * R + k], b3 = boffs[3 * R + k];
-        const unsigned pre1 = boffs[k + 1] - b0;
-        const unsigned pre2 = pre1 + (boffs[R + k + 1] - b1);
-        const unsigned pre3 = pre2 + (boffs[2 * R + k + 1] - b2);
-        q = (i >= pre1) + (i >= pre2) + (i >= pre3);
-        return q == 0 ? b0 + i : q == 1 ? b1 + (i - pre1) : q == 2 ? b2 + (i - pre2) : b3 + (i - pre3);
-    };
+    const int tb = tl0 / p.tb, tin = tl0 - tb * p.tb;
+    const int len = tb == nb - 1 ? nt - (nb - 1) * p.tb : p.tb;
+    const unsigned e0 = (unsigned)(tb * p.tb * Nz * 3 + tin * 3), zs = (unsigned)(len * 3);
+    const TH* colH = H + col * Nz * (size_t)nt * 3;
     T dec = (T)1;
     if constexpr (!std::is_same<T, TH>::value) dec = (T)decode[0];
-
-    int k = nr - 1;
-    while (k >= 0 && count_of(k) == 0u) --k;
-    HPrefetch<TBC, TH> pf;
-    prefetch_h<TBC>(p, colH, geom(k), pf);
-    // the first wavefront holds the next 64 events of the tile in its lanes
-    EvRec<T> rnext;
-    int qnext = 0;
-    if (w == 0 && (unsigned)lane < count_of(k)) rnext = ev[locate(k, (unsigned)lane, qnext)];
-    while (k >= 0) {
-        int kn = k - 1;
-        while (kn >= 0 && count_of(kn) == 0u) --kn;
-        const TileGeom g = geom(k);
-        const unsigned E = count_of(k);
-        __syncthreads();                                 // the previous tile's rows and events are read
-        commit_h<TBC>(p, tl, colH, g, pf, hs);
-        if (kn >= 0) prefetch_h<TBC>(p, colH, geom(kn), pf);   // lands while this tile is processed
-        for (unsigned e0 = 0; e0 < E; e0 += kWave) {
-            if (e0 > 0) __syncthreads();                 // the previous chunk's events are read
-            if (w == 0) {
-                // stage events e0 .. e0 + 63 of this tile, grouped by track
-                const unsigned i = e0 + (unsigned)lane;
-                const bool have = i < E;
-                EvRec<T> r = rnext;
-                int q = qnext;
-                if (e0 > 0 && have) r = ev[locate(k, i, q)];
-                Staged<T> sr;
-                if (have) {
-                    const T wx = (q >> 1) ? (T)1 - r.f[0] : r.f[0];
-                    const T wy = (q & 1) ? (T)1 - r.f[1] : r.f[1];
-                    const T w1 = wx * wy * r.f[2], w0 = wx * wy * ((T)1 - r.f[2]);
-                    const int zl = (int)(r.zm & 0xffffu) - g.zb;
-                    const int m = (int)(r.zm >> 16);
-                    sr.row = zl * slb;
-                    sr.off = sr.row + (64 - m) * LB;
+    const int ntile = (Nz + ZT - 1) / ZT;
+    auto node = [=](int k, int i) {
+        const int z = k * ZT + i;
+        return z < Nz ? z : z % Nz;                      // node N_z is node 0
+    };
+    auto load_tile = [=](RawTile<ZT, TH>& t, int k) {
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        sr.g0[a] = r.g[a] * w0;
-                        sr.g1[a] = r.g[a] * w1;
-                    }
-                }
-                const int trk = have ? r.track : -1;
-                int tab = lane < kSlots ? s_table[lane] : -2;     // the slot table, one entry per lane
-                unsigned long long pending = __ballot(have);
-                const unsigned long long lt = (1ull << lane) - 1ull;
-                int base = 0, pos = 0;
-                while (pending) {
-                    const int tk = __builtin_amdgcn_readlane(trk, (int)__builtin_ctzll(pending));
-                    const unsigned long long same = __ballot(trk == tk) & pending;
-                    const unsigned long long hit = __ballot(tab == tk);
-                    int slot;
-                    if (hit) {
-                        slot = (int)__builtin_ctzll(hit);
-                    } else {
-                        const unsigned long long fr = __ballot(tab == -1);
-                        slot = fr ? (int)__builtin_ctzll(fr) : kSlots;
-                        if (slot < kSlots && lane == slot) {
-                            tab = tk;
-                            s_table[slot] = tk;
-                        }
-                    }
-                    const int cnt = __popcll(same);
-                    if ((same >> lane) & 1ull) {
-                        pos = base + __popcll(same & lt);
-                        sr.info = slot | (pos == base + cnt - 1 ? kLastOfRun : 0) | (tk << 8);
-                    }
-                    base += cnt;
-                    pending &= ~same;
-                }
-                if (have) st[pos] = sr;
-                if (lane == 0) s_nstaged = base;
-                // the next 64 events (of this tile, else of the next one)
-                const unsigned inext = e0 + kWave + (unsigned)lane;
-                if (e0 + kWave < E) {
-                    if (inext < E) rnext = ev[locate(k, inext, qnext)];
-                } else if (kn >= 0 && (unsigned)lane < count_of(kn)) {
-                    rnext = ev[locate(kn, (unsigned)lane, qnext)];
-                }
+        for (int i = 0; i <= ZT; ++i) load_lag(colH, e0 + (unsigned)node(k, i) * zs, t.n[i]);
+    };
+    // float16 values of a lag start at an odd element when e0 + z zs is odd
+    const unsigned zs_odd = zs & 1u;
+    auto write_rows = [=](const RawTile<ZT, TH>& t, int k) {
+        if (tid < nt) {
+#pragma unroll
+            for (int i = 0; i <= ZT; ++i)
+                store_lag(t.n[i], (e0 ^ (zs_odd & (unsigned)node(k, i))) & 1u, rows + i * RL + 64 + tid);
+        }
+    };
+    auto zo = [=](int z) -> unsigned { return __builtin_amdgcn_readfirstlane(zoff[z < Nz ? z : Nz]); };
+    // non-empty tiles, 64 at a time: bit i of ts.msk is tile ts.k0 + i
+    auto scan_tiles = [=](int k) -> unsigned long long {
+        const int t = k + lane;
+        bool ne = false;
+        if (t < ntile) ne = zoff[min(t * ZT + ZT, Nz)] != zoff[t * ZT];
+        return __ballot(ne);
+    };
+    int k0 = 0;
+    unsigned long long msk = 0;
+    auto next_tile = [&scan_tiles, ntile](int k, int& k0, unsigned long long& msk) -> int {
+        while (k < ntile) {
+            if (k >= k0 + kWave) {
+                k0 = k;
+                msk = scan_tiles(k);
             }
-            __syncthreads();
-            // every wavefront walks every event, four at a time; a track's
-            // sum goes to its accumulator after the last event of its run
-            const int ne = s_nstaged;
-            const unsigned char* hb = reinterpret_cast<const unsigned char*>(hs);
-            T cur = (T)0;
-            auto close = [&](int info) {
-                if (!(info & kLastOfRun)) return;
-                const int slot = info & 63;
-                if (slot == kSlots) {                    // a track without a slot
-                    if (n < nt && cur != (T)0) atomicAdd(out + (size_t)(info >> 8) * nt + n, cur * dec);
-                } else {
-                    acc[slot * nthr + n] += cur;
-                }
-                cur = (T)0;
-            };
-            int e = 0;
-            for (; e + 4 <= ne; e += 4) {
-                const Staged<T> s0 = st[e], s1 = st[e + 1], s2 = st[e + 2], s3 = st[e + 3];
-                const T v0 = event_value<T, TH>(s0, hb, nbyte, slb), v1 = event_value<T, TH>(s1, hb, nbyte, slb);
-                const T v2 = event_value<T, TH>(s2, hb, nbyte, slb), v3 = event_value<T, TH>(s3, hb, nbyte, slb);
-                cur += v0;
-                close(__builtin_amdgcn_readfirstlane(s0.info));
-                cur += v1;
-                close(__builtin_amdgcn_readfirstlane(s1.info));
-                cur += v2;
-                close(__builtin_amdgcn_readfirstlane(s2.info));
-                cur += v3;
-                close(__builtin_amdgcn_readfirstlane(s3.info));
-            }
-            for (; e < ne; ++e) {
-                const Staged<T> s0 = st[e];
-                cur += event_value<T, TH>(s0, hb, nbyte, slb);
-                close(__builtin_amdgcn_readfirstlane(s0.info));
+            const unsigned long long rest = msk >> (k - k0);
+            if (rest) return k + (int)__builtin_ctzll(rest);
+            k = k0 + kWave;
+        }
+        return ntile;
+    };
+    __syncthreads();
+    msk = scan_tiles(0);
+    // LDS byte addresses: this lane's lag 0 in row 0, and row 0's first entry
+    const unsigned rows_ab = (unsigned)(size_t)rows;
+    const unsigned lane_ab = rows_ab + (unsigned)(64 + tid) * LB;
+    typename SlotSums<T>::V acc = {};
+    T cur = (T)0;
+    int k = next_tile(0, k0, msk);                                // there is one: the column has records
+    unsigned tend = zo(k * ZT + ZT);
+    unsigned r0 = zo(k * ZT), r1 = min(r0 + (unsigned)RB, tend);
+    RawTile<ZT, TH> nx;
+    RecWords t;
+    stage_load(t, r0, r1);
+    load_tile(nx, k);
+    int kc = -1;                                         // the tile in the rows
+    while (true) {
+        __syncthreads();                                 // the previous chunk's rows and records are read
+        if (k != kc) {
+            write_rows(nx, k);
+            kc = k;
+        }
+        stage_store(t, r0, r1);
+        __syncthreads();
+        // the next chunk: the rest of this tile, else the next tile's first
+        int kn = k;
+        unsigned n0 = r1, nend = tend;
+        if (r1 >= tend) {
+            kn = next_tile(k + 1, k0, msk);
+            if (kn < ntile) {
+                n0 = zo(kn * ZT);
+                nend = zo(kn * ZT + ZT);
             }
         }
+        const bool more = kn < ntile;
+        const unsigned n1 = more ? min(n0 + (unsigned)RB, nend) : n0;
+        stage_load(t, n0, n1);
+        if (more && kn != k) load_tile(nx, kn);          // lands while this chunk is processed
+        // this chunk: every record added to its track's sum
+        for (unsigned r = r0; r < r1; ++r) {
+            NodeRec<T> R = lds_record(rbuf + (r - r0));
+            const int info = __builtin_amdgcn_readfirstlane(R.info);
+            const int m = info & 0xffff, zl = (info >> 16) & 0xff, slot = (info >> 24) & 63;
+            // the weights stay in vector registers
+#pragma unroll
+            for (int a = 0; a < 6; ++a) asm volatile("" : "+v"(R.g[a]));
+            // lag n - m of row zl, or the row's first (zero) lag when n - m < -64
+            const int rb0 = (int)(rows_ab + (unsigned)zl * row_b);
+            const unsigned ab = (unsigned)max((int)(lane_ab + (unsigned)zl * row_b) - m * (int)LB, rb0);
+            const Lds<Lag4<TH>>* h0 = (const Lds<Lag4<TH>>*)(size_t)ab;
+            const Lds<Lag4<TH>>* h1 = (const Lds<Lag4<TH>>*)(size_t)(ab + row_b);
+            // a track past the table uses the last register, from zero, and
+            // goes to the output at once (acc is updated the same way on both
+            // paths, so that its registers stay in place)
+            const bool spill = slot == kNoSlot;
+            const int se = spill ? SlotSums<T>::N - 1 : slot;
+            T v = spill ? (T)0 : acc[se];
+            v = project<T, TH>(h0, R.g, v);
+            v = project<T, TH>(h1, R.g + 3, v);
+            acc[se] = v;
+            if (spill && tid < nt) {
+                const int trk = __builtin_amdgcn_readfirstlane(R.track);
+                atomicAdd(out + (size_t)trk * nt + tid, v * dec);
+            }
+        }
+        if (!more) break;
         k = kn;
+        r0 = n0;
+        r1 = n1;
+        tend = nend;
     }
-    // the per-track sums of this workgroup
-    __syncthreads();
-    for (int s = 0; s < kSlots; ++s) {
-        const int trk = s_table[s];
-        const T v = acc[s * nthr + n];
-        if (trk >= 0 && trk < n_tracks && n < nt && v != (T)0) atomicAdd(out + (size_t)trk * nt + n, v * dec);
+    // the per-track sums of this column
+    const int used = __popcll(__ballot(tabv >= 0));
+    if (tid < nt) {
+        for (int k = 0; k < used; ++k) {
+            const int trk = __builtin_amdgcn_readlane(tabv, k);
+            const T v = acc[k];
+            if (v != (T)0) atomicAdd(out + (size_t)trk * nt + tid, v * dec);
+        }
     }
 }
 
@@ -830,70 +860,64 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
     }
     if (n_carriers == 0) return e;
     const float* decode = reinterpret_cast<const float*>(static_cast<const char*>(h) + p.h_values_bytes);
-    ConvTiling tl = conv_tiling(p, sizeof(TH));
-    // 16-byte loads of whole time blocks: H and every block of every column aligned
-    tl.vec = (reinterpret_cast<uintptr_t>(h) % 16 == 0 && ((size_t)p.N[2] * p.n_time * 3 * sizeof(TH)) % 16 == 0 &&
-              ((size_t)p.tb * 3 * sizeof(TH)) % 16 == 0)
-                 ? 1
-                 : 0;
+    const ConvTiling tl = conv_tiling(p);
     const CurrentLayout cl = current_layout(p, tl, n_carriers);
-    static_assert(sizeof(EvRec<float>) == 32 && sizeof(EvRec<double>) == 64, "event record size");
-    static_assert(sizeof(Staged<float>) == 48 && sizeof(Staged<double>) == 64, "staged event size");
-    // per-bin counts are 32-bit: bin only while every step fits them; below
+    static_assert(sizeof(NodeRec<float>) == 32 && sizeof(NodeRec<double>) == 64, "record size");
+    // per-cell counts are 32-bit: bin only while every step fits them; below
     // kBinnedMinSteps polyline steps the unbinned kernel is faster (its cost
-    // is the steps that move, the binned form's also the grid's columns and
-    // tiles: at 2e4 carriers x 200 samples, 0.39 against 1.4 ms on one MI355X)
+    // is the steps that move, the binned form's also the grid's columns)
     const unsigned long long steps = (unsigned long long)n_carriers * p.n_time;
-    const bool binned = ws != nullptr && ws_bytes >= cl.fixed_bytes + sizeof(EvRec<T>) && steps < 0xfffffff0ull &&
+    const bool binned = ws != nullptr && ws_bytes >= cl.fixed_bytes + 4 * sizeof(NodeRec<T>) && steps < 0xfffffff0ull &&
                         form != 2 && (steps >= kBinnedMinSteps || form == 1);
     unsigned long long* ctl = nullptr;
     if (binned) {
         char* b = static_cast<char*>(ws);
         ctl = reinterpret_cast<unsigned long long*>(b + cl.off_ctl);
         unsigned* count = reinterpret_cast<unsigned*>(b + cl.off_count);
+        unsigned* fill = reinterpret_cast<unsigned*>(b + cl.off_fill);
         unsigned* offs = reinterpret_cast<unsigned*>(b + cl.off_offs);
         unsigned long long* bsum = reinterpret_cast<unsigned long long*>(b + cl.off_bsum);
         unsigned long long* mask = reinterpret_cast<unsigned long long*>(b + cl.off_mask);
-        EvRec<T>* evs = reinterpret_cast<EvRec<T>*>(b + cl.off_events);
-        size_t cap = (ws_bytes - cl.off_events) / sizeof(EvRec<T>);
+        int* tables = reinterpret_cast<int*>(b + cl.off_tables);
+        NodeRec<T>* rec = reinterpret_cast<NodeRec<T>*>(b + cl.off_records);
+        size_t cap = (ws_bytes - cl.off_records) / sizeof(NodeRec<T>);
         if (cap > 0xfffffff0ull) cap = 0xfffffff0ull;
-      if (phase == 1) {
-        // control words and bin counts are one zero-filled run (no memset
-        // nodes, so the sequence can be captured); then the capacity
-        const size_t n_zero = (cl.off_count + tl.n_bins * sizeof(unsigned)) / sizeof(unsigned);
-        hipLaunchKernelGGL(k_fill_zero<unsigned>, dim3((unsigned)std::min<size_t>((n_zero + kBlock - 1) / kBlock, 4096)),
-                           dim3(kBlock), 0, s, reinterpret_cast<unsigned*>(b), n_zero);
-        hipLaunchKernelGGL(k_set_capacity, dim3(1), dim3(1), 0, s, ctl, (unsigned long long)cap);
-        const size_t waves = (size_t)n_carriers * tl.n_chunks;
-        const unsigned grid = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
-        hipLaunchKernelGGL(k_ev_count<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers, n_tracks,
-                           static_cast<const T*>(pos), track, mask, count);
-        const unsigned nb = (unsigned)((tl.n_bins + kScanItems - 1) / kScanItems);
-        hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, count, tl.n_bins, bsum);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, bsum, (int)nb, ctl);
-        hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, s, count, tl.n_bins, bsum, offs);
-        hipLaunchKernelGGL(k_ev_scatter<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers,
-                           static_cast<const T*>(pos), static_cast<const T*>(charge), track, mask, offs, count, ctl,
-                           evs);
-        return hipGetLastError();
-      }
-        auto tiles = [&](auto kernel) {
+        if (phase == 1) {
+            // control words, cell counts and fill counters are one zero-filled
+            // run (no memset nodes, so the sequence can be captured)
+            const size_t n_zero = cl.off_offs / sizeof(unsigned);
+            hipLaunchKernelGGL(k_fill_zero<unsigned>,
+                               dim3((unsigned)std::min<size_t>((n_zero + kBlock - 1) / kBlock, 4096)), dim3(kBlock),
+                               0, s, reinterpret_cast<unsigned*>(b), n_zero);
+            hipLaunchKernelGGL(k_set_capacity, dim3(1), dim3(1), 0, s, ctl, (unsigned long long)cap);
+            const size_t waves = (size_t)n_carriers * tl.n_chunks;
+            const unsigned grid = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
+            hipLaunchKernelGGL(k_ev_count<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers, n_tracks,
+                               static_cast<const T*>(pos), track, mask, count);
+            hipLaunchKernelGGL(k_node_count, dim3((unsigned)std::min<size_t>((tl.n_cells + kBlock - 1) / kBlock,
+                                                                             65536)),
+                               dim3(kBlock), 0, s, p, count, offs);
+            const unsigned nb = (unsigned)((tl.n_cells + kScanItems - 1) / kScanItems);
+            hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, offs, tl.n_cells, bsum);
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, bsum, (int)nb, ctl);
+            hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, s, offs, tl.n_cells, bsum);
+            hipLaunchKernelGGL(k_ev_scatter<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers,
+                               static_cast<const T*>(pos), static_cast<const T*>(charge), track, mask, count, fill,
+                               offs, ctl, rec);
+            hipLaunchKernelGGL(k_slots<T>, dim3((unsigned)((tl.n_cols + kBlock / kWave - 1) / (kBlock / kWave))),
+                               dim3(kBlock), 0, s, p, tl, offs, rec, ctl, tables);
+            return hipGetLastError();
+        }
+        auto rows = [&](auto kernel) {
             e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)tl.lds_bytes);
             if (e != hipSuccess) return;
-            hipLaunchKernelGGL(kernel, dim3((unsigned)((size_t)p.N[0] * p.N[1] * tl.n_zr)), dim3(tl.threads),
-                               tl.lds_bytes, s, p, tl, static_cast<const TH*>(h), decode, offs, evs, ctl, n_tracks,
+            hipLaunchKernelGGL(kernel, dim3((unsigned)tl.n_cols), dim3(tl.threads), tl.lds_bytes, s, p, tl,
+                               static_cast<const TH*>(h), decode, offs, rec, tables, ctl, n_tracks,
                                static_cast<T*>(out));
         };
-        // time blocks of 8 or 16 samples, 16-byte aligned: prefetched in
-        // registers, unless a unit is more than 6 words; otherwise staged
-        // value by value
-        if (tl.vec && p.tb == 16 && 16 * 3 * sizeof(TH) <= 96)
-            tiles(k_conv_tiles<16, T, TH>);
-        else if (tl.vec && p.tb == 8 && 8 * 3 * sizeof(TH) <= 96)
-            tiles(k_conv_tiles<8, T, TH>);
-        else
-            tiles(k_conv_tiles<0, T, TH>);
+        // tiles of conv_tile_nodes(sizeof(TH)) z-nodes
+        rows(k_conv_rows<conv_tile_nodes(sizeof(TH)), T, TH>);
         if (e != hipSuccess) return e;
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

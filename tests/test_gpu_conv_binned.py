@@ -7,12 +7,13 @@
   ragged last time blocks; N_z not a multiple of the z-tile; polylines that
   leave the cell on every side, stationary and absorbed carriers, invalid
   tracks.
-* The workspace's control words: the event count against a count on the
-  host, and the overflow flag: with room for all events the binned form
-  runs, with one event less the unbinned form takes over (same currents).
-* More tracks in one block of node columns than a workgroup has
-  accumulators (the spill path), and more events in one z-tile than a
-  workgroup has lanes (several staging passes).
+* The workspace's control words: the record count (four per event) against
+  a count of events on the host, and the overflow flag: with room for all
+  events the binned form runs, with one event less the unbinned form takes
+  over (same currents).
+* More tracks in one node column than a workgroup has accumulator rows (the
+  direct path), and more records in one z-tile than one LDS chunk holds
+  (several chunks per tile); N_z smaller than a z-tile (nodes wrap).
 * No carriers, and carriers that never move.
 Bars: float64 1e-12 between the forms and 1e-9 against the oracle; float32
 and float16 (exactly representable synthetic field) 1e-5 between the forms
@@ -103,6 +104,8 @@ CASES = [
     (8, 128, 21, wt.WT_F32, wt.WT_H_F16_SCALED, 1),
     (8, 150, 21, wt.WT_F32, wt.WT_H_PLAIN, 0),      # smooth N_z, layout not 16-byte aligned: value by value
     (8, 64, 130, wt.WT_F32, wt.WT_H_PLAIN, 0),      # three wavefronts of output samples
+    (10, 6, 33, wt.WT_F32, wt.WT_H_PLAIN, 0),       # N_z below the z-tile: nodes wrap inside one tile
+    (10, 6, 33, wt.WT_F64, wt.WT_H_PLAIN, 0),
 ]
 
 
@@ -144,7 +147,7 @@ def test_event_count_and_overflow_fallback(ctx):
         torch.cuda.synchronize()
         total, overflow, capacity = _control_words(ws)
         say(f"  capacity {cap}: control words total={total} overflow={overflow} capacity={capacity}")
-        assert total == n_ev and capacity == cap and overflow == (1 if cap < n_ev else 0)
+        assert total == 4 * n_ev and capacity == 4 * cap and overflow == (1 if cap < n_ev else 0)
         out[cap] = o.double().cpu().numpy()
     i_ref = _oracle(Hs, cfg, car)
     for cap, o in out.items():
