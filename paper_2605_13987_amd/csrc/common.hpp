@@ -135,16 +135,21 @@ struct ConvTiling {
     int threads, n_chunks;
     int zt;
     int slots, rb;
+    int rl;               // lags per LDS row: 64 zero lags, n_time rounded up to 16
+    int lb;               // bytes per lag in a row (4 values of the stored H type)
     size_t n_cells, n_cols;
     size_t off_zoff, off_rbuf, lds_bytes;
 };
 // per-track sums per lane (registers), float and double path; the last
-// one takes the tracks past the column's table
-constexpr int kConvSlotsF32 = 32;
+// one takes the tracks past the column's table.  16 leaves each lane 72
+// registers, so that four workgroups of 448 lanes share a CU; the table
+// holds the tracks with the most records (at 256x256x512, 1e6 carriers of
+// 100 tracks, 0.5% of the records belong to tracks past it).
+constexpr int kConvSlotsF32 = 16;
 constexpr int kConvSlotsF64 = 16;
-// z-nodes per tile for h_elem bytes per stored value: about 50 KB of rows
-// at 448 lanes (three workgroups per CU) and (zt + 1) nodes' lags in flight
-// per lane in registers
+// z-nodes per tile for h_elem bytes per stored value: at 400 samples the
+// rows take 33 KB (float16: four workgroups per CU) or 45 KB (float, double:
+// three), and (zt + 1) nodes' lags are in flight per lane in registers
 __host__ __device__ constexpr int conv_tile_nodes(int h_elem) { return h_elem == 2 ? 8 : (h_elem == 4 ? 5 : 2); }
 inline ConvTiling conv_tiling(const Plan& p) {
     ConvTiling t{};
@@ -159,7 +164,12 @@ inline ConvTiling conv_tiling(const Plan& p) {
     // a chunk of records is at most two 16-byte words per thread
     const int rb = (int)(2 * (size_t)t.threads * 16 / recb);
     t.rb = rb < 64 ? rb : 64;
-    const size_t rows = (size_t)(t.zt + 1) * (64 + t.threads) * 4 * h_elem;
+    // rows of 64 + n_time lags (rounded up to 16); lanes past the last
+    // sample read up to threads - n_time lags further, which stay inside the
+    // allocation (garbage they drop)
+    t.rl = 64 + ((p.n_time + 15) & ~15);
+    t.lb = 4 * h_elem;
+    const size_t rows = (size_t)(t.zt + 1) * t.rl * 4 * h_elem + (size_t)64 * 4 * h_elem;
     t.off_zoff = a16(rows);
     t.off_rbuf = t.off_zoff + a16((size_t)(p.N[2] + 1) * sizeof(unsigned));
     t.lds_bytes = t.off_rbuf + (size_t)t.rb * recb;

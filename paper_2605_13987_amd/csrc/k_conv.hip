@@ -11,22 +11,27 @@
 // binned by the grid cell they fall in and H is read node column by node
 // column, each needed lag series once:
 //
-//   k_ev_count     one wavefront per (carrier, 64 steps): which steps move
-//                  (a bit mask), and the number of events per cell;
+//   k_ev_count     one wavefront per carrier, 64 steps at a time: which steps
+//                  move (a bit mask), and the number of events per cell;
 //   k_node_count,  records per (node column, z-node): the events of the four
 //   k_scan_*       cells around it at that z, scanned into offsets;
 //   k_ev_scatter   every event written as four records, one per corner
 //                  column of its cell: step, track and -q dx times the
 //                  trilinear weights of its two z-nodes in that column;
-//   k_slots        one wavefront per node column: its distinct tracks (the
-//                  slots of its per-track sums), and each record's slot;
+//   k_slots        one wavefront per node column: its track table (the
+//                  tracks with the most records, the slots of its per-track
+//                  sums), each record rewritten with its slot and LDS
+//                  offsets, records of tracks past the table moved to an
+//                  overflow list;
 //   k_conv_rows    one workgroup per node column, one lane per output
 //                  sample n.  The column's nodes go through LDS a tile of
 //                  z-nodes at a time, as rows of lags (the next tile and the
 //                  next records loading meanwhile); for each record every
 //                  lane adds the projection at lag n - m of its two z-nodes
 //                  to its track's sum, one register per track; the registers
-//                  go to the output once, when the workgroup ends.
+//                  go to the output once, when the workgroup ends;
+//   k_conv_overflow the overflow list, one wavefront per record, its two
+//                  z-nodes read from global memory.
 //
 // Without a workspace, or when the records do not fit the caller's
 // workspace, k_current runs instead: one wavefront per carrier, lanes over
@@ -48,6 +53,11 @@ constexpr int kScanItems = 4096;       // bin counts per workgroup of the scan
 constexpr unsigned long long kBinnedMinSteps = 1ull << 24;   // polyline steps from which wt_current bins
 
 constexpr int kScanThreads = 1024;
+
+// Control words of the workspace: [0] records (4 per event), [1] 1 when the
+// binned form cannot take the events (the direct form then runs), [2] the
+// record capacity, [3] records on the overflow list.
+constexpr int kCtlRecords = 0, kCtlFallback = 1, kCtlCapacity = 2, kCtlOverflow = 3;
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fill_zero(T* out, size_t n) {
@@ -202,7 +212,7 @@ template <int TBC, typename T, typename TH>
 __global__ void __launch_bounds__(kBlock)
 k_current(Plan p, const TH* H, const float* decode, int n_carriers, int n_tracks, const T* pos, const T* charge,
           const int* track, T* out, const unsigned long long* gate) {
-    if (gate && gate[1] == 0ull) return;
+    if (gate && gate[kCtlFallback] == 0ull) return;
     __shared__ short steps[kBlock / kWave][kMaxTime];
     __shared__ T part[kBlock / kWave][kMaxTime];
     __shared__ int wtrack[kBlock / kWave];
@@ -289,47 +299,59 @@ k_current(Plan p, const TH* H, const float* decode, int n_carriers, int n_tracks
 // ---------------------------------------------------------------- binned form
 
 // A node-column record: one event as seen from one of the four (x, y) corner
-// columns of its cell.  info holds its step m, its lower z-node inside its
-// z-tile and the slot of its track (see kNoSlot); g0 and g1 are -q dx times
-// the trilinear weights of the event's lower and upper z-node in this column.
+// columns of its cell.  As written: w0 = its step m | its lower z-node z0 << 16,
+// w1 = its track; g0 and g1 are -q dx times the trilinear weights of the
+// event's lower and upper z-node in this column.  k_slots rewrites w0 and w1
+// into what the accumulation uses (see there).
 // Records are ordered by (node column, lower z-node); inside one such bin by
 // the cell they come from, then by arrival.
 template <typename T>
 struct alignas(sizeof(T) == 8 ? 64 : 32) NodeRec {
-    int info;
-    int track;
+    int w0;
+    int w1;
     T g[6];
 };
 
-// Workspace control words: [0] number of records (4 per event), [1] 1 when
-// they do not fit (the direct form then runs), [2] the record capacity.
-__global__ void k_set_capacity(unsigned long long* ctl, unsigned long long cap) { ctl[2] = cap; }
+// A record whose track is not in its column's table, as the overflow list
+// holds it: node column, m | z0 << 16, track, -q dx times the two weights.
+template <typename T>
+struct alignas(2 * sizeof(NodeRec<T>)) OvfRec {
+    int col;
+    int zm;
+    int track;
+    int pad;
+    T g[6];
+};
 
-// One wavefront per (carrier, 64 steps): the bit mask of the steps that are
-// events, and one count per event in its cell.
+__global__ void k_set_capacity(unsigned long long* ctl, unsigned long long cap) { ctl[kCtlCapacity] = cap; }
+
+// One wavefront per carrier, 64 steps at a time: the bit mask of the steps
+// that are events, and one count per event in its cell.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_ev_count(Plan p, ConvTiling tl, int n_carriers, int n_tracks, const T* pos, const int* track,
            unsigned long long* mask, unsigned* count) {
     const int lane = threadIdx.x & (kWave - 1);
-    const size_t wave = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    const size_t c = wave / tl.n_chunks;
+    const size_t c = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (c >= (size_t)n_carriers) return;
     const int nt = p.n_time;
-    const int m = (int)(wave - c * tl.n_chunks) * kWave + lane;
     const int tr = track[c];
-    bool ev = false;
-    size_t cell = 0;
-    if (tr >= 0 && tr < n_tracks && m < nt) {
-        const T* P = pos + c * (size_t)(nt + 1) * 3;
-        int x0, y0, z0;
-        T fx, fy, fz, dx, dy, dz;
-        ev = event_cell(p, P, m, x0, y0, z0, fx, fy, fz, dx, dy, dz);
-        cell = ((size_t)x0 * p.N[1] + y0) * p.N[2] + z0;
+    const bool valid = tr >= 0 && tr < n_tracks;
+    const T* P = pos + c * (size_t)(nt + 1) * 3;
+    for (int j = 0; j < tl.n_chunks; ++j) {
+        const int m = j * kWave + lane;
+        bool ev = false;
+        size_t cell = 0;
+        if (valid && m < nt) {
+            int x0, y0, z0;
+            T fx, fy, fz, dx, dy, dz;
+            ev = event_cell(p, P, m, x0, y0, z0, fx, fy, fz, dx, dy, dz);
+            cell = ((size_t)x0 * p.N[1] + y0) * p.N[2] + z0;
+        }
+        const unsigned long long bal = __ballot(ev);
+        if (lane == 0) mask[c * tl.n_chunks + j] = bal;
+        if (ev) atomicAdd(count + cell, 1u);
     }
-    const unsigned long long bal = __ballot(ev);
-    if (lane == 0) mask[wave] = bal;
-    if (ev) atomicAdd(count + cell, 1u);
 }
 
 // Records per (node column, z-node): the events of the four cells that have
@@ -409,8 +431,8 @@ k_scan_top(unsigned long long* bsum, int nb, unsigned long long* ctl) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        ctl[0] = carry;
-        ctl[1] = carry > ctl[2] ? 1ull : 0ull;
+        ctl[kCtlRecords] = carry;
+        ctl[kCtlFallback] = carry > ctl[kCtlCapacity] ? 1ull : 0ull;
     }
 }
 
@@ -440,8 +462,8 @@ k_scan_apply(unsigned* offs, size_t n, const unsigned long long* bsum) {
     if (base < n && base + per >= n) offs[n] = run;
 }
 
-// One wavefront per (carrier, 64 steps) again: every event written as four
-// node-column records.  In the bin of node column (X, Y) and z-node z0 the
+// One wavefront per carrier again: every event written as four node-column
+// records.  In the bin of node column (X, Y) and z-node z0 the
 // records of cell (X, Y) come first, then those of cells (X, Y - 1),
 // (X - 1, Y) and (X - 1, Y - 1); inside one cell in the order the events
 // arrive (fill counter).
@@ -451,92 +473,151 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
              const unsigned long long* mask, const unsigned* count, unsigned* fill, const unsigned* offs,
              const unsigned long long* ctl, NodeRec<T>* rec) {
     const int lane = threadIdx.x & (kWave - 1);
-    const size_t wave = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    const size_t c = wave / tl.n_chunks;
-    if (c >= (size_t)n_carriers) return;
-    const unsigned long long bits = mask[wave];
-    if (bits == 0ull || ctl[1] != 0ull) return;
-    if (!((bits >> lane) & 1ull)) return;
+    const size_t c = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (c >= (size_t)n_carriers || ctl[kCtlFallback] != 0ull) return;
     const int nt = p.n_time, Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
-    const int m = (int)(wave - c * tl.n_chunks) * kWave + lane;
     const T* P = pos + c * (size_t)(nt + 1) * 3;
-    int x0, y0, z0;
-    T fx, fy, fz, dx, dy, dz;
-    if (!event_cell(p, P, m, x0, y0, z0, fx, fy, fz, dx, dy, dz)) return;   // cannot happen: the mask says it moves
-    auto cell = [&](int x, int y) { return ((size_t)x * Ny + y) * Nz + z0; };
-    const int x1 = x0 + 1 == Nx ? 0 : x0 + 1, y1 = y0 + 1 == Ny ? 0 : y0 + 1, ym = y0 == 0 ? Ny - 1 : y0 - 1;
-    const unsigned j = atomicAdd(fill + cell(x0, y0), 1u);
-    // records of the cells before this one in each of the four bins
-    const unsigned cA = count[cell(x0, y1)], cB = count[cell(x1, y0)], cC = count[cell(x1, ym)],
-                   cD = count[cell(x1, y1)];
-    const T q = charge[c];
-    const int tr = track[c];
-    const T gx = -q * dx, gy = -q * dy, gz = -q * dz;
+    for (int jc = 0; jc < tl.n_chunks; ++jc) {
+        const unsigned long long bits = mask[c * tl.n_chunks + jc];
+        if (!((bits >> lane) & 1ull)) continue;
+        const int m = jc * kWave + lane;
+        int x0, y0, z0;
+        T fx, fy, fz, dx, dy, dz;
+        if (!event_cell(p, P, m, x0, y0, z0, fx, fy, fz, dx, dy, dz)) continue;   // cannot happen: the mask says it moves
+        auto cell = [&](int x, int y) { return ((size_t)x * Ny + y) * Nz + z0; };
+        const int x1 = x0 + 1 == Nx ? 0 : x0 + 1, y1 = y0 + 1 == Ny ? 0 : y0 + 1, ym = y0 == 0 ? Ny - 1 : y0 - 1;
+        const unsigned j = atomicAdd(fill + cell(x0, y0), 1u);
+        // records of the cells before this one in each of the four bins
+        const unsigned cA = count[cell(x0, y1)], cB = count[cell(x1, y0)], cC = count[cell(x1, ym)],
+                       cD = count[cell(x1, y1)];
+        const T q = charge[c];
+        const int tr = track[c];
+        const T gx = -q * dx, gy = -q * dy, gz = -q * dz;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int ox = k >> 1, oy = k & 1;
-        const unsigned before = k == 0 ? 0u : k == 1 ? cA : k == 2 ? cB + cC : cD + cB + cA;
-        const size_t slot = offs[cell(ox ? x1 : x0, oy ? y1 : y0)] + before + j;
-        const T wxy = (ox ? fx : (T)1 - fx) * (oy ? fy : (T)1 - fy);
-        const T w0 = wxy * ((T)1 - fz), w1 = wxy * fz;
-        NodeRec<T> r;
-        r.info = m | ((z0 % tl.zt) << 16);
-        r.track = tr;
-        r.g[0] = gx * w0;
-        r.g[1] = gy * w0;
-        r.g[2] = gz * w0;
-        r.g[3] = gx * w1;
-        r.g[4] = gy * w1;
-        r.g[5] = gz * w1;
-        rec[slot] = r;
+        for (int k = 0; k < 4; ++k) {
+            const int ox = k >> 1, oy = k & 1;
+            const unsigned before = k == 0 ? 0u : k == 1 ? cA : k == 2 ? cB + cC : cD + cB + cA;
+            const size_t slot = offs[cell(ox ? x1 : x0, oy ? y1 : y0)] + before + j;
+            const T wxy = (ox ? fx : (T)1 - fx) * (oy ? fy : (T)1 - fy);
+            const T w0 = wxy * ((T)1 - fz), w1 = wxy * fz;
+            NodeRec<T> r;
+            r.w0 = m | (z0 << 16);
+            r.w1 = tr;
+            r.g[0] = gx * w0;
+            r.g[1] = gy * w0;
+            r.g[2] = gz * w0;
+            r.g[3] = gx * w1;
+            r.g[4] = gy * w1;
+            r.g[5] = gz * w1;
+            rec[slot] = r;
+        }
     }
 }
 
-// Info word of a record: step m (bits 0-15), its lower z-node inside its
-// z-tile (bits 16-23), the slot of its track in the column's track table
-// (bits 24-29, kNoSlot when the track is not in it).
-constexpr int kNoSlot = 63;
-
-// One wavefront per node column: the column's distinct tracks in order of
-// first appearance, up to tl.slots of them (-1 pads the table), and every
-// record's slot in its info word.
+// One wavefront per node column.  The column's track table: the tl.slots
+// tracks with the most records (ties: first appearance; -1 pads it).  Then
+// every record rewritten for the accumulation, with zl = z0 mod tl.zt (its
+// lower z-node inside its tile) and rowb = tl.rl * tl.lb (bytes of an LDS
+// row of lags):
+//   w0 = zl rowb - m lb   (LDS byte offset of lag -m of its lower node, from
+//                           row 0's lag 0)
+//   w1 = zl rowb | slot << 24
+// A record whose track is past the table goes to the overflow list (after
+// the records, in the same buffer), and stays with zero weights in the
+// table's spare slot; when the list would not fit, the direct form takes
+// all events (kCtlFallback).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, const unsigned long long* ctl, int* tables) {
+k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned long long* ctl, int* tables) {
     const int lane = threadIdx.x & (kWave - 1);
     const size_t col = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (col >= tl.n_cols || ctl[1] != 0ull) return;
+    if (col >= tl.n_cols || ctl[kCtlFallback] != 0ull) return;
     const int S = tl.slots, Nz = p.N[2];
     const unsigned r0 = offs[col * Nz], r1 = offs[col * Nz + Nz];
-    int tab = -1, used = 0;
-    for (unsigned b = r0; b < r1 && used < S; b += kWave) {
+    // candidates: the column's first 64 distinct tracks (lane i: the i-th)
+    // with their record counts
+    int cand = -1, cnt = 0, nc = 0;
+    for (unsigned b = r0; b < r1; b += kWave) {
         const unsigned r = b + (unsigned)lane;
-        const int trk = r < r1 ? rec[r].track : -1;
+        const int trk = r < r1 ? rec[r].w1 : -1;
         unsigned long long pending = __ballot(trk >= 0);
-        while (pending && used < S) {
+        while (pending) {
             const int tk = __builtin_amdgcn_readlane(trk, (int)__builtin_ctzll(pending));
-            pending &= ~__ballot(trk == tk);
-            if (__ballot(tab == tk) == 0ull) {
-                if (lane == used) tab = tk;
-                ++used;
+            const unsigned long long same = __ballot(trk == tk);
+            pending &= ~same;
+            const unsigned long long at = __ballot(cand == tk);
+            const int i = at ? (int)__builtin_ctzll(at) : nc;
+            if (i < kWave) {
+                if (lane == i) {
+                    cand = tk;
+                    cnt += __popcll(same);
+                }
+                if (!at) ++nc;
             }
         }
     }
+    // the table: the candidates with the most records, most first
+    int tab = -1;
+    for (int k = 0; k < S; ++k) {
+        int best = cnt, who = lane;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int ob = __shfl_xor(best, d, kWave), ow = __shfl_xor(who, d, kWave);
+            if (ob > best || (ob == best && ow < who)) {
+                best = ob;
+                who = ow;
+            }
+        }
+        if (best <= 0) break;
+        const int tk = __builtin_amdgcn_readlane(cand, who);
+        if (lane == k) tab = tk;
+        if (lane == who) cnt = -1;
+    }
     if (lane < S) tables[col * S + lane] = tab;
+    const int rowb = tl.rl * tl.lb;
+    const unsigned long long total = ctl[kCtlRecords], cap = ctl[kCtlCapacity];
+    OvfRec<T>* ovf = reinterpret_cast<OvfRec<T>*>(rec + ((total + 1) & ~1ull));
+    const unsigned long long ovf_cap = cap > total + 1 ? (cap - total - 1) / 2 : 0ull;
     for (unsigned b = r0; b < r1; b += kWave) {
         const unsigned r = b + (unsigned)lane;
         const bool have = r < r1;
-        const int trk = have ? rec[r].track : -1;
-        int slot = kNoSlot;
+        NodeRec<T> R;
+        int trk = -1;
+        if (have) {
+            R = rec[r];
+            trk = R.w1;
+        }
+        int slot = S;
         unsigned long long pending = __ballot(have);
         while (pending) {
             const int tk = __builtin_amdgcn_readlane(trk, (int)__builtin_ctzll(pending));
             const unsigned long long same = __ballot(trk == tk) & pending;
             const unsigned long long hs = __ballot(tab == tk);
-            if ((same >> lane) & 1ull) slot = hs ? (int)__builtin_ctzll(hs) : kNoSlot;
+            if ((same >> lane) & 1ull) slot = hs ? (int)__builtin_ctzll(hs) : S;
             pending &= ~same;
         }
-        if (have) rec[r].info |= slot << 24;
+        if (!have) continue;
+        const int m = R.w0 & 0xffff, z0 = R.w0 >> 16, zl = z0 % tl.zt;
+        if (slot == S) {
+            const unsigned long long i = atomicAdd(ctl + kCtlOverflow, 1ull);
+            if (i < ovf_cap) {
+                OvfRec<T> o;
+                o.col = (int)col;
+                o.zm = R.w0;
+                o.track = trk;
+                o.pad = 0;
+#pragma unroll
+                for (int a = 0; a < 6; ++a) o.g[a] = R.g[a];
+                ovf[i] = o;
+            } else {
+                ctl[kCtlFallback] = 1ull;                // no room: the direct form runs
+            }
+#pragma unroll
+            for (int a = 0; a < 6; ++a) R.g[a] = (T)0;
+        }
+        R.w0 = zl * rowb - m * tl.lb;
+        R.w1 = (zl * rowb) | (slot << 24);
+        rec[r] = R;
     }
 }
 
@@ -663,11 +744,11 @@ struct SlotSums {
 // the chunk starts one, are in flight.  The registers go to the output at
 // the end, one atomic per sample and track.
 template <int ZT, typename T, typename TH>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 6)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 7)))
 k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __restrict__ decode,
             const unsigned* __restrict__ offs, const NodeRec<T>* __restrict__ rec, const int* __restrict__ tables,
             const unsigned long long* __restrict__ ctl, int n_tracks, T* __restrict__ out) {
-    if (ctl[1] != 0ull) return;                          // the direct form takes these events
+    if (ctl[kCtlFallback] != 0ull) return;               // the direct form takes these events
     const int Nz = p.N[2], nt = p.n_time;
     const size_t col = blockIdx.x;
     const unsigned* no = offs + col * Nz;
@@ -679,7 +760,7 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
     Lds<unsigned>* zoff = reinterpret_cast<Lds<unsigned>*>(lds + tl.off_zoff);   // [Nz + 1]
     Lds<NodeRec<T>>* rbuf = reinterpret_cast<Lds<NodeRec<T>>*>(lds + tl.off_rbuf);   // [rb]
     const int tid = threadIdx.x, lane = tid & (kWave - 1), nthr = blockDim.x;
-    const int S = tl.slots, RB = tl.rb, RL = 64 + nthr;
+    const int S = tl.slots, RB = tl.rb, RL = tl.rl;
     constexpr unsigned LB = sizeof(Lag4<TH>);
     const unsigned row_b = (unsigned)RL * LB;
     for (int i = tid; i < (ZT + 1) * 64; i += nthr) {
@@ -800,32 +881,24 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
         const unsigned n1 = more ? min(n0 + (unsigned)RB, nend) : n0;
         stage_load(t, n0, n1);
         if (more && kn != k) load_tile(nx, kn);          // lands while this chunk is processed
-        // this chunk: every record added to its track's sum
+        // this chunk: every record added to its track's sum (records of
+        // tracks past the table have zero weights and the spare slot)
         for (unsigned r = r0; r < r1; ++r) {
             NodeRec<T> R = lds_record(rbuf + (r - r0));
-            const int info = __builtin_amdgcn_readfirstlane(R.info);
-            const int m = info & 0xffff, zl = (info >> 16) & 0xff, slot = (info >> 24) & 63;
+            const int w0 = __builtin_amdgcn_readfirstlane(R.w0), w1 = __builtin_amdgcn_readfirstlane(R.w1);
             // the weights stay in vector registers
 #pragma unroll
             for (int a = 0; a < 6; ++a) asm volatile("" : "+v"(R.g[a]));
             // lag n - m of row zl, or the row's first (zero) lag when n - m < -64
-            const int rb0 = (int)(rows_ab + (unsigned)zl * row_b);
-            const unsigned ab = (unsigned)max((int)(lane_ab + (unsigned)zl * row_b) - m * (int)LB, rb0);
+            const int rb0 = (int)rows_ab + (w1 & 0xffffff);
+            const unsigned ab = (unsigned)max((int)lane_ab + w0, rb0);
             const Lds<Lag4<TH>>* h0 = (const Lds<Lag4<TH>>*)(size_t)ab;
             const Lds<Lag4<TH>>* h1 = (const Lds<Lag4<TH>>*)(size_t)(ab + row_b);
-            // a track past the table uses the last register, from zero, and
-            // goes to the output at once (acc is updated the same way on both
-            // paths, so that its registers stay in place)
-            const bool spill = slot == kNoSlot;
-            const int se = spill ? SlotSums<T>::N - 1 : slot;
-            T v = spill ? (T)0 : acc[se];
+            const int slot = (unsigned)w1 >> 24;
+            T v = acc[slot];
             v = project<T, TH>(h0, R.g, v);
             v = project<T, TH>(h1, R.g + 3, v);
-            acc[se] = v;
-            if (spill && tid < nt) {
-                const int trk = __builtin_amdgcn_readfirstlane(R.track);
-                atomicAdd(out + (size_t)trk * nt + tid, v * dec);
-            }
+            acc[slot] = v;
         }
         if (!more) break;
         k = kn;
@@ -840,6 +913,42 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
             const int trk = __builtin_amdgcn_readlane(tabv, k);
             const T v = acc[k];
             if (v != (T)0) atomicAdd(out + (size_t)trk * nt + tid, v * dec);
+        }
+    }
+}
+
+// The overflow list: one wavefront per record (a grid-stride loop over the
+// count k_slots left), lanes over output samples n; the record's two
+// z-nodes read from global memory at lag n - m, the sum added to its
+// track's output with one atomic per sample.
+template <typename T, typename TH>
+__device__ inline T node_lag_dot(const Plan& p, const TH* colH, int z, int lag, const T* g) {
+    const int TB = p.tb, nt = p.n_time, Nz = p.N[2];
+    const int tb = lag / TB, tin = lag - tb * TB, nb = (nt + TB - 1) / TB;
+    const int len = tb == nb - 1 ? nt - (nb - 1) * TB : TB;
+    const TH* h = colH + (size_t)tb * TB * Nz * 3 + (size_t)z * len * 3 + tin * 3;
+    return g[0] * (T)h[0] + g[1] * (T)h[1] + g[2] * (T)h[2];
+}
+
+template <typename T, typename TH>
+__global__ void __launch_bounds__(kBlock)
+k_conv_overflow(Plan p, const TH* __restrict__ H, const float* __restrict__ decode, const NodeRec<T>* rec,
+                const unsigned long long* __restrict__ ctl, T* __restrict__ out) {
+    if (ctl[kCtlFallback] != 0ull) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const unsigned long long n_ovf = ctl[kCtlOverflow];
+    const OvfRec<T>* ovf = reinterpret_cast<const OvfRec<T>*>(rec + ((ctl[kCtlRecords] + 1) & ~1ull));
+    const int nt = p.n_time, Nz = p.N[2];
+    T dec = (T)1;
+    if constexpr (!std::is_same<T, TH>::value) dec = (T)decode[0];
+    const size_t waves = (size_t)gridDim.x * (kBlock / kWave);
+    for (size_t i = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < n_ovf; i += waves) {
+        const OvfRec<T> o = ovf[i];
+        const int m = o.zm & 0xffff, z0 = o.zm >> 16, z1 = z0 + 1 == Nz ? 0 : z0 + 1;
+        const TH* colH = H + (size_t)o.col * Nz * nt * 3;
+        for (int n = m + lane; n < nt; n += kWave) {
+            const T v = node_lag_dot<T, TH>(p, colH, z0, n - m, o.g) + node_lag_dot<T, TH>(p, colH, z1, n - m, o.g + 3);
+            if (v != (T)0) atomicAdd(out + (size_t)o.track * nt + n, v * dec);
         }
     }
 }
@@ -890,8 +999,7 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
                                dim3((unsigned)std::min<size_t>((n_zero + kBlock - 1) / kBlock, 4096)), dim3(kBlock),
                                0, s, reinterpret_cast<unsigned*>(b), n_zero);
             hipLaunchKernelGGL(k_set_capacity, dim3(1), dim3(1), 0, s, ctl, (unsigned long long)cap);
-            const size_t waves = (size_t)n_carriers * tl.n_chunks;
-            const unsigned grid = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
+            const unsigned grid = (unsigned)(((size_t)n_carriers + kBlock / kWave - 1) / (kBlock / kWave));
             hipLaunchKernelGGL(k_ev_count<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers, n_tracks,
                                static_cast<const T*>(pos), track, mask, count);
             hipLaunchKernelGGL(k_node_count, dim3((unsigned)std::min<size_t>((tl.n_cells + kBlock - 1) / kBlock,
@@ -919,6 +1027,9 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
         // tiles of conv_tile_nodes(sizeof(TH)) z-nodes
         rows(k_conv_rows<conv_tile_nodes(sizeof(TH)), T, TH>);
         if (e != hipSuccess) return e;
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_conv_overflow<T, TH>), dim3(1024), dim3(kBlock), 0, s, p, static_cast<const TH*>(h),
+                           decode, rec, ctl, static_cast<T*>(out));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (phase == 1) return hipSuccess;

@@ -88,9 +88,11 @@ def h_columns(run, cfg, cols_ij):
     return layout.to_standard(cols, N, nt, run["layout"]["h_time_block"])
 
 
-def current(ctx, run, carriers, precision=None, subset=None, binned=True, max_events=0):
+def current(ctx, run, carriers, precision=None, subset=None, binned=True, max_events=0, control=None):
     """wt_current through the C ABI; binned=True gives it a workspace (room
-    for max_events moving steps, default every step), binned=False none."""
+    for max_events moving steps, default every step), binned=False none.
+    control: a list that receives the workspace's four control words
+    (records, fallback flag, record capacity, overflow records)."""
     precision = run["precision"] if precision is None else precision
     dt = dtype_of(precision)
     pos = np.asarray(carriers["pos"])
@@ -113,6 +115,8 @@ def current(ctx, run, carriers, precision=None, subset=None, binned=True, max_ev
                   d_q.data_ptr(), d_tr.data_ptr(), out.data_ptr(), 0 if ws is None else ws.data_ptr(),
                   0 if ws is None else ws.numel())
     torch.cuda.synchronize()
+    if control is not None and ws is not None:
+        control.extend(int(v) for v in ws[:32].view(torch.int64).cpu())
     return out.cpu().numpy().astype(np.float64)
 
 

@@ -93,7 +93,9 @@ def _currents(ctx, plan, hbuf, car, idx, nt, binned=True):
     out = torch.empty((car["n_tracks"], nt), dtype=torch.float32, device="cuda")
     ws = None
     if binned:
-        ws = torch.empty(wt.wt_current_workspace(plan, pos.shape[0]), dtype=torch.uint8, device="cuda")
+        # room for 64 moving steps per carrier (these stop within 40)
+        ws = torch.empty(wt.wt_current_workspace(plan, pos.shape[0], 64 * pos.shape[0]), dtype=torch.uint8,
+                         device="cuda")
     say(f"  wt_current on {pos.shape[0]} carriers, workspace {0 if ws is None else ws.numel()} B")
     wt.wt_current(ctx, plan, hbuf.data_ptr(), pos.shape[0], car["n_tracks"], pos.data_ptr(), q.data_ptr(),
                   tr.data_ptr(), out.data_ptr(), 0 if ws is None else ws.data_ptr(), 0 if ws is None else ws.numel())

@@ -11,8 +11,9 @@
   a count of events on the host, and the overflow flag: with room for all
   events the binned form runs, with one event less the unbinned form takes
   over (same currents).
-* More tracks in one node column than a workgroup has accumulator rows (the
-  direct path), and more records in one z-tile than one LDS chunk holds
+* More tracks in one node column than a lane has per-track sums (records of
+  the others on the overflow list, and with no room for that list the
+  direct form), and more records in one z-tile than one LDS chunk holds
   (several chunks per tile); N_z smaller than a z-tile (nodes wrap).
 * No carriers, and carriers that never move.
 Bars: float64 1e-12 between the forms and 1e-9 against the oracle; float32
@@ -180,12 +181,22 @@ def test_many_tracks_and_crowded_tiles(ctx, precision):
     q = rng.choice([-1.0, 1.0], 500) * workloads.E_CHARGE
     track = np.concatenate([np.arange(200), rng.integers(0, 200, 300)]).astype(np.int32)
     car = rounded_carriers(dict(pos=pos, charge=q, track=track, n_tracks=200), precision)
-    i_bin = current(ctx, run, car)
+    ctl = []
+    # room for three times the steps: the records and the overflow list
+    i_bin = current(ctx, run, car, max_events=3 * 500 * nt, control=ctl)
     i_dir = current(ctx, run, car, binned=False)
     i_ref = _oracle(Hs, cfg, car)
     e_forms, e_ref = rel_l2(i_bin, i_dir), rel_l2(i_bin, i_ref)
-    say(f"  binned vs unbinned {e_forms:.2e}, vs oracle {e_ref:.2e}")
+    say(f"  binned vs unbinned {e_forms:.2e}, vs oracle {e_ref:.2e}; control words {ctl}")
     assert e_forms <= TOL_FORMS[precision] and e_ref <= TOL_ORACLE[precision]
+    assert ctl[1] == 0 and ctl[3] > 0                          # binned, with records on the overflow list
+    # room for the events only: the overflow list does not fit, the direct form runs
+    n_ev = _host_event_count(car, precision)
+    ctl = []
+    i_tight = current(ctx, run, car, max_events=n_ev, control=ctl)
+    say(f"  workspace for {n_ev} events only: control words {ctl}")
+    assert ctl[0] == 4 * n_ev and ctl[1] == 1
+    assert rel_l2(i_tight, i_dir) <= TOL_FORMS[precision]
     wt.wt_h_plan_destroy(run["plan"])
 
 
