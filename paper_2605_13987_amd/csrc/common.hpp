@@ -161,8 +161,8 @@ inline ConvTiling conv_tiling(const Plan& p) {
     const size_t recb = p.precision == 0 ? 64 : 32;
     t.zt = conv_tile_nodes(h_elem);
     t.slots = (p.precision == 0 ? kConvSlotsF64 : kConvSlotsF32) - 1;
-    // a chunk of records is at most two 16-byte words per thread
-    const int rb = (int)(2 * (size_t)t.threads * 16 / recb);
+    // a chunk of records is at most one 16-byte word per thread
+    const int rb = (int)((size_t)t.threads * 16 / recb);
     t.rb = rb < 64 ? rb : 64;
     // rows of 64 + n_time lags (rounded up to 16); lanes past the last
     // sample read up to threads - n_time lags further, which stay inside the
@@ -200,8 +200,9 @@ inline CurrentLayout current_layout(const Plan& p, const ConvTiling& t, long lon
     (void)p;
     return c;
 }
-// Bytes of the four records of one binned event (precision 0: double).
-inline size_t current_event_bytes(const Plan& p) { return 4 * (p.precision == 0 ? 64 : 32); }
+// Bytes of the four records of one binned event and their tracks
+// (precision 0: double).
+inline size_t current_event_bytes(const Plan& p) { return 4 * ((p.precision == 0 ? 64 : 32) + sizeof(int)); }
 // d_ws may be null (then one wavefront per carrier, no binning).  phase 1:
 // zero the output and bin the events; phase 2 (after phase 1 on the same
 // stream): accumulate.  form: 0 binned from kBinnedMinSteps polyline steps

@@ -20,8 +20,7 @@
 //                  trilinear weights of its two z-nodes in that column;
 //   k_slots        one wavefront per node column: its track table (the
 //                  tracks with the most records, the slots of its per-track
-//                  sums), each record rewritten with its slot and LDS
-//                  offsets, records of tracks past the table moved to an
+//                  sums), and the records of the other tracks copied to an
 //                  overflow list;
 //   k_conv_rows    one workgroup per node column, one lane per output
 //                  sample n.  The column's nodes go through LDS a tile of
@@ -53,6 +52,7 @@ constexpr int kScanItems = 4096;       // bin counts per workgroup of the scan
 constexpr unsigned long long kBinnedMinSteps = 1ull << 24;   // polyline steps from which wt_current bins
 
 constexpr int kScanThreads = 1024;
+constexpr unsigned kFlushRecords = 1024;   // records between flushes of the binned form's per-track sums
 
 // Control words of the workspace: [0] records (4 per event), [1] 1 when the
 // binned form cannot take the events (the direct form then runs), [2] the
@@ -299,10 +299,10 @@ k_current(Plan p, const TH* H, const float* decode, int n_carriers, int n_tracks
 // ---------------------------------------------------------------- binned form
 
 // A node-column record: one event as seen from one of the four (x, y) corner
-// columns of its cell.  As written: w0 = its step m | its lower z-node z0 << 16,
-// w1 = its track; g0 and g1 are -q dx times the trilinear weights of the
-// event's lower and upper z-node in this column.  k_slots rewrites w0 and w1
-// into what the accumulation uses (see there).
+// columns of its cell: w0 = its step m | its lower z-node z0 << 16, w1 = its
+// track; g0 and g1 are -q dx times the trilinear weights of the event's
+// lower and upper z-node in this column.  The accumulation rewrites w0 and
+// w1 as it stages them (see k_conv_rows).
 // Records are ordered by (node column, lower z-node); inside one such bin by
 // the cell they come from, then by arrival.
 template <typename T>
@@ -463,7 +463,7 @@ k_scan_apply(unsigned* offs, size_t n, const unsigned long long* bsum) {
 }
 
 // One wavefront per carrier again: every event written as four node-column
-// records.  In the bin of node column (X, Y) and z-node z0 the
+// records (and their tracks into a separate array, for k_slots).  In the bin of node column (X, Y) and z-node z0 the
 // records of cell (X, Y) come first, then those of cells (X, Y - 1),
 // (X - 1, Y) and (X - 1, Y - 1); inside one cell in the order the events
 // arrive (fill counter).
@@ -471,7 +471,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charge, const int* track,
              const unsigned long long* mask, const unsigned* count, unsigned* fill, const unsigned* offs,
-             const unsigned long long* ctl, NodeRec<T>* rec) {
+             const unsigned long long* ctl, NodeRec<T>* rec, int* rtrack) {
     const int lane = threadIdx.x & (kWave - 1);
     const size_t c = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (c >= (size_t)n_carriers || ctl[kCtlFallback] != 0ull) return;
@@ -503,6 +503,7 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
             NodeRec<T> r;
             r.w0 = m | (z0 << 16);
             r.w1 = tr;
+            rtrack[slot] = tr;
             r.g[0] = gx * w0;
             r.g[1] = gy * w0;
             r.g[2] = gz * w0;
@@ -516,19 +517,20 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
 
 // One wavefront per node column.  The column's track table: the tl.slots
 // tracks with the most records (ties: first appearance; -1 pads it).  Then
-// every record rewritten for the accumulation, with zl = z0 mod tl.zt (its
-// lower z-node inside its tile) and rowb = tl.rl * tl.lb (bytes of an LDS
-// row of lags):
-//   w0 = zl rowb - m lb   (LDS byte offset of lag -m of its lower node, from
+// the first two words of every record rewritten for the accumulation, with
+// zl = z0 mod tl.zt (its lower z-node inside its tile) and rowb = tl.rl *
+// tl.lb (bytes of an LDS row of lags):
+//   w0 = zl rowb - m lb    (LDS byte offset of lag -m of its lower node, from
 //                           row 0's lag 0)
 //   w1 = zl rowb | slot << 24
-// A record whose track is past the table goes to the overflow list (after
-// the records, in the same buffer), and stays with zero weights in the
-// table's spare slot; when the list would not fit, the direct form takes
-// all events (kCtlFallback).
+// A record whose track is past the table takes the spare slot (a sum that
+// is never used) and is copied to the overflow list (after the records, in
+// the same buffer); when the list would not fit, the direct form takes all
+// events (kCtlFallback).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned long long* ctl, int* tables) {
+k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, const int* rtrack, unsigned long long* ctl,
+        int* tables) {
     const int lane = threadIdx.x & (kWave - 1);
     const size_t col = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (col >= tl.n_cols || ctl[kCtlFallback] != 0ull) return;
@@ -539,7 +541,7 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned l
     int cand = -1, cnt = 0, nc = 0;
     for (unsigned b = r0; b < r1; b += kWave) {
         const unsigned r = b + (unsigned)lane;
-        const int trk = r < r1 ? rec[r].w1 : -1;
+        const int trk = r < r1 ? rtrack[r] : -1;
         unsigned long long pending = __ballot(trk >= 0);
         while (pending) {
             const int tk = __builtin_amdgcn_readlane(trk, (int)__builtin_ctzll(pending));
@@ -557,7 +559,7 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned l
         }
     }
     // the table: the candidates with the most records, most first
-    int tab = -1;
+    int tab = -1, used = 0;
     for (int k = 0; k < S; ++k) {
         int best = cnt, who = lane;
 #pragma unroll
@@ -572,6 +574,7 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned l
         const int tk = __builtin_amdgcn_readlane(cand, who);
         if (lane == k) tab = tk;
         if (lane == who) cnt = -1;
+        ++used;
     }
     if (lane < S) tables[col * S + lane] = tab;
     const int rowb = tl.rl * tl.lb;
@@ -581,12 +584,7 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned l
     for (unsigned b = r0; b < r1; b += kWave) {
         const unsigned r = b + (unsigned)lane;
         const bool have = r < r1;
-        NodeRec<T> R;
-        int trk = -1;
-        if (have) {
-            R = rec[r];
-            trk = R.w1;
-        }
+        const int trk = have ? rtrack[r] : -1;
         int slot = S;
         unsigned long long pending = __ballot(have);
         while (pending) {
@@ -597,13 +595,14 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned l
             pending &= ~same;
         }
         if (!have) continue;
-        const int m = R.w0 & 0xffff, z0 = R.w0 >> 16, zl = z0 % tl.zt;
+        const int w0 = rec[r].w0, m = w0 & 0xffff, zl = (w0 >> 16) % tl.zt;
         if (slot == S) {
             const unsigned long long i = atomicAdd(ctl + kCtlOverflow, 1ull);
             if (i < ovf_cap) {
+                const NodeRec<T> R = rec[r];
                 OvfRec<T> o;
                 o.col = (int)col;
-                o.zm = R.w0;
+                o.zm = w0;
                 o.track = trk;
                 o.pad = 0;
 #pragma unroll
@@ -612,12 +611,11 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned l
             } else {
                 ctl[kCtlFallback] = 1ull;                // no room: the direct form runs
             }
-#pragma unroll
-            for (int a = 0; a < 6; ++a) R.g[a] = (T)0;
         }
-        R.w0 = zl * rowb - m * tl.lb;
-        R.w1 = (zl * rowb) | (slot << 24);
-        rec[r] = R;
+        int2 w;
+        w.x = zl * rowb - m * tl.lb;
+        w.y = (zl * rowb) | (slot << 24);
+        *reinterpret_cast<int2*>(&rec[r].w0) = w;
     }
 }
 
@@ -717,10 +715,11 @@ __device__ __attribute__((always_inline)) inline NodeRec<T> lds_record(const Lds
     return u.r;
 }
 
-// Up to two 16-byte words per thread of a run of records, in flight between
-// their load and their store into LDS.
+// One 16-byte word per thread of a run of records (tl.rb records fill at
+// most one word per thread), in flight between its load and its store into
+// LDS.
 struct RecWords {
-    NU4 w[2];
+    NU4 w;
 };
 
 // The per-track sums of one lane: a block of registers indexed with the
@@ -779,19 +778,14 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
         const int n = (int)(b - a) * U4;
         const size_t base = n > 0 ? (size_t)a * U4 : 0;
         const int last = n > 0 ? n - 1 : 0;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            // volatile: issued here, ahead of the chunk's work, not moved down
-            // to the store that uses them
-            t.w[j] = *reinterpret_cast<const volatile NU4*>(rsrc + base + min(tid + j * nthr, last));
-        }
+        // volatile: issued here, ahead of the chunk's work, not moved down to
+        // the store that uses it
+        t.w = *reinterpret_cast<const volatile NU4*>(rsrc + base + min(tid, last));
     };
     auto stage_store = [=](const RecWords& t, unsigned a, unsigned b) {
         const int n = (int)(b - a) * U4;
         const int last = n > 0 ? n - 1 : 0;
-        Lds<NU4>* dst = reinterpret_cast<Lds<NU4>*>(rbuf);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) dst[min(tid + j * nthr, last)] = t.w[j];
+        reinterpret_cast<Lds<NU4>*>(rbuf)[min(tid, last)] = t.w;
     };
 
     // the lag this lane loads (lanes past the last lag load the last one and
@@ -817,9 +811,13 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
     const unsigned zs_odd = zs & 1u;
     auto write_rows = [=](const RawTile<ZT, TH>& t, int k) {
         if (tid < nt) {
+            // the lane's entry in row 0, made opaque so that the ZT + 1 row
+            // addresses are added here rather than kept live across the loop
+            int base = 64 + tid;
+            asm volatile("" : "+v"(base));
 #pragma unroll
             for (int i = 0; i <= ZT; ++i)
-                store_lag(t.n[i], (e0 ^ (zs_odd & (unsigned)node(k, i))) & 1u, rows + i * RL + 64 + tid);
+                store_lag(t.n[i], (e0 ^ (zs_odd & (unsigned)node(k, i))) & 1u, rows + base + i * RL);
         }
     };
     auto zo = [=](int z) -> unsigned { return __builtin_amdgcn_readfirstlane(zoff[z < Nz ? z : Nz]); };
@@ -850,6 +848,18 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
     const unsigned rows_ab = (unsigned)(size_t)rows;
     const unsigned lane_ab = rows_ab + (unsigned)(64 + tid) * LB;
     typename SlotSums<T>::V acc = {};
+    // the per-track sums to the output: one atomic per sample and track
+    const int used = __popcll(__ballot(tabv >= 0));
+    auto flush = [=](const typename SlotSums<T>::V& a) {
+        if (tid < nt) {
+            for (int k = 0; k < used; ++k) {
+                const int trk = __builtin_amdgcn_readlane(tabv, k);
+                const T v = a[k];
+                if (v != (T)0) atomicAdd(out + (size_t)trk * nt + tid, v * dec);
+            }
+        }
+    };
+    unsigned since = 0;
     T cur = (T)0;
     int k = next_tile(0, k0, msk);                                // there is one: the column has records
     unsigned tend = zo(k * ZT + ZT);
@@ -859,7 +869,12 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
     stage_load(t, r0, r1);
     load_tile(nx, k);
     int kc = -1;                                         // the tile in the rows
-    while (true) {
+    // groups of chunks of about kFlushRecords records, after each of which
+    // the sums go to the output (which bounds the length of each float sum)
+    bool more = true;
+    while (more) {
+      unsigned since = 0;
+      do {
         __syncthreads();                                 // the previous chunk's rows and records are read
         if (k != kc) {
             write_rows(nx, k);
@@ -877,43 +892,55 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
                 nend = zo(kn * ZT + ZT);
             }
         }
-        const bool more = kn < ntile;
+        more = kn < ntile;
         const unsigned n1 = more ? min(n0 + (unsigned)RB, nend) : n0;
         stage_load(t, n0, n1);
         if (more && kn != k) load_tile(nx, kn);          // lands while this chunk is processed
         // this chunk: every record added to its track's sum (records of
-        // tracks past the table have zero weights and the spare slot)
-        for (unsigned r = r0; r < r1; ++r) {
-            NodeRec<T> R = lds_record(rbuf + (r - r0));
-            const int w0 = __builtin_amdgcn_readfirstlane(R.w0), w1 = __builtin_amdgcn_readfirstlane(R.w1);
-            // the weights stay in vector registers
+        // tracks past the table go to the spare slot).  The first word of
+        // the next record is read while this one is processed.
+        if (r0 < r1) {
+            const Lds<NU4>* rw = reinterpret_cast<const Lds<NU4>*>(rbuf);
+            NU4 q0n = rw[0];
+            for (unsigned r = r0; r < r1; ++r) {
+                const unsigned i = r - r0;
+                union {
+                    NU4 w[U4];
+                    NodeRec<T> rec;
+                } u;
+                u.w[0] = q0n;
+                q0n = rw[min(i + 1, r1 - r0 - 1) * U4];
 #pragma unroll
-            for (int a = 0; a < 6; ++a) asm volatile("" : "+v"(R.g[a]));
-            // lag n - m of row zl, or the row's first (zero) lag when n - m < -64
-            const int rb0 = (int)rows_ab + (w1 & 0xffffff);
-            const unsigned ab = (unsigned)max((int)lane_ab + w0, rb0);
-            const Lds<Lag4<TH>>* h0 = (const Lds<Lag4<TH>>*)(size_t)ab;
-            const Lds<Lag4<TH>>* h1 = (const Lds<Lag4<TH>>*)(size_t)(ab + row_b);
-            const int slot = (unsigned)w1 >> 24;
-            T v = acc[slot];
-            v = project<T, TH>(h0, R.g, v);
-            v = project<T, TH>(h1, R.g + 3, v);
-            acc[slot] = v;
+                for (int k = 1; k < U4; ++k) u.w[k] = rw[i * U4 + k];
+                const int w0 = __builtin_amdgcn_readfirstlane(u.rec.w0);
+                const int w1 = __builtin_amdgcn_readfirstlane(u.rec.w1);
+                // the weights stay in vector registers
+#pragma unroll
+                for (int a = 0; a < 6; ++a) asm volatile("" : "+v"(u.rec.g[a]));
+                // lag n - m of row zl, or the row's first (zero) lag when n - m < -64
+                const int rb0 = (int)rows_ab + (w1 & 0xffffff);
+                const unsigned ab = (unsigned)max((int)lane_ab + w0, rb0);
+                const Lds<Lag4<TH>>* h0 = (const Lds<Lag4<TH>>*)(size_t)ab;
+                const Lds<Lag4<TH>>* h1 = (const Lds<Lag4<TH>>*)(size_t)(ab + row_b);
+                const int slot = (unsigned)w1 >> 24;
+                // the record's six products summed first, then added to the
+                // track's sum with one rounding (the sum runs over all the
+                // column's records)
+                T v = project<T, TH>(h0, u.rec.g, (T)0);
+                v = project<T, TH>(h1, u.rec.g + 3, v);
+                acc[slot] += v;
+            }
         }
-        if (!more) break;
-        k = kn;
-        r0 = n0;
-        r1 = n1;
-        tend = nend;
-    }
-    // the per-track sums of this column
-    const int used = __popcll(__ballot(tabv >= 0));
-    if (tid < nt) {
-        for (int k = 0; k < used; ++k) {
-            const int trk = __builtin_amdgcn_readlane(tabv, k);
-            const T v = acc[k];
-            if (v != (T)0) atomicAdd(out + (size_t)trk * nt + tid, v * dec);
+        since += r1 - r0;
+        if (more) {
+            k = kn;
+            r0 = n0;
+            r1 = n1;
+            tend = nend;
         }
+      } while (more && since < kFlushRecords);
+      flush(acc);
+      acc = typename SlotSums<T>::V{};
     }
 }
 
@@ -976,7 +1003,7 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
     // kBinnedMinSteps polyline steps the unbinned kernel is faster (its cost
     // is the steps that move, the binned form's also the grid's columns)
     const unsigned long long steps = (unsigned long long)n_carriers * p.n_time;
-    const bool binned = ws != nullptr && ws_bytes >= cl.fixed_bytes + 4 * sizeof(NodeRec<T>) && steps < 0xfffffff0ull &&
+    const bool binned = ws != nullptr && ws_bytes >= cl.fixed_bytes + 4 * (sizeof(NodeRec<T>) + sizeof(int)) && steps < 0xfffffff0ull &&
                         form != 2 && (steps >= kBinnedMinSteps || form == 1);
     unsigned long long* ctl = nullptr;
     if (binned) {
@@ -989,8 +1016,10 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
         unsigned long long* mask = reinterpret_cast<unsigned long long*>(b + cl.off_mask);
         int* tables = reinterpret_cast<int*>(b + cl.off_tables);
         NodeRec<T>* rec = reinterpret_cast<NodeRec<T>*>(b + cl.off_records);
-        size_t cap = (ws_bytes - cl.off_records) / sizeof(NodeRec<T>);
+        // records, then one track per record
+        size_t cap = (ws_bytes - cl.off_records) / (sizeof(NodeRec<T>) + sizeof(int));
         if (cap > 0xfffffff0ull) cap = 0xfffffff0ull;
+        int* rtrack = reinterpret_cast<int*>(rec + cap);
         if (phase == 1) {
             // control words, cell counts and fill counters are one zero-filled
             // run (no memset nodes, so the sequence can be captured)
@@ -1011,9 +1040,9 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
             hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, s, offs, tl.n_cells, bsum);
             hipLaunchKernelGGL(k_ev_scatter<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers,
                                static_cast<const T*>(pos), static_cast<const T*>(charge), track, mask, count, fill,
-                               offs, ctl, rec);
+                               offs, ctl, rec, rtrack);
             hipLaunchKernelGGL(k_slots<T>, dim3((unsigned)((tl.n_cols + kBlock / kWave - 1) / (kBlock / kWave))),
-                               dim3(kBlock), 0, s, p, tl, offs, rec, ctl, tables);
+                               dim3(kBlock), 0, s, p, tl, offs, rec, rtrack, ctl, tables);
             return hipGetLastError();
         }
         auto rows = [&](auto kernel) {
