@@ -129,16 +129,17 @@ hipError_t launch_electronics(int precision, int n_tracks, int nt, double dt, co
 // per node column, one lane per output sample: threads = 64 ceil(n_time /
 // 64); the column's z-nodes are taken zt at a time.  LDS: the tile's zt + 1
 // nodes as rows of 64 + threads lags (4 values each, of the stored H type),
-// the column's record offsets per z-node (N_z + 1), and rb records.  Per-track
-// sums live in registers: slots of them (the column's track table).
+// and the column's record offsets per z-node (N_z + 1).  Records are read
+// from global memory into scalar registers.  Per-track sums live in
+// registers: slots of them (the column's track table).
 struct ConvTiling {
     int threads, n_chunks;
     int zt;
-    int slots, rb;
+    int slots;
     int rl;               // lags per LDS row: 64 zero lags, n_time rounded up to 16
     int lb;               // bytes per lag in a row (4 values of the stored H type)
     size_t n_cells, n_cols;
-    size_t off_zoff, off_rbuf, lds_bytes;
+    size_t off_zoff, lds_bytes;
 };
 // per-track sums per lane (registers), float and double path; the last
 // one takes the tracks past the column's table.  16 leaves each lane 72
@@ -158,12 +159,8 @@ inline ConvTiling conv_tiling(const Plan& p) {
     t.threads = 64 * nw;
     t.n_chunks = nw;
     const int h_elem = p.precision == 0 ? 8 : (p.h_format == 1 ? 2 : 4);
-    const size_t recb = p.precision == 0 ? 64 : 32;
     t.zt = conv_tile_nodes(h_elem);
     t.slots = (p.precision == 0 ? kConvSlotsF64 : kConvSlotsF32) - 1;
-    // a chunk of records is at most one 16-byte word per thread
-    const int rb = (int)((size_t)t.threads * 16 / recb);
-    t.rb = rb < 64 ? rb : 64;
     // rows of 64 + n_time lags (rounded up to 16); lanes past the last
     // sample read up to threads - n_time lags further, which stay inside the
     // allocation (garbage they drop)
@@ -171,8 +168,7 @@ inline ConvTiling conv_tiling(const Plan& p) {
     t.lb = 4 * h_elem;
     const size_t rows = (size_t)(t.zt + 1) * t.rl * 4 * h_elem + (size_t)64 * 4 * h_elem;
     t.off_zoff = a16(rows);
-    t.off_rbuf = t.off_zoff + a16((size_t)(p.N[2] + 1) * sizeof(unsigned));
-    t.lds_bytes = t.off_rbuf + (size_t)t.rb * recb;
+    t.lds_bytes = t.off_zoff + a16((size_t)(p.N[2] + 1) * sizeof(unsigned));
     t.n_cols = (size_t)p.N[0] * p.N[1];
     t.n_cells = t.n_cols * p.N[2];
     return t;

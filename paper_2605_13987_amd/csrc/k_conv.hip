@@ -620,7 +620,8 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, const int*
 }
 
 // One node at one lane's lag as loaded: float16 as the 8 bytes from the
-// 4-byte aligned word at or below its three values, else the three values.
+// 4-byte aligned word at or below its first value (which holds its three
+// values), else the three values.
 template <typename TH>
 struct LagRaw {
     TH v[3];
@@ -639,6 +640,10 @@ struct RawTile {
 // types only.
 template <typename X>
 using Lds = __attribute__((address_space(3))) X;
+// An object in the constant address space (4): read-only while the kernel
+// runs.
+template <typename X>
+using Const = __attribute__((address_space(4))) X;
 typedef unsigned NU2 __attribute__((ext_vector_type(2)));
 typedef unsigned NU4 __attribute__((ext_vector_type(4)));
 template <typename X>
@@ -650,27 +655,27 @@ struct alignas(4 * sizeof(TH)) Lag4 {
     TH v[4];
 };
 
-// Load this lane's lag of a node (e = element offset of the lag in the
-// column; a float16 buffer has at least 2 bytes after its last value).
+// Load this lane's lag of a node (off = byte offset of the lag's first value
+// in the column; a float16 buffer has at least 2 bytes after its last value).
 template <typename TH>
-__device__ inline void load_lag(const TH* colH, unsigned e, LagRaw<TH>& o) {
+__device__ inline void load_lag(const unsigned char* colB, unsigned off, LagRaw<TH>& o) {
     if constexpr (std::is_same<TH, _Float16>::value) {
-        const Dword2 w = *reinterpret_cast<const Dword2*>(colH + (e & ~1u));
-        o.lo = w.lo;
-        o.hi = w.hi;
+        const NU2 w = *reinterpret_cast<const NU2*>(colB + (off & ~3u));
+        o.lo = w.x;
+        o.hi = w.y;
     } else {
-        o.v[0] = colH[e];
-        o.v[1] = colH[e + 1];
-        o.v[2] = colH[e + 2];
+        const TH* h = reinterpret_cast<const TH*>(colB + off);
+        o.v[0] = h[0];
+        o.v[1] = h[1];
+        o.v[2] = h[2];
     }
 }
 
-// A loaded lag as a row entry (odd: float16 values starting at an odd
-// element, in the high half of the first word).
+// A loaded lag as a row entry (sh: for float16, 16 when the lag's values
+// start in the high half of the first word, else 0).
 template <typename TH>
-__device__ __attribute__((always_inline)) inline void store_lag(const LagRaw<TH>& a, unsigned odd, Lds<Lag4<TH>>* dst) {
+__device__ __attribute__((always_inline)) inline void store_lag(const LagRaw<TH>& a, unsigned sh, Lds<Lag4<TH>>* dst) {
     if constexpr (std::is_same<TH, _Float16>::value) {
-        const unsigned sh = odd * 16u;
         NU2 w;
         w.x = __builtin_amdgcn_alignbit(a.hi, a.lo, sh);
         w.y = a.hi >> sh;
@@ -702,25 +707,35 @@ __device__ __attribute__((always_inline)) inline T project(const Lds<Lag4<TH>>* 
     return v;
 }
 
-// A record from LDS, as whole 16-byte words.
+// A record in scalar registers (read field by field through the constant
+// address space; used together, the reads merge into one load).
 template <typename T>
-__device__ __attribute__((always_inline)) inline NodeRec<T> lds_record(const Lds<NodeRec<T>>* p) {
-    union {
-        NU4 w[sizeof(NodeRec<T>) / 16];
-        NodeRec<T> r;
-    } u;
-    const Lds<NU4>* s = reinterpret_cast<const Lds<NU4>*>(p);
+struct RecRegs {
+    int w0, w1;
+    T g[6];
+};
+template <typename T>
+__device__ __attribute__((always_inline)) inline RecRegs<T> record_regs(const Const<NodeRec<T>>* q) {
+    RecRegs<T> r;
+    r.w0 = q->w0;
+    r.w1 = q->w1;
 #pragma unroll
-    for (int k = 0; k < (int)(sizeof(NodeRec<T>) / 16); ++k) u.w[k] = s[k];
-    return u.r;
+    for (int a = 0; a < 6; ++a) r.g[a] = q->g[a];
+    return r;
 }
 
-// One 16-byte word per thread of a run of records (tl.rb records fill at
-// most one word per thread), in flight between its load and its store into
-// LDS.
-struct RecWords {
-    NU4 w;
-};
+// One record's g0 . H(z0) + g1 . H(z0 + 1) at lag n - m (lane_ab: the LDS
+// byte address of this lane's lag 0 in row 0; rows_ab: that of row 0's first
+// entry; row_b: bytes per row).  Lag n - m of row zl, or the row's first
+// (zero) lag when n - m < -64.  The six products are summed first, so that
+// the record's term reaches its track's sum with one rounding.
+template <typename T, typename TH>
+__device__ __attribute__((always_inline)) inline T record_term(unsigned lane_ab, unsigned rows_ab, unsigned row_b,
+                                                               const RecRegs<T>& R) {
+    const unsigned ab = (unsigned)max((int)lane_ab + R.w0, (int)rows_ab + (R.w1 & 0xffffff));
+    const T v = project<T, TH>((const Lds<Lag4<TH>>*)(size_t)ab, R.g, (T)0);
+    return project<T, TH>((const Lds<Lag4<TH>>*)(size_t)(ab + row_b), R.g + 3, v);
+}
 
 // The per-track sums of one lane: a block of registers indexed with the
 // slot (uniform across the wavefront).
@@ -735,13 +750,15 @@ struct SlotSums {
 // The column's z-nodes go in tiles of ZT: the tile's ZT + 1 nodes are rows of
 // lags in LDS (64 zero lags, then lags 0 .. n_time - 1), written by the lanes
 // from the lag each loaded (lane tau: lag tau of every node of the tile).
-// Records go through LDS in chunks of at most tl.rb.  For each record every
-// lane reads lag n - m of its two z-nodes and adds g0 . H(z0) + g1 . H(z0 + 1)
-// to the sum of the record's track (one register per slot of the column's
-// track table; tracks past the table go to the output directly).  While a
-// chunk is processed the next chunk's records, and the next tile's nodes when
-// the chunk starts one, are in flight.  The registers go to the output at
-// the end, one atomic per sample and track.
+// A record is the same for every lane, so each wavefront reads it from global
+// memory into scalar registers; for each record every lane reads lag n - m of
+// its two z-nodes and adds g0 . H(z0) + g1 . H(z0 + 1) to the sum of the
+// record's track (one register per slot of the column's track table; tracks
+// past the table go to the output directly).  Records go four at a time,
+// whatever their tracks.  While a tile's records are processed the next
+// tile's nodes are in flight, and its records are pulled into the caches.
+// The registers go to the output after about every kFlushRecords records,
+// one atomic per sample and track.
 template <int ZT, typename T, typename TH>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 7)))
 k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __restrict__ decode,
@@ -757,9 +774,8 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
     Lds<unsigned char>* lds = (Lds<unsigned char>*)smem;
     Lds<Lag4<TH>>* rows = reinterpret_cast<Lds<Lag4<TH>>*>(lds);                 // [ZT + 1][RL]
     Lds<unsigned>* zoff = reinterpret_cast<Lds<unsigned>*>(lds + tl.off_zoff);   // [Nz + 1]
-    Lds<NodeRec<T>>* rbuf = reinterpret_cast<Lds<NodeRec<T>>*>(lds + tl.off_rbuf);   // [rb]
     const int tid = threadIdx.x, lane = tid & (kWave - 1), nthr = blockDim.x;
-    const int S = tl.slots, RB = tl.rb, RL = tl.rl;
+    const int S = tl.slots, RL = tl.rl;
     constexpr unsigned LB = sizeof(Lag4<TH>);
     const unsigned row_b = (unsigned)RL * LB;
     for (int i = tid; i < (ZT + 1) * 64; i += nthr) {
@@ -769,24 +785,9 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
     }
     for (int i = tid; i <= Nz; i += nthr) zoff[i] = no[i] - cbeg;       // record offsets inside the column
     const int tabv = lane < S ? tables[col * S + lane] : -1;
-    constexpr int U4 = (int)(sizeof(NodeRec<T>) / 16);
-    const NU4* rsrc = reinterpret_cast<const NU4*>(rec + cbeg);
-    // records [a, b) of the column into registers (every thread loads: past
-    // the run its last word, an empty run the column's first), then into LDS
-    // (every thread stores: past the run the last word again)
-    auto stage_load = [=](RecWords& t, unsigned a, unsigned b) {
-        const int n = (int)(b - a) * U4;
-        const size_t base = n > 0 ? (size_t)a * U4 : 0;
-        const int last = n > 0 ? n - 1 : 0;
-        // volatile: issued here, ahead of the chunk's work, not moved down to
-        // the store that uses it
-        t.w = *reinterpret_cast<const volatile NU4*>(rsrc + base + min(tid, last));
-    };
-    auto stage_store = [=](const RecWords& t, unsigned a, unsigned b) {
-        const int n = (int)(b - a) * U4;
-        const int last = n > 0 ? n - 1 : 0;
-        reinterpret_cast<Lds<NU4>*>(rbuf)[min(tid, last)] = t.w;
-    };
+    // the column's records through the constant address space: read-only
+    // for the whole kernel, so uniform reads of them are scalar loads
+    const Const<NodeRec<T>>* crec = (const Const<NodeRec<T>>*)(size_t)(rec + cbeg);
 
     // the lag this lane loads (lanes past the last lag load the last one and
     // do not store it)
@@ -794,34 +795,50 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
     const int nb = (nt + p.tb - 1) / p.tb;
     const int tb = tl0 / p.tb, tin = tl0 - tb * p.tb;
     const int len = tb == nb - 1 ? nt - (nb - 1) * p.tb : p.tb;
-    const unsigned e0 = (unsigned)(tb * p.tb * Nz * 3 + tin * 3), zs = (unsigned)(len * 3);
-    const TH* colH = H + col * Nz * (size_t)nt * 3;
+    // byte offsets in the column: this lane's lag of node 0, and from one
+    // node to the next
+    const unsigned off0 = (unsigned)(tb * p.tb * Nz * 3 + tin * 3) * (unsigned)sizeof(TH);
+    const unsigned zs_b = (unsigned)(len * 3) * (unsigned)sizeof(TH);
+    const unsigned char* colB = reinterpret_cast<const unsigned char*>(H + col * Nz * (size_t)nt * 3);
     T dec = (T)1;
     if constexpr (!std::is_same<T, TH>::value) dec = (T)decode[0];
     const int ntile = (Nz + ZT - 1) / ZT;
-    auto node = [=](int k, int i) {
+    // the tile's ZT + 1 nodes k ZT + i; past node N_z - 1 they wrap (node N_z
+    // is node 0), which only the last tile reaches
+    auto wraps = [=](int k) { return k * ZT + ZT >= Nz; };
+    auto node_off = [=](int k, int i) {
         const int z = k * ZT + i;
-        return z < Nz ? z : z % Nz;                      // node N_z is node 0
+        return off0 + (unsigned)(z < Nz ? z : z % Nz) * zs_b;
     };
     auto load_tile = [=](RawTile<ZT, TH>& t, int k) {
+        if (!wraps(k)) {
 #pragma unroll
-        for (int i = 0; i <= ZT; ++i) load_lag(colH, e0 + (unsigned)node(k, i) * zs, t.n[i]);
+            for (int i = 0; i <= ZT; ++i) load_lag(colB, off0 + (unsigned)(k * ZT + i) * zs_b, t.n[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i <= ZT; ++i) load_lag(colB, node_off(k, i), t.n[i]);
+        }
     };
-    // float16 values of a lag start at an odd element when e0 + z zs is odd
-    const unsigned zs_odd = zs & 1u;
+    // float16: the shift of node k ZT + i's lag in its loaded word; with ZT
+    // even it only depends on the parity of i, except in the last tile
+    const unsigned sh_even = (off0 & 2u) * 8u, sh_odd = ((off0 + zs_b) & 2u) * 8u;
     auto write_rows = [=](const RawTile<ZT, TH>& t, int k) {
         if (tid < nt) {
             // the lane's entry in row 0, made opaque so that the ZT + 1 row
             // addresses are added here rather than kept live across the loop
             int base = 64 + tid;
             asm volatile("" : "+v"(base));
+            if (ZT % 2 == 0 && !wraps(k)) {
 #pragma unroll
-            for (int i = 0; i <= ZT; ++i)
-                store_lag(t.n[i], (e0 ^ (zs_odd & (unsigned)node(k, i))) & 1u, rows + base + i * RL);
+                for (int i = 0; i <= ZT; ++i) store_lag(t.n[i], (i & 1) ? sh_odd : sh_even, rows + base + i * RL);
+            } else {
+#pragma unroll
+                for (int i = 0; i <= ZT; ++i) store_lag(t.n[i], (node_off(k, i) & 2u) * 8u, rows + base + i * RL);
+            }
         }
     };
     auto zo = [=](int z) -> unsigned { return __builtin_amdgcn_readfirstlane(zoff[z < Nz ? z : Nz]); };
-    // non-empty tiles, 64 at a time: bit i of ts.msk is tile ts.k0 + i
+    // non-empty tiles, 64 at a time: bit i of msk is tile k0 + i
     auto scan_tiles = [=](int k) -> unsigned long long {
         const int t = k + lane;
         bool ne = false;
@@ -850,98 +867,80 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
     typename SlotSums<T>::V acc = {};
     // the per-track sums to the output: one atomic per sample and track
     const int used = __popcll(__ballot(tabv >= 0));
+    // (the lane test inside the loop: a branch on it around the loop would
+    // join with the record loop's control flow and make that divergent)
     auto flush = [=](const typename SlotSums<T>::V& a) {
-        if (tid < nt) {
-            for (int k = 0; k < used; ++k) {
-                const int trk = __builtin_amdgcn_readlane(tabv, k);
-                const T v = a[k];
-                if (v != (T)0) atomicAdd(out + (size_t)trk * nt + tid, v * dec);
-            }
+        for (int k = 0; k < used; ++k) {
+            const int trk = __builtin_amdgcn_readlane(tabv, k);
+            const T v = a[k];
+            if (tid < nt && v != (T)0) atomicAdd(out + (size_t)trk * nt + tid, v * dec);
         }
     };
-    unsigned since = 0;
-    T cur = (T)0;
-    int k = next_tile(0, k0, msk);                                // there is one: the column has records
-    unsigned tend = zo(k * ZT + ZT);
-    unsigned r0 = zo(k * ZT), r1 = min(r0 + (unsigned)RB, tend);
+    unsigned since = 0, pf = 0;
+    int k = next_tile(0, k0, msk);                       // there is one: the column has records
     RawTile<ZT, TH> nx;
-    RecWords t;
-    stage_load(t, r0, r1);
     load_tile(nx, k);
-    int kc = -1;                                         // the tile in the rows
-    // groups of chunks of about kFlushRecords records, after each of which
-    // the sums go to the output (which bounds the length of each float sum)
-    bool more = true;
-    while (more) {
-      unsigned since = 0;
-      do {
-        __syncthreads();                                 // the previous chunk's rows and records are read
-        if (k != kc) {
-            write_rows(nx, k);
-            kc = k;
-        }
-        stage_store(t, r0, r1);
+    while (k < ntile) {
+        __syncthreads();                                 // the previous tile's rows are read
+        write_rows(nx, k);
         __syncthreads();
-        // the next chunk: the rest of this tile, else the next tile's first
-        int kn = k;
-        unsigned n0 = r1, nend = tend;
-        if (r1 >= tend) {
-            kn = next_tile(k + 1, k0, msk);
-            if (kn < ntile) {
-                n0 = zo(kn * ZT);
-                nend = zo(kn * ZT + ZT);
+        const unsigned rbeg = zo(k * ZT), rend = zo(k * ZT + ZT);
+        {
+            // the first lines of the tile's records into the scalar cache,
+            // all in flight together (a word of each, the last record's
+            // past the end)
+            const Const<unsigned>* tw = (const Const<unsigned>*)(crec + rbeg);
+            constexpr unsigned RW = sizeof(NodeRec<T>) / 4, LW = 64 / 4;
+            const unsigned lastw = (rend - rbeg - 1) * RW;
+            unsigned x = 0;
+#pragma unroll
+            for (unsigned j = 0; j < 8; ++j) x ^= tw[min(j * LW, lastw)];
+            asm volatile("" ::"s"(x));
+        }
+        const int kn = next_tile(k + 1, k0, msk);
+        if (kn < ntile) {
+            load_tile(nx, kn);                           // lands while this tile is processed
+            // the next tile's records pulled into the caches (a word of
+            // every 64 bytes, up to 4 KB), so that its scalar reads hit
+            asm volatile("" ::"v"(pf));                  // the previous pull has landed
+            const unsigned a = zo(kn * ZT), b = zo(kn * ZT + ZT);
+            const unsigned words = (b - a) * (unsigned)(sizeof(NodeRec<T>) / 4);
+            const unsigned w = min((unsigned)lane * 16u, words - 1u);
+            pf = reinterpret_cast<const unsigned*>(rec + cbeg + a)[w];
+        }
+        // the tile's records in groups that end where the sums are due out,
+        // four at a time (their loads and LDS reads in flight together),
+        // each added to its track's sum
+        for (unsigned s0 = rbeg; s0 < rend;) {
+            const unsigned s1 = min(s0 + (kFlushRecords - since), rend);
+            const Const<NodeRec<T>>* q = crec + s0;
+            for (; q + 4 <= crec + s1; q += 4) {
+                const RecRegs<T> R0 = record_regs(q), R1 = record_regs(q + 1);
+                const RecRegs<T> R2 = record_regs(q + 2), R3 = record_regs(q + 3);
+                const T v0 = record_term<T, TH>(lane_ab, rows_ab, row_b, R0);
+                const T v1 = record_term<T, TH>(lane_ab, rows_ab, row_b, R1);
+                const T v2 = record_term<T, TH>(lane_ab, rows_ab, row_b, R2);
+                const T v3 = record_term<T, TH>(lane_ab, rows_ab, row_b, R3);
+                acc[(unsigned)R0.w1 >> 24] += v0;
+                acc[(unsigned)R1.w1 >> 24] += v1;
+                acc[(unsigned)R2.w1 >> 24] += v2;
+                acc[(unsigned)R3.w1 >> 24] += v3;
+            }
+            for (; q != crec + s1; ++q) {
+                const RecRegs<T> R = record_regs(q);
+                acc[(unsigned)R.w1 >> 24] += record_term<T, TH>(lane_ab, rows_ab, row_b, R);
+            }
+            since += s1 - s0;
+            s0 = s1;
+            if (since >= kFlushRecords) {
+                flush(acc);
+                acc = typename SlotSums<T>::V{};
+                since = 0;
             }
         }
-        more = kn < ntile;
-        const unsigned n1 = more ? min(n0 + (unsigned)RB, nend) : n0;
-        stage_load(t, n0, n1);
-        if (more && kn != k) load_tile(nx, kn);          // lands while this chunk is processed
-        // this chunk: every record added to its track's sum (records of
-        // tracks past the table go to the spare slot).  The first word of
-        // the next record is read while this one is processed.
-        if (r0 < r1) {
-            const Lds<NU4>* rw = reinterpret_cast<const Lds<NU4>*>(rbuf);
-            NU4 q0n = rw[0];
-            for (unsigned r = r0; r < r1; ++r) {
-                const unsigned i = r - r0;
-                union {
-                    NU4 w[U4];
-                    NodeRec<T> rec;
-                } u;
-                u.w[0] = q0n;
-                q0n = rw[min(i + 1, r1 - r0 - 1) * U4];
-#pragma unroll
-                for (int k = 1; k < U4; ++k) u.w[k] = rw[i * U4 + k];
-                const int w0 = __builtin_amdgcn_readfirstlane(u.rec.w0);
-                const int w1 = __builtin_amdgcn_readfirstlane(u.rec.w1);
-                // the weights stay in vector registers
-#pragma unroll
-                for (int a = 0; a < 6; ++a) asm volatile("" : "+v"(u.rec.g[a]));
-                // lag n - m of row zl, or the row's first (zero) lag when n - m < -64
-                const int rb0 = (int)rows_ab + (w1 & 0xffffff);
-                const unsigned ab = (unsigned)max((int)lane_ab + w0, rb0);
-                const Lds<Lag4<TH>>* h0 = (const Lds<Lag4<TH>>*)(size_t)ab;
-                const Lds<Lag4<TH>>* h1 = (const Lds<Lag4<TH>>*)(size_t)(ab + row_b);
-                const int slot = (unsigned)w1 >> 24;
-                // the record's six products summed first, then added to the
-                // track's sum with one rounding (the sum runs over all the
-                // column's records)
-                T v = project<T, TH>(h0, u.rec.g, (T)0);
-                v = project<T, TH>(h1, u.rec.g + 3, v);
-                acc[slot] += v;
-            }
-        }
-        since += r1 - r0;
-        if (more) {
-            k = kn;
-            r0 = n0;
-            r1 = n1;
-            tend = nend;
-        }
-      } while (more && since < kFlushRecords);
-      flush(acc);
-      acc = typename SlotSums<T>::V{};
+        k = kn;
     }
+    flush(acc);
 }
 
 // The overflow list: one wavefront per record (a grid-stride loop over the
