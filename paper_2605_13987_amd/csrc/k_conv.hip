@@ -760,7 +760,7 @@ struct SlotSums {
 // The registers go to the output after about every kFlushRecords records,
 // one atomic per sample and track.
 template <int ZT, typename T, typename TH>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 7)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : (sizeof(TH) == 2 ? 6 : 7))))
 k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __restrict__ decode,
             const unsigned* __restrict__ offs, const NodeRec<T>* __restrict__ rec, const int* __restrict__ tables,
             const unsigned long long* __restrict__ ctl, int n_tracks, T* __restrict__ out) {
