@@ -253,6 +253,7 @@ def c5_step(torch, wt, np, cfg, h_format, steps, warmup, cur_bytes, subset, n_co
            "tracks_per_s": n_tr / t_cur_all, "carriers_per_s": n_c / t_cur_all,
            "events_per_s": ctl[0] // 4 / t_cur_all, "moving_steps": ctl[0] // 4,
            "h_bytes": lay["h_bytes"], "h_scale": rep["h_scale"], "backward_error_max": rep["backward_error_max"],
+           "fit": fit_fp64(lay["n_q"], spec["n_freq"], stage["collocation_solve"]),
            "stage_ms": {k: round(v, 4) for k, v in stage.items()},
            "roofline_dominant": rl[dom], "roofline_other": rl["k_conv_rows" if dom == "k_synthesis_pipe"
                                                             else "k_synthesis_pipe"]}
@@ -581,6 +582,7 @@ def px128_section(torch, wt, np, steps, warmup, oracle_on):
                      "tracks_per_s": n_tr / t_cur, "carriers_per_s": n_c / t_cur,
                      "stage_ms": {k: round(v, 4) for k, v in stage.items()},
                      "synthesis_hbm_frac": synth_bytes / (stage["synthesis"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "fit": fit_fp64(lay["n_q"], spec["n_freq"], stage["collocation_solve"]),
                      "cols": layout.to_standard(vals, N, nt, lay["h_time_block"]), "i": o.double().cpu().numpy()}
         print(f"# 128x128x256 {name}: {ms:.3f} ms/step, stages {out[name]['stage_ms']}", file=sys.stderr,
               flush=True)
@@ -627,12 +629,19 @@ def m256_section(torch, wt, np):
     wt.wt_context_enable_timing(ctx, False)
     wt.wt_h_plan_destroy(plan)
     wt.wt_context_destroy(ctx)
-    n = lay["n_q"] + 1
-    ms = float(np.median(t))
-    flops = 512 * (8.0 / 3.0 * n ** 3)       # complex LU, 4 real flops per complex multiply-add
-    return {"n_unknowns": n, "n_freq": 512, "ms": ms, "fp64_tflops": flops / (ms * 1e-3) / 1e12,
-            "fp64_frac_of_78.6": flops / (ms * 1e-3) / 78.6e12,
-            "backward_error_max": rep["backward_error_max"], "ir_iters_max": rep["ir_iters_max"]}
+    res = fit_fp64(lay["n_q"], 512, float(np.median(t)))
+    res.update(backward_error_max=rep["backward_error_max"], ir_iters_max=rep["ir_iters_max"])
+    return res
+
+
+def fit_fp64(n_q, n_freq, ms):
+    """FP64 rate of the boundary fit over its stage time: the LU of the
+    (n_q + 1)-unknown bordered complex system per frequency, 8/3 n^3 real
+    flops (4 per complex multiply-add), against the 78.6 TFLOP/s FP64 peak."""
+    n = n_q + 1
+    flops = n_freq * (8.0 / 3.0 * n ** 3)
+    return {"n_unknowns": n, "n_freq": n_freq, "ms": ms, "fp64_tflops": flops / (ms * 1e-3) / 1e12,
+            "fp64_frac_of_78.6": flops / (ms * 1e-3) / 78.6e12}
 
 
 def electronics_section(torch, wt, workloads, i_cur, spec):
@@ -827,11 +836,12 @@ def main():
         "roofline": mixed["roofline_dominant"],
         "roofline_other_kernel": mixed["roofline_other"],
         "plain": {k: plain[k] for k in ("value", "ms_per_step", "tracks_per_s", "carriers_per_s", "events_per_s",
-                                        "h_grid_freq_pts_per_s", "stage_ms", "h_bytes")}
+                                        "h_grid_freq_pts_per_s", "stage_ms", "h_bytes", "fit")}
                  | {"roofline": plain["roofline_dominant"], "roofline_other_kernel": plain["roofline_other"],
                     "h_storage": "float32"},
         "moving_steps": mixed["moving_steps"],
         "backward_error_max": mixed["backward_error_max"],
+        "fit": mixed["fit"],
         "rel_err": err,
     }
     if cpu_base is not None:

@@ -175,11 +175,12 @@ inline ConvTiling conv_tiling(const Plan& p) {
 }
 // Workspace of the binned convolution (byte offsets): control words, cell
 // counts and fill counters (zeroed together), record offsets per (node
-// column, z-node) (n_cells + 1), scan block sums, the per-(carrier, 64 steps)
-// moving masks, the per-column track tables, then the records (as many as
-// fit; four per event).
+// column, z-node) (n_cells + 1), scan block sums, per cell the first record
+// of its events in each of its four bins (4 u32), the per-(carrier, 64
+// steps) moving masks, the per-column track tables, then the records (as
+// many as fit; four per event).
 struct CurrentLayout {
-    size_t off_ctl, off_count, off_fill, off_offs, off_bsum, off_mask, off_tables, off_records, fixed_bytes;
+    size_t off_ctl, off_count, off_fill, off_offs, off_bsum, off_base, off_mask, off_tables, off_records, fixed_bytes;
 };
 inline CurrentLayout current_layout(const Plan& p, const ConvTiling& t, long long n_carriers) {
     auto a256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -189,7 +190,8 @@ inline CurrentLayout current_layout(const Plan& p, const ConvTiling& t, long lon
     c.off_fill = c.off_count + t.n_cells * sizeof(unsigned);
     c.off_offs = a256(c.off_fill + t.n_cells * sizeof(unsigned));
     c.off_bsum = a256(c.off_offs + (t.n_cells + 1) * sizeof(unsigned));
-    c.off_mask = a256(c.off_bsum + ((t.n_cells + 4095) / 4096) * sizeof(unsigned long long));
+    c.off_base = a256(c.off_bsum + ((t.n_cells + 4095) / 4096) * sizeof(unsigned long long));
+    c.off_mask = a256(c.off_base + t.n_cells * 4 * sizeof(unsigned));
     c.off_tables = a256(c.off_mask + (size_t)n_carriers * t.n_chunks * sizeof(unsigned long long));
     c.off_records = a256(c.off_tables + t.n_cols * t.slots * sizeof(int));
     c.fixed_bytes = c.off_records;

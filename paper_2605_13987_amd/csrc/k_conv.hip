@@ -15,6 +15,8 @@
 //                  move (a bit mask), and the number of events per cell;
 //   k_node_count,  records per (node column, z-node): the events of the four
 //   k_scan_*       cells around it at that z, scanned into offsets;
+//   k_cell_bases   per cell with events, where its records start in each of
+//                  the four bins it feeds;
 //   k_ev_scatter   every event written as four records, one per corner
 //                  column of its cell: step, track and -q dx times the
 //                  trilinear weights of its two z-nodes in that column;
@@ -27,8 +29,9 @@
 //                  z-nodes at a time, as rows of lags (the next tile and the
 //                  next records loading meanwhile); for each record every
 //                  lane adds the projection at lag n - m of its two z-nodes
-//                  to its track's sum, one register per track; the registers
-//                  go to the output once, when the workgroup ends;
+//                  to its track's sum, one register per track (records read
+//                  into scalar registers, four at a time); the registers go
+//                  to the output every thousand or so records;
 //   k_conv_overflow the overflow list, one wavefront per record, its two
 //                  z-nodes read from global memory.
 //
@@ -370,6 +373,29 @@ k_node_count(Plan p, const unsigned* count, unsigned* nodes) {
     }
 }
 
+// Per grid cell with events: where its events' records start in each of the
+// four bins it feeds (the bins of its corner node columns (x0, y0), (x0,
+// y1), (x1, y0), (x1, y1) at its z0): the bin's offset plus the records of
+// the cells that come before it in that bin (a bin holds the events of cell
+// (X, Y), then (X, Y - 1), (X - 1, Y), (X - 1, Y - 1)).
+__global__ void __launch_bounds__(kBlock)
+k_cell_bases(Plan p, const unsigned* count, const unsigned* offs, uint4* base) {
+    const int Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
+    const size_t n = (size_t)Nx * Ny * Nz;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        if (count[i] == 0) continue;
+        const size_t col = i / Nz;
+        const int z = (int)(i - col * Nz);
+        const int x0 = (int)(col / Ny), y0 = (int)(col - (size_t)x0 * Ny);
+        const int x1 = x0 + 1 == Nx ? 0 : x0 + 1, y1 = y0 + 1 == Ny ? 0 : y0 + 1, ym = y0 == 0 ? Ny - 1 : y0 - 1;
+        auto cell = [&](int x, int y) { return ((size_t)x * Ny + y) * Nz + z; };
+        const unsigned cA = count[cell(x0, y1)], cB = count[cell(x1, y0)], cC = count[cell(x1, ym)],
+                       cD = count[cell(x1, y1)];
+        base[i] = make_uint4(offs[i], offs[cell(x0, y1)] + cA, offs[cell(x1, y0)] + cB + cC,
+                             offs[cell(x1, y1)] + cD + cB + cA);
+    }
+}
+
 // Inclusive scan of one value per thread over the workgroup (LDS scratch of
 // one value per wavefront); *total receives the workgroup's sum.
 template <typename U>
@@ -470,12 +496,12 @@ k_scan_apply(unsigned* offs, size_t n, const unsigned long long* bsum) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charge, const int* track,
-             const unsigned long long* mask, const unsigned* count, unsigned* fill, const unsigned* offs,
-             const unsigned long long* ctl, NodeRec<T>* rec, int* rtrack) {
+             const unsigned long long* mask, unsigned* fill, const uint4* base, const unsigned long long* ctl,
+             NodeRec<T>* rec, int* rtrack) {
     const int lane = threadIdx.x & (kWave - 1);
     const size_t c = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (c >= (size_t)n_carriers || ctl[kCtlFallback] != 0ull) return;
-    const int nt = p.n_time, Nx = p.N[0], Ny = p.N[1], Nz = p.N[2];
+    const int nt = p.n_time, Ny = p.N[1], Nz = p.N[2];
     const T* P = pos + c * (size_t)(nt + 1) * 3;
     for (int jc = 0; jc < tl.n_chunks; ++jc) {
         const unsigned long long bits = mask[c * tl.n_chunks + jc];
@@ -484,20 +510,17 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
         int x0, y0, z0;
         T fx, fy, fz, dx, dy, dz;
         if (!event_cell(p, P, m, x0, y0, z0, fx, fy, fz, dx, dy, dz)) continue;   // cannot happen: the mask says it moves
-        auto cell = [&](int x, int y) { return ((size_t)x * Ny + y) * Nz + z0; };
-        const int x1 = x0 + 1 == Nx ? 0 : x0 + 1, y1 = y0 + 1 == Ny ? 0 : y0 + 1, ym = y0 == 0 ? Ny - 1 : y0 - 1;
-        const unsigned j = atomicAdd(fill + cell(x0, y0), 1u);
-        // records of the cells before this one in each of the four bins
-        const unsigned cA = count[cell(x0, y1)], cB = count[cell(x1, y0)], cC = count[cell(x1, ym)],
-                       cD = count[cell(x1, y1)];
+        const size_t cell = ((size_t)x0 * Ny + y0) * Nz + z0;
+        const unsigned j = atomicAdd(fill + cell, 1u);
+        // where this cell's records start in each of its four bins
+        const uint4 bs = base[cell];
         const T q = charge[c];
         const int tr = track[c];
         const T gx = -q * dx, gy = -q * dy, gz = -q * dz;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int ox = k >> 1, oy = k & 1;
-            const unsigned before = k == 0 ? 0u : k == 1 ? cA : k == 2 ? cB + cC : cD + cB + cA;
-            const size_t slot = offs[cell(ox ? x1 : x0, oy ? y1 : y0)] + before + j;
+            const size_t slot = (size_t)(k == 0 ? bs.x : k == 1 ? bs.y : k == 2 ? bs.z : bs.w) + j;
             const T wxy = (ox ? fx : (T)1 - fx) * (oy ? fy : (T)1 - fy);
             const T w0 = wxy * ((T)1 - fz), w1 = wxy * fz;
             NodeRec<T> r;
@@ -1012,6 +1035,7 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
         unsigned* fill = reinterpret_cast<unsigned*>(b + cl.off_fill);
         unsigned* offs = reinterpret_cast<unsigned*>(b + cl.off_offs);
         unsigned long long* bsum = reinterpret_cast<unsigned long long*>(b + cl.off_bsum);
+        uint4* base = reinterpret_cast<uint4*>(b + cl.off_base);
         unsigned long long* mask = reinterpret_cast<unsigned long long*>(b + cl.off_mask);
         int* tables = reinterpret_cast<int*>(b + cl.off_tables);
         NodeRec<T>* rec = reinterpret_cast<NodeRec<T>*>(b + cl.off_records);
@@ -1037,9 +1061,12 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
             hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, offs, tl.n_cells, bsum);
             hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, bsum, (int)nb, ctl);
             hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, s, offs, tl.n_cells, bsum);
+            hipLaunchKernelGGL(k_cell_bases, dim3((unsigned)std::min<size_t>((tl.n_cells + kBlock - 1) / kBlock,
+                                                                              65536)),
+                               dim3(kBlock), 0, s, p, count, offs, base);
             hipLaunchKernelGGL(k_ev_scatter<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers,
-                               static_cast<const T*>(pos), static_cast<const T*>(charge), track, mask, count, fill,
-                               offs, ctl, rec, rtrack);
+                               static_cast<const T*>(pos), static_cast<const T*>(charge), track, mask, fill, base,
+                               ctl, rec, rtrack);
             hipLaunchKernelGGL(k_slots<T>, dim3((unsigned)((tl.n_cols + kBlock / kWave - 1) / (kBlock / kWave))),
                                dim3(kBlock), 0, s, p, tl, offs, rec, rtrack, ctl, tables);
             return hipGetLastError();
