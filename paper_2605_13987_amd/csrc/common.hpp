@@ -198,9 +198,8 @@ inline CurrentLayout current_layout(const Plan& p, const ConvTiling& t, long lon
     (void)p;
     return c;
 }
-// Bytes of the four records of one binned event and their tracks
-// (precision 0: double).
-inline size_t current_event_bytes(const Plan& p) { return 4 * ((p.precision == 0 ? 64 : 32) + sizeof(int)); }
+// Bytes of the four records of one binned event (precision 0: double).
+inline size_t current_event_bytes(const Plan& p) { return 4 * (size_t)(p.precision == 0 ? 64 : 32); }
 // d_ws may be null (then one wavefront per carrier, no binning).  phase 1:
 // zero the output and bin the events; phase 2 (after phase 1 on the same
 // stream): accumulate.  form: 0 binned from kBinnedMinSteps polyline steps

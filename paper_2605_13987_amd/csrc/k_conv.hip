@@ -489,15 +489,16 @@ k_scan_apply(unsigned* offs, size_t n, const unsigned long long* bsum) {
 }
 
 // One wavefront per carrier again: every event written as four node-column
-// records (and their tracks into a separate array, for k_slots).  In the bin of node column (X, Y) and z-node z0 the
-// records of cell (X, Y) come first, then those of cells (X, Y - 1),
-// (X - 1, Y) and (X - 1, Y - 1); inside one cell in the order the events
-// arrive (fill counter).
+// records (w1: the track, until k_slots rewrites it), each at its cell's base
+// in that bin (k_cell_bases) plus its arrival index in the cell (fill
+// counter).  In the bin of node column (X, Y) and z-node z0 the records of
+// cell (X, Y) come first, then those of cells (X, Y - 1), (X - 1, Y) and
+// (X - 1, Y - 1).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charge, const int* track,
              const unsigned long long* mask, unsigned* fill, const uint4* base, const unsigned long long* ctl,
-             NodeRec<T>* rec, int* rtrack) {
+             NodeRec<T>* rec) {
     const int lane = threadIdx.x & (kWave - 1);
     const size_t c = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (c >= (size_t)n_carriers || ctl[kCtlFallback] != 0ull) return;
@@ -526,7 +527,6 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
             NodeRec<T> r;
             r.w0 = m | (z0 << 16);
             r.w1 = tr;
-            rtrack[slot] = tr;
             r.g[0] = gx * w0;
             r.g[1] = gy * w0;
             r.g[2] = gz * w0;
@@ -552,7 +552,7 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
 // events (kCtlFallback).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, const int* rtrack, unsigned long long* ctl,
+k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned long long* ctl,
         int* tables) {
     const int lane = threadIdx.x & (kWave - 1);
     const size_t col = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
@@ -564,7 +564,7 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, const int*
     int cand = -1, cnt = 0, nc = 0;
     for (unsigned b = r0; b < r1; b += kWave) {
         const unsigned r = b + (unsigned)lane;
-        const int trk = r < r1 ? rtrack[r] : -1;
+        const int trk = r < r1 ? rec[r].w1 : -1;             // the track, as k_ev_scatter wrote it
         unsigned long long pending = __ballot(trk >= 0);
         while (pending) {
             const int tk = __builtin_amdgcn_readlane(trk, (int)__builtin_ctzll(pending));
@@ -607,7 +607,7 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, const int*
     for (unsigned b = r0; b < r1; b += kWave) {
         const unsigned r = b + (unsigned)lane;
         const bool have = r < r1;
-        const int trk = have ? rtrack[r] : -1;
+        const int trk = have ? rec[r].w1 : -1;
         int slot = S;
         unsigned long long pending = __ballot(have);
         while (pending) {
@@ -1025,7 +1025,7 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
     // kBinnedMinSteps polyline steps the unbinned kernel is faster (its cost
     // is the steps that move, the binned form's also the grid's columns)
     const unsigned long long steps = (unsigned long long)n_carriers * p.n_time;
-    const bool binned = ws != nullptr && ws_bytes >= cl.fixed_bytes + 4 * (sizeof(NodeRec<T>) + sizeof(int)) && steps < 0xfffffff0ull &&
+    const bool binned = ws != nullptr && ws_bytes >= cl.fixed_bytes + 4 * sizeof(NodeRec<T>) && steps < 0xfffffff0ull &&
                         form != 2 && (steps >= kBinnedMinSteps || form == 1);
     unsigned long long* ctl = nullptr;
     if (binned) {
@@ -1039,10 +1039,8 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
         unsigned long long* mask = reinterpret_cast<unsigned long long*>(b + cl.off_mask);
         int* tables = reinterpret_cast<int*>(b + cl.off_tables);
         NodeRec<T>* rec = reinterpret_cast<NodeRec<T>*>(b + cl.off_records);
-        // records, then one track per record
-        size_t cap = (ws_bytes - cl.off_records) / (sizeof(NodeRec<T>) + sizeof(int));
+        size_t cap = (ws_bytes - cl.off_records) / sizeof(NodeRec<T>);
         if (cap > 0xfffffff0ull) cap = 0xfffffff0ull;
-        int* rtrack = reinterpret_cast<int*>(rec + cap);
         if (phase == 1) {
             // control words, cell counts and fill counters are one zero-filled
             // run (no memset nodes, so the sequence can be captured)
@@ -1066,9 +1064,9 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
                                dim3(kBlock), 0, s, p, count, offs, base);
             hipLaunchKernelGGL(k_ev_scatter<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers,
                                static_cast<const T*>(pos), static_cast<const T*>(charge), track, mask, fill, base,
-                               ctl, rec, rtrack);
+                               ctl, rec);
             hipLaunchKernelGGL(k_slots<T>, dim3((unsigned)((tl.n_cols + kBlock / kWave - 1) / (kBlock / kWave))),
-                               dim3(kBlock), 0, s, p, tl, offs, rec, rtrack, ctl, tables);
+                               dim3(kBlock), 0, s, p, tl, offs, rec, ctl, tables);
             return hipGetLastError();
         }
         auto rows = [&](auto kernel) {
