@@ -908,18 +908,6 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
         write_rows(nx, k);
         __syncthreads();
         const unsigned rbeg = zo(k * ZT), rend = zo(k * ZT + ZT);
-        {
-            // the first lines of the tile's records into the scalar cache,
-            // all in flight together (a word of each, the last record's
-            // past the end)
-            const Const<unsigned>* tw = (const Const<unsigned>*)(crec + rbeg);
-            constexpr unsigned RW = sizeof(NodeRec<T>) / 4, LW = 64 / 4;
-            const unsigned lastw = (rend - rbeg - 1) * RW;
-            unsigned x = 0;
-#pragma unroll
-            for (unsigned j = 0; j < 8; ++j) x ^= tw[min(j * LW, lastw)];
-            asm volatile("" ::"s"(x));
-        }
         const int kn = next_tile(k + 1, k0, msk);
         if (kn < ntile) {
             load_tile(nx, kn);                           // lands while this tile is processed
