@@ -77,3 +77,22 @@ def test_collocation_matrix_entries_match_ewald(px32):
         col = px32["columns"][0 if j < 64 else 1]
         ge = ewald.potential(x[i] - y[j], px32["cell"]["L"], px32["cell"]["eps_r"], green.collocation_width(col))
         assert abs(A[i, j] - ge[0]) <= 1e-12 * abs(A[0, 0])
+
+
+def test_full_collocation_matrix_matches_ewald(px32):
+    """Every entry of the oracle's A (in-plane lattice sums times a k_z
+    series) against an Ewald sum of the same width-r/4 Gaussian charges,
+    which shares none of that structure: A_ij = G(x_i - y_j) exactly."""
+    cell, columns = px32["cell"], px32["columns"]
+    A = collocation.collocation_matrix(cell, columns)
+    x = collocation.collocation_points(columns)
+    y = collocation.sources(columns)
+    n = A.shape[0]
+    assert n % len(columns) == 0
+    m = n // len(columns)                               # sources per column, column by column
+    Ae = np.empty_like(A)
+    for w, col in enumerate(columns):
+        js = np.arange(w * m, (w + 1) * m)
+        d = (x[:, None, :] - y[None, js, :]).reshape(-1, 3)
+        Ae[:, js] = ewald.potential(d, cell["L"], cell["eps_r"], green.collocation_width(col)).reshape(n, m)
+    assert np.max(np.abs(A - Ae)) <= 1e-12 * np.max(np.abs(Ae))
