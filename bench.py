@@ -44,8 +44,8 @@ CSRC = os.path.join(ROOT, "paper_2605_13987_amd", "csrc")
 # Summaries and commands in profiles/.
 TRAFFIC = {
     # (kernel, workload key): (bytes per launch, sha256 of the sources)
-    ("k_conv_rows", "256x256x512 f16"): (72579668070, "0d60b6e61fa582afc4af5e3ebb2ec0253e394c558ac56273a678e89d105af260"),
-    ("k_conv_rows", "256x256x512 f32"): (141832804352, "0d60b6e61fa582afc4af5e3ebb2ec0253e394c558ac56273a678e89d105af260"),
+    ("k_conv_rows", "256x256x512 f16"): (72582013338, "4fe6ff2a9ba17f972faad4d2ea419a53203ce5d024ae5c743b4aef3e93e2f830"),
+    ("k_conv_rows", "256x256x512 f32"): (141824572314, "4fe6ff2a9ba17f972faad4d2ea419a53203ce5d024ae5c743b4aef3e93e2f830"),
     ("k_synthesis_pipe", "256x256x512 f16"): (81350514893, "a0d865c98b27151ef77e5a1c26e20c7c56283e0a612df704235c7f72b88ed518"),
     ("k_synthesis_pipe", "256x256x512 f32"): (161882316698, "a0d865c98b27151ef77e5a1c26e20c7c56283e0a612df704235c7f72b88ed518"),
 }

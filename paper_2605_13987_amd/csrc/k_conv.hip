@@ -304,8 +304,8 @@ k_current(Plan p, const TH* H, const float* decode, int n_carriers, int n_tracks
 // A node-column record: one event as seen from one of the four (x, y) corner
 // columns of its cell: w0 = its step m | its lower z-node z0 << 16, w1 = its
 // track; g0 and g1 are -q dx times the trilinear weights of the event's
-// lower and upper z-node in this column.  The accumulation rewrites w0 and
-// w1 as it stages them (see k_conv_rows).
+// lower and upper z-node in this column.  k_slots rewrites w0 and w1 into
+// what the accumulation reads (see there).
 // Records are ordered by (node column, lower z-node); inside one such bin by
 // the cell they come from, then by arrival.
 template <typename T>
@@ -582,7 +582,7 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned l
         }
     }
     // the table: the candidates with the most records, most first
-    int tab = -1, used = 0;
+    int tab = -1;
     for (int k = 0; k < S; ++k) {
         int best = cnt, who = lane;
 #pragma unroll
@@ -597,7 +597,6 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned l
         const int tk = __builtin_amdgcn_readlane(cand, who);
         if (lane == k) tab = tk;
         if (lane == who) cnt = -1;
-        ++used;
     }
     if (lane < S) tables[col * S + lane] = tab;
     const int rowb = tl.rl * tl.lb;
@@ -786,7 +785,7 @@ template <int ZT, typename T, typename TH>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : (sizeof(TH) == 2 ? 6 : 7))))
 k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __restrict__ decode,
             const unsigned* __restrict__ offs, const NodeRec<T>* __restrict__ rec, const int* __restrict__ tables,
-            const unsigned long long* __restrict__ ctl, int n_tracks, T* __restrict__ out) {
+            const unsigned long long* __restrict__ ctl, T* __restrict__ out) {
     if (ctl[kCtlFallback] != 0ull) return;               // the direct form takes these events
     const int Nz = p.N[2], nt = p.n_time;
     const size_t col = blockIdx.x;
@@ -1062,7 +1061,7 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
                                     (int)tl.lds_bytes);
             if (e != hipSuccess) return;
             hipLaunchKernelGGL(kernel, dim3((unsigned)tl.n_cols), dim3(tl.threads), tl.lds_bytes, s, p, tl,
-                               static_cast<const TH*>(h), decode, offs, rec, tables, ctl, n_tracks,
+                               static_cast<const TH*>(h), decode, offs, rec, tables, ctl,
                                static_cast<T*>(out));
         };
         // tiles of conv_tile_nodes(sizeof(TH)) z-nodes

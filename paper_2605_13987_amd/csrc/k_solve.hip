@@ -24,7 +24,6 @@ namespace wt {
 
 namespace {
 
-constexpr int kBlock = 256;
 constexpr int kMaxN = 528;
 
 using c64 = cplx<double>;
