@@ -56,6 +56,7 @@ constexpr unsigned long long kBinnedMinSteps = 1ull << 24;   // polyline steps f
 
 constexpr int kScanThreads = 1024;
 constexpr unsigned kFlushRecords = 1024;   // records between flushes of the binned form's per-track sums
+constexpr int kOvfRun = 32;                // consecutive overflow entries per wavefront and pass
 
 // Control words of the workspace: [0] records (4 per event), [1] 1 when the
 // binned form cannot take the events (the direct form then runs), [2] the
@@ -953,10 +954,13 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
     flush(acc);
 }
 
-// The overflow list: one wavefront per record (a grid-stride loop over the
-// count k_slots left), lanes over output samples n; the record's two
-// z-nodes read from global memory at lag n - m, the sum added to its
-// track's output with one atomic per sample.
+// The overflow list: each wavefront takes runs of kOvfRun consecutive
+// entries (a grid-stride loop over the count k_slots left), lanes over output
+// samples n = lane + 64 j; each entry's two z-nodes are read from global
+// memory at lag n - m and added to the lane's sums, which go to the output
+// (one atomic per sample) when the track changes and at the end of the run.
+// Entries of one column and chunk are consecutive in the list, so a run
+// mostly holds few tracks.
 template <typename T, typename TH>
 __device__ inline T node_lag_dot(const Plan& p, const TH* colH, int z, int lag, const T* g) {
     const int TB = p.tb, nt = p.n_time, Nz = p.N[2];
@@ -978,14 +982,38 @@ k_conv_overflow(Plan p, const TH* __restrict__ H, const float* __restrict__ deco
     T dec = (T)1;
     if constexpr (!std::is_same<T, TH>::value) dec = (T)decode[0];
     const size_t waves = (size_t)gridDim.x * (kBlock / kWave);
-    for (size_t i = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < n_ovf; i += waves) {
-        const OvfRec<T> o = ovf[i];
-        const int m = o.zm & 0xffff, z0 = o.zm >> 16, z1 = z0 + 1 == Nz ? 0 : z0 + 1;
-        const TH* colH = H + (size_t)o.col * Nz * nt * 3;
-        for (int n = m + lane; n < nt; n += kWave) {
-            const T v = node_lag_dot<T, TH>(p, colH, z0, n - m, o.g) + node_lag_dot<T, TH>(p, colH, z1, n - m, o.g + 3);
-            if (v != (T)0) atomicAdd(out + (size_t)o.track * nt + n, v * dec);
+    T acc[kMaxJ];
+    auto flush = [&](int track) {
+#pragma unroll
+        for (int j = 0; j < kMaxJ; ++j) {
+            const int n = lane + kWave * j;
+            if (n < nt && acc[j] != (T)0) atomicAdd(out + (size_t)track * nt + n, acc[j] * dec);
+            acc[j] = (T)0;
         }
+    };
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j) acc[j] = (T)0;
+    for (size_t i0 = ((size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * kOvfRun; i0 < n_ovf;
+         i0 += waves * kOvfRun) {
+        const size_t i1 = min(i0 + (size_t)kOvfRun, (size_t)n_ovf);
+        int cur = ovf[i0].track;
+        for (size_t i = i0; i < i1; ++i) {
+            const OvfRec<T> o = ovf[i];
+            if (o.track != cur) {
+                flush(cur);
+                cur = o.track;
+            }
+            const int m = o.zm & 0xffff, z0 = o.zm >> 16, z1 = z0 + 1 == Nz ? 0 : z0 + 1;
+            const TH* colH = H + (size_t)o.col * Nz * nt * 3;
+#pragma unroll
+            for (int j = 0; j < kMaxJ; ++j) {
+                const int n = lane + kWave * j;
+                if (n >= m && n < nt)
+                    acc[j] += node_lag_dot<T, TH>(p, colH, z0, n - m, o.g) +
+                              node_lag_dot<T, TH>(p, colH, z1, n - m, o.g + 3);
+            }
+        }
+        flush(cur);
     }
 }
 
