@@ -44,8 +44,8 @@ CSRC = os.path.join(ROOT, "paper_2605_13987_amd", "csrc")
 # Summaries and commands in profiles/.
 TRAFFIC = {
     # (kernel, workload key): (bytes per launch, sha256 of the sources)
-    ("k_conv_rows", "256x256x512 f16"): (72582013338, "4fe6ff2a9ba17f972faad4d2ea419a53203ce5d024ae5c743b4aef3e93e2f830"),
-    ("k_conv_rows", "256x256x512 f32"): (141824572314, "4fe6ff2a9ba17f972faad4d2ea419a53203ce5d024ae5c743b4aef3e93e2f830"),
+    ("k_conv_rows", "256x256x512 f16"): (72589210624, "b8ded86e64944e68f4e0b286976443a383c38ce9de85ef74dabd7e557c7fbe94"),
+    ("k_conv_rows", "256x256x512 f32"): (141824669901, "b8ded86e64944e68f4e0b286976443a383c38ce9de85ef74dabd7e557c7fbe94"),
     ("k_synthesis_pipe", "256x256x512 f16"): (81350514893, "a0d865c98b27151ef77e5a1c26e20c7c56283e0a612df704235c7f72b88ed518"),
     ("k_synthesis_pipe", "256x256x512 f32"): (161882316698, "a0d865c98b27151ef77e5a1c26e20c7c56283e0a612df704235c7f72b88ed518"),
 }
