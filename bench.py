@@ -44,10 +44,10 @@ CSRC = os.path.join(ROOT, "paper_2605_13987_amd", "csrc")
 # Summaries and commands in profiles/.
 TRAFFIC = {
     # (kernel, workload key): (bytes per launch, sha256 of the sources)
-    ("k_conv_rows", "256x256x512 f16"): (72589210624, "b8ded86e64944e68f4e0b286976443a383c38ce9de85ef74dabd7e557c7fbe94"),
-    ("k_conv_rows", "256x256x512 f32"): (141824669901, "b8ded86e64944e68f4e0b286976443a383c38ce9de85ef74dabd7e557c7fbe94"),
-    ("k_synthesis_pipe", "256x256x512 f16"): (81350514893, "a0d865c98b27151ef77e5a1c26e20c7c56283e0a612df704235c7f72b88ed518"),
-    ("k_synthesis_pipe", "256x256x512 f32"): (161882316698, "a0d865c98b27151ef77e5a1c26e20c7c56283e0a612df704235c7f72b88ed518"),
+    ("k_conv_rows", "256x256x512 f16"): (72604829901, "ef69c7e8751f507d0a92be1033aa56c6051a2113290b6e13c73d35b4d21db733"),
+    ("k_conv_rows", "256x256x512 f32"): (141882414080, "ef69c7e8751f507d0a92be1033aa56c6051a2113290b6e13c73d35b4d21db733"),
+    ("k_synthesis_pipe", "256x256x512 f16"): (81350519706, "a0d865c98b27151ef77e5a1c26e20c7c56283e0a612df704235c7f72b88ed518"),
+    ("k_synthesis_pipe", "256x256x512 f32"): (161882930995, "a0d865c98b27151ef77e5a1c26e20c7c56283e0a612df704235c7f72b88ed518"),
 }
 KERNEL_SOURCES = {
     "k_synthesis_pipe": ("k_bulk.hip", "synth_pipe.hpp", "fft.hpp"),
@@ -176,8 +176,10 @@ def c5_step(torch, wt, np, cfg, h_format, steps, warmup, cur_bytes, subset, n_co
                       o.data_ptr(), cws.data_ptr(), cws.numel())
 
     def step():
-        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
-        current(n_c, car["pos"], car["charge"], car["track"], out)
+        # H solve and current in one call: the binning runs beside the synthesis
+        wt.wt_step(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], n_c, n_tr,
+                   car["pos"].data_ptr(), car["charge"].data_ptr(), car["track"].data_ptr(), out.data_ptr(),
+                   cws.data_ptr(), cws.numel())
 
     _, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True)
     for _ in range(warmup):
@@ -199,12 +201,15 @@ def c5_step(torch, wt, np, cfg, h_format, steps, warmup, cur_bytes, subset, n_co
     stage = {}
     reps = max(3, min(steps, 5))
     for _ in range(reps):
-        wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
+        step()
         for name, t in wt.wt_context_stage_times(ctx):
             stage[name] = stage.get(name, 0.0) + t / reps
+    # the binning on its own (wt_current): beside the synthesis its stage
+    # time is only what the accumulation still waits for
+    bin_alone = 0.0
+    for _ in range(reps):
         current(n_c, car["pos"], car["charge"], car["track"], out)
-        for name, t in wt.wt_context_stage_times(ctx):
-            stage[name] = stage.get(name, 0.0) + t / reps
+        bin_alone += dict(wt.wt_context_stage_times(ctx))["current_binning"] / reps
     wt.wt_context_enable_timing(ctx, False)
     ctl = [int(v) for v in cws[:24].view(torch.int64).cpu()]
     # H on sampled columns, the currents of the carrier subset
@@ -233,7 +238,9 @@ def c5_step(torch, wt, np, cfg, h_format, steps, warmup, cur_bytes, subset, n_co
     torch.cuda.empty_cache()
     synth_bytes = n_pts * nt * 3 * eb + N[0] * N[1] * len(cfg["columns"]) * (N[2] // 2) * 3 * 8
     t_syn, t_cur = stage["synthesis"] * 1e-3, stage["current"] * 1e-3
-    t_cur_all = (stage["current"] + stage["current_binning"]) * 1e-3
+    # the current on its own: the accumulation and the binning alone (in the
+    # step the binning runs beside the synthesis)
+    t_cur_all = (stage["current"] + bin_alone) * 1e-3
     key = f"256x256x512 {'f16' if eb == 2 else 'f32'}"
     rl = {
         "k_synthesis_pipe": {"kernel": "k_synthesis_pipe", "bound": "hbm", "achieved": synth_bytes / t_syn / 1e9,
@@ -254,7 +261,7 @@ def c5_step(torch, wt, np, cfg, h_format, steps, warmup, cur_bytes, subset, n_co
            "events_per_s": ctl[0] // 4 / t_cur_all, "moving_steps": ctl[0] // 4,
            "h_bytes": lay["h_bytes"], "h_scale": rep["h_scale"], "backward_error_max": rep["backward_error_max"],
            "fit": fit_fp64(lay["n_q"], spec["n_freq"], stage["collocation_solve"]),
-           "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+           "stage_ms": {k: round(v, 4) for k, v in stage.items()}, "current_binning_alone_ms": round(bin_alone, 4),
            "roofline_dominant": rl[dom], "roofline_other": rl["k_conv_rows" if dom == "k_synthesis_pipe"
                                                             else "k_synthesis_pipe"]}
     print(f"# 256x256x512 {key}: {ms:.2f} ms/step, stages {res['stage_ms']}", file=sys.stderr, flush=True)
@@ -542,9 +549,8 @@ def px128_section(torch, wt, np, steps, warmup, oracle_on):
         pos_p, q_p = (pos.double(), q.double()) if f64 else (pos, q)
 
         def step():
-            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
-            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos_p.data_ptr(), q_p.data_ptr(), tr.data_ptr(),
-                          o.data_ptr(), cws.data_ptr(), cws.numel())
+            wt.wt_step(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], n_c, n_tr,
+                       pos_p.data_ptr(), q_p.data_ptr(), tr.data_ptr(), o.data_ptr(), cws.data_ptr(), cws.numel())
 
         _, rep = wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"], report=True)
         for _ in range(warmup):
@@ -561,11 +567,7 @@ def px128_section(torch, wt, np, steps, warmup, oracle_on):
         stage = {}
         reps = max(3, min(steps, 10))
         for _ in range(reps):
-            wt.wt_h_solve(ctx, plan, ws.data_ptr(), ws.numel(), hbuf.data_ptr(), lay["h_bytes"])
-            for k, t in wt.wt_context_stage_times(ctx):
-                stage[k] = stage.get(k, 0.0) + t / reps
-            wt.wt_current(ctx, plan, hbuf.data_ptr(), n_c, n_tr, pos_p.data_ptr(), q_p.data_ptr(), tr.data_ptr(),
-                          o.data_ptr(), cws.data_ptr(), cws.numel())
+            step()
             for k, t in wt.wt_context_stage_times(ctx):
                 stage[k] = stage.get(k, 0.0) + t / reps
         wt.wt_context_enable_timing(ctx, False)
@@ -833,10 +835,12 @@ def main():
         "events_per_s": mixed["events_per_s"],
         "h_grid_freq_pts_per_s": mixed["h_grid_freq_pts_per_s"],
         "stage_ms": mixed["stage_ms"],
+        "current_binning_alone_ms": mixed["current_binning_alone_ms"],
         "roofline": mixed["roofline_dominant"],
         "roofline_other_kernel": mixed["roofline_other"],
         "plain": {k: plain[k] for k in ("value", "ms_per_step", "tracks_per_s", "carriers_per_s", "events_per_s",
-                                        "h_grid_freq_pts_per_s", "stage_ms", "h_bytes", "fit")}
+                                        "h_grid_freq_pts_per_s", "stage_ms", "current_binning_alone_ms", "h_bytes",
+                                        "fit")}
                  | {"roofline": plain["roofline_dominant"], "roofline_other_kernel": plain["roofline_other"],
                     "h_storage": "float32"},
         "moving_steps": mixed["moving_steps"],

@@ -325,6 +325,22 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h,
                      const wt_carriers* carriers, void* d_workspace, size_t workspace_bytes,
                      void* d_i_out);
 
+/* One pass of the whole path (Sections 3 and 4): wt_h_solve into d_h, then
+ * wt_current (Eq. 1) on that H, with the arguments, checks, results and
+ * report of the two calls (the report covers the H solve; with a report the
+ * call synchronises).  The current's binning needs only the carriers, so it
+ * runs on a stream of the context beside the synthesis: forked from the
+ * context's stream by an event after the boundary fit and the field table,
+ * joined back by an event before the accumulation.  Under stream capture
+ * the two run one after the other on the context's stream.  The stage time
+ * "current_binning" is then the wait for the binning after the synthesis.
+ * Stream-ordered like every call: the next call on the context's stream
+ * sees the current written. */
+wt_status wt_step(wt_context* ctx, const wt_h_plan* plan,
+                  void* d_workspace, size_t workspace_bytes, void* d_h, size_t h_bytes,
+                  const wt_carriers* carriers, void* d_cur_workspace, size_t cur_workspace_bytes,
+                  void* d_i_out, wt_h_report* report);
+
 /* Batched forward runs over many geometry variants (each variant is one
  * cell, column set and spectrum: one plan; the workloads of the paper's
  * Section 5 results vary pitch, diameter and resistivity).  For every item,

@@ -28,6 +28,11 @@ struct wt_context {
     // the field table is built while the boundary fit runs
     hipStream_t aux;
     hipEvent_t aux_fork, aux_join;
+    // wt_step: a third stream (and its events) on which the current's
+    // binning runs beside the synthesis
+    hipStream_t bin;
+    hipEvent_t bin_fork, bin_join;
+    int n_cu;           // compute units of the device
     // wt_current's form (wt_context_set_current_form)
     int current_form;
     // wt_batch_run: lane streams and their events, made on first use
@@ -378,10 +383,11 @@ wt_status mark(wt_context* ctx, int stage) {
 // workspace) is built on the context's second stream while the Green's
 // tables, the boundary fit and the time transform run on s; s waits for it
 // before the synthesis.  The stage mark of the field table then measures
-// only what s still waits for.
-template <typename Mark>
+// only what s still waits for.  before_synthesis() is called right before
+// the synthesis launch is enqueued.
+template <typename Mark, typename Hook>
 wt_status enqueue_solve(wt_context* ctx, const Plan& p, void* ws, void* d_h, hipStream_t s, Mark mark_stage,
-                        bool fork) {
+                        bool fork, Hook before_synthesis) {
     wt_status st;
     if ((st = mark_stage(-1)) != WT_OK) return st;
     WT_HIP(ctx, wt::launch_twiddles(p, ws, s), "twiddles");
@@ -403,6 +409,7 @@ wt_status enqueue_solve(wt_context* ctx, const Plan& p, void* ws, void* d_h, hip
         WT_HIP(ctx, wt::launch_field_table(p, ws, s), "field_table");
     if (p.h_format == WT_H_F16_SCALED) WT_HIP(ctx, wt::launch_h_scale(p, ws, d_h, s), "h_scale");
     if ((st = mark_stage(kStageFieldTable)) != WT_OK) return st;
+    if ((st = before_synthesis()) != WT_OK) return st;
     WT_HIP(ctx, wt::launch_synthesis(p, ws, d_h, s), "synthesis");
     return mark_stage(kStageSynthesis);
 }
@@ -467,20 +474,96 @@ bool carriers_ok(const wt_carriers* car) {
     return car->n_carriers == 0 || (car->d_pos && car->d_charge && car->d_track);
 }
 
-// Body of wt_h_solve and wt_h_solve_static, once the workspace is known.
-wt_status solve_on(wt_context* ctx, const Plan& p, void* d_workspace, void* d_h, wt_h_report* report) {
+// The current computed after the H solve by wt_step.
+struct CurrentCall {
+    const wt_carriers* car;
+    void* ws;
+    size_t ws_bytes;
+    void* out;
+};
+
+// Checks of wt_current's arguments (its workspace may be NULL).
+wt_status current_args_ok(const wt_h_plan* plan, const wt_carriers* car, const void* d_workspace,
+                          size_t workspace_bytes, const void* d_i_out) {
+    if (!car || !d_i_out || !carriers_ok(car)) return WT_E_INVALID_ARG;
+    if (d_workspace) {
+        if (reinterpret_cast<uintptr_t>(d_workspace) & 255) return WT_E_INVALID_ARG;
+        size_t need = 0;
+        (void)wt_current_workspace(plan, car->n_carriers, 1, &need);
+        if (workspace_bytes < need) return WT_E_WORKSPACE;
+    }
+    return WT_OK;
+}
+
+hipError_t launch_current_phase(const wt_context* ctx, const Plan& p, const void* d_h, const CurrentCall& c,
+                                hipStream_t s, int phase, int max_blocks = 0) {
+    return wt::launch_current(p, d_h, c.car->n_carriers, c.car->n_tracks, c.car->d_pos, c.car->d_charge,
+                              c.car->d_track, c.ws, c.ws ? c.ws_bytes : 0, c.out, s, phase, ctx->current_form,
+                              max_blocks);
+}
+
+// Workgroups of the binning kernels beside the synthesis: the fewest that
+// still let the binning end within the synthesis, so that the synthesis
+// workgroups (one per compute unit at N_z = 512) keep finding room.  At
+// 256 x 256 x 512 with 1e6 carriers (400 steps each; 6.5 ms of binning
+// alone) one workgroup per unit ends within the synthesis and slows it from
+// 36.8 to 40.4 ms; half as many outlast it by 1.8 ms; two per unit slow it
+// to 43 ms and uncapped grids to 43-45 ms.  So one workgroup per unit for
+// every N_x N_y N_z / 32 carriers.
+int bin_beside_blocks(const wt_context* ctx, const Plan& p, int n_carriers) {
+    const double nodes = (double)p.N[0] * p.N[1] * p.N[2];
+    const double per_cu = std::min(64.0, std::max(1.0, std::ceil(32.0 * n_carriers / nodes)));
+    return (int)per_cu * ctx->n_cu;
+}
+
+// Body of wt_h_solve and wt_h_solve_static, once the workspace is known, and
+// of wt_step (cur != nullptr: the current on the H just written).
+wt_status solve_on(wt_context* ctx, const Plan& p, void* d_workspace, void* d_h, wt_h_report* report,
+                   const CurrentCall* cur = nullptr) {
     wt_status st = bind(ctx);
     if (st != WT_OK) return st;
     ctx->n_events = 0;
     hipStream_t s = ctx->stream;
-    // the field table on the second stream, except under stream capture: a
-    // replayed graph ran the forked form slower (3.95 ms against 3.57 ms
-    // eager at 128 x 128 x 256) than the sequential one (3.74 ms)
+    // The field table goes on the second stream only when the boundary fit
+    // (one workgroup per frequency, each filling a compute unit) runs in a
+    // single round.  With more frequencies than compute units the fit keeps
+    // every unit busy and the field table only delays its workgroups
+    // (256 x 256 x 512, 512 frequencies: fit 1.04 ms alone, 2.46 ms beside
+    // the table; the whole solve 0.4 ms slower forked).  Never under stream
+    // capture: a replayed graph ran the forked form slower (3.95 ms against
+    // 3.57 ms eager at 128 x 128 x 256) than the sequential one (3.74 ms).
     hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
     WT_HIP(ctx, hipStreamIsCapturing(s, &capture), "hipStreamIsCapturing");
-    st = enqueue_solve(ctx, p, d_workspace, d_h, s, [ctx](int stage) { return mark(ctx, stage); },
-                       capture == hipStreamCaptureStatusNone);
+    const bool fork = capture == hipStreamCaptureStatusNone && p.n_freq <= ctx->n_cu;
+    // wt_step: the current's binning reads only the carriers, so it runs on
+    // the third stream beside the synthesis, which leaves issue slots and
+    // registers free on every compute unit (one workgroup per unit at
+    // N_z = 512), with grids capped by bin_beside_blocks; it starts after the
+    // boundary fit, which needs whole units.  Under stream capture
+    // everything stays on the caller's stream.
+    const bool beside = cur && capture == hipStreamCaptureStatusNone;
+    auto before_synthesis = [&]() -> wt_status {
+        if (!beside) return WT_OK;
+        WT_HIP(ctx, hipEventRecord(ctx->bin_fork, s), "hipEventRecord");
+        WT_HIP(ctx, hipStreamWaitEvent(ctx->bin, ctx->bin_fork, 0), "hipStreamWaitEvent");
+        WT_HIP(ctx, launch_current_phase(ctx, p, d_h, *cur, ctx->bin, 1,
+                                         bin_beside_blocks(ctx, p, cur->car->n_carriers)),
+               "current_binning");
+        WT_HIP(ctx, hipEventRecord(ctx->bin_join, ctx->bin), "hipEventRecord");
+        return WT_OK;
+    };
+    st = enqueue_solve(ctx, p, d_workspace, d_h, s, [ctx](int stage) { return mark(ctx, stage); }, fork,
+                       before_synthesis);
     if (st != WT_OK) return st;
+    if (cur) {
+        if (beside)
+            WT_HIP(ctx, hipStreamWaitEvent(s, ctx->bin_join, 0), "hipStreamWaitEvent");
+        else
+            WT_HIP(ctx, launch_current_phase(ctx, p, d_h, *cur, s, 1), "current_binning");
+        if ((st = mark(ctx, kStageCurrentBinning)) != WT_OK) return st;
+        WT_HIP(ctx, launch_current_phase(ctx, p, d_h, *cur, s, 2), "current");
+        if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
+    }
     if (!report) return WT_OK;
 
     std::vector<wt::SolveReport> rep(p.n_freq);
@@ -565,7 +648,15 @@ wt_status wt_context_create(wt_context** out, int hip_device, void* hip_stream) 
     ctx->fork = nullptr;
     ctx->aux = nullptr;
     ctx->aux_fork = ctx->aux_join = nullptr;
+    ctx->bin = nullptr;
+    ctx->bin_fork = ctx->bin_join = nullptr;
     ctx->current_form = 0;
+    ctx->n_cu = 0;
+    if ((err = hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device)) != hipSuccess) {
+        g_create_error = std::string("hipDeviceGetAttribute: ") + hipGetErrorString(err);
+        delete ctx;
+        return WT_E_HIP;
+    }
     // the static workspace of wt_h_solve_static on this device (its address
     // is resolved here, once per device; a failure is reported by that call)
     hipError_t scratch_err = hipSuccess;
@@ -573,7 +664,10 @@ wt_status wt_context_create(wt_context** out, int hip_device, void* hip_stream) 
     // the second stream of wt_h_solve (default priority, non-blocking)
     if ((err = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking)) != hipSuccess ||
         (err = hipEventCreateWithFlags(&ctx->aux_fork, hipEventDisableTiming)) != hipSuccess ||
-        (err = hipEventCreateWithFlags(&ctx->aux_join, hipEventDisableTiming)) != hipSuccess) {
+        (err = hipEventCreateWithFlags(&ctx->aux_join, hipEventDisableTiming)) != hipSuccess ||
+        (err = hipStreamCreateWithFlags(&ctx->bin, hipStreamNonBlocking)) != hipSuccess ||
+        (err = hipEventCreateWithFlags(&ctx->bin_fork, hipEventDisableTiming)) != hipSuccess ||
+        (err = hipEventCreateWithFlags(&ctx->bin_join, hipEventDisableTiming)) != hipSuccess) {
         g_create_error = std::string("stream/event creation: ") + hipGetErrorString(err);
         wt_context_destroy(ctx);
         return WT_E_HIP;
@@ -594,6 +688,9 @@ wt_status wt_context_destroy(wt_context* ctx) {
     if (ctx->aux_fork) (void)hipEventDestroy(ctx->aux_fork);
     if (ctx->aux_join) (void)hipEventDestroy(ctx->aux_join);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    if (ctx->bin_fork) (void)hipEventDestroy(ctx->bin_fork);
+    if (ctx->bin_join) (void)hipEventDestroy(ctx->bin_join);
+    if (ctx->bin) (void)hipStreamDestroy(ctx->bin);
     delete ctx;
     return WT_OK;
 }
@@ -707,30 +804,33 @@ wt_status wt_current_workspace(const wt_h_plan* plan, int n_carriers, long long 
 
 wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, const wt_carriers* car,
                      void* d_workspace, size_t workspace_bytes, void* d_i_out) {
-    if (!ctx || !plan || !d_h || !car || !d_i_out) return WT_E_INVALID_ARG;
-    if (!carriers_ok(car)) return WT_E_INVALID_ARG;
-    const Plan& p = plan->p;
-    if (d_workspace) {
-        if (reinterpret_cast<uintptr_t>(d_workspace) & 255) return WT_E_INVALID_ARG;
-        size_t need = 0;
-        (void)wt_current_workspace(plan, car->n_carriers, 1, &need);
-        if (workspace_bytes < need) return WT_E_WORKSPACE;
-    }
-    wt_status st = bind(ctx);
+    if (!ctx || !plan || !d_h) return WT_E_INVALID_ARG;
+    wt_status st = current_args_ok(plan, car, d_workspace, workspace_bytes, d_i_out);
     if (st != WT_OK) return st;
+    const Plan& p = plan->p;
+    if ((st = bind(ctx)) != WT_OK) return st;
     ctx->n_events = 0;
     if ((st = mark(ctx, -1)) != WT_OK) return st;
-    WT_HIP(ctx, wt::launch_current(p, d_h, car->n_carriers, car->n_tracks, car->d_pos, car->d_charge, car->d_track,
-                                   d_workspace, d_workspace ? workspace_bytes : 0, d_i_out, ctx->stream, 1,
-                                   ctx->current_form),
-           "current_binning");
+    const CurrentCall c{car, d_workspace, workspace_bytes, d_i_out};
+    WT_HIP(ctx, launch_current_phase(ctx, p, d_h, c, ctx->stream, 1), "current_binning");
     if ((st = mark(ctx, kStageCurrentBinning)) != WT_OK) return st;
-    WT_HIP(ctx, wt::launch_current(p, d_h, car->n_carriers, car->n_tracks, car->d_pos, car->d_charge, car->d_track,
-                                   d_workspace, d_workspace ? workspace_bytes : 0, d_i_out, ctx->stream, 2,
-                                   ctx->current_form),
-           "current");
+    WT_HIP(ctx, launch_current_phase(ctx, p, d_h, c, ctx->stream, 2), "current");
     if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
     return WT_OK;
+}
+
+wt_status wt_step(wt_context* ctx, const wt_h_plan* plan, void* d_workspace, size_t workspace_bytes, void* d_h,
+                  size_t h_bytes, const wt_carriers* car, void* d_cur_workspace, size_t cur_workspace_bytes,
+                  void* d_i_out, wt_h_report* report) {
+    if (!ctx || !plan || !d_workspace || !d_h) return WT_E_INVALID_ARG;
+    const Plan& p = plan->p;
+    if (workspace_bytes < p.ws_bytes || h_bytes < p.h_bytes) return WT_E_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) || (reinterpret_cast<uintptr_t>(d_h) & 15))
+        return WT_E_INVALID_ARG;
+    wt_status st = current_args_ok(plan, car, d_cur_workspace, cur_workspace_bytes, d_i_out);
+    if (st != WT_OK) return st;
+    const CurrentCall c{car, d_cur_workspace, cur_workspace_bytes, d_i_out};
+    return solve_on(ctx, p, d_workspace, d_h, report, &c);
 }
 
 wt_status wt_context_set_tune_cache(wt_context* ctx, const char* path) {
@@ -828,7 +928,8 @@ wt_status wt_batch_run(wt_context* ctx, int n_items, const wt_batch_item* items,
         for (int i : queue[l]) {
             const wt_batch_item& it = items[i];
             const Plan& p = it.plan->p;
-            st = enqueue_solve(ctx, p, d_workspace[l], d_h[l], s, [](int) { return WT_OK; }, false);
+            st = enqueue_solve(ctx, p, d_workspace[l], d_h[l], s, [](int) { return WT_OK; }, false,
+                               []() { return WT_OK; });
             if (st != WT_OK) return fail(st);
             const wt_carriers& c = it.carriers;
             // the lane's workspace is free again once H is written: the

@@ -203,10 +203,13 @@ inline size_t current_event_bytes(const Plan& p) { return 4 * (size_t)(p.precisi
 // d_ws may be null (then one wavefront per carrier, no binning).  phase 1:
 // zero the output and bin the events; phase 2 (after phase 1 on the same
 // stream): accumulate.  form: 0 binned from kBinnedMinSteps polyline steps
-// on, 1 binned whenever there is a workspace, 2 never binned.
+// on, 1 binned whenever there is a workspace, 2 never binned.  max_blocks >
+// 0 caps the grids of the largest binning kernels (0: one wavefront per
+// carrier and per node column).
 hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks,
                           const void* pos, const void* charge, const int* track,
-                          void* ws, size_t ws_bytes, void* out, hipStream_t s, int phase, int form);
+                          void* ws, size_t ws_bytes, void* out, hipStream_t s, int phase, int form,
+                          int max_blocks = 0);
 // Adjoint: lattice-sum derivatives (d/d collocation offset, d/d source width)
 // into gd; transposed boundary-fit solves with right-hand sides rhs into lam;
 // the event projection to dL/dq(w) (right-hand sides) and the final

@@ -329,15 +329,10 @@ struct alignas(2 * sizeof(NodeRec<T>)) OvfRec {
 
 __global__ void k_set_capacity(unsigned long long* ctl, unsigned long long cap) { ctl[kCtlCapacity] = cap; }
 
-// One wavefront per carrier, 64 steps at a time: the bit mask of the steps
-// that are events, and one count per event in its cell.
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_ev_count(Plan p, ConvTiling tl, int n_carriers, int n_tracks, const T* pos, const int* track,
-           unsigned long long* mask, unsigned* count) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const size_t c = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (c >= (size_t)n_carriers) return;
+__device__ __forceinline__ void ev_count_carrier(const Plan& p, const ConvTiling& tl, size_t c, int n_tracks,
+                                                 const T* pos, const int* track, unsigned long long* mask,
+                                                 unsigned* count, int lane) {
     const int nt = p.n_time;
     const int tr = track[c];
     const bool valid = tr >= 0 && tr < n_tracks;
@@ -356,6 +351,21 @@ k_ev_count(Plan p, ConvTiling tl, int n_carriers, int n_tracks, const T* pos, co
         if (lane == 0) mask[c * tl.n_chunks + j] = bal;
         if (ev) atomicAdd(count + cell, 1u);
     }
+}
+
+// One wavefront per carrier, 64 steps at a time: the bit mask of the steps
+// that are events, and one count per event in its cell.  The wavefronts
+// stride over the carriers, so the grid may be smaller than one wavefront
+// per carrier (as it is beside the synthesis).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_ev_count(Plan p, ConvTiling tl, int n_carriers, int n_tracks, const T* pos, const int* track,
+           unsigned long long* mask, unsigned* count) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const size_t stride = (size_t)gridDim.x * (kBlock / kWave);
+    for (size_t c = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; c < (size_t)n_carriers;
+         c += stride)
+        ev_count_carrier(p, tl, c, n_tracks, pos, track, mask, count, lane);
 }
 
 // Records per (node column, z-node): the events of the four cells that have
@@ -501,45 +511,49 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
              const unsigned long long* mask, unsigned* fill, const uint4* base, const unsigned long long* ctl,
              NodeRec<T>* rec) {
     const int lane = threadIdx.x & (kWave - 1);
-    const size_t c = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (c >= (size_t)n_carriers || ctl[kCtlFallback] != 0ull) return;
+    if (ctl[kCtlFallback] != 0ull) return;
     const int nt = p.n_time, Ny = p.N[1], Nz = p.N[2];
-    const T* P = pos + c * (size_t)(nt + 1) * 3;
-    for (int jc = 0; jc < tl.n_chunks; ++jc) {
-        const unsigned long long bits = mask[c * tl.n_chunks + jc];
-        if (!((bits >> lane) & 1ull)) continue;
-        const int m = jc * kWave + lane;
-        int x0, y0, z0;
-        T fx, fy, fz, dx, dy, dz;
-        if (!event_cell(p, P, m, x0, y0, z0, fx, fy, fz, dx, dy, dz)) continue;   // cannot happen: the mask says it moves
-        const size_t cell = ((size_t)x0 * Ny + y0) * Nz + z0;
-        const unsigned j = atomicAdd(fill + cell, 1u);
-        // where this cell's records start in each of its four bins
-        const uint4 bs = base[cell];
-        const T q = charge[c];
-        const int tr = track[c];
-        const T gx = -q * dx, gy = -q * dy, gz = -q * dz;
+    const size_t stride = (size_t)gridDim.x * (kBlock / kWave);
+    for (size_t c = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; c < (size_t)n_carriers;
+         c += stride) {
+        const T* P = pos + c * (size_t)(nt + 1) * 3;
+        for (int jc = 0; jc < tl.n_chunks; ++jc) {
+            const unsigned long long bits = mask[c * tl.n_chunks + jc];
+            if (!((bits >> lane) & 1ull)) continue;
+            const int m = jc * kWave + lane;
+            int x0, y0, z0;
+            T fx, fy, fz, dx, dy, dz;
+            // cannot fail: the mask says that this step moves
+            if (!event_cell(p, P, m, x0, y0, z0, fx, fy, fz, dx, dy, dz)) continue;
+            const size_t cell = ((size_t)x0 * Ny + y0) * Nz + z0;
+            const unsigned j = atomicAdd(fill + cell, 1u);
+            // where this cell's records start in each of its four bins
+            const uint4 bs = base[cell];
+            const T q = charge[c];
+            const int tr = track[c];
+            const T gx = -q * dx, gy = -q * dy, gz = -q * dz;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int ox = k >> 1, oy = k & 1;
-            const size_t slot = (size_t)(k == 0 ? bs.x : k == 1 ? bs.y : k == 2 ? bs.z : bs.w) + j;
-            const T wxy = (ox ? fx : (T)1 - fx) * (oy ? fy : (T)1 - fy);
-            const T w0 = wxy * ((T)1 - fz), w1 = wxy * fz;
-            NodeRec<T> r;
-            r.w0 = m | (z0 << 16);
-            r.w1 = tr;
-            r.g[0] = gx * w0;
-            r.g[1] = gy * w0;
-            r.g[2] = gz * w0;
-            r.g[3] = gx * w1;
-            r.g[4] = gy * w1;
-            r.g[5] = gz * w1;
-            rec[slot] = r;
+            for (int k = 0; k < 4; ++k) {
+                const int ox = k >> 1, oy = k & 1;
+                const size_t slot = (size_t)(k == 0 ? bs.x : k == 1 ? bs.y : k == 2 ? bs.z : bs.w) + j;
+                const T wxy = (ox ? fx : (T)1 - fx) * (oy ? fy : (T)1 - fy);
+                const T w0 = wxy * ((T)1 - fz), w1 = wxy * fz;
+                NodeRec<T> r;
+                r.w0 = m | (z0 << 16);
+                r.w1 = tr;
+                r.g[0] = gx * w0;
+                r.g[1] = gy * w0;
+                r.g[2] = gz * w0;
+                r.g[3] = gx * w1;
+                r.g[4] = gy * w1;
+                r.g[5] = gz * w1;
+                rec[slot] = r;
+            }
         }
     }
 }
 
-// One wavefront per node column.  The column's track table: the tl.slots
+// One node column, by one wavefront.  The column's track table: the tl.slots
 // tracks with the most records (ties: first appearance; -1 pads it).  Then
 // the first two words of every record rewritten for the accumulation, with
 // zl = z0 mod tl.zt (its lower z-node inside its tile) and rowb = tl.rl *
@@ -552,12 +566,9 @@ k_ev_scatter(Plan p, ConvTiling tl, int n_carriers, const T* pos, const T* charg
 // the same buffer); when the list would not fit, the direct form takes all
 // events (kCtlFallback).
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned long long* ctl,
-        int* tables) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const size_t col = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (col >= tl.n_cols || ctl[kCtlFallback] != 0ull) return;
+__device__ __forceinline__ void slots_column(const Plan& p, const ConvTiling& tl, const unsigned* offs,
+                                             NodeRec<T>* rec, unsigned long long* ctl, int* tables, size_t col,
+                                             int lane) {
     const int S = tl.slots, Nz = p.N[2];
     const unsigned r0 = offs[col * Nz], r1 = offs[col * Nz + Nz];
     // candidates: the column's first 64 distinct tracks (lane i: the i-th)
@@ -639,6 +650,23 @@ k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned l
         w.x = zl * rowb - m * tl.lb;
         w.y = (zl * rowb) | (slot << 24);
         *reinterpret_cast<int2*>(&rec[r].w0) = w;
+    }
+}
+
+// One wavefront per node column (Strided: the wavefronts stride over the
+// columns, for a grid smaller than one wavefront per column).
+template <typename T, bool Strided>
+__global__ void __launch_bounds__(kBlock)
+k_slots(Plan p, ConvTiling tl, const unsigned* offs, NodeRec<T>* rec, unsigned long long* ctl,
+        int* tables) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const size_t first = (size_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (ctl[kCtlFallback] != 0ull) return;
+    if constexpr (!Strided) {
+        if (first < tl.n_cols) slots_column(p, tl, offs, rec, ctl, tables, first, lane);
+    } else {
+        for (size_t col = first; col < tl.n_cols; col += (size_t)gridDim.x * (kBlock / kWave))
+            slots_column(p, tl, offs, rec, ctl, tables, col, lane);
     }
 }
 
@@ -1020,9 +1048,12 @@ k_conv_overflow(Plan p, const TH* __restrict__ H, const float* __restrict__ deco
 // phase 1: the output zeroed and the events binned; phase 2: the
 // accumulation (binned, or the unbinned kernel when the events did not fit
 // or there is no workspace).  Phase 2 follows phase 1 on the same stream.
+// max_blocks > 0 caps the grids of the per-carrier and per-column binning
+// kernels (their wavefronts stride over the work).
 template <typename T, typename TH>
 hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, const void* pos, const void* charge,
-                   const int* track, void* ws, size_t ws_bytes, void* out, hipStream_t s, int phase, int form) {
+                   const int* track, void* ws, size_t ws_bytes, void* out, hipStream_t s, int phase, int form,
+                   int max_blocks) {
     const size_t n_out = (size_t)n_tracks * p.n_time;
     hipError_t e = hipSuccess;
     if (phase == 1) {
@@ -1059,29 +1090,34 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
         if (phase == 1) {
             // control words, cell counts and fill counters are one zero-filled
             // run (no memset nodes, so the sequence can be captured)
+            auto capped = [&](size_t g) {
+                return (unsigned)(max_blocks > 0 && g > (size_t)max_blocks ? (size_t)max_blocks : g);
+            };
             const size_t n_zero = cl.off_offs / sizeof(unsigned);
             hipLaunchKernelGGL(k_fill_zero<unsigned>,
-                               dim3((unsigned)std::min<size_t>((n_zero + kBlock - 1) / kBlock, 4096)), dim3(kBlock),
+                               dim3(capped(std::min<size_t>((n_zero + kBlock - 1) / kBlock, 4096))), dim3(kBlock),
                                0, s, reinterpret_cast<unsigned*>(b), n_zero);
             hipLaunchKernelGGL(k_set_capacity, dim3(1), dim3(1), 0, s, ctl, (unsigned long long)cap);
-            const unsigned grid = (unsigned)(((size_t)n_carriers + kBlock / kWave - 1) / (kBlock / kWave));
+            const unsigned grid = capped(((size_t)n_carriers + kBlock / kWave - 1) / (kBlock / kWave));
             hipLaunchKernelGGL(k_ev_count<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers, n_tracks,
                                static_cast<const T*>(pos), track, mask, count);
-            hipLaunchKernelGGL(k_node_count, dim3((unsigned)std::min<size_t>((tl.n_cells + kBlock - 1) / kBlock,
-                                                                             65536)),
-                               dim3(kBlock), 0, s, p, count, offs);
+            const unsigned cell_grid = capped(std::min<size_t>((tl.n_cells + kBlock - 1) / kBlock, 65536));
+            hipLaunchKernelGGL(k_node_count, dim3(cell_grid), dim3(kBlock), 0, s, p, count, offs);
             const unsigned nb = (unsigned)((tl.n_cells + kScanItems - 1) / kScanItems);
             hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, offs, tl.n_cells, bsum);
             hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, bsum, (int)nb, ctl);
             hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, s, offs, tl.n_cells, bsum);
-            hipLaunchKernelGGL(k_cell_bases, dim3((unsigned)std::min<size_t>((tl.n_cells + kBlock - 1) / kBlock,
-                                                                              65536)),
-                               dim3(kBlock), 0, s, p, count, offs, base);
+            hipLaunchKernelGGL(k_cell_bases, dim3(cell_grid), dim3(kBlock), 0, s, p, count, offs, base);
             hipLaunchKernelGGL(k_ev_scatter<T>, dim3(grid), dim3(kBlock), 0, s, p, tl, n_carriers,
                                static_cast<const T*>(pos), static_cast<const T*>(charge), track, mask, fill, base,
                                ctl, rec);
-            hipLaunchKernelGGL(k_slots<T>, dim3((unsigned)((tl.n_cols + kBlock / kWave - 1) / (kBlock / kWave))),
-                               dim3(kBlock), 0, s, p, tl, offs, rec, ctl, tables);
+            const size_t slots_grid = (tl.n_cols + kBlock / kWave - 1) / (kBlock / kWave);
+            if (capped(slots_grid) < slots_grid)
+                hipLaunchKernelGGL((k_slots<T, true>), dim3(capped(slots_grid)), dim3(kBlock), 0, s, p, tl, offs, rec,
+                                   ctl, tables);
+            else
+                hipLaunchKernelGGL((k_slots<T, false>), dim3(slots_grid), dim3(kBlock), 0, s, p, tl, offs, rec, ctl,
+                                   tables);
             return hipGetLastError();
         }
         auto rows = [&](auto kernel) {
@@ -1123,14 +1159,15 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
 
 hipError_t launch_current(const Plan& p, const void* h, int n_carriers, int n_tracks, const void* pos,
                           const void* charge, const int* track, void* ws, size_t ws_bytes, void* out,
-                          hipStream_t s, int phase, int form) {
+                          hipStream_t s, int phase, int form, int max_blocks) {
     if (p.precision == 0)
         return current<double, double>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s, phase,
-                                       form);
+                                       form, max_blocks);
     if (p.h_format == 1)
         return current<float, _Float16>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s, phase,
-                                        form);
-    return current<float, float>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s, phase, form);
+                                        form, max_blocks);
+    return current<float, float>(p, h, n_carriers, n_tracks, pos, charge, track, ws, ws_bytes, out, s, phase, form,
+                                 max_blocks);
 }
 
 }  // namespace wt

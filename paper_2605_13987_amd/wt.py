@@ -124,6 +124,8 @@ def _load():
         "wt_current_workspace": (c_int, [c_void_p, c_int, ctypes.c_longlong, P(c_size_t)]),
         "wt_context_set_current_form": (c_int, [c_void_p, c_int]),
         "wt_current": (c_int, [c_void_p, c_void_p, c_void_p, P(wt_carriers), c_void_p, c_size_t, c_void_p]),
+        "wt_step": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_carriers), c_void_p,
+                            c_size_t, c_void_p, P(wt_h_report)]),
         "wt_electronics": (c_int, [c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p, c_void_p,
                                    c_double, c_double, c_void_p, c_void_p]),
         "wt_h_plan_tune": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, P(wt_tune_report)]),
@@ -315,6 +317,24 @@ def wt_current(ctx, plan, d_h: int, n_carriers: int, n_tracks: int, d_pos: int, 
     car = wt_carriers(int(n_carriers), int(n_tracks), c_void_p(d_pos), c_void_p(d_charge), c_void_p(d_track))
     _check(LIB.wt_current(ctx, plan, c_void_p(d_h), ctypes.byref(car), c_void_p(d_workspace or None),
                           int(workspace_bytes), c_void_p(d_i_out)), "wt_current", ctx)
+
+
+def wt_step(ctx, plan, d_workspace: int, workspace_bytes: int, d_h: int, h_bytes: int, n_carriers: int,
+            n_tracks: int, d_pos: int, d_charge: int, d_track: int, d_i_out: int, d_cur_workspace: int = 0,
+            cur_workspace_bytes: int = 0, report: bool = False, raise_on_error: bool = True):
+    """wt_h_solve then wt_current in one call (the binning beside the
+    synthesis).  Returns (status, report dict or None) like wt_h_solve."""
+    car = wt_carriers(int(n_carriers), int(n_tracks), c_void_p(d_pos), c_void_p(d_charge), c_void_p(d_track))
+    rep = wt_h_report() if report else None
+    st = LIB.wt_step(ctx, plan, c_void_p(d_workspace), int(workspace_bytes), c_void_p(d_h), int(h_bytes),
+                     ctypes.byref(car), c_void_p(d_cur_workspace or None), int(cur_workspace_bytes),
+                     c_void_p(d_i_out), ctypes.byref(rep) if report else None)
+    if raise_on_error and st != WT_OK:
+        _check(st, "wt_step", ctx)
+    out = None
+    if report:
+        out = {name: getattr(rep, name) for name, _ in wt_h_report._fields_}
+    return st, out
 
 
 def wt_context_set_tune_cache(ctx, path, raise_on_error: bool = True) -> int:
