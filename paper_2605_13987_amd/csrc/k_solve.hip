@@ -666,7 +666,6 @@ k_solve_schur(Plan p, const double* A, const c64* rhs, c64* qw, SolveReport* rep
             a[ii][jj] = (i < m && j < m) ? st(i, j) : c64{0.0, 0.0};
         }
 
-    double umax = 0.0, umin = 1e308;
 #pragma unroll
     for (int kq = 0; kq < NB; ++kq)                        // local index of column k: compile-time
     for (int k32 = 0; k32 < 32; ++k32) {
@@ -741,9 +740,6 @@ k_solve_schur(Plan p, const double* A, const c64* rhs, c64* qw, SolveReport* rep
         __syncthreads();
         const c64 pivot = ubuf[k];
         if (tid == 0) diag[k] = pivot;
-        const double pm = cmod(pivot);
-        umax = fmax(umax, pm);
-        umin = fmin(umin, pm);
         const c64 ip = cinv(pivot);
         if (cc == k32) {                                   // multipliers of column k
 #pragma unroll
@@ -779,6 +775,16 @@ k_solve_schur(Plan p, const double* A, const c64* rhs, c64* qw, SolveReport* rep
         }
     }
     __syncthreads();
+    // pivot growth from the pivots kept in diag (not carried through the
+    // elimination, where the two extra live values spilled to scratch)
+    double umax = 0.0, umin = 1e308;
+    for (int i = tid; i < m; i += blockDim.x) {
+        const double pm = cmod(diag[i]);
+        umax = fmax(umax, pm);
+        umin = fmin(umin, pm);
+    }
+    umax = block_max(umax, red);
+    umin = -block_max(-umin, red);
 
     // right-hand sides: applied voltages (ADJ: the given ones) and ones, permuted
     const c64* bf = ADJ ? rhs + (size_t)f * p.n : nullptr;
