@@ -79,6 +79,33 @@ __device__ inline void stockham_pass(const cplx<T>* a, cplx<T>* b, int N, int nf
     }
 }
 
+// stockham_pass with the transform length N and the span P of the passes
+// already applied fixed at compile time: the index arithmetic becomes shifts
+// and masks (N a power of two).
+template <typename T, int R, int N, int P>
+__device__ inline void stockham_pass_pow2(const cplx<T>* a, cplx<T>* b, int nfft, const cplx<T>* tw, int tid,
+                                          int nthr) {
+    constexpr int m = N / R;
+    constexpr int tws = N / (P * R);
+    for (int idx = tid; idx < nfft * m; idx += nthr) {
+        const int f = idx / m;
+        const int i = idx - f * m;
+        const int k = i % P;
+        const cplx<T>* src = a + f * N;
+        cplx<T> x[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) x[q] = src[i + q * m];
+        if (k != 0) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) x[q] = x[q] * tw[q * k * tws];
+        }
+        butterfly<T, R>(x);
+        cplx<T>* dst = b + f * N + (i - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst[q * P] = x[q];
+    }
+}
+
 // nfft transforms of length N stored back to back in a; b is scratch of the
 // same size.  Returns the buffer holding the result.  Ends with a barrier.
 template <typename T>
@@ -101,6 +128,21 @@ __device__ cplx<T>* fft_inverse_lds(cplx<T>* a, cplx<T>* b, int N, int nfft, con
         p *= r;
     }
     return a;
+}
+
+// fft_inverse_lds for a power of two N known at compile time, with the
+// radices in factorize()'s order (4 while four divides what is left, then 2),
+// so that the results equal the general form's bit for bit.
+template <typename T, int N, int P = 1>
+__device__ cplx<T>* fft_inverse_lds_pow2(cplx<T>* a, cplx<T>* b, int nfft, const cplx<T>* tw) {
+    if constexpr (P >= N) {
+        return a;
+    } else {
+        constexpr int R = (N / P) % 4 == 0 ? 4 : 2;
+        stockham_pass_pow2<T, R, N, P>(a, b, nfft, tw, threadIdx.x, blockDim.x);
+        __syncthreads();
+        return fft_inverse_lds_pow2<T, N, P * R>(b, a, nfft, tw);
+    }
 }
 
 }  // namespace wt

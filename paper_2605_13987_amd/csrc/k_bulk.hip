@@ -65,13 +65,14 @@ __global__ void __launch_bounds__(kBlock) k_multiplier(Plan p, int deriv, cplx<T
 // In-place inverse FFTs along one grid axis of a strided array.  Line l has
 // its first element at (l / n_inner) * outer_stride + (l % n_inner) and its
 // elements elem_stride apart; a block transforms lpb lines with consecutive
-// inner index so that loads and stores touch contiguous runs.
-template <typename T>
+// inner index so that loads and stores touch contiguous runs.  NC: the
+// line length when it is a power of two fixed at compile time, else 0.
+template <typename T, int NC>
 __global__ void __launch_bounds__(kBlock)
 k_fft_lines(Plan p, int axis, cplx<T>* data, int n_inner, int n_lines, size_t outer_stride,
             size_t elem_stride, int lpb, const cplx<T>* tw) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = p.N[axis];
+    const int N = NC > 0 ? NC : p.N[axis];
     cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* b = a + (size_t)lpb * N;
     const int l0 = blockIdx.x * lpb;
@@ -83,7 +84,11 @@ k_fft_lines(Plan p, int axis, cplx<T>* data, int n_inner, int n_lines, size_t ou
         a[f * N + e] = data[base + e * elem_stride];
     }
     __syncthreads();
-    const cplx<T>* res = fft_inverse_lds<T>(a, b, N, nl, p.rad[axis], p.nrad[axis], tw);
+    const cplx<T>* res;
+    if constexpr (NC > 0)
+        res = fft_inverse_lds_pow2<T, NC>(a, b, nl, tw);
+    else
+        res = fft_inverse_lds<T>(a, b, N, nl, p.rad[axis], p.nrad[axis], tw);
     for (int idx = threadIdx.x; idx < nl * N; idx += blockDim.x) {
         const int e = idx / nl, f = idx - e * nl;
         const int l = l0 + f;
@@ -282,8 +287,17 @@ hipError_t field_table(const Plan& p, char* b, cplx<T>* e, int deriv, hipStream_
             elem = (size_t)p.N[1] * C;
         }
         const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(b + p.off_tw[axis]);
-        hipLaunchKernelGGL(k_fft_lines<T>, dim3((n_lines + lpb - 1) / lpb), dim3(kBlock), lds, s, p, axis, e, C,
-                           n_lines, outer, elem, lpb, tw);
+        auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, dim3((n_lines + lpb - 1) / lpb), dim3(kBlock), lds, s, p, axis, e, C,
+                               n_lines, outer, elem, lpb, tw);
+        };
+        switch (N) {
+            case 64: go(k_fft_lines<T, 64>); break;
+            case 128: go(k_fft_lines<T, 128>); break;
+            case 256: go(k_fft_lines<T, 256>); break;
+            case 512: go(k_fft_lines<T, 512>); break;
+            default: go(k_fft_lines<T, 0>); break;
+        }
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }

@@ -65,6 +65,10 @@ template <typename T, int N1, int N2, int WC, typename TO, int TB>
 __global__ void __launch_bounds__(pipe_shape_for(N1 * N2, N1, TB).threads)
 k_synthesis_pipe(Plan p, const cplx<T>* ehat, const cplx<T>* qhat, const cplx<T>* twz, const float* h_scale,
                  TO* H) {
+    // Issue priority above the current's binning, which can run beside this
+    // launch on another stream: 256 x 256 x 512 step 65.2 -> 64.5 ms (the
+    // synthesis 40.3 -> 39.6 ms; the binning still ends within it).
+    __builtin_amdgcn_s_setprio(3);
     constexpr int NZ = N1 * N2;
     constexpr int NZH = NZ / 2;
     constexpr PipeShape SH = pipe_shape_for(NZ, N1, TB);
