@@ -46,8 +46,8 @@ TRAFFIC = {
     # (kernel, workload key): (bytes per launch, sha256 of the sources)
     ("k_conv_rows", "256x256x512 f16"): (72604829901, "ef69c7e8751f507d0a92be1033aa56c6051a2113290b6e13c73d35b4d21db733"),
     ("k_conv_rows", "256x256x512 f32"): (141882414080, "ef69c7e8751f507d0a92be1033aa56c6051a2113290b6e13c73d35b4d21db733"),
-    ("k_synthesis_pipe", "256x256x512 f16"): (81350514483, "af09595e88c0f52bc93f131321fdb7a2bbb76bf2d0c6fd4bd3ea596ec210d242"),
-    ("k_synthesis_pipe", "256x256x512 f32"): (161883216384, "af09595e88c0f52bc93f131321fdb7a2bbb76bf2d0c6fd4bd3ea596ec210d242"),
+    ("k_synthesis_pipe", "256x256x512 f16"): (81350517350, "c64640e836734f70f6c195163eb46c79b6c9df4dddd3a2c7c924d6dcccc5a169"),
+    ("k_synthesis_pipe", "256x256x512 f32"): (161883178394, "c64640e836734f70f6c195163eb46c79b6c9df4dddd3a2c7c924d6dcccc5a169"),
 }
 KERNEL_SOURCES = {
     "k_synthesis_pipe": ("k_bulk.hip", "synth_pipe.hpp", "fft.hpp"),
