@@ -502,6 +502,24 @@ hipError_t launch_current_phase(const wt_context* ctx, const Plan& p, const void
                               max_blocks);
 }
 
+// The accumulation on stream s: the overflow list on the context's third
+// stream beside the node-column rows (both only add into the output), joined
+// back by an event; under stream capture, one launch sequence on s.
+wt_status accumulate(wt_context* ctx, const Plan& p, const void* d_h, const CurrentCall& c, hipStream_t s,
+                     bool beside) {
+    if (!beside) {
+        WT_HIP(ctx, launch_current_phase(ctx, p, d_h, c, s, 2), "current");
+        return WT_OK;
+    }
+    WT_HIP(ctx, hipEventRecord(ctx->bin_fork, s), "hipEventRecord");
+    WT_HIP(ctx, hipStreamWaitEvent(ctx->bin, ctx->bin_fork, 0), "hipStreamWaitEvent");
+    WT_HIP(ctx, launch_current_phase(ctx, p, d_h, c, ctx->bin, 3), "current overflow");
+    WT_HIP(ctx, hipEventRecord(ctx->bin_join, ctx->bin), "hipEventRecord");
+    WT_HIP(ctx, launch_current_phase(ctx, p, d_h, c, s, 4), "current");
+    WT_HIP(ctx, hipStreamWaitEvent(s, ctx->bin_join, 0), "hipStreamWaitEvent");
+    return WT_OK;
+}
+
 // Workgroups of the binning kernels beside the synthesis: the fewest that
 // still let the binning end within the synthesis, so that the synthesis
 // workgroups (one per compute unit at N_z = 512) keep finding room.  At
@@ -561,7 +579,7 @@ wt_status solve_on(wt_context* ctx, const Plan& p, void* d_workspace, void* d_h,
         else
             WT_HIP(ctx, launch_current_phase(ctx, p, d_h, *cur, s, 1), "current_binning");
         if ((st = mark(ctx, kStageCurrentBinning)) != WT_OK) return st;
-        WT_HIP(ctx, launch_current_phase(ctx, p, d_h, *cur, s, 2), "current");
+        if ((st = accumulate(ctx, p, d_h, *cur, s, beside)) != WT_OK) return st;
         if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
     }
     if (!report) return WT_OK;
@@ -814,7 +832,9 @@ wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h, co
     const CurrentCall c{car, d_workspace, workspace_bytes, d_i_out};
     WT_HIP(ctx, launch_current_phase(ctx, p, d_h, c, ctx->stream, 1), "current_binning");
     if ((st = mark(ctx, kStageCurrentBinning)) != WT_OK) return st;
-    WT_HIP(ctx, launch_current_phase(ctx, p, d_h, c, ctx->stream, 2), "current");
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    WT_HIP(ctx, hipStreamIsCapturing(ctx->stream, &capture), "hipStreamIsCapturing");
+    if ((st = accumulate(ctx, p, d_h, c, ctx->stream, capture == hipStreamCaptureStatusNone)) != WT_OK) return st;
     if ((st = mark(ctx, kStageCurrent)) != WT_OK) return st;
     return WT_OK;
 }

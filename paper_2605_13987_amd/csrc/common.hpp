@@ -202,7 +202,8 @@ inline CurrentLayout current_layout(const Plan& p, const ConvTiling& t, long lon
 inline size_t current_event_bytes(const Plan& p) { return 4 * (size_t)(p.precision == 0 ? 64 : 32); }
 // d_ws may be null (then one wavefront per carrier, no binning).  phase 1:
 // zero the output and bin the events; phase 2 (after phase 1 on the same
-// stream): accumulate.  form: 0 binned from kBinnedMinSteps polyline steps
+// stream): accumulate; phases 4 and 3 (each after phase 1, in either order
+// or at once): phase 2 without, and with only, the overflow list.  form: 0 binned from kBinnedMinSteps polyline steps
 // on, 1 binned whenever there is a workspace, 2 never binned.  max_blocks >
 // 0 caps the grids of the largest binning kernels (0: one wavefront per
 // carrier and per node column).

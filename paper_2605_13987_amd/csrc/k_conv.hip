@@ -1048,6 +1048,9 @@ k_conv_overflow(Plan p, const TH* __restrict__ H, const float* __restrict__ deco
 // phase 1: the output zeroed and the events binned; phase 2: the
 // accumulation (binned, or the unbinned kernel when the events did not fit
 // or there is no workspace).  Phase 2 follows phase 1 on the same stream.
+// Phase 2 split in two for two streams: phase 4 is the accumulation without
+// the overflow list, phase 3 the overflow list alone (nothing when the form
+// is not binned); both only add into the output, so they may run at once.
 // max_blocks > 0 caps the grids of the per-carrier and per-column binning
 // kernels (their wavefronts stride over the work).
 template <typename T, typename TH>
@@ -1128,15 +1131,19 @@ hipError_t current(const Plan& p, const void* h, int n_carriers, int n_tracks, c
                                static_cast<const TH*>(h), decode, offs, rec, tables, ctl,
                                static_cast<T*>(out));
         };
-        // tiles of conv_tile_nodes(sizeof(TH)) z-nodes
-        rows(k_conv_rows<conv_tile_nodes(sizeof(TH)), T, TH>);
-        if (e != hipSuccess) return e;
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_conv_overflow<T, TH>), dim3(1024), dim3(kBlock), 0, s, p, static_cast<const TH*>(h),
-                           decode, rec, ctl, static_cast<T*>(out));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (phase != 3) {
+            // tiles of conv_tile_nodes(sizeof(TH)) z-nodes
+            rows(k_conv_rows<conv_tile_nodes(sizeof(TH)), T, TH>);
+            if (e != hipSuccess) return e;
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if (phase != 4) {
+            hipLaunchKernelGGL((k_conv_overflow<T, TH>), dim3(1024), dim3(kBlock), 0, s, p,
+                               static_cast<const TH*>(h), decode, rec, ctl, static_cast<T*>(out));
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
-    if (phase == 1) return hipSuccess;
+    if (phase == 1 || phase == 3) return hipSuccess;
     // the carriers of workgroup b come from a permutation of [0, 8 * per_xcd)
     // workgroups (some past the last carrier, which then do nothing)
     const int blocks = (n_carriers + kBlock / kWave - 1) / (kBlock / kWave);
