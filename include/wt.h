@@ -320,7 +320,10 @@ wt_status wt_current_workspace(const wt_h_plan* plan, int n_carriers, long long 
  * without a workspace in the same call (same results, nothing synchronises).
  * d_workspace NULL: one wavefront per carrier gathering its steps' corners.
  * Summation order across carriers is not fixed (atomic accumulation), so
- * results can differ in the last bits. */
+ * results can differ in the last bits.  Outside stream capture the binned
+ * form adds its overflow records (tracks past a column's table) on a stream
+ * of the context beside the node-column accumulation, forked from and joined
+ * back to the context's stream by events; the call stays stream-ordered. */
 wt_status wt_current(wt_context* ctx, const wt_h_plan* plan, const void* d_h,
                      const wt_carriers* carriers, void* d_workspace, size_t workspace_bytes,
                      void* d_i_out);
