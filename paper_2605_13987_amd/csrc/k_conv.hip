@@ -816,6 +816,9 @@ k_conv_rows(Plan p, ConvTiling tl, const TH* __restrict__ H, const float* __rest
             const unsigned* __restrict__ offs, const NodeRec<T>* __restrict__ rec, const int* __restrict__ tables,
             const unsigned long long* __restrict__ ctl, T* __restrict__ out) {
     if (ctl[kCtlFallback] != 0ull) return;               // the direct form takes these events
+    // issue priority above the overflow kernel beside this one (22.12 ->
+    // 21.93 ms at 256 x 256 x 512 with float16 H)
+    __builtin_amdgcn_s_setprio(3);
     const int Nz = p.N[2], nt = p.n_time;
     const size_t col = blockIdx.x;
     const unsigned* no = offs + col * Nz;
