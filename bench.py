@@ -44,8 +44,8 @@ CSRC = os.path.join(ROOT, "paper_2605_13987_amd", "csrc")
 # Summaries and commands in profiles/.
 TRAFFIC = {
     # (kernel, workload key): (bytes per launch, sha256 of the sources)
-    ("k_conv_rows", "256x256x512 f16"): (72609987482, "4daa2dc012a342bd82f56ed055c82c9a966e2a6c71cbcf38b836cdc3c5c2d9d5"),
-    ("k_conv_rows", "256x256x512 f32"): (141869120614, "4daa2dc012a342bd82f56ed055c82c9a966e2a6c71cbcf38b836cdc3c5c2d9d5"),
+    ("k_conv_rows", "256x256x512 f16"): (72621669683, "a5ecf5851691dc0a8998d74e9d1d30fce2270717b33ccd8182b297a97316a3c2"),
+    ("k_conv_rows", "256x256x512 f32"): (141839833088, "a5ecf5851691dc0a8998d74e9d1d30fce2270717b33ccd8182b297a97316a3c2"),
     ("k_synthesis_pipe", "256x256x512 f16"): (81350517350, "c64640e836734f70f6c195163eb46c79b6c9df4dddd3a2c7c924d6dcccc5a169"),
     ("k_synthesis_pipe", "256x256x512 f32"): (161883178394, "c64640e836734f70f6c195163eb46c79b6c9df4dddd3a2c7c924d6dcccc5a169"),
 }
