@@ -4,7 +4,9 @@
 One step = the whole hot path on one batch of synthetic input: Green's tables,
 collocation solves for all frequencies, time transform, in-plane field table,
 synthesis of H(x, y, z, t) on the whole grid, and the Eq. 1 current of all
-carriers.  Inputs are resident on the GPU before timing.
+carriers.  Inputs are resident on the GPU before timing.  Each step is one
+wt_step call (H solve then current, the current's binning on a second
+stream beside the synthesis).
 
 Headline workload: periodic 50x50x300 um pixel on a 256x256x512 grid, five
 seeded column resistivities, 512 frequencies up to 50 GHz, 400 samples of
