@@ -600,6 +600,7 @@ template <int NB, bool ADJ>
 __global__ void __launch_bounds__(1024)
 k_solve_schur(Plan p, const double* A, const c64* rhs, c64* qw, SolveReport* rep) {
     constexpr int NM = 32 * NB;
+    static_assert(NM <= 256, "the pivot key holds the row in 8 bits");
     __shared__ c64 ubuf[NM];
     __shared__ c64 lbuf[NM];
     __shared__ c64 row_k[NM];
@@ -672,25 +673,25 @@ k_solve_schur(Plan p, const double* A, const c64* rhs, c64* qw, SolveReport* rep
         const int k = 32 * kq + k32;
         if (k >= m) break;
         if (cc == k32) {                                   // pivot search in column k
-            double best = -1.0;
-            int bi = m;
+            // One 32-bit key per candidate: the high word of |re| + |im|
+            // (exponent and 20 mantissa bits) with its low 8 bits replaced by
+            // 255 - row.  One integer maximum (one shuffle per step) then
+            // picks the largest magnitude to 12 mantissa bits and, among
+            // magnitudes that agree that far, the first row.
+            unsigned key = 0u;
 #pragma unroll
             for (int ii = 0; ii < NB; ++ii) {
                 const int i = r + 32 * ii;
                 const c64 v = a[ii][kq];
                 if (i >= k && i < m) {
-                    const double mm = cabs1(v);
-                    if (mm > best) { best = mm; bi = i; }
+                    const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(cabs1(v)) >> 32);
+                    key = max(key, (hi & ~255u) | (unsigned)(255 - i));
                 }
             }
-            for (int o = 16; o > 0; o >>= 1) {
-                const double ov = __shfl_xor(best, o, 32);
-                const int oi = __shfl_xor(bi, o, 32);
-                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-            }
+            for (int o = 16; o > 0; o >>= 1) key = max(key, (unsigned)__shfl_xor((int)key, o, 32));
             if (r == 0) {
-                sh_piv = bi;
-                sh_pval = best;
+                sh_piv = key ? 255 - (int)(key & 255u) : k;
+                sh_pval = (key >> 8) ? 1.0 : 0.0;          // 0: the column is zero (singular)
             }
         }
         __syncthreads();
